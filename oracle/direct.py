@@ -1,0 +1,121 @@
+"""Direct sums of the domain Green's function (the definition of the matvec).
+
+Test infrastructure only (see the package docstring).
+
+Paper passages followed:
+* Section 2.4: phi(x) = int u_{x0}(x) rho(x0) dx0, discretised as A v with
+  A_ij = u_{x_j}(x_i).
+* Section 2.1, Eq. freeGreen: g = (i/4) H0^(1)(k1 |x - x0|).
+* Section 2.3, Eq. multitop: the scattered part (see ``sommerfeld``).
+
+Self term (the paper is silent): the free term is dropped for i = j by index,
+the scattered self term G^s(x_i, x_i) is kept.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import hankel1
+
+from .media import Media
+from .sommerfeld import _SHARED, _workers, scattered_matvec, scattered_pairs
+
+_FREE = {}
+
+
+def _free_block(bounds):
+    d = _FREE
+    i0, i1 = bounds
+    xt, yt, tid = d["xt"][i0:i1], d["yt"][i0:i1], d["tid"][i0:i1]
+    xs, ys, q, k = d["xs"], d["ys"], d["q"], d["k"]
+    u = np.zeros((q.shape[0], i1 - i0), dtype=complex)
+    step = max(1, 2_000_000 // max(1, i1 - i0))
+    for j0 in range(0, xs.size, step):
+        j1 = min(xs.size, j0 + step)
+        r = np.hypot(xt[:, None] - xs[None, j0:j1], yt[:, None] - ys[None, j0:j1])
+        same = tid[:, None] == np.arange(j0, j1)[None, :]
+        r = np.where(same, 1.0, r)
+        h = hankel1(0, k * r)
+        h = np.where(same, 0.0, h)
+        u += q[:, j0:j1] @ h.T
+    return 0.25j * u
+
+
+def free_matvec(k1, xt, yt, xs, ys, q, target_ids=None, workers=None):
+    """u_i = (i/4) sum_{j != id_i} H0^(1)(k1 |x_i - x_j|) q_j.
+
+    ``target_ids[i]`` is the source index that coincides with target i (its
+    term is dropped), or -1. q is (nrhs, Ns) or (Ns,).
+    """
+    xt = np.asarray(xt, float)
+    yt = np.asarray(yt, float)
+    q = np.asarray(q, complex)
+    squeeze = q.ndim == 1
+    q = np.atleast_2d(q)
+    if target_ids is None:
+        target_ids = -np.ones(xt.size, dtype=np.int64)
+    _FREE.update(xt=xt, yt=yt, tid=np.asarray(target_ids, np.int64), xs=np.asarray(xs, float),
+                 ys=np.asarray(ys, float), q=q, k=k1)
+    workers = workers or _workers()
+    nt = xt.size
+    if workers > 1 and nt * len(xs) > 2e7:
+        import multiprocessing as mp
+        nchunk = min(nt, workers * 4)
+        edges = np.linspace(0, nt, nchunk + 1).astype(int)
+        tasks = [(int(edges[i]), int(edges[i + 1])) for i in range(nchunk) if edges[i + 1] > edges[i]]
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_free_block, tasks)
+        u = np.concatenate(parts, axis=1)
+    else:
+        u = _free_block((0, nt))
+    _FREE.clear()
+    return u[0] if squeeze else u
+
+
+def direct_apply(media: Media, xy, q, targets=None, *, self_term=True, refine=1.0, workers=None):
+    """(A q)_i for i in ``targets`` (all points if None); caller's frame.
+
+    xy: (N, 2) points, all strictly above the top interface; q: (N,) or
+    (nrhs, N). Returns (len(targets),) or (nrhs, len(targets)).
+    """
+    xy = np.asarray(xy, float)
+    q = np.asarray(q, complex)
+    n = xy.shape[0]
+    tid = np.arange(n) if targets is None else np.asarray(targets, np.int64)
+    x = xy[:, 0]
+    y = media.to_frame(xy[:, 1])
+    if np.any(y <= 0):
+        raise ValueError("points must lie strictly above the top interface")
+    uf = free_matvec(media.k1, x[tid], y[tid], x, y, q, target_ids=tid, workers=workers)
+    us = scattered_matvec(media, x[tid], y[tid], x, y, q, refine=refine, workers=workers)
+    if not self_term:
+        gs_self = scattered_pairs(media, np.zeros(tid.size), 2.0 * y[tid], refine=refine)
+        qq = np.atleast_2d(q)[:, tid]
+        us = us - (gs_self[None, :] * qq).reshape(us.shape)
+    return uf + us
+
+
+def dense_matrix(media: Media, xy, *, refine=1.0):
+    """The dense N x N matrix A (small N only): column j = A applied to e_j."""
+    xy = np.asarray(xy, float)
+    n = xy.shape[0]
+    eye = np.eye(n, dtype=complex)
+    return direct_apply(media, xy, eye, refine=refine, workers=1).T
+
+
+def column(media: Media, xy_targets, x_src, y_src, *, refine=1.0):
+    """A(:, j) for one source at (x_src, y_src) evaluated at the given targets.
+
+    No self exclusion: the caller drops a coincident target if needed.
+    """
+    xy_targets = np.asarray(xy_targets, float)
+    x = xy_targets[:, 0]
+    y = media.to_frame(xy_targets[:, 1])
+    ys = float(media.to_frame(y_src))
+    r = np.hypot(x - x_src, y - ys)
+    free = 0.25j * hankel1(0, media.k1 * r)
+    sc = scattered_matvec(media, x, y, np.array([x_src]), np.array([ys]), np.array([1.0 + 0j]),
+                          refine=refine, workers=1)
+    return free + sc
+
+
+__all__ = ["free_matvec", "direct_apply", "dense_matrix", "column", "_SHARED"]
