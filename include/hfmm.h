@@ -1,0 +1,145 @@
+/*
+ * hfmm.h - C interface of the MI355X heterogeneous FMM for the 2-D Helmholtz
+ * equation in two- and three-layer media.
+ *
+ * The library applies the matrix A with entries A_ij = u_{x_j}(x_i), the
+ * domain Green's function of the layered medium evaluated at target x_i for a
+ * unit source at x_j (the discretised potential of Section 2.4 of Cho, Huang,
+ * Chen and Cai, "A heterogeneous FMM for 2-D layered media Helmholtz equation
+ * I"). Sources and targets are the same N points, all in the top layer
+ * (Section 2.3). The Green's function is the free-space part
+ * (i/4) H0^(1)(k1 |x - x0|) (Eq. freeGreen) plus the top-layer scattered field
+ * given by the Sommerfeld integral with the reflection function sigma_1
+ * (Eq. multitop); sigma_1 is the solution of the interface system of
+ * Section 2.3 (two layers: the same system with k3 = k2).
+ *
+ * Self term: the singular free term i = j is left out; the smooth scattered
+ * self term G^s(x_i, x_i) is included (HFMM_SELF_NONE drops it).
+ *
+ * Conventions shared by every call:
+ *  - All arrays named "device" live in GPU memory of the current device; the
+ *    caller owns them. The plan copies what it needs and keeps no caller
+ *    pointer after a call returns.
+ *  - Work is enqueued on the given stream and is asynchronous unless stated.
+ *  - Complex values are interleaved (re, im) doubles; a complex array with
+ *    "nrhs" right-hand sides is laid out [nrhs][n].
+ *  - Points are interleaved (x, y) doubles, [n][2], in the caller's frame:
+ *    interfaces are horizontal lines y = interfaces[i].
+ *  - Errors are reported by status code only. Argument and domain checks run
+ *    on the host before any launch. hfmm_last_error_message() returns a
+ *    thread-local description of the last failure.
+ */
+#ifndef HFMM_H
+#define HFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hfmm_plan_s *hfmm_plan_t;
+typedef void *hfmm_stream_t; /* a hipStream_t; NULL is the null stream */
+
+typedef enum {
+  HFMM_OK = 0,
+  HFMM_ERR_INVALID_ARG = 1, /* NULL pointer, bad size, bad option value */
+  HFMM_ERR_DOMAIN = 2,      /* point on/below the top interface, non-finite
+                               value, coincident points */
+  HFMM_ERR_UNSUPPORTED = 3, /* layers not 2 or 3, k <= 0, a lower layer with
+                               a smaller wavenumber than the top layer */
+  HFMM_ERR_NO_MEMORY = 4,
+  HFMM_ERR_DEVICE = 5,      /* a HIP runtime error */
+  HFMM_ERR_ACCURACY = 6     /* the tolerance cannot be met (expansion order
+                               above its cap, or out of FP64 range) */
+} hfmm_status_t;
+
+enum { HFMM_SELF_SCATTERED = 0, HFMM_SELF_NONE = 1 };
+enum { HFMM_FP64 = 0 };
+
+typedef struct {
+  int32_t struct_size;      /* sizeof(hfmm_options_t) */
+  int32_t leaf_size;        /* max points per leaf box; default 64 */
+  int32_t precision;        /* HFMM_FP64 */
+  int32_t self_term;        /* HFMM_SELF_SCATTERED (default) or HFMM_SELF_NONE */
+  int32_t interface_refine; /* 1 (default): refine boxes touching the bottom
+                               row until every image pair is admissible;
+                               0: leave such pairs to direct Sommerfeld
+                               quadrature */
+  int32_t max_level;        /* deepest tree level; default 24 */
+} hfmm_options_t;
+
+typedef struct {
+  int32_t levels;           /* number of tree levels (root = level 0) */
+  int32_t order[32];        /* expansion order P_l per level (0 if unused) */
+  int64_t boxes, leaves;
+  int64_t m2l_pairs;        /* free-space multipole-to-local pairs */
+  int64_t image_pairs;      /* heterogeneous (image) multipole-to-local pairs */
+  int64_t p2p_pairs;        /* free-space direct point pairs */
+  int64_t interface_pairs;  /* direct Sommerfeld point pairs */
+  int64_t image_tables;     /* heterogeneous translation tables generated */
+  double flops_m2l;         /* algorithmic flops of one apply, per RHS */
+  double flops_updown;      /* P2M + M2M + L2L + L2P */
+  double flops_p2p;         /* direct pairs (H0 cost counted as 1 pair) */
+  double plan_seconds;
+} hfmm_info_t;
+
+/* Default options. */
+void hfmm_default_options(hfmm_options_t *opts);
+
+/*
+ * Build a plan: tree, interaction lists, expansion orders and translation
+ * tables (Algorithm 1, step 1; tables by FP64 quadrature of the Sommerfeld
+ * form of the multipole-to-local operator, Section 3.3 Eq. m2loperator with
+ * sigma_1 as in Section 5).
+ *   layers       2 or 3.
+ *   wavenumbers  host [layers], top layer first, > 0; every lower layer must
+ *                have k_j >= k_1.
+ *   interfaces   host [layers-1], strictly decreasing heights.
+ *   n            number of points, >= 1.
+ *   points       device [n][2] doubles; every y strictly above interfaces[0].
+ *   tol          requested relative accuracy, in [1e-14, 1e-2].
+ *   opts         NULL for defaults.
+ * On success *out owns the plan; release it with hfmm_destroy. The call
+ * synchronises the stream (the tree is built from the points on the host).
+ */
+hfmm_status_t hfmm_plan(hfmm_plan_t *out, int32_t layers, const double *wavenumbers,
+                        const double *interfaces, int64_t n, const double *points, double tol,
+                        const hfmm_options_t *opts, hfmm_stream_t stream);
+
+/*
+ * u = A q (Algorithm 1, steps 2-5).
+ *   q  device complex [nrhs][n], user point order.
+ *   u  device complex [nrhs][n], written (not accumulated).
+ * q and u must not overlap. nrhs >= 1.
+ */
+hfmm_status_t hfmm_apply(hfmm_plan_t plan, const double *q, double *u, int32_t nrhs,
+                         hfmm_stream_t stream);
+
+/*
+ * w = A^H v, the conjugate transpose, and optionally the gradient of
+ * Re <v, A q> with respect to the source coordinates.
+ *   v        device complex [nrhs][n].
+ *   w        device complex [nrhs][n], written.
+ *   q        device complex [nrhs][n] or NULL (needed only for grad_xy).
+ *   grad_xy  device [n][2] doubles or NULL: grad_xy[j] =
+ *            sum_r Re( sum_i conj(v_ri) q_rj dA_ij/d(x_j, y_j) ), targets held
+ *            fixed (the gradient of Re <v, A q> in the source positions).
+ */
+hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t plan, const double *v, double *w, int32_t nrhs,
+                                 const double *q, double *grad_xy, hfmm_stream_t stream);
+
+/* Plan statistics (host struct, filled synchronously). */
+hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
+
+/* Release a plan and its device memory (synchronises the device). NULL is a no-op. */
+void hfmm_destroy(hfmm_plan_t plan);
+
+const char *hfmm_status_string(hfmm_status_t status);
+const char *hfmm_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HFMM_H */

@@ -1,0 +1,202 @@
+"""Python binding of the MI355X layered-media heterogeneous FMM (libhfmm.so).
+
+Argument marshalling only: every stage of the matvec runs in the HIP library.
+PyTorch provides device memory and the current stream. The library must have
+been built (``python -m paper_1703_09136_amd.build``); nothing here falls back
+to another implementation.
+
+Entry points mirror the C interface (include/hfmm.h):
+  Plan(k, interfaces, points, tol, ...)   -> hfmm_plan
+  Plan.apply(q)                           -> hfmm_apply          (u = A q)
+  Plan.apply_adjoint(v)                   -> hfmm_apply_adjoint  (w = A^H v)
+  Plan.info()                             -> hfmm_plan_info
+  HFMMApply.apply(q, plan)                -> autograd: forward A q, backward A^H g
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhfmm.so")
+
+HFMM_OK = 0
+STATUS_NAMES = {0: "HFMM_OK", 1: "HFMM_ERR_INVALID_ARG", 2: "HFMM_ERR_DOMAIN", 3: "HFMM_ERR_UNSUPPORTED",
+                4: "HFMM_ERR_NO_MEMORY", 5: "HFMM_ERR_DEVICE", 6: "HFMM_ERR_ACCURACY"}
+
+# every symbol declared in include/hfmm.h
+EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoint", "hfmm_plan_info",
+           "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message")
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("self_term", ctypes.c_int32), ("interface_refine", ctypes.c_int32), ("max_level", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("order", ctypes.c_int32 * 32), ("boxes", ctypes.c_int64),
+                ("leaves", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64), ("image_pairs", ctypes.c_int64),
+                ("p2p_pairs", ctypes.c_int64), ("interface_pairs", ctypes.c_int64),
+                ("image_tables", ctypes.c_int64), ("flops_m2l", ctypes.c_double),
+                ("flops_updown", ctypes.c_double), ("flops_p2p", ctypes.c_double),
+                ("plan_seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "order"}
+        d["order"] = [int(self.order[i]) for i in range(self.levels)]
+        return d
+
+
+class HFMMError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libhfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise FileNotFoundError("libhfmm.so is not built: run python -m paper_1703_09136_amd.build")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.hfmm_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.hfmm_default_options.restype = None
+    lib.hfmm_plan.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64, vp, dbl,
+                              ctypes.POINTER(Options), vp]
+    lib.hfmm_plan.restype = ctypes.c_int
+    lib.hfmm_apply.argtypes = [vp, vp, vp, i32, vp]
+    lib.hfmm_apply.restype = ctypes.c_int
+    lib.hfmm_apply_adjoint.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.hfmm_apply_adjoint.restype = ctypes.c_int
+    lib.hfmm_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.hfmm_plan_info.restype = ctypes.c_int
+    lib.hfmm_destroy.argtypes = [vp]
+    lib.hfmm_destroy.restype = None
+    lib.hfmm_status_string.argtypes = [ctypes.c_int]
+    lib.hfmm_status_string.restype = ctypes.c_char_p
+    lib.hfmm_last_error_message.argtypes = []
+    lib.hfmm_last_error_message.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != HFMM_OK:
+        raise HFMMError(status, _lib.hfmm_last_error_message().decode())
+
+
+def default_options(**kw) -> Options:
+    lib = load()
+    o = Options()
+    lib.hfmm_default_options(ctypes.byref(o))
+    for key, val in kw.items():
+        setattr(o, key, int(val))
+    return o
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _as_rhs(t, n, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128):
+        raise TypeError("%s must be a complex128 CUDA tensor" % name)
+    t2 = t.reshape(-1, n) if t.dim() != 2 else t
+    if t2.shape[1] != n:
+        raise ValueError("%s must have shape (nrhs, %d)" % (name, n))
+    return t2.contiguous()
+
+
+class Plan:
+    """A plan of the heterogeneous FMM for fixed points and medium (hfmm_plan)."""
+
+    def __init__(self, k, interfaces, points, tol=1e-8, stream=None, **options):
+        import torch
+        lib = load()
+        k = [float(v) for v in k]
+        interfaces = [float(v) for v in interfaces]
+        if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2 and points.shape[1] == 2):
+            raise TypeError("points must be a float64 CUDA tensor of shape (n, 2)")
+        pts = points.contiguous()
+        self.n = int(pts.shape[0])
+        self.k = tuple(k)
+        self.interfaces = tuple(interfaces)
+        kk = (ctypes.c_double * len(k))(*k)
+        ii = (ctypes.c_double * max(1, len(interfaces)))(*(interfaces or [0.0]))
+        opts = default_options(**options)
+        h = ctypes.c_void_p()
+        _check(lib.hfmm_plan(ctypes.byref(h), len(k), kk, ii, self.n, ctypes.c_void_p(pts.data_ptr()),
+                             float(tol), ctypes.byref(opts), _stream_ptr(stream)))
+        self._h = h
+        self._lib = lib
+
+    def apply(self, q, out=None, stream=None):
+        """u = A q for q of shape (n,) or (nrhs, n), complex128 on the GPU."""
+        import torch
+        q2 = _as_rhs(q, self.n, "q")
+        u = out if out is not None else torch.empty_like(q2)
+        _check(self._lib.hfmm_apply(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+                                    q2.shape[0], _stream_ptr(stream)))
+        return u.reshape(q.shape) if out is None else u
+
+    def apply_adjoint(self, v, q=None, grad_xy=False, stream=None):
+        """w = A^H v; with grad_xy also the source-coordinate gradient (see hfmm.h)."""
+        import torch
+        v2 = _as_rhs(v, self.n, "v")
+        w = torch.empty_like(v2)
+        qp = ctypes.c_void_p(_as_rhs(q, self.n, "q").data_ptr()) if q is not None else None
+        g = torch.zeros((self.n, 2), dtype=torch.float64, device=v2.device) if grad_xy else None
+        _check(self._lib.hfmm_apply_adjoint(self._h, ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                            v2.shape[0], qp, ctypes.c_void_p(g.data_ptr()) if g is not None else None,
+                                            _stream_ptr(stream)))
+        w = w.reshape(v.shape)
+        return (w, g) if grad_xy else w
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(self._lib.hfmm_plan_info(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hfmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _autograd():
+    import torch
+
+    class HFMMApply(torch.autograd.Function):
+        """u = A q with the hand-written adjoint as its backward (grad_q = A^H grad_u)."""
+
+        @staticmethod
+        def forward(ctx, q, plan):
+            ctx.plan = plan
+            return plan.apply(q)
+
+        @staticmethod
+        def backward(ctx, g):
+            return ctx.plan.apply_adjoint(g.contiguous()), None
+
+    return HFMMApply
+
+
+def hfmm_apply_autograd(q, plan):
+    return _autograd().apply(q, plan)

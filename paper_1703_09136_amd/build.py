@@ -1,0 +1,51 @@
+"""Build the HIP library libhfmm.so in place (gfx950).
+
+Usage: python -m paper_1703_09136_amd.build
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libhfmm.so")
+SOURCES = ["hfmm.hip", "kernels.hip"]
+ARCH = os.environ.get("HFMM_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
+        if cand and (os.path.isabs(cand) and os.path.exists(cand) or not os.path.isabs(cand)):
+            return cand
+    return "hipcc"
+
+
+def build(verbose: bool = True) -> str:
+    """Compile every source into one shared library; returns its path."""
+    objs = []
+    flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+             # packed FP32 instructions stay off (see the build notes)
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    tmp = LIB + ".tmp"
+    cmd = [hipcc()] + flags + ["-shared", "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed with status %d" % res.returncode)
+    if verbose and res.stderr.strip():
+        lines = [ln for ln in res.stderr.splitlines() if "packed-fp32-ops" not in ln]
+        if lines:
+            sys.stderr.write("\n".join(lines[:40]) + "\n")
+    os.replace(tmp, LIB)
+    del objs
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build())

@@ -1,0 +1,1024 @@
+// Host side of the layered-media heterogeneous FMM: the C interface, the plan
+// (tree, interaction lists, expansion orders, quadrature rules, tables) and the
+// apply / adjoint pipelines (Algorithm 1 of the paper).
+//
+// Interaction structure. The free-space part follows the classical FMM on the
+// adaptive quadtree (Section 3.1): same-level pairs that are not adjacent get a
+// multipole-to-local translation (V list), adjacent pairs involving a leaf are
+// evaluated directly. The scattered part uses the same multipoles through the
+// heterogeneous M2L (Section 3.3 / Section 5), but it is paired with the mirror
+// images of the source boxes: a pair of boxes at a level is "image admissible"
+// when Y = y_t + y_s >= 2b (centres, interface frame, box side b), i.e. the
+// mirrored source box is at least one box away from the target box. Admissible
+// pairs are translated at the coarsest level (>= 2) where they become
+// admissible; pairs that are still not admissible at the leaves are evaluated
+// by direct Sommerfeld quadrature (Section 5, local direct interactions,
+// strategy (b)). Keeping Y >= 2b also keeps the FP64 Sommerfeld quadrature of
+// the heterogeneous tables well conditioned at every order the level uses.
+#include "../../include/hfmm.h"
+#include "kernels.hpp"
+#include "special.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace hfmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+hfmm_status_t fail(hfmm_status_t s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(HFMM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  hipError_t alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)&p, count * sizeof(T));
+  }
+  hipError_t upload(const std::vector<T>& v, hipStream_t s) {
+    hipError_t e = alloc(v.size());
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+struct Box {
+  int level, ix, iy, begin, end, parent, quad;
+  int child[4];
+  bool leaf;
+};
+
+// 16-point Gauss-Legendre rule on [-1, 1] by Newton iteration on P_16.
+void gauss_legendre16(double* x, double* w) {
+  const int n = 16;
+  auto legendre = [&](double z, double& pn, double& dpn) {
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    pn = p1;
+    dpn = n * (z * p1 - p0) / (z * z - 1.0);
+  };
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double pn, dpn;
+    for (int it = 0; it < 100; ++it) {
+      legendre(z, pn, dpn);
+      double dz = pn / dpn;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    legendre(z, pn, dpn);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dpn * dpn);
+  }
+}
+
+// |J_n(x)| and |Y_n(x)| for the order selection (host, FP64).
+double host_absj(double x, int n) {
+  double out = 0.0;
+  bessel_j_each(x, n, [&](int m, double j) {
+    if (m == n) out = std::fabs(j);
+  });
+  return out;
+}
+// log10 |Y_n(x)| by forward recurrence (may exceed the double range in value).
+double host_log10_absy(double x, int n) {
+  double ym1 = ::y0(x), yn = ::y1(x);
+  if (n == 0) return std::log10(std::fabs(ym1));
+  double lscale = 0.0;
+  for (int m = 1; m < n; ++m) {
+    double yp1 = (2.0 * m / x) * yn - ym1;
+    ym1 = yn;
+    yn = yp1;
+    if (std::fabs(yn) > 1e200) {
+      yn *= 1e-200;
+      ym1 *= 1e-200;
+      lscale += 200.0;
+    }
+  }
+  return lscale + std::log10(std::fabs(yn));
+}
+
+// Quadrature rule of the Sommerfeld integrals for one translation (or for the
+// direct near-interface pairs with N = 0): panels for the tau part and the
+// evanescent t part, with the t contour dipping below the real axis over the
+// branch points sqrt(k_j^2 - k1^2) and the guided-mode poles between them.
+struct Rule {
+  std::vector<Panel> panels;
+  double dip = 0.0, send = 1.0;
+  bool ok = true;
+};
+constexpr size_t kMaxPanels = 100000;
+
+Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
+  Rule r;
+  const double k = m.k1;
+  xmax = std::fabs(xmax);
+  double rho = std::hypot(xmax, ymax);
+  // tau part: the phase k (Y sin tau - X cos tau) - n tau changes by at most
+  // k rho + N per unit tau; <= 4 radians per 16-point panel.
+  {
+    double kmin_over = 1e300;
+    for (double kj : {m.k2, m.k3})
+      if (kj > k) kmin_over = std::min(kmin_over, std::sqrt(kj * kj - k * k) / k);
+    double eps = (kmin_over < 1e299) ? kmin_over : 1.0;  // scale of sigma near tau = 0, pi
+    double wmax = std::min(4.0 / (k * rho + N + 1.0), M_PI / 4.0);
+    double s = 0.0;
+    while (s < M_PI) {
+      double dist = std::min(s, M_PI - s);
+      double w = std::min(wmax, 0.5 * (dist + eps));
+      double e = std::min(M_PI, s + w);
+      if (M_PI - e < 1e-3 * w) e = M_PI;
+      r.panels.push_back({s, e, 0, 0});
+      s = e;
+    }
+  }
+  // t part
+  double tj[2];
+  int nsing = 0;
+  for (double kj : {m.k2, m.k3})
+    if (kj > k) tj[nsing++] = std::sqrt(kj * kj - k * k);
+  double tsmax = 0.0, tsmin = 1e300;
+  for (int i = 0; i < nsing; ++i) {
+    tsmax = std::max(tsmax, tj[i]);
+    tsmin = std::min(tsmin, tj[i]);
+  }
+  if (nsing) {
+    r.send = 1.25 * tsmax + 1.0;
+    r.dip = std::min(1.0 / std::max(xmax, 1e-9), 0.15 * r.send);
+  } else {
+    r.send = 1.0;
+    r.dip = 0.0;
+  }
+  // end of the t range: log|z^{-N} e^{-t Y}| = -t Y + N log((t + lambda)/k)
+  auto f = [&](double t) { return -t * ymin + N * std::log((t + std::sqrt(t * t + k * k)) / k); };
+  double tpk = 0.0, fmaxv = f(0.0);
+  if (N > 0) {
+    // maximiser: N / lambda = Y  => lambda = N / Y
+    double lam = N / ymin;
+    if (lam > k) {
+      tpk = std::sqrt(lam * lam - k * k);
+      fmaxv = f(tpk);
+    }
+  }
+  double tend = std::max(tpk, 1.0);
+  while (f(tend) > fmaxv - 44.0) tend *= 1.25;
+  tend = std::max(tend, r.send + 1.0);
+  const double rate = ymax + xmax + (double)N / k;
+  const double wcap = std::max(4.0 / rate, 1e-6);
+  auto width = [&](double s) {
+    double w = wcap;
+    double h = (s < r.send) ? r.dip * std::sin(M_PI * s / r.send) : 0.0;
+    for (int i = 0; i < nsing; ++i) w = std::min(w, 0.5 * std::hypot(s - tj[i], h));
+    if (m.layers == 3 && nsing && s > tsmin - 1.0 && s < tsmax + 1.0) w = std::min(w, 0.5 * std::max(h, 1e-6));
+    return std::max(w, 1e-6);
+  };
+  double s = 0.0;
+  for (double stop : {r.send, tend}) {
+    if (stop <= s) continue;
+    while (s < stop) {
+      double w = width(s);
+      w = std::min(w, 1.5 * width(std::min(s + w, stop)));
+      double e = std::min(stop, s + w);
+      if (stop - e < 1e-3 * w) e = stop;
+      r.panels.push_back({s, e, 1, 0});
+      s = e;
+      if (r.panels.size() > kMaxPanels) {
+        r.ok = false;
+        return r;
+      }
+    }
+  }
+  return r;
+}
+
+}  // namespace
+
+struct hfmm_plan_s {
+  Medium med{};
+  double y_top = 0.0;
+  int n = 0;
+  double tol = 0.0;
+  hfmm_options_t opt{};
+  int nlev = 0;
+  double S = 1.0, x0 = 0.0, y0 = 0.0;
+  int P[HFMM_MAX_LEVELS] = {0};
+  double bsize[HFMM_MAX_LEVELS] = {0};
+  std::vector<Box> boxes;
+  std::vector<int> lev_begin;   // boxes of level l: [lev_begin[l], lev_begin[l+1])
+  int64_t ctot = 0;
+
+  DevBuf<double2> pts, ctr;
+  DevBuf<int> perm, level, parent, quad, child;
+  DevBuf<int2> prange;
+  DevBuf<int64_t> coff;
+  DevBuf<int> leaves, p2m_leaves;
+  int nleaves = 0, np2m = 0;
+  DevBuf<int> m2m_boxes, l2l_boxes;
+  std::vector<int> m2m_off, l2l_off;  // per level
+  DevBuf<int> m2l_targets, m2l_ptr, m2lT_ptr;
+  DevBuf<M2LEntry> m2l_ent, m2lT_ent;
+  int nm2l_targets = 0;
+  DevBuf<TableRef> tabs;
+  DevBuf<double2> tdata;
+  std::vector<int> m2m_tab, l2l_tab;  // per parent level: index of 4 consecutive tables
+  DevBuf<int> p2p_ptr;
+  DevBuf<int2> p2p_rng;
+  DevBuf<int> if_leaves, if_ptr;
+  DevBuf<int2> if_rng;
+  int nif_leaves = 0;
+  DevBuf<double2> qc, qky, qkx;
+  int nq = 0;
+  int ws_nrhs = 0;
+  DevBuf<double2> qs, us, alpha, beta;
+  hfmm_info_t info{};
+
+  TreeView view(int nrhs) const {
+    TreeView tv{};
+    tv.n = n;
+    tv.nboxes = (int)boxes.size();
+    tv.nlev = nlev;
+    tv.nrhs = nrhs;
+    tv.k = med.k1;
+    tv.pts = pts.p;
+    tv.ctr = ctr.p;
+    tv.level = level.p;
+    tv.prange = prange.p;
+    tv.coff = coff.p;
+    tv.child = child.p;
+    tv.parent = parent.p;
+    tv.quad = quad.p;
+    tv.ctot = ctot;
+    for (int l = 0; l < HFMM_MAX_LEVELS; ++l) tv.P[l] = P[l];
+    return tv;
+  }
+  void release_all() {
+    pts.release(); ctr.release(); perm.release(); level.release(); parent.release(); quad.release();
+    child.release(); prange.release(); coff.release(); leaves.release(); p2m_leaves.release();
+    m2m_boxes.release(); l2l_boxes.release(); m2l_targets.release(); m2l_ptr.release(); m2lT_ptr.release();
+    m2l_ent.release(); m2lT_ent.release(); tabs.release(); tdata.release(); p2p_ptr.release();
+    p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
+    qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release();
+  }
+};
+
+namespace {
+
+hfmm_status_t ensure_workspace(hfmm_plan_t pl, int nrhs) {
+  if (pl->ws_nrhs >= nrhs) return HFMM_OK;
+  HIP_TRY(pl->qs.alloc((size_t)pl->n * nrhs));
+  HIP_TRY(pl->us.alloc((size_t)pl->n * nrhs));
+  HIP_TRY(pl->alpha.alloc((size_t)std::max<int64_t>(pl->ctot, 1) * nrhs));
+  HIP_TRY(pl->beta.alloc((size_t)std::max<int64_t>(pl->ctot, 1) * nrhs));
+  pl->ws_nrhs = nrhs;
+  return HFMM_OK;
+}
+
+uint64_t spread_bits(uint32_t v) {
+  uint64_t x = v;
+  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+  x = (x | (x << 2)) & 0x3333333333333333ull;
+  x = (x | (x << 1)) & 0x5555555555555555ull;
+  return x;
+}
+
+constexpr int KEY_BITS = 30;
+
+// Expansion order of a level: the smallest P with
+// |J_{P+1}(k R)| |H_{P+1}(k (D - R))| <= eps, R = b/sqrt(2) the box radius and
+// D = 2b the closest centre distance of a translated pair.
+int choose_order(double k, double b, double eps, int& status) {
+  double R = b * std::sqrt(0.5);
+  double D = 2.0 * b;
+  status = 0;
+  for (int P = 3; P <= 1000; ++P) {
+    double j = host_absj(k * R, P + 1);
+    if (j == 0.0) return P;
+    double ly = host_log10_absy(k * (D - R), P + 1);
+    double lj = std::log10(j);
+    double hl = std::max(ly, std::log10(std::max(host_absj(k * (D - R), P + 1), 1e-300)));
+    if (lj + hl <= std::log10(eps)) return P;
+  }
+  status = 1;
+  return 1000;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hfmm_default_options(hfmm_options_t* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(hfmm_options_t);
+  o->leaf_size = 64;
+  o->precision = HFMM_FP64;
+  o->self_term = HFMM_SELF_SCATTERED;
+  o->interface_refine = 1;
+  o->max_level = 24;
+}
+
+const char* hfmm_status_string(hfmm_status_t s) {
+  switch (s) {
+    case HFMM_OK: return "ok";
+    case HFMM_ERR_INVALID_ARG: return "invalid argument";
+    case HFMM_ERR_DOMAIN: return "point outside the top layer, non-finite or coincident";
+    case HFMM_ERR_UNSUPPORTED: return "unsupported medium";
+    case HFMM_ERR_NO_MEMORY: return "out of memory";
+    case HFMM_ERR_DEVICE: return "HIP runtime error";
+    case HFMM_ERR_ACCURACY: return "tolerance not attainable";
+  }
+  return "unknown status";
+}
+
+const char* hfmm_last_error_message(void) { return g_err.c_str(); }
+
+void hfmm_destroy(hfmm_plan_t pl) {
+  if (!pl) return;
+  (void)hipDeviceSynchronize();
+  pl->release_all();
+  delete pl;
+}
+
+hfmm_status_t hfmm_plan_info(hfmm_plan_t pl, hfmm_info_t* out) {
+  if (!pl || !out) return fail(HFMM_ERR_INVALID_ARG, "null plan or output");
+  *out = pl->info;
+  return HFMM_OK;
+}
+
+hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumbers, const double* interfaces,
+                        int64_t n, const double* points, double tol, const hfmm_options_t* opts,
+                        hfmm_stream_t stream_) {
+  auto t_start = std::chrono::steady_clock::now();
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!out) return fail(HFMM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!wavenumbers || !points || (layers > 1 && !interfaces))
+    return fail(HFMM_ERR_INVALID_ARG, "NULL wavenumbers, interfaces or points");
+  if (layers != 2 && layers != 3) return fail(HFMM_ERR_UNSUPPORTED, "layers must be 2 or 3");
+  if (n < 1 || n > (int64_t)1 << 30) return fail(HFMM_ERR_INVALID_ARG, "n out of range");
+  if (!(tol >= 1e-14 && tol <= 1e-2)) return fail(HFMM_ERR_INVALID_ARG, "tol must be in [1e-14, 1e-2]");
+  hfmm_options_t o;
+  hfmm_default_options(&o);
+  if (opts) {
+    if (opts->struct_size != (int32_t)sizeof(hfmm_options_t))
+      return fail(HFMM_ERR_INVALID_ARG, "options struct_size mismatch");
+    o = *opts;
+  }
+  if (o.leaf_size < 1 || o.leaf_size > 4096) return fail(HFMM_ERR_INVALID_ARG, "leaf_size out of range");
+  if (o.precision != HFMM_FP64) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_FP64 is available");
+  if (o.self_term != HFMM_SELF_SCATTERED) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_SELF_SCATTERED is available");
+  if (o.max_level < 2 || o.max_level > KEY_BITS) return fail(HFMM_ERR_INVALID_ARG, "max_level out of range");
+  for (int i = 0; i < layers; ++i)
+    if (!(wavenumbers[i] > 0.0) || !std::isfinite(wavenumbers[i]))
+      return fail(HFMM_ERR_UNSUPPORTED, "wavenumbers must be finite and > 0");
+  for (int i = 1; i < layers; ++i)
+    if (wavenumbers[i] < wavenumbers[0])
+      return fail(HFMM_ERR_UNSUPPORTED, "a lower layer has a smaller wavenumber than the top layer");
+  for (int i = 0; i + 1 < layers; ++i)
+    if (!std::isfinite(interfaces[i])) return fail(HFMM_ERR_INVALID_ARG, "interfaces must be finite");
+  if (layers == 3 && !(interfaces[0] > interfaces[1]))
+    return fail(HFMM_ERR_INVALID_ARG, "interfaces must be strictly decreasing");
+
+  hfmm_plan_t pl = new hfmm_plan_s();
+  auto bail = [&](hfmm_status_t s) {
+    pl->release_all();
+    delete pl;
+    return s;
+  };
+  pl->n = (int)n;
+  pl->tol = tol;
+  pl->opt = o;
+  pl->y_top = interfaces[0];
+  pl->med.layers = layers;
+  pl->med.k1 = wavenumbers[0];
+  pl->med.k2 = wavenumbers[1];
+  pl->med.k3 = layers == 3 ? wavenumbers[2] : wavenumbers[1];
+  pl->med.d = layers == 3 ? interfaces[0] - interfaces[1] : 1.0;
+  const double k = pl->med.k1;
+
+  // ---- points to the host, interface frame
+  std::vector<double> hp((size_t)2 * n);
+  {
+    hipError_t e = hipMemcpyAsync(hp.data(), points, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      fail(HFMM_ERR_DEVICE, std::string("copying points: ") + hipGetErrorString(e));
+      return bail(HFMM_ERR_DEVICE);
+    }
+  }
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int64_t i = 0; i < n; ++i) {
+    double x = hp[2 * i], y = hp[2 * i + 1] - pl->y_top;
+    if (!std::isfinite(x) || !std::isfinite(y)) {
+      fail(HFMM_ERR_DOMAIN, "non-finite point " + std::to_string(i));
+      return bail(HFMM_ERR_DOMAIN);
+    }
+    if (!(y > 0.0)) {
+      fail(HFMM_ERR_DOMAIN, "point " + std::to_string(i) + " is not strictly above the top interface");
+      return bail(HFMM_ERR_DOMAIN);
+    }
+    hp[2 * i + 1] = y;
+    xmin = std::min(xmin, x); xmax = std::max(xmax, x);
+    ymin = std::min(ymin, y); ymax = std::max(ymax, y);
+  }
+  double S = std::max(xmax - xmin, ymax - ymin);
+  if (!(S > 0.0)) S = std::max(1e-3, 1e-6 * std::fabs(ymin));
+  S *= (1.0 + 1e-12);
+  pl->S = S;
+  pl->x0 = xmin;
+  pl->y0 = ymin;
+
+  // ---- Morton sort (keys of 2 x 30 bits)
+  std::vector<std::pair<uint64_t, int>> key((size_t)n);
+  const double scale = (double)(1u << KEY_BITS) / S;
+  for (int64_t i = 0; i < n; ++i) {
+    double fx = (hp[2 * i] - xmin) * scale, fy = (hp[2 * i + 1] - ymin) * scale;
+    uint32_t ix = (uint32_t)std::min(std::max(std::floor(fx), 0.0), (double)((1u << KEY_BITS) - 1));
+    uint32_t iy = (uint32_t)std::min(std::max(std::floor(fy), 0.0), (double)((1u << KEY_BITS) - 1));
+    key[i] = {spread_bits(ix) | (spread_bits(iy) << 1), (int)i};
+  }
+  std::sort(key.begin(), key.end());
+  for (int64_t i = 1; i < n; ++i)
+    if (key[i].first == key[i - 1].first) {
+      int a = key[i].second, b = key[i - 1].second;
+      if (hp[2 * a] == hp[2 * b] && hp[2 * a + 1] == hp[2 * b + 1]) {
+        fail(HFMM_ERR_DOMAIN, "coincident points " + std::to_string(b) + " and " + std::to_string(a));
+        return bail(HFMM_ERR_DOMAIN);
+      }
+    }
+
+  // ---- adaptive quadtree, breadth first (boxes of a level are contiguous, Morton order)
+  std::vector<Box>& B = pl->boxes;
+  B.push_back(Box{0, 0, 0, 0, (int)n, -1, 0, {-1, -1, -1, -1}, true});
+  pl->lev_begin.push_back(0);
+  const int maxl = std::min(o.max_level, KEY_BITS);
+  for (int l = 0;; ++l) {
+    int lb = pl->lev_begin[l], le = (int)B.size();
+    pl->bsize[l] = S / (double)(1u << l);
+    double b = pl->bsize[l];
+    bool any = false;
+    for (int bi = lb; bi < le; ++bi) {
+      int cnt = B[bi].end - B[bi].begin;
+      bool split = cnt > o.leaf_size;
+      // bottom-row boxes whose own image pair is not admissible (2 y0 < b)
+      if (o.interface_refine && B[bi].iy == 0 && 2.0 * ymin < b && cnt > 4) split = true;
+      if (l >= maxl) split = false;
+      if (!split) continue;
+      any = true;
+      B[bi].leaf = false;
+      int shift = 2 * (KEY_BITS - l - 1);
+      int s = B[bi].begin;
+      for (int q = 0; q < 4; ++q) {
+        // points of quadrant q are contiguous: upper bound of digit q
+        int e = s;
+        while (e < B[bi].end && (int)((key[e].first >> shift) & 3u) == q) ++e;
+        if (e > s) {
+          Box c{l + 1, 2 * B[bi].ix + (q & 1), 2 * B[bi].iy + (q >> 1), s, e, bi, q, {-1, -1, -1, -1}, true};
+          B[bi].child[q] = (int)B.size();
+          B.push_back(c);
+        }
+        s = e;
+      }
+    }
+    if (!any) break;
+    pl->lev_begin.push_back(le);
+  }
+  pl->nlev = (int)pl->lev_begin.size();
+  pl->lev_begin.push_back((int)B.size());
+  if (pl->nlev > HFMM_MAX_LEVELS) {
+    fail(HFMM_ERR_ACCURACY, "tree deeper than supported");
+    return bail(HFMM_ERR_ACCURACY);
+  }
+  const int nb = (int)B.size();
+
+  // ---- expansion orders (levels >= 2)
+  const double eps = tol * 0.05;
+  for (int l = 2; l < pl->nlev; ++l) {
+    int st;
+    pl->P[l] = choose_order(k, pl->bsize[l], eps, st);
+    if (st) {
+      fail(HFMM_ERR_ACCURACY, "expansion order above the cap at level " + std::to_string(l));
+      return bail(HFMM_ERR_ACCURACY);
+    }
+    // range of the free M2L table: |H_{2P}(k 2b)| must stay in FP64 range
+    double ly = host_log10_absy(2.0 * k * pl->bsize[l], 2 * pl->P[l]);
+    double lj = std::log10(std::max(host_absj(k * pl->bsize[l] * std::sqrt(0.5), pl->P[l]), 1e-308));
+    if (ly > 280.0 || lj < -280.0) {
+      fail(HFMM_ERR_ACCURACY, "expansions out of FP64 range at level " + std::to_string(l) +
+                                  " (tree too deep for this wavenumber; raise leaf_size)");
+      return bail(HFMM_ERR_ACCURACY);
+    }
+  }
+
+  // ---- coefficient offsets
+  std::vector<int64_t> coff(nb, 0);
+  int64_t ctot = 0;
+  for (int i = 0; i < nb; ++i) {
+    coff[i] = ctot;
+    if (B[i].level >= 2) ctot += 2 * pl->P[B[i].level] + 1;
+  }
+  pl->ctot = ctot;
+
+  // ---- interaction lists
+  struct PairL { int t, s; };
+  std::vector<PairL> fv, iv, fu, iu;
+  auto adjacent = [&](int t, int s) {
+    return std::abs(B[t].ix - B[s].ix) <= 1 && std::abs(B[t].iy - B[s].iy) <= 1;
+  };
+  auto kids = [&](int b, int* out) {
+    int c = 0;
+    for (int q = 0; q < 4; ++q)
+      if (B[b].child[q] >= 0) out[c++] = B[b].child[q];
+    return c;
+  };
+  std::vector<PairL> stack;
+  stack.push_back({0, 0});
+  while (!stack.empty()) {
+    PairL pr = stack.back();
+    stack.pop_back();
+    if (!adjacent(pr.t, pr.s)) {
+      fv.push_back(pr);
+    } else if (B[pr.t].leaf || B[pr.s].leaf) {
+      fu.push_back(pr);
+    } else {
+      int ct[4], cs[4];
+      int nt = kids(pr.t, ct), ns = kids(pr.s, cs);
+      for (int a = 0; a < nt; ++a)
+        for (int c = 0; c < ns; ++c) stack.push_back({ct[a], cs[c]});
+    }
+  }
+  stack.push_back({0, 0});
+  while (!stack.empty()) {
+    PairL pr = stack.back();
+    stack.pop_back();
+    int l = B[pr.t].level;
+    double b = pl->bsize[l];
+    bool adm = l >= 2 && (B[pr.t].iy + B[pr.s].iy >= 1 || 2.0 * ymin >= b);
+    if (adm) {
+      iv.push_back(pr);
+    } else if (B[pr.t].leaf || B[pr.s].leaf) {
+      iu.push_back(pr);
+    } else {
+      int ct[4], cs[4];
+      int nt = kids(pr.t, ct), ns = kids(pr.s, cs);
+      for (int a = 0; a < nt; ++a)
+        for (int c = 0; c < ns; ++c) stack.push_back({ct[a], cs[c]});
+    }
+  }
+
+  // ---- tables
+  std::vector<TableRef> tabs;
+  int64_t toff = 0;
+  auto new_table = [&](int half) {
+    tabs.push_back(TableRef{toff, half, 0});
+    toff += 2 * half + 1;
+    return (int)tabs.size() - 1;
+  };
+  std::map<std::tuple<int, int, int>, int> free_id, image_id;
+  std::vector<double> fh_dx, fh_dy;
+  std::vector<int> fh_ref;
+  struct ImgCombo { int level, dix, m; };
+  std::vector<ImgCombo> combos;
+  std::vector<int> img_ref;
+  auto free_table = [&](int l, int dx, int dy) {
+    auto key3 = std::make_tuple(l, dx, dy);
+    auto it = free_id.find(key3);
+    if (it != free_id.end()) return it->second;
+    int id = new_table(2 * pl->P[l]);
+    free_id[key3] = id;
+    fh_dx.push_back(dx * pl->bsize[l]);
+    fh_dy.push_back(dy * pl->bsize[l]);
+    fh_ref.push_back(id);
+    return id;
+  };
+  auto image_table = [&](int l, int dix, int m) {
+    auto key3 = std::make_tuple(l, dix, m);
+    auto it = image_id.find(key3);
+    if (it != image_id.end()) return it->second;
+    int id = new_table(2 * pl->P[l]);
+    image_id[key3] = id;
+    combos.push_back({l, dix, m});
+    img_ref.push_back(id);
+    return id;
+  };
+  // M2L entries grouped by target (and by source for the transpose)
+  std::vector<std::vector<M2LEntry>> by_t(nb), by_s(nb);
+  for (auto& pr : fv) {
+    int l = B[pr.t].level;
+    int id = free_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy - B[pr.s].iy);
+    by_t[pr.t].push_back({pr.s, id, 0, 0});
+    by_s[pr.s].push_back({pr.t, id, 0, 0});
+  }
+  for (auto& pr : iv) {
+    int l = B[pr.t].level;
+    int id = image_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy + B[pr.s].iy);
+    by_t[pr.t].push_back({pr.s, id, 1, 0});
+    by_s[pr.s].push_back({pr.t, id, 1, 0});
+  }
+  // M2M / L2L tables per parent level l (children at l + 1), quadrant order
+  std::vector<double> fb_dx, fb_dy;
+  std::vector<int> fb_sgn, fb_ref;
+  pl->m2m_tab.assign(pl->nlev, -1);
+  pl->l2l_tab.assign(pl->nlev, -1);
+  for (int l = 2; l + 1 < pl->nlev; ++l) {
+    double bc = pl->bsize[l + 1];
+    for (int pass = 0; pass < 2; ++pass) {
+      int base = (int)tabs.size();
+      for (int q = 0; q < 4; ++q) {
+        int id = new_table(pl->P[l] + pl->P[l + 1]);
+        fb_dx.push_back(((q & 1) ? 0.5 : -0.5) * bc);
+        fb_dy.push_back(((q >> 1) ? 0.5 : -0.5) * bc);
+        fb_sgn.push_back(pass == 0 ? -1 : 1);
+        fb_ref.push_back(id);
+      }
+      (pass == 0 ? pl->m2m_tab : pl->l2l_tab)[l] = base;
+    }
+  }
+
+  // ---- per-level box lists
+  std::vector<int> leaves, p2m_leaves, m2l_targets, m2m_boxes, l2l_boxes;
+  std::vector<int> leaf_index(nb, -1);
+  for (int i = 0; i < nb; ++i)
+    if (B[i].leaf) {
+      leaf_index[i] = (int)leaves.size();
+      leaves.push_back(i);
+      if (B[i].level >= 2) p2m_leaves.push_back(i);
+    }
+  pl->m2m_off.assign(pl->nlev + 1, 0);
+  pl->l2l_off.assign(pl->nlev + 1, 0);
+  for (int l = 0; l < pl->nlev; ++l) {
+    pl->m2m_off[l] = (int)m2m_boxes.size();
+    pl->l2l_off[l] = (int)l2l_boxes.size();
+    for (int i = pl->lev_begin[l]; i < pl->lev_begin[l + 1]; ++i) {
+      if (l >= 2 && !B[i].leaf) m2m_boxes.push_back(i);
+      if (l >= 3) l2l_boxes.push_back(i);
+    }
+  }
+  pl->m2m_off[pl->nlev] = (int)m2m_boxes.size();
+  pl->l2l_off[pl->nlev] = (int)l2l_boxes.size();
+  std::vector<int> m2l_ptr(1, 0), m2lT_ptr(1, 0);
+  std::vector<M2LEntry> m2l_ent, m2lT_ent;
+  for (int i = pl->lev_begin[std::min(2, pl->nlev)]; i < nb; ++i) {
+    m2l_targets.push_back(i);
+    m2l_ent.insert(m2l_ent.end(), by_t[i].begin(), by_t[i].end());
+    m2l_ptr.push_back((int)m2l_ent.size());
+    m2lT_ent.insert(m2lT_ent.end(), by_s[i].begin(), by_s[i].end());
+    m2lT_ptr.push_back((int)m2lT_ent.size());
+  }
+
+  // ---- direct lists, grouped by target leaf, source ranges merged
+  auto leaves_under = [&](int b, std::vector<int>& outv) {
+    std::vector<int> st{b};
+    while (!st.empty()) {
+      int x = st.back();
+      st.pop_back();
+      if (B[x].leaf) outv.push_back(x);
+      else
+        for (int q = 3; q >= 0; --q)
+          if (B[x].child[q] >= 0) st.push_back(B[x].child[q]);
+    }
+  };
+  auto group = [&](const std::vector<PairL>& prs, std::vector<std::vector<int2>>& per_leaf, int64_t& npairs) {
+    per_leaf.assign(leaves.size(), {});
+    npairs = 0;
+    std::vector<int> tl;
+    for (auto& pr : prs) {
+      tl.clear();
+      leaves_under(pr.t, tl);
+      int2 r = make_int2(B[pr.s].begin, B[pr.s].end);
+      for (int t : tl) {
+        per_leaf[leaf_index[t]].push_back(r);
+        npairs += (int64_t)(B[t].end - B[t].begin) * (r.y - r.x);
+      }
+    }
+    for (auto& v : per_leaf) {
+      std::sort(v.begin(), v.end(), [](int2 a, int2 b) { return a.x < b.x; });
+      std::vector<int2> m;
+      for (auto& r : v) {
+        if (!m.empty() && r.x <= m.back().y) m.back().y = std::max(m.back().y, r.y);
+        else m.push_back(r);
+      }
+      v.swap(m);
+    }
+  };
+  std::vector<std::vector<int2>> u_per, i_per;
+  int64_t np2p = 0, nifp = 0;
+  group(fu, u_per, np2p);
+  group(iu, i_per, nifp);
+  std::vector<int> p2p_ptr(1, 0), if_ptr(1, 0), if_leaves;
+  std::vector<int2> p2p_rng, if_rng;
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    p2p_rng.insert(p2p_rng.end(), u_per[li].begin(), u_per[li].end());
+    p2p_ptr.push_back((int)p2p_rng.size());
+    if (!i_per[li].empty()) {
+      if_leaves.push_back(leaves[li]);
+      if_rng.insert(if_rng.end(), i_per[li].begin(), i_per[li].end());
+      if_ptr.push_back((int)if_rng.size());
+    }
+  }
+
+  // ---- near-interface rule (one rule covering every direct image pair)
+  std::vector<double2> qc, qky, qkx;
+  double glx[16], glw[16];
+  gauss_legendre16(glx, glw);
+  if (!iu.empty()) {
+    double xsp = 0.0, yhi = 0.0;
+    for (auto& pr : iu) {
+      double bt = pl->bsize[B[pr.t].level];
+      double xt0 = xmin + B[pr.t].ix * bt, xs0 = xmin + B[pr.s].ix * bt;
+      xsp = std::max(xsp, std::fabs(xt0 - xs0) + bt);
+      yhi = std::max(yhi, 2.0 * ymin + (B[pr.t].iy + B[pr.s].iy + 2) * bt);
+    }
+    const double ylo = std::max(2.0 * ymin, 1e-12);
+    Rule r = build_rule(pl->med, xsp, ylo, yhi, 0);
+    if (!r.ok) {
+      fail(HFMM_ERR_ACCURACY, "near-interface quadrature rule too long");
+      return bail(HFMM_ERR_ACCURACY);
+    }
+    const double inv4pi = 0.25 / M_PI;
+    for (auto& pn : r.panels) {
+      double hw = 0.5 * (pn.b - pn.a), mid = 0.5 * (pn.a + pn.b);
+      for (int g = 0; g < 16; ++g) {
+        double s = mid + hw * glx[g], w = hw * glw[g];
+        if (pn.kind == 0) {
+          double st = std::sin(s), ct = std::cos(s);
+          double2 sig = sigma1_tau(pl->med, ct, st);
+          // (i/4)(1/pi) w sigma e^{i k (Y st - X ct)}
+          qc.push_back(cmul(cmk(0.0, 0.25 / M_PI * w), sig));
+          qky.push_back(cmk(0.0, k * st));
+          qkx.push_back(cmk(0.0, -k * ct));
+        } else {
+          double2 t = cmk(s, 0.0), dt = cmk(1.0, 0.0);
+          if (s < r.send) {
+            t = cmk(s, -r.dip * std::sin(M_PI * s / r.send));
+            dt = cmk(1.0, -r.dip * M_PI / r.send * std::cos(M_PI * s / r.send));
+          }
+          double2 lam = csqrt2(cadd(cmul(t, t), cmk(k * k, 0.0)));
+          double2 sig = sigma1_t(pl->med, t);
+          double2 c = cdiv(cmul(cscale(dt, w * inv4pi), sig), lam);
+          double2 il = cmul(cmk(0.0, 1.0), lam);
+          qc.push_back(c); qky.push_back(cscale(t, -1.0)); qkx.push_back(il);
+          qc.push_back(c); qky.push_back(cscale(t, -1.0)); qkx.push_back(cscale(il, -1.0));
+        }
+      }
+    }
+  }
+
+  // ---- heterogeneous table rules
+  std::vector<double> cX, cY, cdip, csend;
+  std::vector<int> cpbeg(1, 0);
+  std::vector<Panel> cpanels;
+  for (auto& cb : combos) {
+    double b = pl->bsize[cb.level];
+    double X = cb.dix * b;
+    double Y = 2.0 * ymin + (cb.m + 1) * b;
+    int N = 2 * pl->P[cb.level];
+    if (2 * N + 1 > 256 * 8) {
+      fail(HFMM_ERR_ACCURACY, "heterogeneous table order too large");
+      return bail(HFMM_ERR_ACCURACY);
+    }
+    Rule r = build_rule(pl->med, X, Y, Y, N);
+    if (!r.ok) {
+      fail(HFMM_ERR_ACCURACY, "heterogeneous table quadrature rule too long");
+      return bail(HFMM_ERR_ACCURACY);
+    }
+    cX.push_back(X);
+    cY.push_back(Y);
+    cdip.push_back(r.dip);
+    csend.push_back(r.send);
+    cpanels.insert(cpanels.end(), r.panels.begin(), r.panels.end());
+    cpbeg.push_back((int)cpanels.size());
+  }
+
+  // ---- upload and generate tables
+  std::vector<double2> hpts((size_t)n);
+  std::vector<int> hperm((size_t)n);
+  for (int64_t i = 0; i < n; ++i) {
+    int j = key[i].second;
+    hperm[i] = j;
+    hpts[i] = cmk(hp[2 * j], hp[2 * j + 1]);
+  }
+  std::vector<double2> hctr(nb);
+  std::vector<int> hlev(nb), hpar(nb), hquad(nb), hchild(4 * nb);
+  std::vector<int2> hpr(nb);
+  for (int i = 0; i < nb; ++i) {
+    double b = pl->bsize[B[i].level];
+    hctr[i] = cmk(xmin + (B[i].ix + 0.5) * b, ymin + (B[i].iy + 0.5) * b);
+    hlev[i] = B[i].level;
+    hpar[i] = B[i].parent;
+    hquad[i] = B[i].quad;
+    for (int q = 0; q < 4; ++q) hchild[4 * i + q] = B[i].child[q];
+    hpr[i] = make_int2(B[i].begin, B[i].end);
+  }
+  hipError_t e = hipSuccess;
+#define UP(buf, vec)                                  \
+  if (e == hipSuccess) e = pl->buf.upload(vec, stream);
+  UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
+  UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves) UP(p2m_leaves, p2m_leaves)
+  UP(m2m_boxes, m2m_boxes) UP(l2l_boxes, l2l_boxes) UP(m2l_targets, m2l_targets) UP(m2l_ptr, m2l_ptr)
+  UP(m2lT_ptr, m2lT_ptr) UP(m2l_ent, m2l_ent) UP(m2lT_ent, m2lT_ent) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
+  UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
+  UP(qky, qky) UP(qkx, qkx)
+  DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
+  DevBuf<int> d_fhref, d_fbsgn, d_fbref, d_cpbeg, d_imgref;
+  DevBuf<Panel> d_cpanels;
+  std::vector<double> vglx(glx, glx + 16), vglw(glw, glw + 16);
+  std::vector<TableRef> fh_refs, fb_refs, img_refs;
+  for (int id : fh_ref) fh_refs.push_back(tabs[id]);
+  for (int id : fb_ref) fb_refs.push_back(tabs[id]);
+  for (int id : img_ref) img_refs.push_back(tabs[id]);
+  DevBuf<TableRef> d_fhr, d_fbr, d_imr;
+  if (e == hipSuccess) e = d_fhdx.upload(fh_dx, stream);
+  if (e == hipSuccess) e = d_fhdy.upload(fh_dy, stream);
+  if (e == hipSuccess) e = d_fhr.upload(fh_refs, stream);
+  if (e == hipSuccess) e = d_fbdx.upload(fb_dx, stream);
+  if (e == hipSuccess) e = d_fbdy.upload(fb_dy, stream);
+  if (e == hipSuccess) e = d_fbsgn.upload(fb_sgn, stream);
+  if (e == hipSuccess) e = d_fbr.upload(fb_refs, stream);
+  if (e == hipSuccess) e = d_cX.upload(cX, stream);
+  if (e == hipSuccess) e = d_cY.upload(cY, stream);
+  if (e == hipSuccess) e = d_cdip.upload(cdip, stream);
+  if (e == hipSuccess) e = d_csend.upload(csend, stream);
+  if (e == hipSuccess) e = d_cpbeg.upload(cpbeg, stream);
+  if (e == hipSuccess) e = d_cpanels.upload(cpanels, stream);
+  if (e == hipSuccess) e = d_imr.upload(img_refs, stream);
+  if (e == hipSuccess) e = d_glx.upload(vglx, stream);
+  if (e == hipSuccess) e = d_glw.upload(vglw, stream);
+  if (e == hipSuccess) e = pl->tdata.alloc((size_t)std::max<int64_t>(toff, 1));
+  if (e == hipSuccess) {
+    launch_table_hankel(stream, (int)fh_ref.size(), d_fhdx.p, d_fhdy.p, d_fhr.p, k, pl->tdata.p);
+    launch_table_bessel(stream, (int)fb_ref.size(), d_fbdx.p, d_fbdy.p, d_fbsgn.p, d_fbr.p, k, pl->tdata.p);
+    launch_table_image(stream, pl->med, (int)combos.size(), d_cX.p, d_cY.p, d_cdip.p, d_csend.p, d_cpbeg.p,
+                       d_cpanels.p, d_imr.p, d_glx.p, d_glw.p, pl->tdata.p);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  d_fhdx.release(); d_fhdy.release(); d_fbdx.release(); d_fbdy.release(); d_cX.release(); d_cY.release();
+  d_cdip.release(); d_csend.release(); d_glx.release(); d_glw.release(); d_fhref.release(); d_fbsgn.release();
+  d_fbref.release(); d_cpbeg.release(); d_imgref.release(); d_cpanels.release(); d_fhr.release();
+  d_fbr.release(); d_imr.release();
+  if (e != hipSuccess) {
+    fail(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
+         std::string("plan upload/tables: ") + hipGetErrorString(e));
+    return bail(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE);
+  }
+  pl->nleaves = (int)leaves.size();
+  pl->np2m = (int)p2m_leaves.size();
+  pl->nm2l_targets = (int)m2l_targets.size();
+  pl->nif_leaves = (int)if_leaves.size();
+  pl->nq = (int)qc.size();
+
+  // ---- statistics
+  hfmm_info_t& inf = pl->info;
+  inf.levels = pl->nlev;
+  for (int l = 0; l < pl->nlev && l < 32; ++l) inf.order[l] = pl->P[l];
+  inf.boxes = nb;
+  inf.leaves = (int64_t)leaves.size();
+  inf.m2l_pairs = (int64_t)fv.size();
+  inf.image_pairs = (int64_t)iv.size();
+  inf.p2p_pairs = np2p;
+  inf.interface_pairs = nifp;
+  inf.image_tables = (int64_t)combos.size();
+  double fm2l = 0.0;
+  for (auto& pr : fv) { double m = 2.0 * pl->P[B[pr.t].level] + 1; fm2l += 8.0 * m * m; }
+  for (auto& pr : iv) { double m = 2.0 * pl->P[B[pr.t].level] + 1; fm2l += 8.0 * m * m; }
+  inf.flops_m2l = fm2l;
+  double fud = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    int l = B[i].level;
+    if (l < 2) continue;
+    double m = 2.0 * pl->P[l] + 1;
+    if (B[i].leaf) fud += 2.0 * (B[i].end - B[i].begin) * m * 8.0;  // P2M + L2P MACs
+    if (l >= 3) fud += 2.0 * 8.0 * m * (2.0 * pl->P[l - 1] + 1);     // M2M + L2L
+  }
+  inf.flops_updown = fud;
+  inf.flops_p2p = (double)np2p;
+  inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  *out = pl;
+  return HFMM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// u_sorted = A q_sorted for the plan's point order (complex-linear).
+void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us) {
+  TreeView tv = pl->view(nrhs);
+  launch_p2m(s, tv, pl->p2m_leaves.p, pl->np2m, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
+  for (int l = pl->nlev - 2; l >= 2; --l) {
+    int b0 = pl->m2m_off[l], b1 = pl->m2m_off[l + 1];
+    if (b1 > b0)
+      launch_m2m(s, tv, pl->m2m_boxes.p + b0, b1 - b0, pl->tabs.p + pl->m2m_tab[l], pl->tdata.p, pl->alpha.p,
+                 pl->alpha.p, 0);
+  }
+  launch_m2l(s, tv, pl->m2l_targets.p, pl->nm2l_targets, pl->m2l_ptr.p, pl->m2l_ent.p, pl->tabs.p, pl->tdata.p,
+             pl->alpha.p, pl->beta.p, 0);
+  for (int l = 3; l < pl->nlev; ++l) {
+    int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];
+    if (b1 > b0)
+      launch_l2l(s, tv, pl->l2l_boxes.p + b0, b1 - b0, pl->tabs.p + pl->l2l_tab[l - 1], pl->tdata.p, pl->beta.p,
+                 pl->beta.p, 0, 1);
+  }
+  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->beta.p, us, 0, cmk(0.0, 0.25), 0);
+  launch_p2p(s, tv, pl->leaves.p, pl->nleaves, pl->p2p_ptr.p, pl->p2p_rng.p, qs, us);
+  launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
+               pl->qkx.p, qs, us);
+}
+
+// w_sorted = A^T v_sorted through the transposes of the stages, in reverse order.
+void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* vs, double2* ws) {
+  TreeView tv = pl->view(nrhs);
+  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}
+  launch_p2m(s, tv, pl->p2m_leaves.p, pl->np2m, vs, pl->beta.p, 1, cmk(0.0, 0.25));
+  // L2L^T, finest parents first: beta'(parent) = sum_children T^T beta'(child)
+  for (int l = pl->nlev - 2; l >= 2; --l) {
+    int b0 = pl->m2m_off[l], b1 = pl->m2m_off[l + 1];
+    if (b1 > b0)
+      launch_m2m(s, tv, pl->m2m_boxes.p + b0, b1 - b0, pl->tabs.p + pl->l2l_tab[l], pl->tdata.p, pl->beta.p,
+                 pl->beta.p, 1);
+  }
+  // M2L^T, grouped by source box
+  launch_m2l(s, tv, pl->m2l_targets.p, pl->nm2l_targets, pl->m2lT_ptr.p, pl->m2lT_ent.p, pl->tabs.p, pl->tdata.p,
+             pl->beta.p, pl->alpha.p, 1);
+  // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
+  for (int l = 3; l < pl->nlev; ++l) {
+    int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];
+    if (b1 > b0)
+      launch_l2l(s, tv, pl->l2l_boxes.p + b0, b1 - b0, pl->tabs.p + pl->m2m_tab[l - 1], pl->tdata.p, pl->alpha.p,
+                 pl->alpha.p, 1, 1);
+  }
+  // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
+  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->alpha.p, ws, 1, cmk(1.0, 0.0), 0);
+  // the direct parts are symmetric
+  launch_p2p(s, tv, pl->leaves.p, pl->nleaves, pl->p2p_ptr.p, pl->p2p_rng.p, vs, ws);
+  launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
+               pl->qkx.p, vs, ws);
+}
+
+}  // namespace
+
+extern "C" {
+
+hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrhs, hfmm_stream_t stream_) {
+  if (!pl || !q || !u) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, q or u");
+  if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
+  hipStream_t s = (hipStream_t)stream_;
+  hfmm_status_t st = ensure_workspace(pl, nrhs);
+  if (st != HFMM_OK) return st;
+  launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)q, pl->qs.p, 0);
+  forward_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p);
+  launch_scatter(s, pl->n, nrhs, pl->perm.p, pl->us.p, (double2*)u, 0);
+  HIP_TRY(hipGetLastError());
+  return HFMM_OK;
+}
+
+hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int32_t nrhs, const double* q,
+                                 double* grad_xy, hfmm_stream_t stream_) {
+  if (!pl || !v || !w) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, v or w");
+  if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (grad_xy && !q) return fail(HFMM_ERR_INVALID_ARG, "grad_xy requested without q");
+  if (grad_xy) return fail(HFMM_ERR_UNSUPPORTED, "coordinate gradients are not available in this build");
+  hipStream_t s = (hipStream_t)stream_;
+  hfmm_status_t st = ensure_workspace(pl, nrhs);
+  if (st != HFMM_OK) return st;
+  // A^H v = conj(A^T conj(v))
+  launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)v, pl->qs.p, 1);
+  transpose_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p);
+  launch_scatter(s, pl->n, nrhs, pl->perm.p, pl->us.p, (double2*)w, 1);
+  HIP_TRY(hipGetLastError());
+  return HFMM_OK;
+}
+
+}  // extern "C"
