@@ -133,6 +133,18 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t plan, const double *v, double *w, i
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 
+/*
+ * Stage timing (diagnostics). While enabled, every hfmm_apply records HIP
+ * events on its stream between its stages. hfmm_profile_read synchronises the
+ * device, writes the accumulated milliseconds per stage and the number of
+ * applies into stage_ms[0..HFMM_NSTAGES-1] and *napplies, and clears the
+ * accumulators. Stages: see hfmm_stage_name.
+ */
+enum { HFMM_NSTAGES = 9 };
+hfmm_status_t hfmm_profile_enable(hfmm_plan_t plan, int32_t enable);
+hfmm_status_t hfmm_profile_read(hfmm_plan_t plan, double *stage_ms, int32_t *napplies);
+const char *hfmm_stage_name(int32_t stage);
+
 /* Release a plan and its device memory (synchronises the device). NULL is a no-op. */
 void hfmm_destroy(hfmm_plan_t plan);
 

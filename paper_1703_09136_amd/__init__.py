@@ -26,7 +26,9 @@ STATUS_NAMES = {0: "HFMM_OK", 1: "HFMM_ERR_INVALID_ARG", 2: "HFMM_ERR_DOMAIN", 3
 
 # every symbol declared in include/hfmm.h
 EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoint", "hfmm_plan_info",
+           "hfmm_profile_enable", "hfmm_profile_read", "hfmm_stage_name",
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message")
+NSTAGES = 9
 
 
 class Options(ctypes.Structure):
@@ -78,6 +80,12 @@ def load(path: str | None = None):
     lib.hfmm_apply_adjoint.restype = ctypes.c_int
     lib.hfmm_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
     lib.hfmm_plan_info.restype = ctypes.c_int
+    lib.hfmm_profile_enable.argtypes = [vp, i32]
+    lib.hfmm_profile_enable.restype = ctypes.c_int
+    lib.hfmm_profile_read.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i32)]
+    lib.hfmm_profile_read.restype = ctypes.c_int
+    lib.hfmm_stage_name.argtypes = [i32]
+    lib.hfmm_stage_name.restype = ctypes.c_char_p
     lib.hfmm_destroy.argtypes = [vp]
     lib.hfmm_destroy.restype = None
     lib.hfmm_status_string.argtypes = [ctypes.c_int]
@@ -167,6 +175,18 @@ class Plan:
         inf = Info()
         _check(self._lib.hfmm_plan_info(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def profile(self, enable=True):
+        """Record HIP events between the stages of every apply (hfmm_profile_enable)."""
+        _check(self._lib.hfmm_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """Accumulated milliseconds per stage and the number of applies (hfmm_profile_read)."""
+        ms = (ctypes.c_double * NSTAGES)()
+        cnt = ctypes.c_int32()
+        _check(self._lib.hfmm_profile_read(self._h, ms, ctypes.byref(cnt)))
+        names = [self._lib.hfmm_stage_name(i).decode() for i in range(NSTAGES)]
+        return dict(zip(names, list(ms))), cnt.value
 
     def close(self):
         if getattr(self, "_h", None):

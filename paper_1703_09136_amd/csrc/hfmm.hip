@@ -137,6 +137,7 @@ struct Rule {
   bool ok = true;
 };
 constexpr size_t kMaxPanels = 100000;
+constexpr int kItemSources = 2048;   // sources per direct work item
 
 Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
   Rule r;
@@ -250,8 +251,9 @@ struct hfmm_plan_s {
   DevBuf<TableRef> tabs;
   DevBuf<double2> tdata;
   std::vector<int> m2m_tab, l2l_tab;  // per parent level: index of 4 consecutive tables
-  DevBuf<int> p2p_ptr;
+  DevBuf<int> p2p_ptr, p2p_items, p2p_atomic;
   DevBuf<int2> p2p_rng;
+  int np2p_items = 0;
   DevBuf<int> if_leaves, if_ptr;
   DevBuf<int2> if_rng;
   int nif_leaves = 0;
@@ -260,6 +262,11 @@ struct hfmm_plan_s {
   int ws_nrhs = 0;
   DevBuf<double2> qs, us, alpha, beta;
   hfmm_info_t info{};
+  // stage timing
+  bool prof_on = false;
+  std::vector<std::vector<hipEvent_t>> prof_pending;
+  double prof_ms[HFMM_NSTAGES] = {0};
+  int prof_n = 0;
 
   TreeView view(int nrhs) const {
     TreeView tv{};
@@ -285,7 +292,7 @@ struct hfmm_plan_s {
     child.release(); prange.release(); coff.release(); leaves.release(); p2m_leaves.release();
     m2m_boxes.release(); l2l_boxes.release(); m2l_targets.release(); m2l_ptr.release(); m2lT_ptr.release();
     m2l_ent.release(); m2lT_ent.release(); tabs.release(); tdata.release(); p2p_ptr.release();
-    p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
+    p2p_items.release(); p2p_atomic.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release();
   }
 };
@@ -736,11 +743,52 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   int64_t np2p = 0, nifp = 0;
   group(fu, u_per, np2p);
   group(iu, i_per, nifp);
-  std::vector<int> p2p_ptr(1, 0), if_ptr(1, 0), if_leaves;
-  std::vector<int2> p2p_rng, if_rng;
+  // direct work items: a target leaf with at most kItemSources sources; a leaf
+  // whose sources span several items accumulates atomically. Largest first.
+  struct Item {
+    int leaf;
+    int atomic;
+    int64_t cost;
+    std::vector<int2> r;
+  };
+  std::vector<Item> items;
   for (size_t li = 0; li < leaves.size(); ++li) {
-    p2p_rng.insert(p2p_rng.end(), u_per[li].begin(), u_per[li].end());
+    size_t first = items.size();
+    Item cur{leaves[li], 0, 0, {}};
+    int cur_n = 0;
+    for (const int2& rg : u_per[li]) {
+      int a = rg.x;
+      while (a < rg.y) {
+        int take = std::min(rg.y - a, kItemSources - cur_n);
+        cur.r.push_back(make_int2(a, a + take));
+        cur_n += take;
+        a += take;
+        if (cur_n == kItemSources) {
+          items.push_back(cur);
+          cur = Item{leaves[li], 0, 0, {}};
+          cur_n = 0;
+        }
+      }
+    }
+    if (cur_n > 0) items.push_back(cur);
+    int nt = B[leaves[li]].end - B[leaves[li]].begin;
+    for (size_t it = first; it < items.size(); ++it) {
+      items[it].atomic = (items.size() - first) > 1;
+      int64_t ns = 0;
+      for (auto& r : items[it].r) ns += r.y - r.x;
+      items[it].cost = ns * nt;
+    }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  std::vector<int> p2p_ptr(1, 0), p2p_items, p2p_atomic, if_ptr(1, 0), if_leaves;
+  std::vector<int2> p2p_rng, if_rng;
+  for (auto& it : items) {
+    p2p_items.push_back(it.leaf);
+    p2p_atomic.push_back(it.atomic);
+    p2p_rng.insert(p2p_rng.end(), it.r.begin(), it.r.end());
     p2p_ptr.push_back((int)p2p_rng.size());
+  }
+  for (size_t li = 0; li < leaves.size(); ++li) {
     if (!i_per[li].empty()) {
       if_leaves.push_back(leaves[li]);
       if_rng.insert(if_rng.end(), i_per[li].begin(), i_per[li].end());
@@ -848,7 +896,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves) UP(p2m_leaves, p2m_leaves)
   UP(m2m_boxes, m2m_boxes) UP(l2l_boxes, l2l_boxes) UP(m2l_targets, m2l_targets) UP(m2l_ptr, m2l_ptr)
   UP(m2lT_ptr, m2lT_ptr) UP(m2l_ent, m2l_ent) UP(m2lT_ent, m2lT_ent) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
-  UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
+  UP(p2p_items, p2p_items) UP(p2p_atomic, p2p_atomic) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
   DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
   DevBuf<int> d_fhref, d_fbsgn, d_fbref, d_cpbeg, d_imgref;
@@ -894,6 +942,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     return bail(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE);
   }
   pl->nleaves = (int)leaves.size();
+  pl->np2p_items = (int)p2p_items.size();
   pl->np2m = (int)p2m_leaves.size();
   pl->nm2l_targets = (int)m2l_targets.size();
   pl->nif_leaves = (int)if_leaves.size();
@@ -934,27 +983,48 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
 namespace {
 
 // u_sorted = A q_sorted for the plan's point order (complex-linear).
-void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us) {
+// Records an event on the stream at each stage boundary while profiling is on.
+struct Marker {
+  std::vector<hipEvent_t>* ev = nullptr;
+  hipStream_t s = nullptr;
+  void operator()() {
+    if (!ev) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+      (void)hipEventRecord(e, s);
+      ev->push_back(e);
+    }
+  }
+};
+
+void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
   TreeView tv = pl->view(nrhs);
   launch_p2m(s, tv, pl->p2m_leaves.p, pl->np2m, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
+  mark();
   for (int l = pl->nlev - 2; l >= 2; --l) {
     int b0 = pl->m2m_off[l], b1 = pl->m2m_off[l + 1];
     if (b1 > b0)
       launch_m2m(s, tv, pl->m2m_boxes.p + b0, b1 - b0, pl->tabs.p + pl->m2m_tab[l], pl->tdata.p, pl->alpha.p,
                  pl->alpha.p, 0);
   }
+  mark();
   launch_m2l(s, tv, pl->m2l_targets.p, pl->nm2l_targets, pl->m2l_ptr.p, pl->m2l_ent.p, pl->tabs.p, pl->tdata.p,
              pl->alpha.p, pl->beta.p, 0);
+  mark();
   for (int l = 3; l < pl->nlev; ++l) {
     int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];
     if (b1 > b0)
       launch_l2l(s, tv, pl->l2l_boxes.p + b0, b1 - b0, pl->tabs.p + pl->l2l_tab[l - 1], pl->tdata.p, pl->beta.p,
                  pl->beta.p, 0, 1);
   }
+  mark();
   launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->beta.p, us, 0, cmk(0.0, 0.25), 0);
-  launch_p2p(s, tv, pl->leaves.p, pl->nleaves, pl->p2p_ptr.p, pl->p2p_rng.p, qs, us);
+  mark();
+  launch_p2p(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, qs, us);
+  mark();
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, qs, us);
+  mark();
 }
 
 // w_sorted = A^T v_sorted through the transposes of the stages, in reverse order.
@@ -982,7 +1052,7 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
   launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->alpha.p, ws, 1, cmk(1.0, 0.0), 0);
   // the direct parts are symmetric
-  launch_p2p(s, tv, pl->leaves.p, pl->nleaves, pl->p2p_ptr.p, pl->p2p_rng.p, vs, ws);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, vs, ws);
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, vs, ws);
 }
@@ -997,11 +1067,54 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
   hipStream_t s = (hipStream_t)stream_;
   hfmm_status_t st = ensure_workspace(pl, nrhs);
   if (st != HFMM_OK) return st;
+  Marker mark;
+  mark.s = s;
+  if (pl->prof_on) {
+    pl->prof_pending.emplace_back();
+    mark.ev = &pl->prof_pending.back();
+  }
+  mark();
   launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)q, pl->qs.p, 0);
-  forward_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p);
+  mark();
+  forward_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p, mark);
   launch_scatter(s, pl->n, nrhs, pl->perm.p, pl->us.p, (double2*)u, 0);
+  mark();
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
+}
+
+hfmm_status_t hfmm_profile_enable(hfmm_plan_t pl, int32_t enable) {
+  if (!pl) return fail(HFMM_ERR_INVALID_ARG, "NULL plan");
+  pl->prof_on = enable != 0;
+  return HFMM_OK;
+}
+
+hfmm_status_t hfmm_profile_read(hfmm_plan_t pl, double* stage_ms, int32_t* napplies) {
+  if (!pl || !stage_ms || !napplies) return fail(HFMM_ERR_INVALID_ARG, "NULL argument");
+  HIP_TRY(hipDeviceSynchronize());
+  for (auto& ev : pl->prof_pending) {
+    if (ev.size() == HFMM_NSTAGES + 1) {
+      for (int i = 0; i < HFMM_NSTAGES; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess) pl->prof_ms[i] += ms;
+      }
+      ++pl->prof_n;
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  pl->prof_pending.clear();
+  for (int i = 0; i < HFMM_NSTAGES; ++i) {
+    stage_ms[i] = pl->prof_ms[i];
+    pl->prof_ms[i] = 0.0;
+  }
+  *napplies = pl->prof_n;
+  pl->prof_n = 0;
+  return HFMM_OK;
+}
+
+const char* hfmm_stage_name(int32_t stage) {
+  static const char* names[HFMM_NSTAGES] = {"gather", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "interface", "scatter"};
+  return (stage >= 0 && stage < HFMM_NSTAGES) ? names[stage] : "unknown";
 }
 
 hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int32_t nrhs, const double* q,

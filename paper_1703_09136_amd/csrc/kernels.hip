@@ -20,6 +20,8 @@ namespace hfmm {
 
 constexpr int WAVE = 64;
 
+__device__ __noinline__ double2 hankel0_large_call(double x) { return hankel0_large(x); }
+
 __device__ inline double2 shfl_xor_c(double2 v, int mask) {
   return cmk(__shfl_xor(v.x, mask, WAVE), __shfl_xor(v.y, mask, WAVE));
 }
@@ -281,49 +283,95 @@ __global__ void __launch_bounds__(WAVE) k_l2l(TreeView tv, const int* __restrict
 // u_i += (i/4) sum_{j in U(i), j != i} q_j H0^(1)(k |x_i - x_j|). One wave per
 // target leaf; when the leaf holds fewer than 64 points several lanes share a
 // target and split its sources, then combine by shuffles.
+// Sources are staged through LDS 64 at a time; RB right-hand sides share each
+// H0 evaluation (right-hand sides r0 .. r0+RB-1 in this launch).
+template <int RB>
 __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const int* __restrict__ ptr, const int2* __restrict__ rng,
-                                              const double2* __restrict__ qs, double2* __restrict__ us) {
+                                              const int* __restrict__ atomic, const double2* __restrict__ qs,
+                                              double2* __restrict__ us, int r0) {
+  __shared__ double2 s_x[WAVE];
+  __shared__ double2 s_q[RB][WAVE];
   int li = blockIdx.x;
   if (li >= nleaves) return;
   int b = leaves[li];
   int lane = threadIdx.x;
   int2 pr = tv.prange[b];
   int e0 = ptr[li], e1 = ptr[li + 1];
-  constexpr int RB = 4;
-  for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
-    int nt = min(WAVE, pr.y - c0);
-    int g = 1;
-    while (g * 2 * nt <= WAVE) g *= 2;  // lanes per target
+  const double qk2 = 0.25 * tv.k * tv.k;
+  // targets in chunks of 32 (two lanes per target), the remainder in a chunk of
+  // the next power of two with more lanes per target
+  for (int c0 = pr.x, csz = 0; c0 < pr.y; c0 += csz) {
+    int rem = pr.y - c0;
+    csz = 32;
+    if (rem < 32) {
+      csz = 1;
+      while (csz < rem) csz *= 2;
+    }
+    int nt = min(csz, rem);
+    int g = WAVE / csz;  // lanes per target
     int ti = lane / g, sub = lane % g;
     int i = c0 + ti;
     bool valid = ti < nt;
     double2 xi = valid ? tv.pts[i] : cmk(0, 0);
-    for (int r0 = 0; r0 < tv.nrhs; r0 += RB) {
-      double2 acc[RB];
-      for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk(0, 0);
-      if (valid) {
-        for (int e = e0; e < e1; ++e) {
-          int2 sr = rng[e];
-          for (int j = sr.x + sub; j < sr.y; j += g) {
-            if (j == i) continue;
-            double2 xj = tv.pts[j];
-            double2 h = hankel0(tv.k * hypot(xi.x - xj.x, xi.y - xj.y));
-            for (int rr = 0; rr < RB; ++rr)
-              if (r0 + rr < tv.nrhs) acc[rr] = cadd(acc[rr], cmul(h, qs[(int64_t)(r0 + rr) * tv.n + j]));
+    double2 acc[RB];
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk(0, 0);
+    for (int e = e0; e < e1; ++e) {
+      int2 sr = rng[e];
+      for (int j0 = sr.x; j0 < sr.y; j0 += WAVE) {
+        int cnt = min(WAVE, sr.y - j0);
+        __syncthreads();
+        if (lane < cnt) {
+          s_x[lane] = tv.pts[j0 + lane];
+#pragma unroll
+          for (int rr = 0; rr < RB; ++rr)
+            s_q[rr][lane] = (r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + j0 + lane] : cmk(0, 0);
+        }
+        __syncthreads();
+        if (valid) {
+          // four sources per step: z = (k r / 2)^2; dropped terms (the target
+          // itself, past the chunk) get a harmless z = 1 and weight 0
+          for (int jj = sub; jj < cnt; jj += 4 * g) {
+            double z[4];
+            bool use[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              int jl = jj + u * g;
+              use[u] = jl < cnt && (j0 + jl) != i;
+              double2 xj = s_x[use[u] ? jl : 0];
+              double dx = xi.x - xj.x, dy = xi.y - xj.y;
+              z[u] = use[u] ? qk2 * (dx * dx + dy * dy) : 1.0;
+            }
+            double2 h[4];
+            hankel0_x4(z, h);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (!use[u]) continue;
+              int jl = jj + u * g;
+#pragma unroll
+              for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(h[u], s_q[rr][jl]));
+            }
           }
         }
       }
-      for (int rr = 0; rr < RB; ++rr)
-        for (int m = 1; m < g; m <<= 1) acc[rr] = cadd(acc[rr], shfl_xor_c(acc[rr], m));
-      if (valid && sub == 0)
-        for (int rr = 0; rr < RB; ++rr)
-          if (r0 + rr < tv.nrhs) {
-            int64_t idx = (int64_t)(r0 + rr) * tv.n + i;
-            double2 v = acc[rr];
-            us[idx] = cadd(us[idx], cmk(-0.25 * v.y, 0.25 * v.x));  // (i/4) v
-          }
     }
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr)
+      for (int m = 1; m < g; m <<= 1) acc[rr] = cadd(acc[rr], shfl_xor_c(acc[rr], m));
+    if (valid && sub == 0)
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+        if (r0 + rr < tv.nrhs) {
+          int64_t idx = (int64_t)(r0 + rr) * tv.n + i;
+          double2 v = cmk(-0.25 * acc[rr].y, 0.25 * acc[rr].x);  // (i/4) acc
+          if (atomic[li]) {
+            unsafeAtomicAdd(&us[idx].x, v.x);
+            unsafeAtomicAdd(&us[idx].y, v.y);
+          } else {
+            us[idx] = cadd(us[idx], v);
+          }
+        }
   }
 }
 
@@ -605,9 +653,15 @@ void launch_l2l(hipStream_t s, const TreeView& tv, const int* boxes, int nb, con
                 const double2* tdata, const double2* src, double2* dst, int rev, int accumulate) {
   if (nb) hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(WAVE), 0, s, tv, boxes, nb, tabs4, tdata, src, dst, rev, accumulate);
 }
-void launch_p2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
-                const double2* qs, double2* us) {
-  if (nl) hipLaunchKernelGGL(k_p2p, dim3(nl), dim3(WAVE), 0, s, tv, leaves, nl, ptr, rng, qs, us);
+void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr, const int2* rng,
+                const int* atomic, const double2* qs, double2* us) {
+  if (!nl) return;
+  if (tv.nrhs == 1) {
+    hipLaunchKernelGGL(k_p2p<1>, dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, 0);
+    return;
+  }
+  for (int r0 = 0; r0 < tv.nrhs; r0 += 4)
+    hipLaunchKernelGGL(k_p2p<4>, dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, r0);
 }
 void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                   int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* qs, double2* us) {

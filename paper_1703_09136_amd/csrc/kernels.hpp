@@ -17,8 +17,8 @@ void launch_m2m(hipStream_t s, const TreeView& tv, const int* boxes, int nb, con
                 const double2* tdata, const double2* src, double2* dst, int rev);
 void launch_l2l(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
                 const double2* tdata, const double2* src, double2* dst, int rev, int accumulate);
-void launch_p2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
-                const double2* qs, double2* us);
+void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr, const int2* rng,
+                const int* atomic, const double2* qs, double2* us);
 void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                   int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* qs, double2* us);
 void launch_table_hankel(hipStream_t s, int ntab, const double* dx, const double* dy, const TableRef* refs, double k,

@@ -6,12 +6,15 @@
 //    identity J_0 + 2 sum_k J_{2k} = 1 (Abramowitz & Stegun 9.1.27, 9.1.46).
 //    Values are rescaled by exact powers of two to stay in range; a first pass
 //    finds the normalisation, a second pass emits the values.
-//  * H_0^(1)(x) = J_0 + i Y_0: ascending series (A&S 9.1.12, 9.1.13) for
-//    x < 8, the library j0/y0 above.
+//  * H_0^(1)(x) = J_0 + i Y_0: ascending series (A&S 9.1.12, 9.1.13) in
+//    Horner form for x <= 6; beyond, the modulus-phase form of Hankel's
+//    asymptotic representation with its smooth factor interpolated by
+//    Chebyshev polynomials in 1/x (coefficients from 34-digit values).
 //  * Y_n by the forward recurrence from Y_0, Y_1 (stable upward).
 #pragma once
 
 #include "common.hpp"
+#include "h0_cheb.hpp"
 
 namespace hfmm {
 
@@ -82,24 +85,112 @@ __host__ __device__ inline void bessel_j_each(double x, int nmax, F f) {
   miller_emit(x, ns, nmax, inv_s, nres, f);
 }
 
-// H_0^(1)(x) = J_0(x) + i Y_0(x), x > 0.
-__device__ inline double2 hankel0(double x) {
-  if (x < 8.0) {
-    const double q = 0.25 * x * x;
-    double t = 1.0, j0s = 1.0, ys = 0.0, hm = 0.0;
-    for (int m = 1; m < 40; ++m) {
-      t *= -q / ((double)m * (double)m);
+// Coefficients of the ascending series in z = x^2/4 (A&S 9.1.12, 9.1.13):
+//   J_0 = sum_m c_m z^m,  c_m = (-1)^m / (m!)^2,
+//   Y_0 = (2/pi) [ (ln(x/2) + gamma) J_0 + sum_{m>=1} d_m z^m ],  d_m = -H_m c_m,
+// with H_m the harmonic numbers; generated at compile time.
+constexpr int kSeriesTerms = 28;
+struct H0Series {
+  double c[kSeriesTerms];
+  double d[kSeriesTerms];
+  constexpr H0Series() : c(), d() {
+    double cm = 1.0, hm = 0.0;
+    c[0] = 1.0;
+    d[0] = 0.0;
+    for (int m = 1; m < kSeriesTerms; ++m) {
+      cm = cm * (-1.0 / ((double)m * (double)m));
       hm += 1.0 / (double)m;
-      j0s += t;
-      ys -= hm * t;
-      if (fabs(t) * hm < 1e-18) break;
+      c[m] = cm;
+      d[m] = -hm * cm;
     }
-    const double two_pi = 0.63661977236758134308;   // 2/pi
-    const double euler = 0.57721566490153286061;
-    double y0v = two_pi * ((log(0.5 * x) + euler) * j0s + ys);
-    return cmk(j0s, y0v);
   }
-  return cmk(::j0(x), ::y0(x));
+};
+constexpr H0Series kH0{};
+
+// H_0^(1)(x) by the ascending series in Horner form, for 0 < x <= 6. The
+// number of terms follows the range: the tail term z^M / (M!)^2 stays below
+// 1e-18 (M = 13 for x <= 2, 21 for x <= 6).
+template <int M>
+__host__ __device__ inline double2 hankel0_series(double x) {
+  const double z = 0.25 * x * x;
+  double j = kH0.c[M - 1], s = kH0.d[M - 1];
+#pragma unroll
+  for (int m = M - 2; m >= 0; --m) {
+    j = fma(j, z, kH0.c[m]);
+    s = fma(s, z, kH0.d[m]);
+  }
+  const double two_over_pi = 0.63661977236758134308;
+  const double euler = 0.57721566490153286061;
+  return cmk(j, two_over_pi * ((0.5 * log(z) + euler) * j + s));
+}
+
+// H_0^(1)(x) for x >= 6 from its modulus-phase form
+// sqrt(2/(pi x)) F(1/x) e^{i(x - pi/4)}, with F interpolated by Chebyshev
+// polynomials in w = 1/x on [0, 1/6] (coefficients in h0_cheb.hpp) and summed
+// by Clenshaw's recurrence.
+__host__ __device__ inline double2 hankel0_large(double x) {
+  const double t = 2.0 * kH0ChebX0 / x - 1.0;
+  const double t2 = 2.0 * t;
+  double br1 = 0.0, br2 = 0.0, bi1 = 0.0, bi2 = 0.0;
+#pragma unroll
+  for (int k = kH0ChebN - 1; k >= 1; --k) {
+    double br = fma(t2, br1, kH0ChebRe[k] - br2);
+    double bi = fma(t2, bi1, kH0ChebIm[k] - bi2);
+    br2 = br1; br1 = br;
+    bi2 = bi1; bi1 = bi;
+  }
+  double fr = fma(t, br1, kH0ChebRe[0] - br2);
+  double fi = fma(t, bi1, kH0ChebIm[0] - bi2);
+  double s, c;
+  sincos(x - 0.78539816339744830962, &s, &c);
+  double a = sqrt(0.63661977236758134308 / x);
+  return cmk(a * (fr * c - fi * s), a * (fr * s + fi * c));
+}
+
+// H_0^(1)(x) = J_0(x) + i Y_0(x), x > 0: the ascending series up to x = 6,
+// the Chebyshev modulus-phase form beyond.
+__host__ __device__ inline double2 hankel0(double x) {
+  if (x <= 2.0) return hankel0_series<13>(x);
+  if (x <= 6.0) return hankel0_series<21>(x);
+  return hankel0_large(x);
+}
+
+// Out-of-line large-argument form for the pair loops (keeps its coefficients
+// out of the registers of the caller).
+__device__ __noinline__ double2 hankel0_large_call(double x);
+
+// Four values of H_0^(1) at once from z_u = x_u^2/4: the series for z <= 9
+// (x <= 6) with the four Horner chains interleaved, the large-argument form
+// for the rest.
+static __constant__ H0Series kH0dev = H0Series();
+
+__device__ inline void hankel0_x4(const double z[4], double2 h[4]) {
+  double j[4], s[4];
+  const H0Series* co = &kH0dev;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    j[u] = co->c[20];
+    s[u] = co->d[20];
+  }
+#pragma unroll
+  for (int m = 19; m >= 0; --m) {
+    const double cm = co->c[m], dm = co->d[m];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      j[u] = fma(j[u], z[u], cm);
+      s[u] = fma(s[u], z[u], dm);
+    }
+  }
+  const double two_over_pi = 0.63661977236758134308;
+  const double euler = 0.57721566490153286061;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (z[u] <= 9.0) {
+      h[u] = cmk(j[u], two_over_pi * ((0.5 * log(z[u]) + euler) * j[u] + s[u]));
+    } else {
+      h[u] = hankel0_large_call(2.0 * sqrt(z[u]));
+    }
+  }
 }
 
 }  // namespace hfmm
