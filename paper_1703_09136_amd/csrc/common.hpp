@@ -119,6 +119,19 @@ struct Panel {
   int32_t pad;
 };
 
+// A work item of the batched M2L contraction: one translation table and up to
+// 64 (source, target) pairs that use it, pairs [pbeg, pbeg + npairs) of the
+// pair arrays; rt_base is the first row tile of the real-embedded operator.
+struct M2LItem {
+  int32_t table;
+  int32_t level;
+  int32_t pbeg;
+  int32_t npairs;
+  int32_t image;
+  int32_t rt_base;
+  int32_t pad0, pad1;
+};
+
 struct TreeView {
   int32_t n;
   int32_t nboxes;

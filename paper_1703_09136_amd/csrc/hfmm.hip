@@ -138,6 +138,14 @@ struct Rule {
 };
 constexpr size_t kMaxPanels = 100000;
 constexpr int kItemSources = 2048;   // sources per direct work item
+// per-translation truncation bound as a fraction of the requested tolerance
+#ifndef HFMM_ORDER_SAFETY
+#define HFMM_ORDER_SAFETY 0.5
+#endif
+constexpr double kOrderSafety = HFMM_ORDER_SAFETY;
+// largest expansion order: the batched M2L keeps a 16-pair operand tile of
+// 2P+1 coefficients and the 4P+1 table entries in LDS
+constexpr int kMaxOrder = 255;
 
 Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
   Rule r;
@@ -245,9 +253,9 @@ struct hfmm_plan_s {
   int nleaves = 0, np2m = 0;
   DevBuf<int> m2m_boxes, l2l_boxes;
   std::vector<int> m2m_off, l2l_off;  // per level
-  DevBuf<int> m2l_targets, m2l_ptr, m2lT_ptr;
-  DevBuf<M2LEntry> m2l_ent, m2lT_ent;
-  int nm2l_targets = 0;
+  DevBuf<M2LItem> m2l_items;
+  DevBuf<int> m2l_psrc, m2l_pdst;
+  std::vector<int> m2l_item_first;  // per level, host
   DevBuf<TableRef> tabs;
   DevBuf<double2> tdata;
   std::vector<int> m2m_tab, l2l_tab;  // per parent level: index of 4 consecutive tables
@@ -290,8 +298,8 @@ struct hfmm_plan_s {
   void release_all() {
     pts.release(); ctr.release(); perm.release(); level.release(); parent.release(); quad.release();
     child.release(); prange.release(); coff.release(); leaves.release(); p2m_leaves.release();
-    m2m_boxes.release(); l2l_boxes.release(); m2l_targets.release(); m2l_ptr.release(); m2lT_ptr.release();
-    m2l_ent.release(); m2lT_ent.release(); tabs.release(); tdata.release(); p2p_ptr.release();
+    m2m_boxes.release(); l2l_boxes.release(); m2l_items.release(); m2l_psrc.release(); m2l_pdst.release();
+    tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_atomic.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release();
   }
@@ -328,7 +336,7 @@ int choose_order(double k, double b, double eps, int& status) {
   double R = b * std::sqrt(0.5);
   double D = 2.0 * b;
   status = 0;
-  for (int P = 3; P <= 1000; ++P) {
+  for (int P = 3; P <= kMaxOrder; ++P) {
     double j = host_absj(k * R, P + 1);
     if (j == 0.0) return P;
     double ly = host_log10_absy(k * (D - R), P + 1);
@@ -337,7 +345,7 @@ int choose_order(double k, double b, double eps, int& status) {
     if (lj + hl <= std::log10(eps)) return P;
   }
   status = 1;
-  return 1000;
+  return kMaxOrder;
 }
 
 }  // namespace
@@ -530,7 +538,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   const int nb = (int)B.size();
 
   // ---- expansion orders (levels >= 2)
-  const double eps = tol * 0.05;
+  const double eps = tol * kOrderSafety;
   for (int l = 2; l < pl->nlev; ++l) {
     int st;
     pl->P[l] = choose_order(k, pl->bsize[l], eps, st);
@@ -639,20 +647,55 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     img_ref.push_back(id);
     return id;
   };
-  // M2L entries grouped by target (and by source for the transpose)
-  std::vector<std::vector<M2LEntry>> by_t(nb), by_s(nb);
+  // M2L pairs grouped by translation table (the batched contraction works per table)
+  std::vector<std::vector<std::pair<int, int>>> pairs_of;   // (source, target) per table id
+  std::vector<int> table_level, table_image;
+  auto add_pair = [&](int id, int l, int img, int s, int t) {
+    if ((int)pairs_of.size() <= id) {
+      pairs_of.resize(id + 1);
+      table_level.resize(id + 1, -1);
+      table_image.resize(id + 1, 0);
+    }
+    pairs_of[id].push_back({s, t});
+    table_level[id] = l;
+    table_image[id] = img;
+  };
   for (auto& pr : fv) {
     int l = B[pr.t].level;
     int id = free_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy - B[pr.s].iy);
-    by_t[pr.t].push_back({pr.s, id, 0, 0});
-    by_s[pr.s].push_back({pr.t, id, 0, 0});
+    add_pair(id, l, 0, pr.s, pr.t);
   }
   for (auto& pr : iv) {
     int l = B[pr.t].level;
     int id = image_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy + B[pr.s].iy);
-    by_t[pr.t].push_back({pr.s, id, 1, 0});
-    by_s[pr.s].push_back({pr.t, id, 1, 0});
+    add_pair(id, l, 1, pr.s, pr.t);
   }
+  // work items: per level, per table, batches of 64 pairs (16 when 2P+1 > 64),
+  // and groups of 32 row tiles of the real-embedded operator
+  std::vector<M2LItem> m2l_items;
+  std::vector<int> m2l_psrc, m2l_pdst;
+  pl->m2l_item_first.assign(pl->nlev + 1, 0);
+  for (int l = 0; l < pl->nlev; ++l) {
+    pl->m2l_item_first[l] = (int)m2l_items.size();
+    const int M = 2 * pl->P[l] + 1;
+    const int npi = (M <= 64) ? 64 : 16;
+    const int nrt = (2 * M + 15) / 16;
+    for (size_t id = 0; id < pairs_of.size(); ++id) {
+      if (table_level[id] != l) continue;
+      auto& v = pairs_of[id];
+      for (size_t c0 = 0; c0 < v.size(); c0 += npi) {
+        int cnt = (int)std::min<size_t>(npi, v.size() - c0);
+        int pbeg = (int)m2l_psrc.size();
+        for (int c = 0; c < cnt; ++c) {
+          m2l_psrc.push_back(v[c0 + c].first);
+          m2l_pdst.push_back(v[c0 + c].second);
+        }
+        for (int rt = 0; rt < nrt; rt += 32)
+          m2l_items.push_back(M2LItem{(int)id, l, pbeg, cnt, table_image[id], rt, 0, 0});
+      }
+    }
+  }
+  pl->m2l_item_first[pl->nlev] = (int)m2l_items.size();
   // M2M / L2L tables per parent level l (children at l + 1), quadrant order
   std::vector<double> fb_dx, fb_dy;
   std::vector<int> fb_sgn, fb_ref;
@@ -674,7 +717,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
 
   // ---- per-level box lists
-  std::vector<int> leaves, p2m_leaves, m2l_targets, m2m_boxes, l2l_boxes;
+  std::vector<int> leaves, p2m_leaves, m2m_boxes, l2l_boxes;
   std::vector<int> leaf_index(nb, -1);
   for (int i = 0; i < nb; ++i)
     if (B[i].leaf) {
@@ -694,15 +737,6 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
   pl->m2m_off[pl->nlev] = (int)m2m_boxes.size();
   pl->l2l_off[pl->nlev] = (int)l2l_boxes.size();
-  std::vector<int> m2l_ptr(1, 0), m2lT_ptr(1, 0);
-  std::vector<M2LEntry> m2l_ent, m2lT_ent;
-  for (int i = pl->lev_begin[std::min(2, pl->nlev)]; i < nb; ++i) {
-    m2l_targets.push_back(i);
-    m2l_ent.insert(m2l_ent.end(), by_t[i].begin(), by_t[i].end());
-    m2l_ptr.push_back((int)m2l_ent.size());
-    m2lT_ent.insert(m2lT_ent.end(), by_s[i].begin(), by_s[i].end());
-    m2lT_ptr.push_back((int)m2lT_ent.size());
-  }
 
   // ---- direct lists, grouped by target leaf, source ranges merged
   auto leaves_under = [&](int b, std::vector<int>& outv) {
@@ -894,8 +928,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
   UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
   UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves) UP(p2m_leaves, p2m_leaves)
-  UP(m2m_boxes, m2m_boxes) UP(l2l_boxes, l2l_boxes) UP(m2l_targets, m2l_targets) UP(m2l_ptr, m2l_ptr)
-  UP(m2lT_ptr, m2lT_ptr) UP(m2l_ent, m2l_ent) UP(m2lT_ent, m2lT_ent) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
+  UP(m2m_boxes, m2m_boxes) UP(l2l_boxes, l2l_boxes) UP(m2l_items, m2l_items) UP(m2l_psrc, m2l_psrc)
+  UP(m2l_pdst, m2l_pdst) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
   UP(p2p_items, p2p_items) UP(p2p_atomic, p2p_atomic) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
   DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
@@ -944,7 +978,6 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->nleaves = (int)leaves.size();
   pl->np2p_items = (int)p2p_items.size();
   pl->np2m = (int)p2m_leaves.size();
-  pl->nm2l_targets = (int)m2l_targets.size();
   pl->nif_leaves = (int)if_leaves.size();
   pl->nq = (int)qc.size();
 
@@ -1008,8 +1041,9 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
                  pl->alpha.p, 0);
   }
   mark();
-  launch_m2l(s, tv, pl->m2l_targets.p, pl->nm2l_targets, pl->m2l_ptr.p, pl->m2l_ent.p, pl->tabs.p, pl->tdata.p,
-             pl->alpha.p, pl->beta.p, 0);
+  launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
+  launch_m2l_mfma(s, tv, pl->m2l_items.p, pl->m2l_item_first.data(), pl->nlev, pl->m2l_psrc.p, pl->m2l_pdst.p,
+                  pl->tabs.p, pl->tdata.p, pl->alpha.p, pl->beta.p, 0);
   mark();
   for (int l = 3; l < pl->nlev; ++l) {
     int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];
@@ -1040,8 +1074,9 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
                  pl->beta.p, 1);
   }
   // M2L^T, grouped by source box
-  launch_m2l(s, tv, pl->m2l_targets.p, pl->nm2l_targets, pl->m2lT_ptr.p, pl->m2lT_ent.p, pl->tabs.p, pl->tdata.p,
-             pl->beta.p, pl->alpha.p, 1);
+  launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
+  launch_m2l_mfma(s, tv, pl->m2l_items.p, pl->m2l_item_first.data(), pl->nlev, pl->m2l_pdst.p, pl->m2l_psrc.p,
+                  pl->tabs.p, pl->tdata.p, pl->beta.p, pl->alpha.p, 1);
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
   for (int l = 3; l < pl->nlev; ++l) {
     int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];

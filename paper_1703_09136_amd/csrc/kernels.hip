@@ -220,6 +220,137 @@ __global__ void __launch_bounds__(WAVE) k_m2l(TreeView tv, const int* __restrict
   }
 }
 
+// ------------------------------------------------------------------ batched M2L on MFMA
+// For one table t (t[n], n = m - p in [-2P, 2P]) and a batch of (source,
+// target) pairs using it:
+//   out_c[p] += sum_m t[m - p] S_c[m]        (REV: t[p - m], the transpose)
+// computed as a real GEMM through the 2x2 embedding of complex numbers,
+//   [Re out; Im out] = [[Tr, -Ti], [Ti, Tr]] [Re S; Im S],
+// with 16x16x4 FP64 MFMA tiles: rows = 2M (M = 2P + 1) in tiles of 16, k = 2M
+// in steps of 4, columns = 16 pairs per wave. Operator tiles are expanded from
+// the Toeplitz vector in LDS on the fly. Image pairs use the reflected source
+// coefficients abar_m = (-1)^m alpha_{-m}; in the transpose the reflection
+// moves to the output. Results are added atomically into the target boxes.
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int M2L_THREADS = 256;
+
+template <bool REV>
+__global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2LItem* __restrict__ items,
+                                                         const int* __restrict__ psrc, const int* __restrict__ pdst,
+                                                         const TableRef* __restrict__ tabs,
+                                                         const double2* __restrict__ tdata,
+                                                         const double2* __restrict__ src, double2* __restrict__ dst,
+                                                         int r) {
+  extern __shared__ double2 lds[];
+  const M2LItem it = items[blockIdx.x];
+  const int P = tv.P[it.level];
+  const int M = 2 * P + 1;
+  const int M2 = 2 * M;
+  const int nrt = (M2 + 15) / 16;
+  const int nks = (M2 + 3) / 4;
+  const int npi = (M <= 64) ? 64 : 16;
+  double2* s_t = lds;
+  double2* s_s = lds + (4 * P + 1);
+  const int tid = threadIdx.x;
+  const TableRef tr = tabs[it.table];
+  const double2* T = tdata + tr.off + tr.half - 2 * P;  // T[0] = t[-2P]
+  for (int i = tid; i < 4 * P + 1; i += M2L_THREADS) s_t[i] = T[i];
+  const bool reflect_in = it.image && !REV;
+  for (int idx = tid; idx < npi * M; idx += M2L_THREADS) {
+    int c = idx / M, m = idx - c * M;
+    double2 v = cmk(0, 0);
+    if (c < it.npairs) {
+      const double2* S = src + (int64_t)r * tv.ctot + tv.coff[psrc[it.pbeg + c]];
+      if (reflect_in) {
+        v = S[M - 1 - m];
+        if ((m + P) & 1) v = cscale(v, -1.0);
+      } else {
+        v = S[m];
+      }
+    }
+    s_s[idx] = v;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63;
+  int ntile, rt_lo, rt_stride, rt_cnt;
+  const int rt_end = min(nrt, it.rt_base + 32);
+  if (npi == 64) {
+    ntile = wave;
+    rt_lo = it.rt_base;
+    rt_stride = 1;
+    rt_cnt = min(rt_end - rt_lo, 8);
+  } else {
+    ntile = 0;
+    rt_lo = it.rt_base + wave;
+    rt_stride = 4;
+    rt_cnt = rt_lo < rt_end ? min((rt_end - rt_lo + 3) / 4, 8) : 0;
+  }
+  if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const double2* Scol = s_s + (ntile * 16 + lrow) * M;
+  d4 acc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int ks = 0; ks < nks; ++ks) {
+    const int k = 4 * ks + lk;
+    double b = 0.0;
+    int mk = -1;
+    bool kim = false;
+    if (k < M) {
+      b = Scol[k].x;
+      mk = k;
+    } else if (k < M2) {
+      b = Scol[k - M].y;
+      mk = k - M;
+      kim = true;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < rt_cnt) {
+        const int row = (rt_lo + j * rt_stride) * 16 + lrow;
+        double a = 0.0;
+        if (mk >= 0 && row < M2) {
+          const bool rim = row >= M;
+          const int p = rim ? row - M : row;
+          const int tix = REV ? (p - mk + 2 * P) : (mk - p + 2 * P);
+          const double2 t = s_t[tix];
+          a = (rim == kim) ? t.x : (rim ? t.y : -t.y);
+        }
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+      }
+    }
+  }
+  const int col = ntile * 16 + lrow;
+  if (col >= it.npairs) return;
+  double2* out = dst + (int64_t)r * tv.ctot + tv.coff[pdst[it.pbeg + col]];
+  const bool reflect_out = REV && it.image;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    if (j >= rt_cnt) continue;
+    const int rt = rt_lo + j * rt_stride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      // D[row][col] of a 16x16x4 FP64 tile sits in lane col + 16 (row % 4), register row / 4
+      const int row = rt * 16 + 4 * i + lk;
+      if (row >= M2) continue;
+      const bool rim = row >= M;
+      const int p = rim ? row - M : row;
+      double v = acc[j][i];
+      int po = p;
+      if (reflect_out) {
+        po = M - 1 - p;
+        if ((p + P) & 1) v = -v;
+      }
+      unsafeAtomicAdd(rim ? &out[po].y : &out[po].x, v);
+    }
+  }
+}
+
+__global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = cmk(0.0, 0.0);
+}
+
 // M2M: alpha_parent = sum over children of T_q * alpha_child (q = quadrant of
 // the child). One wave per parent box of the level.
 __global__ void __launch_bounds__(WAVE) k_m2m(TreeView tv, const int* __restrict__ boxes, int nb,
@@ -645,6 +776,45 @@ void launch_m2l(hipStream_t s, const TreeView& tv, const int* targets, int nt, c
                 const TableRef* tabs, const double2* tdata, const double2* src, double2* dst, int rev) {
   if (nt) hipLaunchKernelGGL(k_m2l, dim3(nt), dim3(WAVE), 0, s, tv, targets, nt, ptr, ent, tabs, tdata, src, dst, rev);
 }
+// LDS bytes of an M2L item at order P.
+static size_t m2l_lds_bytes(int P) {
+  int M = 2 * P + 1;
+  int npi = (M <= 64) ? 64 : 16;
+  return sizeof(double2) * (size_t)(4 * P + 1 + npi * M);
+}
+
+void launch_m2l_mfma(hipStream_t s, const TreeView& tv, const M2LItem* items, const int* item_level_first,
+                     int nlev, const int* psrc, const int* pdst, const TableRef* tabs, const double2* tdata,
+                     const double2* src, double2* dst, int rev) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)k_m2l_mfma<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipFuncSetAttribute((const void*)k_m2l_mfma<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr_done = true;
+  }
+  // items are grouped by level (item_level_first[l] .. item_level_first[l+1]);
+  // one launch per level with that level's LDS size
+  for (int l = 0; l < nlev; ++l) {
+    int i0 = item_level_first[l], i1 = item_level_first[l + 1];
+    if (i1 <= i0) continue;
+    size_t lds = m2l_lds_bytes(tv.P[l]);
+    for (int r = 0; r < tv.nrhs; ++r) {
+      if (rev)
+        hipLaunchKernelGGL(k_m2l_mfma<true>, dim3(i1 - i0), dim3(M2L_THREADS), lds, s, tv, items + i0, psrc, pdst,
+                           tabs, tdata, src, dst, r);
+      else
+        hipLaunchKernelGGL(k_m2l_mfma<false>, dim3(i1 - i0), dim3(M2L_THREADS), lds, s, tv, items + i0, psrc, pdst,
+                           tabs, tdata, src, dst, r);
+    }
+  }
+}
+
+void launch_fill_zero(hipStream_t s, double2* p, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_zero, dim3(blocks(n, 256)), dim3(256), 0, s, p, n);
+}
+
 void launch_m2m(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
                 const double2* tdata, const double2* src, double2* dst, int rev) {
   if (nb) hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(WAVE), 0, s, tv, boxes, nb, tabs4, tdata, src, dst, rev);

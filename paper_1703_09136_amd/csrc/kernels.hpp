@@ -13,6 +13,10 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, co
                 int conj_w, double2 pref, int accumulate);
 void launch_m2l(hipStream_t s, const TreeView& tv, const int* targets, int nt, const int* ptr, const M2LEntry* ent,
                 const TableRef* tabs, const double2* tdata, const double2* src, double2* dst, int rev);
+void launch_m2l_mfma(hipStream_t s, const TreeView& tv, const M2LItem* items, const int* item_level_first,
+                     int nlev, const int* psrc, const int* pdst, const TableRef* tabs, const double2* tdata,
+                     const double2* src, double2* dst, int rev);
+void launch_fill_zero(hipStream_t s, double2* p, int64_t n);
 void launch_m2m(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
                 const double2* tdata, const double2* src, double2* dst, int rev);
 void launch_l2l(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
