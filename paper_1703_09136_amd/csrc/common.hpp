@@ -102,14 +102,6 @@ struct TableRef {
   int32_t pad;
 };
 
-// One entry of the multipole-to-local list of a target box.
-struct M2LEntry {
-  int32_t src;    // source box
-  int32_t table;  // table id
-  int32_t image;  // 1: heterogeneous (source coefficients reflected)
-  int32_t pad;
-};
-
 // A contour panel for the Sommerfeld quadratures: kind 0 = tau in [a, b]
 // (propagating part), kind 1 = s in [a, b] on the evanescent contour
 // t(s) = s - i*dip*sin(pi s / send) for s < send, t = s beyond.
@@ -119,18 +111,26 @@ struct Panel {
   int32_t pad;
 };
 
-// A work item of the batched M2L contraction: one translation table and up to
-// 64 (source, target) pairs that use it, pairs [pbeg, pbeg + npairs) of the
-// pair arrays; rt_base is the first row tile of the real-embedded operator.
-struct M2LItem {
+// A work item of the batched translation contraction: one translation table
+// and up to 64 (source, target) box pairs that use it, pairs
+// [pbeg, pbeg + npairs) of the pair arrays; source order Ps, target order Pd;
+// rt_base is the first row tile of the real-embedded operator; image marks
+// heterogeneous M2L tables (reflected source coefficients).
+struct TransItem {
   int32_t table;
-  int32_t level;
   int32_t pbeg;
   int32_t npairs;
   int32_t image;
   int32_t rt_base;
-  int32_t pad0, pad1;
+  int32_t Ps, Pd;
+  int32_t pad;
 };
+
+// Pairs per translation item: 64 (four 16-column MFMA tiles, one per wave) when
+// both expansions fit 64 coefficients, else 16 (the waves split the rows).
+__host__ __device__ inline int trans_pairs_per_item(int Ps, int Pd) {
+  return (2 * Ps + 1 <= 64 && 2 * Pd + 1 <= 64) ? 64 : 16;
+}
 
 struct TreeView {
   int32_t n;

@@ -249,13 +249,28 @@ struct hfmm_plan_s {
   DevBuf<int> perm, level, parent, quad, child;
   DevBuf<int2> prange;
   DevBuf<int64_t> coff;
-  DevBuf<int> leaves, p2m_leaves;
-  int nleaves = 0, np2m = 0;
-  DevBuf<int> m2m_boxes, l2l_boxes;
-  std::vector<int> m2m_off, l2l_off;  // per level
-  DevBuf<M2LItem> m2l_items;
+  DevBuf<int> leaves;  // leaf boxes, ascending level
+  int nleaves = 0;
+  std::vector<int> leaf_lev;  // leaves of level l: [leaf_lev[l], leaf_lev[l + 1])
+  // batched translations: item groups sharing (Ps, Pd), per level
+  struct Group {
+    int first = 0, count = 0, Ps = 0, Pd = 0;
+  };
+  // M2L: items, (source, target) pair arrays, contribution row offsets, and the
+  // per-box lists of pairs for the reduction by target (forward) / by source
+  DevBuf<TransItem> m2l_items;
   DevBuf<int> m2l_psrc, m2l_pdst;
-  std::vector<int> m2l_item_first;  // per level, host
+  DevBuf<int64_t> m2l_pcoff;
+  std::vector<Group> m2l_groups;
+  int64_t cstride = 0;  // contribution doubles per right-hand side
+  DevBuf<int> red_boxes, red_ptr, red_pairs, redT_ptr, redT_pairs;
+  int nred_boxes = 0;
+  // M2M / L2L: (child, parent) pairs grouped by parent level and quadrant;
+  // items shaped child -> parent (up) and parent -> child (down), by parent level
+  DevBuf<int> cp_child, cp_parent;
+  DevBuf<TransItem> up_items, down_items;
+  std::vector<Group> up_groups, down_groups;
+  DevBuf<double> contrib;
   DevBuf<TableRef> tabs;
   DevBuf<double2> tdata;
   std::vector<int> m2m_tab, l2l_tab;  // per parent level: index of 4 consecutive tables
@@ -297,8 +312,10 @@ struct hfmm_plan_s {
   }
   void release_all() {
     pts.release(); ctr.release(); perm.release(); level.release(); parent.release(); quad.release();
-    child.release(); prange.release(); coff.release(); leaves.release(); p2m_leaves.release();
-    m2m_boxes.release(); l2l_boxes.release(); m2l_items.release(); m2l_psrc.release(); m2l_pdst.release();
+    child.release(); prange.release(); coff.release(); leaves.release();
+    m2l_items.release(); m2l_psrc.release(); m2l_pdst.release(); m2l_pcoff.release(); red_boxes.release();
+    red_ptr.release(); red_pairs.release(); redT_ptr.release(); redT_pairs.release(); cp_child.release();
+    cp_parent.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_atomic.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release();
@@ -313,6 +330,7 @@ hfmm_status_t ensure_workspace(hfmm_plan_t pl, int nrhs) {
   HIP_TRY(pl->us.alloc((size_t)pl->n * nrhs));
   HIP_TRY(pl->alpha.alloc((size_t)std::max<int64_t>(pl->ctot, 1) * nrhs));
   HIP_TRY(pl->beta.alloc((size_t)std::max<int64_t>(pl->ctot, 1) * nrhs));
+  HIP_TRY(pl->contrib.alloc((size_t)std::max<int64_t>(pl->cstride, 1) * nrhs));
   pl->ws_nrhs = nrhs;
   return HFMM_OK;
 }
@@ -670,16 +688,22 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     int id = image_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy + B[pr.s].iy);
     add_pair(id, l, 1, pr.s, pr.t);
   }
-  // work items: per level, per table, batches of 64 pairs (16 when 2P+1 > 64),
-  // and groups of 32 row tiles of the real-embedded operator
-  std::vector<M2LItem> m2l_items;
+  // batched M2L items: per level, per table, batches of up to 64 pairs (16 when
+  // 2P+1 > 64), and groups of 32 row tiles of the real-embedded operator. Each
+  // pair owns a contribution row of 2(2P+1) doubles, reduced per box afterwards.
+  auto add_items = [](std::vector<TransItem>& items, int table, int pbeg, int cnt, int image, int Ps, int Pd) {
+    const int nrt = (2 * (2 * Pd + 1) + 15) / 16;
+    for (int rt = 0; rt < nrt; rt += 32) items.push_back(TransItem{table, pbeg, cnt, image, rt, Ps, Pd, 0});
+  };
+  std::vector<TransItem> m2l_items;
   std::vector<int> m2l_psrc, m2l_pdst;
-  pl->m2l_item_first.assign(pl->nlev + 1, 0);
+  std::vector<int64_t> m2l_pcoff;
+  int64_t cstride = 0;
   for (int l = 0; l < pl->nlev; ++l) {
-    pl->m2l_item_first[l] = (int)m2l_items.size();
-    const int M = 2 * pl->P[l] + 1;
-    const int npi = (M <= 64) ? 64 : 16;
-    const int nrt = (2 * M + 15) / 16;
+    hfmm_plan_s::Group g;
+    g.first = (int)m2l_items.size();
+    g.Ps = g.Pd = pl->P[l];
+    const int npi = trans_pairs_per_item(pl->P[l], pl->P[l]);
     for (size_t id = 0; id < pairs_of.size(); ++id) {
       if (table_level[id] != l) continue;
       auto& v = pairs_of[id];
@@ -689,13 +713,32 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         for (int c = 0; c < cnt; ++c) {
           m2l_psrc.push_back(v[c0 + c].first);
           m2l_pdst.push_back(v[c0 + c].second);
+          m2l_pcoff.push_back(cstride);
+          cstride += 2 * (2 * pl->P[l] + 1);
         }
-        for (int rt = 0; rt < nrt; rt += 32)
-          m2l_items.push_back(M2LItem{(int)id, l, pbeg, cnt, table_image[id], rt, 0, 0});
+        add_items(m2l_items, (int)id, pbeg, cnt, table_image[id], pl->P[l], pl->P[l]);
       }
     }
+    g.count = (int)m2l_items.size() - g.first;
+    if (g.count) pl->m2l_groups.push_back(g);
   }
-  pl->m2l_item_first[pl->nlev] = (int)m2l_items.size();
+  pl->cstride = cstride;
+  // per-box pair lists for the reductions (by target, and by source for the transpose)
+  std::vector<int> red_boxes, red_ptr(1, 0), red_pairs, redT_ptr(1, 0), redT_pairs;
+  {
+    std::vector<std::vector<int>> as_t(nb), as_s(nb);
+    for (int i = 0; i < (int)m2l_psrc.size(); ++i) {
+      as_t[m2l_pdst[i]].push_back(i);
+      as_s[m2l_psrc[i]].push_back(i);
+    }
+    for (int i = pl->lev_begin[std::min(2, pl->nlev)]; i < nb; ++i) {
+      red_boxes.push_back(i);
+      red_pairs.insert(red_pairs.end(), as_t[i].begin(), as_t[i].end());
+      red_ptr.push_back((int)red_pairs.size());
+      redT_pairs.insert(redT_pairs.end(), as_s[i].begin(), as_s[i].end());
+      redT_ptr.push_back((int)redT_pairs.size());
+    }
+  }
   // M2M / L2L tables per parent level l (children at l + 1), quadrant order
   std::vector<double> fb_dx, fb_dy;
   std::vector<int> fb_sgn, fb_ref;
@@ -716,27 +759,52 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     }
   }
 
+  // (child, parent) pairs per parent level l >= 2 and quadrant q, with items
+  // shaped child -> parent ("up": M2M, transposed L2L) and parent -> child
+  // ("down": L2L, transposed M2M); the table of an item is the quadrant, taken
+  // relative to the level's four M2M or L2L tables at launch.
+  std::vector<int> cp_child, cp_parent;
+  std::vector<TransItem> up_items, down_items;
+  pl->up_groups.assign(pl->nlev, {});
+  pl->down_groups.assign(pl->nlev, {});
+  for (int l = 2; l + 1 < pl->nlev; ++l) {
+    auto& gu = pl->up_groups[l];
+    auto& gd = pl->down_groups[l];
+    gu.first = (int)up_items.size();
+    gd.first = (int)down_items.size();
+    gu.Ps = gd.Pd = pl->P[l + 1];
+    gu.Pd = gd.Ps = pl->P[l];
+    const int npi = trans_pairs_per_item(pl->P[l + 1], pl->P[l]);
+    for (int q = 0; q < 4; ++q) {
+      std::vector<int> kids_q;
+      for (int i = pl->lev_begin[l + 1]; i < pl->lev_begin[l + 2]; ++i)
+        if (B[i].quad == q) kids_q.push_back(i);
+      for (size_t c0 = 0; c0 < kids_q.size(); c0 += npi) {
+        int cnt = (int)std::min<size_t>(npi, kids_q.size() - c0);
+        int pbeg = (int)cp_child.size();
+        for (int c = 0; c < cnt; ++c) {
+          cp_child.push_back(kids_q[c0 + c]);
+          cp_parent.push_back(B[kids_q[c0 + c]].parent);
+        }
+        add_items(up_items, q, pbeg, cnt, 0, pl->P[l + 1], pl->P[l]);
+        add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1]);
+      }
+    }
+    gu.count = (int)up_items.size() - gu.first;
+    gd.count = (int)down_items.size() - gd.first;
+  }
+
   // ---- per-level box lists
-  std::vector<int> leaves, p2m_leaves, m2m_boxes, l2l_boxes;
+  std::vector<int> leaves;
   std::vector<int> leaf_index(nb, -1);
-  for (int i = 0; i < nb; ++i)
+  pl->leaf_lev.assign(pl->nlev + 1, 0);
+  for (int i = 0; i < nb; ++i)  // boxes are in level order, so are the leaves
     if (B[i].leaf) {
       leaf_index[i] = (int)leaves.size();
       leaves.push_back(i);
-      if (B[i].level >= 2) p2m_leaves.push_back(i);
+      pl->leaf_lev[B[i].level + 1] = (int)leaves.size();
     }
-  pl->m2m_off.assign(pl->nlev + 1, 0);
-  pl->l2l_off.assign(pl->nlev + 1, 0);
-  for (int l = 0; l < pl->nlev; ++l) {
-    pl->m2m_off[l] = (int)m2m_boxes.size();
-    pl->l2l_off[l] = (int)l2l_boxes.size();
-    for (int i = pl->lev_begin[l]; i < pl->lev_begin[l + 1]; ++i) {
-      if (l >= 2 && !B[i].leaf) m2m_boxes.push_back(i);
-      if (l >= 3) l2l_boxes.push_back(i);
-    }
-  }
-  pl->m2m_off[pl->nlev] = (int)m2m_boxes.size();
-  pl->l2l_off[pl->nlev] = (int)l2l_boxes.size();
+  for (int l = 1; l <= pl->nlev; ++l) pl->leaf_lev[l] = std::max(pl->leaf_lev[l], pl->leaf_lev[l - 1]);
 
   // ---- direct lists, grouped by target leaf, source ranges merged
   auto leaves_under = [&](int b, std::vector<int>& outv) {
@@ -927,9 +995,11 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
 #define UP(buf, vec)                                  \
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
   UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
-  UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves) UP(p2m_leaves, p2m_leaves)
-  UP(m2m_boxes, m2m_boxes) UP(l2l_boxes, l2l_boxes) UP(m2l_items, m2l_items) UP(m2l_psrc, m2l_psrc)
-  UP(m2l_pdst, m2l_pdst) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
+  UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves)
+  UP(m2l_items, m2l_items) UP(m2l_psrc, m2l_psrc) UP(m2l_pdst, m2l_pdst) UP(m2l_pcoff, m2l_pcoff)
+  UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_pairs, red_pairs) UP(redT_ptr, redT_ptr)
+  UP(redT_pairs, redT_pairs) UP(cp_child, cp_child) UP(cp_parent, cp_parent) UP(up_items, up_items)
+  UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
   UP(p2p_items, p2p_items) UP(p2p_atomic, p2p_atomic) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
   DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
@@ -977,7 +1047,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
   pl->nleaves = (int)leaves.size();
   pl->np2p_items = (int)p2p_items.size();
-  pl->np2m = (int)p2m_leaves.size();
+  pl->nred_boxes = (int)red_boxes.size();
   pl->nif_leaves = (int)if_leaves.size();
   pl->nq = (int)qc.size();
 
@@ -1030,29 +1100,59 @@ struct Marker {
   }
 };
 
+// P2M (or L2P^T) over the leaves of level l.
+void launch_p2m_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, int l, const double2* qs, double2* alpha,
+                      int conj_w, double2 pref) {
+  const int b0 = pl->leaf_lev[l], b1 = pl->leaf_lev[l + 1];
+  launch_p2m(s, tv, pl->leaves.p + b0, b1 - b0, tv.P[l], qs, alpha, conj_w, pref);
+}
+
+// L2P (or P2M^T) over the leaves of level l; the first writer of u.
+void launch_l2p_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, int l, const double2* beta, double2* us,
+                      int conj_w, double2 pref) {
+  const int b0 = pl->leaf_lev[l], b1 = pl->leaf_lev[l + 1];
+  launch_l2p(s, tv, pl->leaves.p + b0, b1 - b0, tv.P[l], beta, us, conj_w, pref, 0);
+}
+
+// One level of child -> parent (up) or parent -> child (down) translations.
+void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, int l, bool m2m_tables,
+                  const double2* src, double2* dst, int rev) {
+  const hfmm_plan_s::Group& g = up ? pl->up_groups[l] : pl->down_groups[l];
+  if (!g.count) return;
+  const TableRef* tabs4 = pl->tabs.p + (m2m_tables ? pl->m2m_tab[l] : pl->l2l_tab[l]);
+  const TransItem* items = (up ? pl->up_items.p : pl->down_items.p) + g.first;
+  const int* psrc = up ? pl->cp_child.p : pl->cp_parent.p;
+  const int* pdst = up ? pl->cp_parent.p : pl->cp_child.p;
+  // a child has one parent: parent -> child writes never collide
+  launch_trans(s, tv, items, g.count, g.Ps, g.Pd, psrc, pdst, nullptr, tabs4, pl->tdata.p, src, dst, nullptr, 0, rev,
+               up ? 0 : 1);
+}
+
+// All M2L items (forward: source -> target; transpose: target -> source) into
+// the per-pair contribution rows, then the per-box reduction into dst.
+void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* src, double2* dst, int rev) {
+  const int* psrc = rev ? pl->m2l_pdst.p : pl->m2l_psrc.p;
+  const int* pdst = rev ? pl->m2l_psrc.p : pl->m2l_pdst.p;
+  for (const auto& g : pl->m2l_groups)
+    launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, psrc, pdst, pl->m2l_pcoff.p, pl->tabs.p,
+                 pl->tdata.p, src, nullptr, pl->contrib.p, pl->cstride, rev, 0);
+  launch_reduce_contrib(s, tv, pl->red_boxes.p, pl->nred_boxes, rev ? pl->redT_ptr.p : pl->red_ptr.p,
+                        rev ? pl->redT_pairs.p : pl->red_pairs.p, pl->m2l_pcoff.p, pl->contrib.p, pl->cstride, dst);
+}
+
 void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
   TreeView tv = pl->view(nrhs);
-  launch_p2m(s, tv, pl->p2m_leaves.p, pl->np2m, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
+  // parents accumulate their children's translated multipoles
+  launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
+  for (int l = 2; l < pl->nlev; ++l) launch_p2m_level(pl, tv, s, l, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
   mark();
-  for (int l = pl->nlev - 2; l >= 2; --l) {
-    int b0 = pl->m2m_off[l], b1 = pl->m2m_off[l + 1];
-    if (b1 > b0)
-      launch_m2m(s, tv, pl->m2m_boxes.p + b0, b1 - b0, pl->tabs.p + pl->m2m_tab[l], pl->tdata.p, pl->alpha.p,
-                 pl->alpha.p, 0);
-  }
+  for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0);
   mark();
-  launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
-  launch_m2l_mfma(s, tv, pl->m2l_items.p, pl->m2l_item_first.data(), pl->nlev, pl->m2l_psrc.p, pl->m2l_pdst.p,
-                  pl->tabs.p, pl->tdata.p, pl->alpha.p, pl->beta.p, 0);
+  launch_m2l_all(pl, tv, s, pl->alpha.p, pl->beta.p, 0);
   mark();
-  for (int l = 3; l < pl->nlev; ++l) {
-    int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];
-    if (b1 > b0)
-      launch_l2l(s, tv, pl->l2l_boxes.p + b0, b1 - b0, pl->tabs.p + pl->l2l_tab[l - 1], pl->tdata.p, pl->beta.p,
-                 pl->beta.p, 0, 1);
-  }
+  for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0);
   mark();
-  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->beta.p, us, 0, cmk(0.0, 0.25), 0);
+  for (int l = 0; l < pl->nlev; ++l) launch_l2p_level(pl, tv, s, l, pl->beta.p, us, 0, cmk(0.0, 0.25));
   mark();
   launch_p2p(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, qs, us);
   mark();
@@ -1064,28 +1164,17 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
 // w_sorted = A^T v_sorted through the transposes of the stages, in reverse order.
 void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* vs, double2* ws) {
   TreeView tv = pl->view(nrhs);
-  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}
-  launch_p2m(s, tv, pl->p2m_leaves.p, pl->np2m, vs, pl->beta.p, 1, cmk(0.0, 0.25));
-  // L2L^T, finest parents first: beta'(parent) = sum_children T^T beta'(child)
-  for (int l = pl->nlev - 2; l >= 2; --l) {
-    int b0 = pl->m2m_off[l], b1 = pl->m2m_off[l + 1];
-    if (b1 > b0)
-      launch_m2m(s, tv, pl->m2m_boxes.p + b0, b1 - b0, pl->tabs.p + pl->l2l_tab[l], pl->tdata.p, pl->beta.p,
-                 pl->beta.p, 1);
-  }
-  // M2L^T, grouped by source box
-  launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
-  launch_m2l_mfma(s, tv, pl->m2l_items.p, pl->m2l_item_first.data(), pl->nlev, pl->m2l_pdst.p, pl->m2l_psrc.p,
-                  pl->tabs.p, pl->tdata.p, pl->beta.p, pl->alpha.p, 1);
+  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}; parents accumulate
+  launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
+  for (int l = 2; l < pl->nlev; ++l) launch_p2m_level(pl, tv, s, l, vs, pl->beta.p, 1, cmk(0.0, 0.25));
+  // L2L^T, finest parents first: beta'(parent) += T^T beta'(child)
+  for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
+  // M2L^T, reduced by source box
+  launch_m2l_all(pl, tv, s, pl->beta.p, pl->alpha.p, 1);
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
-  for (int l = 3; l < pl->nlev; ++l) {
-    int b0 = pl->l2l_off[l], b1 = pl->l2l_off[l + 1];
-    if (b1 > b0)
-      launch_l2l(s, tv, pl->l2l_boxes.p + b0, b1 - b0, pl->tabs.p + pl->m2m_tab[l - 1], pl->tdata.p, pl->alpha.p,
-                 pl->alpha.p, 1, 1);
-  }
+  for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1);
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
-  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->alpha.p, ws, 1, cmk(1.0, 0.0), 0);
+  for (int l = 0; l < pl->nlev; ++l) launch_l2p_level(pl, tv, s, l, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
   // the direct parts are symmetric
   launch_p2p(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, vs, ws);
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,

@@ -53,21 +53,32 @@ __global__ void k_scatter(int n, int nrhs, const int* __restrict__ perm, const d
 
 // ------------------------------------------------------------------ P2M
 // alpha_p = sum_j q_j J_p(k rho_j) e^{-i p theta_j}, p in [-P, P] (Eq. multi_coeff).
-// One wave per leaf; lanes own points; every order is reduced across the wave.
-// With conj_w the phase is e^{+i p theta_j} and the result is scaled by pref:
-// this is the transpose of L2P, used by the adjoint.
-__global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict__ leaves, int nleaves,
+// One wave per leaf, a lane per point. Each lane walks the backward Bessel
+// recurrence once and parks V_{n,j} = J_n(k rho_j) w_j^n (w = e^{-i theta}) for a
+// chunk of P2M_CH orders in LDS; the chunk is then reduced over the points
+// for every right-hand side, giving alpha_n = sum q V and, through
+// J_{-n} = (-1)^n J_n, alpha_{-n} = (-1)^n sum q conj(V). The coefficients
+// accumulate in LDS and are stored once. With conj_w the phase is
+// e^{+i p theta} and the result is scaled by pref: the transpose of L2P.
+constexpr int P2M_CH = 16;  // orders per reduction chunk
+constexpr int P2M_RB = 4;   // right-hand sides per pass
+constexpr int P2M_VS = WAVE + 1;  // padded row of the V tile
+
+__global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict__ leaves, int nleaves, int P,
                                               const double2* __restrict__ qs, double2* __restrict__ alpha,
                                               int conj_w, double2 pref) {
-  int li = blockIdx.x;
+  extern __shared__ double2 lds_c[];
+  double2* s_V = lds_c;                     // [P2M_CH][P2M_VS]
+  double2* s_q = s_V + P2M_CH * P2M_VS;     // [P2M_RB][WAVE]
+  double2* s_a = s_q + P2M_RB * WAVE;       // [P2M_RB][2P + 1]
+  const int li = blockIdx.x;
   if (li >= nleaves) return;
-  int b = leaves[li];
-  int lane = threadIdx.x;
-  int P = tv.P[tv.level[b]];
-  int2 pr = tv.prange[b];
-  double2 c = tv.ctr[b];
-  for (int r = 0; r < tv.nrhs; ++r)
-    for (int o = lane; o < 2 * P + 1; o += WAVE) alpha[r * tv.ctot + tv.coff[b] + o] = cmk(0, 0);
+  const int b = leaves[li];
+  const int lane = threadIdx.x;
+  const int M = 2 * P + 1;
+  const int2 pr = tv.prange[b];
+  const double2 c = tv.ctr[b];
+  const int64_t cb = tv.coff[b];
   // a bound on k*rho for the whole box gives one recurrence length per wave
   double rmax = 0.0;
   for (int j = pr.x + lane; j < pr.y; j += WAVE) {
@@ -75,203 +86,261 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
     rmax = fmax(rmax, hypot(p.x - c.x, p.y - c.y));
   }
   for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
-  int nstart = miller_start(tv.k * rmax, P);
-  for (int j0 = pr.x; j0 < pr.y; j0 += WAVE) {
-    int j = j0 + lane;
-    bool valid = j < pr.y;
-    double dx = 0, dy = 0;
-    if (valid) { double2 p = tv.pts[j]; dx = p.x - c.x; dy = p.y - c.y; }
-    double rho = hypot(dx, dy);
-    double x = fmax(tv.k * rho, 1e-100);
-    double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1, 0);
-    double th = atan2(w.y, w.x);
-    double s, co;
-    sincos((double)P * th, &s, &co);
-    double2 wn = cmk(co, s);  // w^P
-    double inv_s;
-    int nres;
-    miller_norm(x, nstart, inv_s, nres);
-    miller_emit(x, nstart, P, inv_s, nres, [&](int n, double jn) {
-      if (!valid) jn = 0.0;
-      double2 wpos = cscale(wn, jn);
-      double2 wneg = cscale(cconj(wn), (n & 1) ? -jn : jn);
-      for (int r = 0; r < tv.nrhs; ++r) {
-        double2 q = valid ? qs[(int64_t)r * tv.n + j] : cmk(0, 0);
-        double2 cp = wave_sum(cmul(q, wpos));
-        double2 cm = n > 0 ? wave_sum(cmul(q, wneg)) : cmk(0, 0);
-        if (lane == 0) {
-          double2* a = alpha + r * tv.ctot + tv.coff[b] + P;
-          a[n] = cadd(a[n], cmul(pref, cp));
-          if (n > 0) a[-n] = cadd(a[-n], cmul(pref, cm));
-        }
+  const int nstart = miller_start(tv.k * rmax, P);
+  // reduction role of this lane: order slot t of the chunk, point quarter part
+  const int t_red = lane & (P2M_CH - 1), part = lane / P2M_CH;
+  for (int r0 = 0; r0 < tv.nrhs; r0 += P2M_RB) {
+    const int nr = min(P2M_RB, tv.nrhs - r0);
+    for (int e = lane; e < nr * M; e += WAVE) s_a[e] = cmk(0.0, 0.0);
+    for (int j0 = pr.x; j0 < pr.y; j0 += WAVE) {
+      const int j = j0 + lane;
+      const bool valid = j < pr.y;
+      double dx = 0, dy = 0;
+      if (valid) {
+        double2 p = tv.pts[j];
+        dx = p.x - c.x;
+        dy = p.y - c.y;
       }
-      wn = cmul(wn, cconj(w));
-    });
+#pragma unroll
+      for (int rr = 0; rr < P2M_RB; ++rr)
+        if (rr < nr) s_q[rr * WAVE + lane] = valid ? qs[(int64_t)(r0 + rr) * tv.n + j] : cmk(0.0, 0.0);
+      const double rho = hypot(dx, dy);
+      const double x = fmax(tv.k * rho, 1e-100);
+      const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1, 0);
+      double sn, cs;
+      sincos((double)P * atan2(w.y, w.x), &sn, &cs);
+      double2 wn = cmk(cs, sn);  // w^P
+      double inv_s;
+      int nres;
+      miller_norm(x, nstart, inv_s, nres);
+      MillerWalk mw(x, nstart, inv_s, nres);
+      while (mw.n > P) mw.step();
+      for (int nh = P; nh >= 0; nh -= P2M_CH) {
+#pragma unroll
+        for (int t = 0; t < P2M_CH; ++t) {
+          if (nh - t >= 0) {
+            s_V[t * P2M_VS + lane] = cscale(wn, valid ? mw.value() : 0.0);
+            wn = cmul(wn, cconj(w));
+            if (mw.n > 0) mw.step();
+          }
+        }
+        __syncthreads();
+        const int n = nh - t_red;
+#pragma unroll
+        for (int rr = 0; rr < P2M_RB; ++rr) {
+          if (rr >= nr) break;
+          double2 sp = cmk(0.0, 0.0), sm = cmk(0.0, 0.0);
+          if (n >= 0) {
+            const double2* V = s_V + t_red * P2M_VS + part * (WAVE / 4);
+            const double2* Q = s_q + rr * WAVE + part * (WAVE / 4);
+#pragma unroll 4
+            for (int i = 0; i < WAVE / 4; ++i) {
+              const double2 v = V[i], q = Q[i];
+              sp = cadd(sp, cmul(q, v));
+              sm = cadd(sm, cmul(q, cconj(v)));
+            }
+          }
+          sp = cadd(sp, shfl_xor_c(sp, P2M_CH));
+          sp = cadd(sp, shfl_xor_c(sp, 2 * P2M_CH));
+          sm = cadd(sm, shfl_xor_c(sm, P2M_CH));
+          sm = cadd(sm, shfl_xor_c(sm, 2 * P2M_CH));
+          if (part == 0 && n >= 0) {
+            double2* a = s_a + rr * M + P;
+            a[n] = cadd(a[n], cmul(pref, sp));
+            if (n > 0) a[-n] = cadd(a[-n], cmul(pref, (n & 1) ? cscale(sm, -1.0) : sm));
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int e = lane; e < nr * M; e += WAVE) {
+      const int rr = e / M;
+      alpha[(int64_t)(r0 + rr) * tv.ctot + cb + (e - rr * M)] = s_a[e];
+    }
+    __syncthreads();
   }
+}
+
+size_t p2m_lds_bytes(int P) {
+  return sizeof(double2) * (size_t)(P2M_CH * P2M_VS + P2M_RB * WAVE + P2M_RB * (2 * P + 1));
 }
 
 // ------------------------------------------------------------------ L2P
 // u_i (+)= pref * sum_p beta_p J_p(k r_i) e^{i p theta_i} (local expansion,
-// Section 3.2). One wave per leaf, a lane per point. With conj_w the phase is
-// e^{-i p theta_i} (transpose of P2M, used by the adjoint). Leaves above level 2
-// have no local expansion and write zeros. accumulate = 0 stores.
-__global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
+// Section 3.2). One wave per leaf, a lane per point; the leaf's coefficients
+// for up to L2P_RB right-hand sides are staged in LDS and one recurrence walk
+// serves all of them. With conj_w the phase is e^{-i p theta_i}: the
+// transpose of P2M, used by the adjoint.
+constexpr int L2P_RB = 4;
+
+__global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict__ leaves, int nleaves, int P,
                                               const double2* __restrict__ beta, double2* __restrict__ us,
                                               int conj_w, double2 pref, int accumulate) {
-  int li = blockIdx.x;
+  extern __shared__ double2 lds_c[];  // [L2P_RB][2P + 1]
+  const int li = blockIdx.x;
   if (li >= nleaves) return;
-  int b = leaves[li];
-  int lane = threadIdx.x;
-  int lev = tv.level[b];
-  int P = tv.P[lev];
-  int2 pr = tv.prange[b];
-  double2 c = tv.ctr[b];
-  bool has_local = lev >= 2;
-  for (int j = pr.x + lane; j < pr.y; j += WAVE) {
-    double2 p = tv.pts[j];
-    double dx = p.x - c.x, dy = p.y - c.y;
-    double rho = hypot(dx, dy);
-    double x = fmax(tv.k * rho, 1e-100);
-    double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1, 0);
-    for (int r = 0; r < tv.nrhs; ++r) {
-      double2 acc = cmk(0, 0);
+  const int b = leaves[li];
+  const int lane = threadIdx.x;
+  const bool has_local = tv.level[b] >= 2;
+  const int M = 2 * P + 1;
+  const int2 pr = tv.prange[b];
+  const double2 c = tv.ctr[b];
+  const int64_t cb = tv.coff[b];
+  int nstart = 0;
+  if (has_local) {
+    double rmax = 0.0;
+    for (int j = pr.x + lane; j < pr.y; j += WAVE) {
+      double2 p = tv.pts[j];
+      rmax = fmax(rmax, hypot(p.x - c.x, p.y - c.y));
+    }
+    for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
+    nstart = miller_start(tv.k * rmax, P);
+  }
+  for (int r0 = 0; r0 < tv.nrhs; r0 += L2P_RB) {
+    const int nr = min(L2P_RB, tv.nrhs - r0);
+    if (has_local) {
+      for (int e = lane; e < nr * M; e += WAVE) {
+        const int rr = e / M;
+        lds_c[e] = beta[(int64_t)(r0 + rr) * tv.ctot + cb + (e - rr * M)];
+      }
+      __syncthreads();
+    }
+    for (int j = pr.x + lane; j < pr.y; j += WAVE) {
+      double2 acc[L2P_RB];
+#pragma unroll
+      for (int rr = 0; rr < L2P_RB; ++rr) acc[rr] = cmk(0.0, 0.0);
       if (has_local) {
-        const double2* bt = beta + r * tv.ctot + tv.coff[b] + P;
-        double th = atan2(w.y, w.x);
-        double s, co;
-        sincos((double)P * th, &s, &co);
-        double2 wn = cmk(co, s);
-        bessel_j_each(x, P, [&](int n, double jn) {
-          double2 t = cmul(bt[n], wn);
-          if (n > 0) {
-            double2 tm = cmul(bt[-n], cconj(wn));
-            t = cadd(t, (n & 1) ? cscale(tm, -1.0) : tm);
+        const double2 p = tv.pts[j];
+        const double dx = p.x - c.x, dy = p.y - c.y;
+        const double rho = hypot(dx, dy);
+        const double x = fmax(tv.k * rho, 1e-100);
+        const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1, 0);
+        double sn, cs;
+        sincos((double)P * atan2(w.y, w.x), &sn, &cs);
+        double2 wn = cmk(cs, sn);  // w^P
+        double inv_s;
+        int nres;
+        miller_norm(x, nstart, inv_s, nres);
+        MillerWalk mw(x, nstart, inv_s, nres);
+        while (mw.n > P) mw.step();
+        for (int n = P; n >= 0; --n) {
+          const double jn = mw.value();
+#pragma unroll
+          for (int rr = 0; rr < L2P_RB; ++rr) {
+            if (rr < nr) {
+              const double2* bt = lds_c + rr * M + P;
+              double2 t = cmul(bt[n], wn);
+              if (n > 0) {
+                const double2 tm = cmul(bt[-n], cconj(wn));
+                t = (n & 1) ? csub(t, tm) : cadd(t, tm);
+              }
+              acc[rr] = cadd(acc[rr], cscale(t, jn));
+            }
           }
-          acc = cadd(acc, cscale(t, jn));
           wn = cmul(wn, cconj(w));
-        });
-      }
-      int64_t idx = (int64_t)r * tv.n + j;
-      double2 v = cmul(pref, acc);
-      us[idx] = accumulate ? cadd(us[idx], v) : v;
-    }
-  }
-}
-
-// ------------------------------------------------------------------ Toeplitz contraction
-// acc(p) = sum_{m=-Ps}^{Ps} T[m - p] s(m), s(m) = src[m] or, for image sources,
-// (-1)^m src[-m]; rev reads T[p - m] instead (the transposed operator).
-__device__ inline double2 toeplitz_dot(const double2* __restrict__ T, const double2* __restrict__ S, int Ps,
-                                       int p, int image, int rev) {
-  double2 acc = cmk(0, 0);
-  if (!image) {
-    if (!rev)
-      for (int m = -Ps; m <= Ps; ++m) acc = cadd(acc, cmul(T[m - p], S[m]));
-    else
-      for (int m = -Ps; m <= Ps; ++m) acc = cadd(acc, cmul(T[p - m], S[m]));
-  } else {
-    // s(m) = (-1)^m S[-m]  =>  sum_m' T[-m' - p] (-1)^m' S[m']
-    if (!rev)
-      for (int m = -Ps; m <= Ps; ++m) {
-        double2 v = cmul(T[-m - p], S[m]);
-        acc = (m & 1) ? csub(acc, v) : cadd(acc, v);
-      }
-    else {
-      // transpose of the reflected operator: the sign moves to the output,
-      // out(p) = (-1)^p sum_m T[-p - m] S[m]
-      for (int m = -Ps; m <= Ps; ++m) acc = cadd(acc, cmul(T[-p - m], S[m]));
-      if (p & 1) acc = cscale(acc, -1.0);
-    }
-  }
-  return acc;
-}
-
-// M2L: beta_t = sum over the list of t of T_e * s_e (free: alpha of the source
-// box; image: reflected alpha). One wave per target box; the list of a box
-// holds all its free and heterogeneous entries, so beta_t is written once.
-__global__ void __launch_bounds__(WAVE) k_m2l(TreeView tv, const int* __restrict__ targets, int ntargets,
-                                              const int* __restrict__ ptr, const M2LEntry* __restrict__ ent,
-                                              const TableRef* __restrict__ tabs, const double2* __restrict__ tdata,
-                                              const double2* __restrict__ src, double2* __restrict__ dst,
-                                              int rev) {
-  int wi = blockIdx.x;
-  if (wi >= ntargets) return;
-  int t = targets[wi];
-  int lane = threadIdx.x;
-  int P = tv.P[tv.level[t]];
-  int nout = 2 * P + 1;
-  int e0 = ptr[wi], e1 = ptr[wi + 1];
-  for (int r = 0; r < tv.nrhs; ++r) {
-    for (int o0 = 0; o0 < nout; o0 += WAVE) {
-      int o = o0 + lane;
-      double2 acc = cmk(0, 0);
-      if (o < nout) {
-        int p = o - P;
-        for (int e = e0; e < e1; ++e) {
-          M2LEntry en = ent[e];
-          TableRef tr = tabs[en.table];
-          const double2* T = tdata + tr.off + tr.half;
-          const double2* S = src + r * tv.ctot + tv.coff[en.src] + P;
-          acc = cadd(acc, toeplitz_dot(T, S, P, p, en.image, rev));
+          if (n > 0) mw.step();
         }
-        dst[r * tv.ctot + tv.coff[t] + o] = acc;
+      }
+#pragma unroll
+      for (int rr = 0; rr < L2P_RB; ++rr) {
+        if (rr < nr) {
+          const int64_t idx = (int64_t)(r0 + rr) * tv.n + j;
+          const double2 v = cmul(pref, acc[rr]);
+          us[idx] = accumulate ? cadd(us[idx], v) : v;
+        }
       }
     }
+    if (has_local) __syncthreads();
   }
 }
 
-// ------------------------------------------------------------------ batched M2L on MFMA
-// For one table t (t[n], n = m - p in [-2P, 2P]) and a batch of (source,
-// target) pairs using it:
-//   out_c[p] += sum_m t[m - p] S_c[m]        (REV: t[p - m], the transpose)
+size_t l2p_lds_bytes(int P) { return sizeof(double2) * (size_t)(L2P_RB * (2 * P + 1)); }
+
+// ------------------------------------------------------------------ batched translations on MFMA
+// For one table t (t[n], n = m - p, m in [-Ps, Ps] source orders, p in
+// [-Pd, Pd] target orders) and a batch of (source, target) box pairs using it:
+//   out_c[p] = sum_m t[m - p] S_c[m]        (REV: t[p - m], the transpose)
 // computed as a real GEMM through the 2x2 embedding of complex numbers,
 //   [Re out; Im out] = [[Tr, -Ti], [Ti, Tr]] [Re S; Im S],
-// with 16x16x4 FP64 MFMA tiles: rows = 2M (M = 2P + 1) in tiles of 16, k = 2M
-// in steps of 4, columns = 16 pairs per wave. Operator tiles are expanded from
-// the Toeplitz vector in LDS on the fly. Image pairs use the reflected source
+// with 16x16x4 FP64 MFMA tiles: rows = 2 Md in tiles of 16, k = 2 Ms in steps
+// of 4, columns = 16 pairs per wave. Operator tiles are expanded from the
+// Toeplitz vector in LDS on the fly. Image pairs use the reflected source
 // coefficients abar_m = (-1)^m alpha_{-m}; in the transpose the reflection
-// moves to the output. Results are added atomically into the target boxes.
+// moves to the output. The result either goes to a per-pair contribution row
+// (reduced per box afterwards), is added atomically into the target box, or,
+// when every target box of the launch receives exactly one pair (parent to
+// child), is added with a plain read-modify-write.
+// This one kernel runs M2L (free and heterogeneous), M2M, L2L and their
+// transposes.
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int M2L_THREADS = 256;
+constexpr int TR_THREADS = 256;
 
-template <bool REV>
-__global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2LItem* __restrict__ items,
-                                                         const int* __restrict__ psrc, const int* __restrict__ pdst,
-                                                         const TableRef* __restrict__ tabs,
-                                                         const double2* __restrict__ tdata,
-                                                         const double2* __restrict__ src, double2* __restrict__ dst,
-                                                         int r) {
-  extern __shared__ double2 lds[];
-  const M2LItem it = items[blockIdx.x];
-  const int P = tv.P[it.level];
-  const int M = 2 * P + 1;
-  const int M2 = 2 * M;
-  const int nrt = (M2 + 15) / 16;
-  const int nks = (M2 + 3) / 4;
-  const int npi = (M <= 64) ? 64 : 16;
-  double2* s_t = lds;
-  double2* s_s = lds + (4 * P + 1);
-  const int tid = threadIdx.x;
+enum { OUT_ATOMIC = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2 };
+
+template <bool REV, int MODE>
+__global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const TransItem* __restrict__ items,
+                                                          const int* __restrict__ psrc,
+                                                          const int* __restrict__ pdst,
+                                                          const int64_t* __restrict__ pcoff,
+                                                          const TableRef* __restrict__ tabs,
+                                                          const double2* __restrict__ tdata,
+                                                          const double2* __restrict__ src, double2* __restrict__ dst,
+                                                          double* __restrict__ contrib, int64_t cstride, int r) {
+  extern __shared__ double lds_d[];
+  __shared__ int64_t s_off[64];
+  const TransItem it = items[blockIdx.x];
+  const int Ps = it.Ps, Pd = it.Pd;
+  const int Ms = 2 * Ps + 1, Md = 2 * Pd + 1;
+  const int nt = 2 * (Ps + Pd) + 1;           // table length
+  const int nrt = (2 * Md + 15) / 16;
+  const int nks = (2 * Ms + 3) / 4;
+  const int npi = trans_pairs_per_item(Ps, Pd);
+  double* s_tr = lds_d;
+  double* s_ti = lds_d + nt;
+  double2* s_s = (double2*)(lds_d + 2 * ((nt + 1) / 2) * 2);  // 16-byte aligned
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // Every global load of the prologue is issued in one of two rounds: the
+  // pairs' coefficient offsets and the table first, then all source rows.
+  if (tid < npi) s_off[tid] = tid < it.npairs ? tv.coff[psrc[it.pbeg + tid]] : -1;
   const TableRef tr = tabs[it.table];
-  const double2* T = tdata + tr.off + tr.half - 2 * P;  // T[0] = t[-2P]
-  for (int i = tid; i < 4 * P + 1; i += M2L_THREADS) s_t[i] = T[i];
-  const bool reflect_in = it.image && !REV;
-  for (int idx = tid; idx < npi * M; idx += M2L_THREADS) {
-    int c = idx / M, m = idx - c * M;
-    double2 v = cmk(0, 0);
-    if (c < it.npairs) {
-      const double2* S = src + (int64_t)r * tv.ctot + tv.coff[psrc[it.pbeg + c]];
-      if (reflect_in) {
-        v = S[M - 1 - m];
-        if ((m + P) & 1) v = cscale(v, -1.0);
-      } else {
-        v = S[m];
-      }
-    }
-    s_s[idx] = v;
+  const double2* T = tdata + tr.off + tr.half - (Ps + Pd);  // T[0] = t[-(Ps + Pd)]
+  for (int i = tid; i < nt; i += TR_THREADS) {
+    double2 v = T[i];
+    s_tr[i] = v.x;
+    s_ti[i] = v.y;
   }
   __syncthreads();
-  const int wave = tid >> 6, lane = tid & 63;
+  // source coefficients, flattened (pair, order) so consecutive lanes read
+  // consecutive coefficients of a row; four loads in flight per lane
+  const bool reflect_in = it.image && !REV;
+  const double2* Sr = src + (int64_t)r * tv.ctot;
+  const int tot = npi * Ms;
+  for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
+    double2 v[4];
+    int ev[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * TR_THREADS;
+      ev[u] = e;
+      v[u] = cmk(0.0, 0.0);
+      if (e < tot) {
+        const int c = e / Ms, m = e - c * Ms;
+        const int64_t off = s_off[c];
+        if (off >= 0) {
+          if (reflect_in) {
+            v[u] = Sr[off + Ms - 1 - m];
+            if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
+          } else {
+            v[u] = Sr[off + m];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ev[u] < tot) s_s[ev[u]] = v[u];
+  }
+  __syncthreads();
   int ntile, rt_lo, rt_stride, rt_cnt;
   const int rt_end = min(nrt, it.rt_base + 32);
   if (npi == 64) {
@@ -287,7 +356,18 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2L
   }
   if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
   const int lrow = lane & 15, lk = lane >> 4;
-  const double2* Scol = s_s + (ntile * 16 + lrow) * M;
+  const double2* Scol = s_s + (ntile * 16 + lrow) * Ms;
+  // row-dependent parts of the operator index, per row tile of this lane
+  int tb[8];
+  bool rimj[8], rowok[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int row = (rt_lo + j * rt_stride) * 16 + lrow;
+    rowok[j] = (j < rt_cnt) && row < 2 * Md;
+    rimj[j] = row >= Md;
+    const int p = rimj[j] ? row - Md : row;
+    tb[j] = REV ? (p + 2 * Ps) : (2 * Pd - p);
+  }
   d4 acc[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
@@ -296,25 +376,21 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2L
     double b = 0.0;
     int mk = -1;
     bool kim = false;
-    if (k < M) {
+    if (k < Ms) {
       b = Scol[k].x;
       mk = k;
-    } else if (k < M2) {
-      b = Scol[k - M].y;
-      mk = k - M;
+    } else if (k < 2 * Ms) {
+      b = Scol[k - Ms].y;
+      mk = k - Ms;
       kim = true;
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       if (j < rt_cnt) {
-        const int row = (rt_lo + j * rt_stride) * 16 + lrow;
         double a = 0.0;
-        if (mk >= 0 && row < M2) {
-          const bool rim = row >= M;
-          const int p = rim ? row - M : row;
-          const int tix = REV ? (p - mk + 2 * P) : (mk - p + 2 * P);
-          const double2 t = s_t[tix];
-          a = (rim == kim) ? t.x : (rim ? t.y : -t.y);
+        if (rowok[j] && mk >= 0) {
+          const int tix = REV ? tb[j] - mk : tb[j] + mk;
+          a = (rimj[j] == kim) ? s_tr[tix] : (rimj[j] ? s_ti[tix] : -s_ti[tix]);
         }
         acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
       }
@@ -322,7 +398,10 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2L
   }
   const int col = ntile * 16 + lrow;
   if (col >= it.npairs) return;
-  double2* out = dst + (int64_t)r * tv.ctot + tv.coff[pdst[it.pbeg + col]];
+  const int pair = it.pbeg + col;
+  constexpr bool CONTRIB = MODE == OUT_CONTRIB;
+  double2* out = CONTRIB ? nullptr : dst + (int64_t)r * tv.ctot + tv.coff[pdst[pair]];
+  double* crow = CONTRIB ? contrib + (int64_t)r * cstride + pcoff[pair] : nullptr;
   const bool reflect_out = REV && it.image;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
@@ -332,16 +411,51 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2L
     for (int i = 0; i < 4; ++i) {
       // D[row][col] of a 16x16x4 FP64 tile sits in lane col + 16 (row % 4), register row / 4
       const int row = rt * 16 + 4 * i + lk;
-      if (row >= M2) continue;
-      const bool rim = row >= M;
-      const int p = rim ? row - M : row;
+      if (row >= 2 * Md) continue;
+      const bool rim = row >= Md;
+      const int p = rim ? row - Md : row;
       double v = acc[j][i];
       int po = p;
       if (reflect_out) {
-        po = M - 1 - p;
-        if ((p + P) & 1) v = -v;
+        po = Md - 1 - p;
+        if ((p + Pd) & 1) v = -v;
       }
-      unsafeAtomicAdd(rim ? &out[po].y : &out[po].x, v);
+      if (CONTRIB) {
+        crow[(rim ? Md : 0) + po] = v;
+      } else {
+        double* o = rim ? &out[po].y : &out[po].x;
+        if (MODE == OUT_EXCLUSIVE)
+          *o += v;
+        else
+          unsafeAtomicAdd(o, v);
+      }
+    }
+  }
+}
+
+// beta_b = sum of the contribution rows listed for box b (CSR), plain store.
+// One wave per box; a lane per order.
+__global__ void __launch_bounds__(WAVE) k_reduce_contrib(TreeView tv, const int* __restrict__ boxes, int nb,
+                                                         const int* __restrict__ ptr, const int* __restrict__ pairs,
+                                                         const int64_t* __restrict__ pcoff,
+                                                         const double* __restrict__ contrib, int64_t cstride,
+                                                         double2* __restrict__ dst) {
+  int wi = blockIdx.x;
+  if (wi >= nb) return;
+  int b = boxes[wi];
+  int P = tv.P[tv.level[b]];
+  int M = 2 * P + 1;
+  int e0 = ptr[wi], e1 = ptr[wi + 1];
+  for (int r = 0; r < tv.nrhs; ++r) {
+    const double* cr = contrib + (int64_t)r * cstride;
+    for (int p = threadIdx.x; p < M; p += WAVE) {
+      double re = 0.0, im = 0.0;
+      for (int e = e0; e < e1; ++e) {
+        const double* row = cr + pcoff[pairs[e]];
+        re += row[p];
+        im += row[M + p];
+      }
+      dst[(int64_t)r * tv.ctot + tv.coff[b] + p] = cmk(re, im);
     }
   }
 }
@@ -349,65 +463,6 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_mfma(TreeView tv, const M2L
 __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = cmk(0.0, 0.0);
-}
-
-// M2M: alpha_parent = sum over children of T_q * alpha_child (q = quadrant of
-// the child). One wave per parent box of the level.
-__global__ void __launch_bounds__(WAVE) k_m2m(TreeView tv, const int* __restrict__ boxes, int nb,
-                                              const TableRef* __restrict__ tabs4, const double2* __restrict__ tdata,
-                                              const double2* __restrict__ src, double2* __restrict__ dst, int rev) {
-  int wi = blockIdx.x;
-  if (wi >= nb) return;
-  int b = boxes[wi];
-  int lane = threadIdx.x;
-  int lev = tv.level[b];
-  int P = tv.P[lev], Pc = tv.P[lev + 1];
-  int nout = 2 * P + 1;
-  for (int r = 0; r < tv.nrhs; ++r)
-    for (int o0 = 0; o0 < nout; o0 += WAVE) {
-      int o = o0 + lane;
-      if (o >= nout) continue;
-      int p = o - P;
-      double2 acc = cmk(0, 0);
-      for (int qd = 0; qd < 4; ++qd) {
-        int ch = tv.child[4 * b + qd];
-        if (ch < 0) continue;
-        TableRef tr = tabs4[qd];
-        const double2* T = tdata + tr.off + tr.half;
-        const double2* S = src + r * tv.ctot + tv.coff[ch] + Pc;
-        acc = cadd(acc, toeplitz_dot(T, S, Pc, p, 0, rev));
-      }
-      dst[r * tv.ctot + tv.coff[b] + o] = acc;
-    }
-}
-
-// L2L: beta_child += T_q * beta_parent. One wave per child box of the level.
-// The same kernel applies the transpose of M2M in the adjoint (rev = 1,
-// accumulate = 0 writes instead of adding).
-__global__ void __launch_bounds__(WAVE) k_l2l(TreeView tv, const int* __restrict__ boxes, int nb,
-                                              const TableRef* __restrict__ tabs4, const double2* __restrict__ tdata,
-                                              const double2* __restrict__ src, double2* __restrict__ dst, int rev,
-                                              int accumulate) {
-  int wi = blockIdx.x;
-  if (wi >= nb) return;
-  int b = boxes[wi];
-  int par = tv.parent[b];
-  int lane = threadIdx.x;
-  int lev = tv.level[b];
-  int P = tv.P[lev], Pp = tv.P[lev - 1];
-  int nout = 2 * P + 1;
-  TableRef tr = tabs4[tv.quad[b]];
-  const double2* T = tdata + tr.off + tr.half;
-  for (int r = 0; r < tv.nrhs; ++r)
-    for (int o0 = 0; o0 < nout; o0 += WAVE) {
-      int o = o0 + lane;
-      if (o >= nout) continue;
-      int p = o - P;
-      const double2* S = src + r * tv.ctot + tv.coff[par] + Pp;
-      double2 acc = toeplitz_dot(T, S, Pp, p, 0, rev);
-      double2* d = dst + r * tv.ctot + tv.coff[b] + o;
-      *d = accumulate ? cadd(*d, acc) : acc;
-    }
 }
 
 // ------------------------------------------------------------------ P2P (free space)
@@ -464,24 +519,33 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
           // four sources per step: z = (k r / 2)^2; dropped terms (the target
           // itself, past the chunk) get a harmless z = 1 and weight 0
           for (int jj = sub; jj < cnt; jj += 4 * g) {
-            double z[4];
+            // loads first (clamped index, no branches), then the arithmetic
+            double2 xj[4], qv[4][RB];
             bool use[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               int jl = jj + u * g;
               use[u] = jl < cnt && (j0 + jl) != i;
-              double2 xj = s_x[use[u] ? jl : 0];
-              double dx = xi.x - xj.x, dy = xi.y - xj.y;
-              z[u] = use[u] ? qk2 * (dx * dx + dy * dy) : 1.0;
+              int jc = min(jl, cnt - 1);
+              xj[u] = s_x[jc];
+#pragma unroll
+              for (int rr = 0; rr < RB; ++rr) qv[u][rr] = s_q[rr][jc];
+            }
+            double z[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y;
+              double zz = qk2 * (dx * dx + dy * dy);
+              z[u] = use[u] ? zz : 1.0;
             }
             double2 h[4];
             hankel0_x4(z, h);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              if (!use[u]) continue;
-              int jl = jj + u * g;
+              double w = use[u] ? 1.0 : 0.0;
+              double2 hw = cmk(h[u].x * w, h[u].y * w);
 #pragma unroll
-              for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(h[u], s_q[rr][jl]));
+              for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(hw, qv[u][rr]));
             }
           }
         }
@@ -764,64 +828,72 @@ void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const doubl
   int64_t tot = (int64_t)n * nrhs;
   hipLaunchKernelGGL(k_scatter, dim3(blocks(tot, 256)), dim3(256), 0, s, n, nrhs, perm, src, dst, cj);
 }
-void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const double2* qs, double2* alpha,
-                int conj_w, double2 pref) {
-  if (nl) hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(WAVE), 0, s, tv, leaves, nl, qs, alpha, conj_w, pref);
+void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* qs,
+                double2* alpha, int conj_w, double2 pref) {
+  if (nl <= 0) return;
+  // at most 53 KiB (P = 255): within the default dynamic LDS limit
+  hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(WAVE), p2m_lds_bytes(P), s, tv, leaves, nl, P, qs, alpha, conj_w, pref);
 }
-void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const double2* beta, double2* us,
-                int conj_w, double2 pref, int accumulate) {
-  if (nl) hipLaunchKernelGGL(k_l2p, dim3(nl), dim3(WAVE), 0, s, tv, leaves, nl, beta, us, conj_w, pref, accumulate);
+void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* beta,
+                double2* us, int conj_w, double2 pref, int accumulate) {
+  if (nl <= 0) return;
+  hipLaunchKernelGGL(k_l2p, dim3(nl), dim3(WAVE), l2p_lds_bytes(P), s, tv, leaves, nl, P, beta, us, conj_w, pref,
+                     accumulate);
 }
-void launch_m2l(hipStream_t s, const TreeView& tv, const int* targets, int nt, const int* ptr, const M2LEntry* ent,
-                const TableRef* tabs, const double2* tdata, const double2* src, double2* dst, int rev) {
-  if (nt) hipLaunchKernelGGL(k_m2l, dim3(nt), dim3(WAVE), 0, s, tv, targets, nt, ptr, ent, tabs, tdata, src, dst, rev);
-}
-// LDS bytes of an M2L item at order P.
-static size_t m2l_lds_bytes(int P) {
-  int M = 2 * P + 1;
-  int npi = (M <= 64) ? 64 : 16;
-  return sizeof(double2) * (size_t)(4 * P + 1 + npi * M);
+// LDS bytes of a translation item: the table (real and imaginary parts) and
+// the source-coefficient tile.
+size_t trans_lds_bytes(int Ps, int Pd) {
+  int nt = 2 * (Ps + Pd) + 1;
+  int npi = trans_pairs_per_item(Ps, Pd);
+  return sizeof(double) * (size_t)(4 * ((nt + 1) / 2)) + sizeof(double2) * (size_t)npi * (2 * Ps + 1);
 }
 
-void launch_m2l_mfma(hipStream_t s, const TreeView& tv, const M2LItem* items, const int* item_level_first,
-                     int nlev, const int* psrc, const int* pdst, const TableRef* tabs, const double2* tdata,
-                     const double2* src, double2* dst, int rev) {
+template <bool REV, int MODE>
+static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, size_t lds,
+                      const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
+                      const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride) {
   static bool attr_done = false;
   if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)k_m2l_mfma<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    (void)hipFuncSetAttribute((const void*)k_m2l_mfma<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+    // the CU's 160 KiB less the kernel's static LDS; a failure here is left
+    // for the caller's hipGetLastError check
+    const void* f = (const void*)k_trans_mfma<REV, MODE>;
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, f) == hipSuccess)
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
     attr_done = true;
   }
-  // items are grouped by level (item_level_first[l] .. item_level_first[l+1]);
-  // one launch per level with that level's LDS size
-  for (int l = 0; l < nlev; ++l) {
-    int i0 = item_level_first[l], i1 = item_level_first[l + 1];
-    if (i1 <= i0) continue;
-    size_t lds = m2l_lds_bytes(tv.P[l]);
-    for (int r = 0; r < tv.nrhs; ++r) {
-      if (rev)
-        hipLaunchKernelGGL(k_m2l_mfma<true>, dim3(i1 - i0), dim3(M2L_THREADS), lds, s, tv, items + i0, psrc, pdst,
-                           tabs, tdata, src, dst, r);
-      else
-        hipLaunchKernelGGL(k_m2l_mfma<false>, dim3(i1 - i0), dim3(M2L_THREADS), lds, s, tv, items + i0, psrc, pdst,
-                           tabs, tdata, src, dst, r);
-    }
+  for (int r = 0; r < tv.nrhs; ++r)
+    hipLaunchKernelGGL((k_trans_mfma<REV, MODE>), dim3(nitems), dim3(TR_THREADS), lds, s, tv, items, psrc, pdst,
+                       pcoff, tabs, tdata, src, dst, contrib, cstride, r);
+}
+
+void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
+                  const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
+                  const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
+                  int exclusive) {
+  if (nitems <= 0) return;
+  const size_t lds = trans_lds_bytes(Ps, Pd);
+#define HFMM_TRANS(R, M) trans_one<R, M>(s, tv, items, nitems, lds, psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride)
+  if (contrib) {
+    if (rev) HFMM_TRANS(true, OUT_CONTRIB); else HFMM_TRANS(false, OUT_CONTRIB);
+  } else if (exclusive) {
+    if (rev) HFMM_TRANS(true, OUT_EXCLUSIVE); else HFMM_TRANS(false, OUT_EXCLUSIVE);
+  } else {
+    if (rev) HFMM_TRANS(true, OUT_ATOMIC); else HFMM_TRANS(false, OUT_ATOMIC);
   }
+#undef HFMM_TRANS
+}
+
+void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
+                           const int* pairs, const int64_t* pcoff, const double* contrib, int64_t cstride,
+                           double2* dst) {
+  if (nb)
+    hipLaunchKernelGGL(k_reduce_contrib, dim3(nb), dim3(WAVE), 0, s, tv, boxes, nb, ptr, pairs, pcoff, contrib,
+                       cstride, dst);
 }
 
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fill_zero, dim3(blocks(n, 256)), dim3(256), 0, s, p, n);
-}
-
-void launch_m2m(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
-                const double2* tdata, const double2* src, double2* dst, int rev) {
-  if (nb) hipLaunchKernelGGL(k_m2m, dim3(nb), dim3(WAVE), 0, s, tv, boxes, nb, tabs4, tdata, src, dst, rev);
-}
-void launch_l2l(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
-                const double2* tdata, const double2* src, double2* dst, int rev, int accumulate) {
-  if (nb) hipLaunchKernelGGL(k_l2l, dim3(nb), dim3(WAVE), 0, s, tv, boxes, nb, tabs4, tdata, src, dst, rev, accumulate);
 }
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr, const int2* rng,
                 const int* atomic, const double2* qs, double2* us) {

@@ -7,20 +7,25 @@ namespace hfmm {
 
 void launch_gather(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_in);
 void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_out);
-void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const double2* qs, double2* alpha,
-                int conj_w, double2 pref);
-void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const double2* beta, double2* us,
-                int conj_w, double2 pref, int accumulate);
-void launch_m2l(hipStream_t s, const TreeView& tv, const int* targets, int nt, const int* ptr, const M2LEntry* ent,
-                const TableRef* tabs, const double2* tdata, const double2* src, double2* dst, int rev);
-void launch_m2l_mfma(hipStream_t s, const TreeView& tv, const M2LItem* items, const int* item_level_first,
-                     int nlev, const int* psrc, const int* pdst, const TableRef* tabs, const double2* tdata,
-                     const double2* src, double2* dst, int rev);
+// P2M and L2P over leaves of one level (expansion order P).
+void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* qs,
+                double2* alpha, int conj_w, double2 pref);
+void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* beta,
+                double2* us, int conj_w, double2 pref, int accumulate);
+// Batched translation contraction (M2L, M2M, L2L and transposes) for items
+// sharing (Ps, Pd). With contrib != NULL each pair writes its own contribution
+// row at pcoff[pair] (plane stride cstride per right-hand side); otherwise the
+// result is added into dst of the pair's target box, atomically unless
+// exclusive says that no two pairs of the launch share a target box.
+void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
+                  const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
+                  const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
+                  int exclusive);
+void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
+                           const int* pairs, const int64_t* pcoff, const double* contrib, int64_t cstride,
+                           double2* dst);
+size_t trans_lds_bytes(int Ps, int Pd);
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n);
-void launch_m2m(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
-                const double2* tdata, const double2* src, double2* dst, int rev);
-void launch_l2l(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const TableRef* tabs4,
-                const double2* tdata, const double2* src, double2* dst, int rev, int accumulate);
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr, const int2* rng,
                 const int* atomic, const double2* qs, double2* us);
 void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,

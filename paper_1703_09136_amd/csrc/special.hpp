@@ -27,13 +27,16 @@ constexpr double kRescaleHi = 0x1p+700;   // rescale when |J| exceeds this
 constexpr double kRescaleBy = 0x1p-700;
 
 // Pass 1: normalisation of the backward sequence. Returns 1/S in the final
-// scale and the number of rescalings performed.
+// scale and the number of rescalings performed. The recurrence factor is
+// n * (2/x); every pass below uses this same arithmetic so that the passes
+// rescale at the same indices.
 __host__ __device__ inline void miller_norm(double x, int nstart, double& inv_s, int& nres) {
+  const double tx = 2.0 / x;
   double jp1 = 0.0, j = 0x1p-900, s = 0.0;
   nres = 0;
   for (int n = nstart; n >= 1; --n) {
     if ((n & 1) == 0) s += 2.0 * j;
-    double jm1 = (2.0 * n / x) * j - jp1;
+    double jm1 = ((double)n * tx) * j - jp1;
     jp1 = j;
     j = jm1;
     if (fabs(j) > kRescaleHi) {
@@ -45,29 +48,43 @@ __host__ __device__ inline void miller_norm(double x, int nstart, double& inv_s,
   inv_s = 1.0 / s;
 }
 
+// Pass 2 as an explicit walk: value() is the normalised J_n at the current
+// index n (starting at nstart); step() moves to n - 1.
+struct MillerWalk {
+  double tx, j, jp1, inv_s, sc;
+  int n, left;
+  __host__ __device__ MillerWalk(double x, int nstart, double inv_s_, int nres)
+      : tx(2.0 / x), j(0x1p-900), jp1(0.0), inv_s(inv_s_), sc(0.0), n(nstart), left(nres) {
+    sc = scale();
+  }
+  // factor from the current scale to the final one: kRescaleBy^left / S
+  __host__ __device__ double scale() const {
+    double f = inv_s;
+    for (int r = 0; r < left; ++r) f *= kRescaleBy;
+    return f;
+  }
+  __host__ __device__ double value() const { return j * sc; }
+  __host__ __device__ void step() {
+    double jm1 = ((double)n * tx) * j - jp1;
+    jp1 = j;
+    j = jm1;
+    --n;
+    if (fabs(j) > kRescaleHi) {
+      j *= kRescaleBy; jp1 *= kRescaleBy;
+      --left;
+      sc = scale();
+    }
+  }
+};
+
 // Pass 2: calls f(n, J_n) for n = nmax down to 0 with normalised values.
 template <class F>
 __host__ __device__ inline void miller_emit(double x, int nstart, int nmax, double inv_s, int nres, F f) {
-  double jp1 = 0.0, j = 0x1p-900;
-  int done = 0;
-  // scale factor from the current scale to the final one: kRescaleBy^(nres - done)
-  auto scale_now = [&]() {
-    double sc = inv_s;
-    for (int r = done; r < nres; ++r) sc *= kRescaleBy;
-    return sc;
-  };
-  double sc = scale_now();
-  if (nstart <= nmax) f(nstart, j * sc);
-  for (int n = nstart; n >= 1; --n) {
-    double jm1 = (2.0 * n / x) * j - jp1;
-    jp1 = j;
-    j = jm1;
-    if (fabs(j) > kRescaleHi) {
-      j *= kRescaleBy; jp1 *= kRescaleBy;
-      ++done;
-      sc = scale_now();
-    }
-    if (n - 1 <= nmax) f(n - 1, j * sc);
+  MillerWalk w(x, nstart, inv_s, nres);
+  if (nstart <= nmax) f(nstart, w.value());
+  while (w.n >= 1) {
+    w.step();
+    if (w.n <= nmax) f(w.n, w.value());
   }
 }
 
