@@ -68,6 +68,13 @@ typedef struct {
                                0: leave such pairs to direct Sommerfeld
                                quadrature */
   int32_t max_level;        /* deepest tree level; default 24 */
+  double leaf_kb;           /* wavelength bound on leaves, which keeps the
+                               direct pairs at small k1 r: a box is split
+                               while k1 times its side exceeds leaf_kb and it
+                               holds more than leaf_size / 4 points, or
+                               exceeds 2 leaf_kb and holds two or more
+                               (default 1.5; 0 turns the bound off). Must be
+                               0 or >= 0.25. */
 } hfmm_options_t;
 
 typedef struct {

@@ -33,7 +33,8 @@ NSTAGES = 9
 
 class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("self_term", ctypes.c_int32), ("interface_refine", ctypes.c_int32), ("max_level", ctypes.c_int32)]
+                ("self_term", ctypes.c_int32), ("interface_refine", ctypes.c_int32), ("max_level", ctypes.c_int32),
+                ("leaf_kb", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):

@@ -275,6 +275,7 @@ struct hfmm_plan_s {
   DevBuf<double2> tdata;
   std::vector<int> m2m_tab, l2l_tab;  // per parent level: index of 4 consecutive tables
   DevBuf<int> p2p_ptr, p2p_items, p2p_atomic;
+  int p2p_cls_ptr[kH0Classes + 2] = {0};  // items of series class c: [p2p_cls_ptr[c], p2p_cls_ptr[c + 1])
   DevBuf<int2> p2p_rng;
   int np2p_items = 0;
   DevBuf<int> if_leaves, if_ptr;
@@ -379,6 +380,7 @@ void hfmm_default_options(hfmm_options_t* o) {
   o->self_term = HFMM_SELF_SCATTERED;
   o->interface_refine = 1;
   o->max_level = 24;
+  o->leaf_kb = 1.5;
 }
 
 const char* hfmm_status_string(hfmm_status_t s) {
@@ -432,6 +434,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   if (o.precision != HFMM_FP64) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_FP64 is available");
   if (o.self_term != HFMM_SELF_SCATTERED) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_SELF_SCATTERED is available");
   if (o.max_level < 2 || o.max_level > KEY_BITS) return fail(HFMM_ERR_INVALID_ARG, "max_level out of range");
+  if (!(o.leaf_kb == 0.0 || (o.leaf_kb >= 0.25 && std::isfinite(o.leaf_kb))))
+    return fail(HFMM_ERR_INVALID_ARG, "leaf_kb must be 0 or a finite value >= 0.25");
   for (int i = 0; i < layers; ++i)
     if (!(wavenumbers[i] > 0.0) || !std::isfinite(wavenumbers[i]))
       return fail(HFMM_ERR_UNSUPPORTED, "wavenumbers must be finite and > 0");
@@ -524,6 +528,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     for (int bi = lb; bi < le; ++bi) {
       int cnt = B[bi].end - B[bi].begin;
       bool split = cnt > o.leaf_size;
+      // wavelength bound: wide leaves leave direct pairs at large k1 r. Up to
+      // twice the bound, boxes holding a quarter of a leaf or less stay whole
+      // (their pairs are few); beyond it every box with two points splits.
+      if (o.leaf_kb > 0.0 && k * b > o.leaf_kb) {
+        if (cnt > std::max(1, o.leaf_size / 4) || (k * b > 2.0 * o.leaf_kb && cnt > 1)) split = true;
+      }
       // bottom-row boxes whose own image pair is not admissible (2 y0 < b)
       if (o.interface_refine && B[bi].iy == 0 && 2.0 * ymin < b && cnt > 4) split = true;
       if (l >= maxl) split = false;
@@ -845,43 +855,93 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   int64_t np2p = 0, nifp = 0;
   group(fu, u_per, np2p);
   group(iu, i_per, nifp);
-  // direct work items: a target leaf with at most kItemSources sources; a leaf
-  // whose sources span several items accumulates atomically. Largest first.
+  // Bounding boxes of the points of every leaf, then of every merged source
+  // range (a union of whole leaves, found through the leaves in point order).
+  std::vector<double4> leaf_bb(leaves.size());
+  for (size_t li = 0; li < leaves.size(); ++li) {
+    const Box& bx = B[leaves[li]];
+    double4 bb = make_double4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    for (int j = bx.begin; j < bx.end; ++j) {
+      const double px = hp[2 * key[j].second], py = hp[2 * key[j].second + 1];
+      bb.x = std::min(bb.x, px); bb.y = std::max(bb.y, px);
+      bb.z = std::min(bb.z, py); bb.w = std::max(bb.w, py);
+    }
+    leaf_bb[li] = bb;
+  }
+  std::vector<int> leaf_at(pl->n, -1);  // leaf whose points start at index j
+  for (size_t li = 0; li < leaves.size(); ++li) leaf_at[B[leaves[li]].begin] = (int)li;
+  auto range_bb = [&](int2 r) {
+    double4 bb = make_double4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+    for (int j = r.x; j < r.y;) {
+      const int li = leaf_at[j];
+      if (li < 0) return make_double4(-INFINITY, INFINITY, -INFINITY, INFINITY);  // not leaf-aligned: widest class
+      const double4& lb = leaf_bb[li];
+      bb.x = std::min(bb.x, lb.x); bb.y = std::max(bb.y, lb.y);
+      bb.z = std::min(bb.z, lb.z); bb.w = std::max(bb.w, lb.w);
+      j = B[leaves[li]].end;
+    }
+    return bb;
+  };
+  // H0 series class of a (target leaf, source range) pair from the largest
+  // z = (k r / 2)^2 its two boxes allow
+  const double qk2 = 0.25 * pl->med.k1 * pl->med.k1;
+  auto series_class = [&](const double4& t, const double4& r) {
+    const double dx = std::max(t.y - r.x, r.y - t.x), dy = std::max(t.w - r.z, r.w - t.z);
+    const double zmax = qk2 * (dx * dx + dy * dy);
+    int c = 0;
+    while (c < kH0Classes && zmax > kH0ClassZmax[c]) ++c;
+    return c;
+  };
+  // direct work items: a target leaf, one series class, at most kItemSources
+  // sources; a leaf whose sources span several items accumulates atomically.
+  // Largest first.
   struct Item {
     int leaf;
     int atomic;
+    int cls;
     int64_t cost;
     std::vector<int2> r;
   };
   std::vector<Item> items;
   for (size_t li = 0; li < leaves.size(); ++li) {
     size_t first = items.size();
-    Item cur{leaves[li], 0, 0, {}};
-    int cur_n = 0;
-    for (const int2& rg : u_per[li]) {
-      int a = rg.x;
-      while (a < rg.y) {
-        int take = std::min(rg.y - a, kItemSources - cur_n);
-        cur.r.push_back(make_int2(a, a + take));
-        cur_n += take;
-        a += take;
-        if (cur_n == kItemSources) {
-          items.push_back(cur);
-          cur = Item{leaves[li], 0, 0, {}};
-          cur_n = 0;
+    std::vector<int2> by_cls[kH0Classes + 1];
+    for (const int2& rg : u_per[li]) by_cls[series_class(leaf_bb[li], range_bb(rg))].push_back(rg);
+    for (int c = 0; c <= kH0Classes; ++c) {
+      Item cur{leaves[li], 0, c, 0, {}};
+      int cur_n = 0;
+      for (const int2& rg : by_cls[c]) {
+        int a = rg.x;
+        while (a < rg.y) {
+          int take = std::min(rg.y - a, kItemSources - cur_n);
+          cur.r.push_back(make_int2(a, a + take));
+          cur_n += take;
+          a += take;
+          if (cur_n == kItemSources) {
+            items.push_back(cur);
+            cur = Item{leaves[li], 0, c, 0, {}};
+            cur_n = 0;
+          }
         }
       }
+      if (cur_n > 0) items.push_back(cur);
     }
-    if (cur_n > 0) items.push_back(cur);
     int nt = B[leaves[li]].end - B[leaves[li]].begin;
     for (size_t it = first; it < items.size(); ++it) {
       items[it].atomic = (items.size() - first) > 1;
       int64_t ns = 0;
       for (auto& r : items[it].r) ns += r.y - r.x;
-      items[it].cost = ns * nt;
+      const int c = items[it].cls;
+      // per pair: the two series chains plus about 24 operations of logarithm and update
+      items[it].cost = ns * nt * (2 * kH0ClassTerms[c < kH0Classes ? c : kH0Classes - 1] + 24);
     }
   }
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    return a.cls != b.cls ? a.cls < b.cls : a.cost > b.cost;
+  });
+  for (int c = 0; c <= kH0Classes + 1; ++c) pl->p2p_cls_ptr[c] = 0;
+  for (auto& it : items) ++pl->p2p_cls_ptr[it.cls + 1];
+  for (int c = 1; c <= kH0Classes + 1; ++c) pl->p2p_cls_ptr[c] += pl->p2p_cls_ptr[c - 1];
   std::vector<int> p2p_ptr(1, 0), p2p_items, p2p_atomic, if_ptr(1, 0), if_leaves;
   std::vector<int2> p2p_rng, if_rng;
   for (auto& it : items) {
@@ -1154,7 +1214,7 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
   mark();
   for (int l = 0; l < pl->nlev; ++l) launch_l2p_level(pl, tv, s, l, pl->beta.p, us, 0, cmk(0.0, 0.25));
   mark();
-  launch_p2p(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, qs, us);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, qs, us);
   mark();
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, qs, us);
@@ -1176,7 +1236,7 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
   for (int l = 0; l < pl->nlev; ++l) launch_l2p_level(pl, tv, s, l, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
   // the direct parts are symmetric
-  launch_p2p(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, vs, ws);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, vs, ws);
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, vs, ws);
 }

@@ -470,43 +470,78 @@ __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
 // target leaf; when the leaf holds fewer than 64 points several lanes share a
 // target and split its sources, then combine by shuffles.
 // Sources are staged through LDS 64 at a time; RB right-hand sides share each
-// H0 evaluation (right-hand sides r0 .. r0+RB-1 in this launch).
-template <int RB>
-__global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
-                                              const int* __restrict__ ptr, const int2* __restrict__ rng,
-                                              const int* __restrict__ atomic, const double2* __restrict__ qs,
-                                              double2* __restrict__ us, int r0) {
-  __shared__ double2 s_x[WAVE];
-  __shared__ double2 s_q[RB][WAVE];
-  int li = blockIdx.x;
-  if (li >= nleaves) return;
-  int b = leaves[li];
-  int lane = threadIdx.x;
-  int2 pr = tv.prange[b];
-  int e0 = ptr[li], e1 = ptr[li + 1];
+// H0 evaluation (right-hand sides r0 .. r0+RB-1 in this launch). Each staged
+// chunk takes the shortest series that covers its largest pair distance,
+// bounded from the bounding boxes of the targets and of the chunk.
+
+// One staged chunk for one lane: sources jj = sub, sub + g, ... of cnt, four
+// per step; jself is the target's own index within the chunk (if any).
+// z = (k r / 2)^2; dropped terms get a harmless z = 1 and weight 0.
+template <int RB, int M, bool LARGE>
+__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, double2 xi, double qk2,
+                                 const double2* s_x, const double2 (*s_q)[WAVE], double2 acc[RB]) {
+  for (int jj = sub; jj < cnt; jj += 4 * g) {
+    // loads first (clamped index, no branches), then the arithmetic
+    double2 xj[4], qv[4][RB];
+    bool use[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int jl = jj + u * g;
+      use[u] = jl < cnt && jl != jself;
+      const int jc = min(jl, cnt - 1);
+      xj[u] = s_x[jc];
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) qv[u][rr] = s_q[rr][jc];
+    }
+    double z[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y;
+      const double zz = qk2 * (dx * dx + dy * dy);
+      z[u] = use[u] ? zz : 1.0;
+    }
+    double2 h[4];
+    hankel0_x4<M, LARGE>(z, h);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double w = use[u] ? 1.0 : 0.0;
+      const double2 hw = cmk(h[u].x * w, h[u].y * w);
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(hw, qv[u][rr]));
+    }
+  }
+}
+
+// One work item: the target leaf b against source ranges [e0, e1) of rng.
+template <int RB, int M, bool LARGE>
+__device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const int2* __restrict__ rng,
+                                bool atomic, const double2* __restrict__ qs, double2* __restrict__ us, int r0,
+                                double2* s_x, double2 (*s_q)[WAVE]) {
+  const int lane = threadIdx.x;
+  const int2 pr = tv.prange[b];
   const double qk2 = 0.25 * tv.k * tv.k;
   // targets in chunks of 32 (two lanes per target), the remainder in a chunk of
   // the next power of two with more lanes per target
   for (int c0 = pr.x, csz = 0; c0 < pr.y; c0 += csz) {
-    int rem = pr.y - c0;
+    const int rem = pr.y - c0;
     csz = 32;
     if (rem < 32) {
       csz = 1;
       while (csz < rem) csz *= 2;
     }
-    int nt = min(csz, rem);
-    int g = WAVE / csz;  // lanes per target
-    int ti = lane / g, sub = lane % g;
-    int i = c0 + ti;
-    bool valid = ti < nt;
-    double2 xi = valid ? tv.pts[i] : cmk(0, 0);
+    const int nt = min(csz, rem);
+    const int g = WAVE / csz;  // lanes per target
+    const int ti = lane / g, sub = lane % g;
+    const int i = c0 + ti;
+    const bool valid = ti < nt;
+    const double2 xi = valid ? tv.pts[i] : cmk(0, 0);
     double2 acc[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk(0, 0);
     for (int e = e0; e < e1; ++e) {
-      int2 sr = rng[e];
+      const int2 sr = rng[e];
       for (int j0 = sr.x; j0 < sr.y; j0 += WAVE) {
-        int cnt = min(WAVE, sr.y - j0);
+        const int cnt = min(WAVE, sr.y - j0);
         __syncthreads();
         if (lane < cnt) {
           s_x[lane] = tv.pts[j0 + lane];
@@ -515,40 +550,7 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
             s_q[rr][lane] = (r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + j0 + lane] : cmk(0, 0);
         }
         __syncthreads();
-        if (valid) {
-          // four sources per step: z = (k r / 2)^2; dropped terms (the target
-          // itself, past the chunk) get a harmless z = 1 and weight 0
-          for (int jj = sub; jj < cnt; jj += 4 * g) {
-            // loads first (clamped index, no branches), then the arithmetic
-            double2 xj[4], qv[4][RB];
-            bool use[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              int jl = jj + u * g;
-              use[u] = jl < cnt && (j0 + jl) != i;
-              int jc = min(jl, cnt - 1);
-              xj[u] = s_x[jc];
-#pragma unroll
-              for (int rr = 0; rr < RB; ++rr) qv[u][rr] = s_q[rr][jc];
-            }
-            double z[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y;
-              double zz = qk2 * (dx * dx + dy * dy);
-              z[u] = use[u] ? zz : 1.0;
-            }
-            double2 h[4];
-            hankel0_x4(z, h);
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              double w = use[u] ? 1.0 : 0.0;
-              double2 hw = cmk(h[u].x * w, h[u].y * w);
-#pragma unroll
-              for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(hw, qv[u][rr]));
-            }
-          }
-        }
+        if (valid) p2p_chunk<RB, M, LARGE>(sub, g, cnt, i - j0, xi, qk2, s_x, s_q, acc);
       }
     }
 #pragma unroll
@@ -558,9 +560,9 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
         if (r0 + rr < tv.nrhs) {
-          int64_t idx = (int64_t)(r0 + rr) * tv.n + i;
-          double2 v = cmk(-0.25 * acc[rr].y, 0.25 * acc[rr].x);  // (i/4) acc
-          if (atomic[li]) {
+          const int64_t idx = (int64_t)(r0 + rr) * tv.n + i;
+          const double2 v = cmk(-0.25 * acc[rr].y, 0.25 * acc[rr].x);  // (i/4) acc
+          if (atomic) {
             unsafeAtomicAdd(&us[idx].x, v.x);
             unsafeAtomicAdd(&us[idx].y, v.y);
           } else {
@@ -568,6 +570,23 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
           }
         }
   }
+}
+
+// One launch per series class (the host bounds every pair distance of an item
+// and sorts the items by class), so each kernel holds only its own
+// coefficients in scalar registers.
+template <int RB, int CLS>
+__global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
+                                              const int* __restrict__ ptr, const int2* __restrict__ rng,
+                                              const int* __restrict__ atomic, const double2* __restrict__ qs,
+                                              double2* __restrict__ us, int r0) {
+  __shared__ double2 s_x[WAVE];
+  __shared__ double2 s_q[RB][WAVE];
+  const int li = blockIdx.x;
+  if (li >= nleaves) return;
+  constexpr int M = kH0ClassTerms[CLS < kH0Classes ? CLS : kH0Classes - 1];
+  p2p_item<RB, M, (CLS >= kH0Classes)>(tv, leaves[li], ptr[li], ptr[li + 1], rng, atomic[li] != 0, qs, us, r0,
+                                        s_x, s_q);
 }
 
 // ------------------------------------------------------------------ near-interface direct
@@ -895,15 +914,26 @@ void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, 
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fill_zero, dim3(blocks(n, 256)), dim3(256), 0, s, p, n);
 }
-void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr, const int2* rng,
-                const int* atomic, const double2* qs, double2* us) {
-  if (!nl) return;
+template <int CLS>
+static void p2p_class(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr, const int2* rng,
+                      const int* atomic, const double2* qs, double2* us) {
+  if (nl <= 0) return;
   if (tv.nrhs == 1) {
-    hipLaunchKernelGGL(k_p2p<1>, dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, 0);
+    hipLaunchKernelGGL((k_p2p<1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, 0);
     return;
   }
   for (int r0 = 0; r0 < tv.nrhs; r0 += 4)
-    hipLaunchKernelGGL(k_p2p<4>, dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, r0);
+    hipLaunchKernelGGL((k_p2p<4, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, r0);
+}
+
+void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
+                const int2* rng, const int* atomic, const double2* qs, double2* us) {
+#define HFMM_P2P(C)                                                                                       \
+  p2p_class<C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng, atomic + cls_ptr[C], \
+               qs, us)
+  HFMM_P2P(0); HFMM_P2P(1); HFMM_P2P(2); HFMM_P2P(3); HFMM_P2P(4); HFMM_P2P(5);
+#undef HFMM_P2P
+  static_assert(kH0Classes == 5, "one launch per class and one for the large-argument class");
 }
 void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                   int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* qs, double2* us) {

@@ -176,38 +176,91 @@ __host__ __device__ inline double2 hankel0(double x) {
 // out of the registers of the caller).
 __device__ __noinline__ double2 hankel0_large_call(double x);
 
-// Four values of H_0^(1) at once from z_u = x_u^2/4: the series for z <= 9
-// (x <= 6) with the four Horner chains interleaved, the large-argument form
-// for the rest.
-static __constant__ H0Series kH0dev = H0Series();
+// Four values of H_0^(1) at once from z_u = x_u^2/4 by the ascending series
+// with M terms, the four Horner chains interleaved. M is chosen by the caller
+// from a bound on z: the first dropped term max(|c_M|, |d_M|) z^M stays below
+// 2^-56 for z <= h0_series_zmax(M) (from the closed forms of c_M and d_M).
+// With LARGE, entries with z > 9 (x > 6) take the large-argument form.
+// ln(z) for a positive normal z in about 30 operations, for the pair loops:
+// z = 2^e m with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh(s) =
+// 2 sum_k s^(2k+1)/(2k+1) with s = (m - 1)/(m + 1), |s| <= 0.1716, where
+// eleven terms leave a relative remainder below 2^-56; e ln 2 is added in two
+// parts (Cody and Waite's reduction; ln2_hi has 11 trailing zero bits, so
+// e * ln2_hi is exact). The quotient s comes from the hardware reciprocal,
+// two Newton steps and a residual correction.
+__device__ inline double log_pos(double z) {
+  int e;
+  double m = frexp(z, &e);  // m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double num = m - 1.0, den = m + 1.0;
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  r = fma(r, fma(-den, r, 1.0), r);
+  double sq = num * r;
+  sq = fma(r, fma(-sq, den, num), sq);
+  const double s2 = sq * sq;
+  // sum_{k=0..10} s2^k / (2k + 1) by Horner
+  double p = 1.0 / 21.0;
+  p = fma(p, s2, 1.0 / 19.0);
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  const double ln_m = 2.0 * fma(sq * s2, p, sq);
+  const double ln2_hi = 0x1.62e42fefa3800p-1;
+  const double ln2_lo = 0x1.ef35793c76730p-45;
+  const double de = (double)e;
+  return fma(de, ln2_hi, fma(de, ln2_lo, ln_m));
+}
 
+// a * b + c with c a wave-uniform constant, as one VOP3 instruction taking c
+// from scalar registers. Left to itself the compiler keeps such constants in
+// vector registers and copies one into the accumulator before every
+// two-address v_fmac_f64, which doubles the cost of a Horner step.
+__device__ inline double fma_uniform(double a, double b, double c) {
+  double r;
+  asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
+template <int M, bool LARGE>
 __device__ inline void hankel0_x4(const double z[4], double2 h[4]) {
   double j[4], s[4];
-  const H0Series* co = &kH0dev;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    j[u] = co->c[20];
-    s[u] = co->d[20];
+    j[u] = kH0.c[M - 1];
+    s[u] = kH0.d[M - 1];
   }
 #pragma unroll
-  for (int m = 19; m >= 0; --m) {
-    const double cm = co->c[m], dm = co->d[m];
+  for (int m = M - 2; m >= 0; --m) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      j[u] = fma(j[u], z[u], cm);
-      s[u] = fma(s[u], z[u], dm);
+      j[u] = fma_uniform(j[u], z[u], kH0.c[m]);
+      s[u] = fma_uniform(s[u], z[u], kH0.d[m]);
     }
   }
   const double two_over_pi = 0.63661977236758134308;
   const double euler = 0.57721566490153286061;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (z[u] <= 9.0) {
-      h[u] = cmk(j[u], two_over_pi * ((0.5 * log(z[u]) + euler) * j[u] + s[u]));
+    if (!LARGE || z[u] <= 9.0) {
+      h[u] = cmk(j[u], two_over_pi * ((0.5 * log_pos(z[u]) + euler) * j[u] + s[u]));
     } else {
       h[u] = hankel0_large_call(2.0 * sqrt(z[u]));
     }
   }
 }
+
+// Series classes of the pair loops: terms and the largest z each covers.
+constexpr int kH0Classes = 5;
+constexpr int kH0ClassTerms[kH0Classes] = {8, 10, 12, 15, 20};
+constexpr double kH0ClassZmax[kH0Classes] = {0.0976, 0.3797, 1.0021, 2.8639, 9.0};
 
 }  // namespace hfmm

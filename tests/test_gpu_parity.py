@@ -38,7 +38,7 @@ def ref_apply(w, q=None):
 def test_one_leaf_plan_is_the_direct_sum(gpu_lib):
     """Every pair direct: free H0 pairs plus Sommerfeld quadrature of the image."""
     w = workloads.two_layer_uniform(n=200, seed=11)
-    plan, u = run(gpu_lib, w, 1e-10, leaf_size=256, interface_refine=0)
+    plan, u = run(gpu_lib, w, 1e-10, leaf_size=256, interface_refine=0, leaf_kb=0.0)
     assert plan.info()["levels"] == 1
     e = rel(u, ref_apply(w))
     print("one-leaf E =", e)
@@ -58,7 +58,7 @@ def test_two_layer_n1024_full_tree(gpu_lib):
 def test_two_layer_without_interface_refinement(gpu_lib):
     """Image pairs left non-admissible at the leaves go to direct quadrature."""
     w = workloads.two_layer_uniform(n=1024, seed=12)
-    plan, u = run(gpu_lib, w, 1e-10, leaf_size=32, interface_refine=0)
+    plan, u = run(gpu_lib, w, 1e-10, leaf_size=32, interface_refine=0, leaf_kb=0.0)
     inf = plan.info()
     e = rel(u, ref_apply(w))
     print("no-refine E =", e, inf)
