@@ -27,8 +27,13 @@ def build(verbose: bool = True) -> str:
     """Compile every source into one shared library; returns its path."""
     objs = []
     flags = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-             # packed FP32 instructions stay off (see the build notes)
+             # packed FP32 instructions stay off: some of their forms have
+             # given intermittently wrong results on gfx950
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # MFMA accumulators in ordinary VGPRs: with AGPRs the compiler
+             # copies every accumulator across on each step of the
+             # translation kernel's first contraction loop
+             "-mllvm", "-amdgpu-mfma-vgpr-form",
              "-I", os.path.join(ROOT, "include"), "-I", CSRC]
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + flags + ["-shared", "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]

@@ -111,11 +111,18 @@ struct Panel {
   int32_t pad;
 };
 
+// Pairs per translation item: 64 (four 16-column MFMA tiles, one per wave) when
+// both expansions fit 64 coefficients, else 16 (the waves split the rows).
+__host__ __device__ inline int trans_pairs_per_item(int Ps, int Pd) {
+  return (2 * Ps + 1 <= 64 && 2 * Pd + 1 <= 64) ? 64 : 16;
+}
+
 // A work item of the batched translation contraction: one translation table
 // and up to 64 (source, target) box pairs that use it, pairs
 // [pbeg, pbeg + npairs) of the pair arrays; source order Ps, target order Pd;
-// rt_base is the first row tile of the real-embedded operator; image marks
-// heterogeneous M2L tables (reflected source coefficients).
+// rt_base is the first row tile of the real-embedded operator and ntw the
+// number of row tiles per wave (1..8); image marks heterogeneous M2L tables
+// (reflected source coefficients).
 struct TransItem {
   int32_t table;
   int32_t pbeg;
@@ -123,14 +130,15 @@ struct TransItem {
   int32_t image;
   int32_t rt_base;
   int32_t Ps, Pd;
-  int32_t pad;
+  int32_t ntw;
 };
 
-// Pairs per translation item: 64 (four 16-column MFMA tiles, one per wave) when
-// both expansions fit 64 coefficients, else 16 (the waves split the rows).
-__host__ __device__ inline int trans_pairs_per_item(int Ps, int Pd) {
-  return (2 * Ps + 1 <= 64 && 2 * Pd + 1 <= 64) ? 64 : 16;
+// Row tiles one item covers: ntw per wave, the four waves side by side (64
+// pairs per item) or interleaved over rows (16 pairs per item).
+__host__ __device__ inline int trans_rows_per_item(int Ps, int Pd, int ntw) {
+  return trans_pairs_per_item(Ps, Pd) == 64 ? ntw : 4 * ntw;
 }
+
 
 struct TreeView {
   int32_t n;

@@ -699,11 +699,24 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     add_pair(id, l, 1, pr.s, pr.t);
   }
   // batched M2L items: per level, per table, batches of up to 64 pairs (16 when
-  // 2P+1 > 64), and groups of 32 row tiles of the real-embedded operator. Each
-  // pair owns a contribution row of 2(2P+1) doubles, reduced per box afterwards.
-  auto add_items = [](std::vector<TransItem>& items, int table, int pbeg, int cnt, int image, int Ps, int Pd) {
+  // 2P+1 > 64), and groups of row tiles of the real-embedded operator (ntw per
+  // wave). Each pair owns a contribution row of 2(2P+1) doubles, reduced per
+  // box afterwards.
+  auto add_items = [](std::vector<TransItem>& items, int table, int pbeg, int cnt, int image, int Ps, int Pd,
+                      int ntw) {
     const int nrt = (2 * (2 * Pd + 1) + 15) / 16;
-    for (int rt = 0; rt < nrt; rt += 32) items.push_back(TransItem{table, pbeg, cnt, image, rt, Ps, Pd, 0});
+    const int step = trans_rows_per_item(Ps, Pd, ntw);
+    for (int rt = 0; rt < nrt; rt += step) items.push_back(TransItem{table, pbeg, cnt, image, rt, Ps, Pd, ntw});
+  };
+  // row tiles per wave for a launch of `batches` pair batches: the most (up to
+  // 8, the longest MFMA chains) that still give about four blocks per CU
+  auto choose_ntw = [](int64_t batches, int Ps, int Pd) {
+    const int nrt = (2 * (2 * Pd + 1) + 15) / 16;
+    for (int ntw = 8; ntw > 1; ntw /= 2) {
+      const int step = trans_rows_per_item(Ps, Pd, ntw);
+      if (batches * ((nrt + step - 1) / step) >= 1024) return ntw;
+    }
+    return 1;
   };
   std::vector<TransItem> m2l_items;
   std::vector<int> m2l_psrc, m2l_pdst;
@@ -714,6 +727,10 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     g.first = (int)m2l_items.size();
     g.Ps = g.Pd = pl->P[l];
     const int npi = trans_pairs_per_item(pl->P[l], pl->P[l]);
+    int64_t batches = 0;
+    for (size_t id = 0; id < pairs_of.size(); ++id)
+      if (table_level[id] == l) batches += ((int64_t)pairs_of[id].size() + npi - 1) / npi;
+    const int ntw = choose_ntw(batches, pl->P[l], pl->P[l]);
     for (size_t id = 0; id < pairs_of.size(); ++id) {
       if (table_level[id] != l) continue;
       auto& v = pairs_of[id];
@@ -726,7 +743,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
           m2l_pcoff.push_back(cstride);
           cstride += 2 * (2 * pl->P[l] + 1);
         }
-        add_items(m2l_items, (int)id, pbeg, cnt, table_image[id], pl->P[l], pl->P[l]);
+        add_items(m2l_items, (int)id, pbeg, cnt, table_image[id], pl->P[l], pl->P[l], ntw);
       }
     }
     g.count = (int)m2l_items.size() - g.first;
@@ -785,10 +802,14 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     gu.Ps = gd.Pd = pl->P[l + 1];
     gu.Pd = gd.Ps = pl->P[l];
     const int npi = trans_pairs_per_item(pl->P[l + 1], pl->P[l]);
+    std::vector<int> kids[4];
+    for (int i = pl->lev_begin[l + 1]; i < pl->lev_begin[l + 2]; ++i) kids[B[i].quad].push_back(i);
+    int64_t batches = 0;
+    for (int q = 0; q < 4; ++q) batches += ((int64_t)kids[q].size() + npi - 1) / npi;
+    const int ntw_up = choose_ntw(batches, pl->P[l + 1], pl->P[l]);
+    const int ntw_down = choose_ntw(batches, pl->P[l], pl->P[l + 1]);
     for (int q = 0; q < 4; ++q) {
-      std::vector<int> kids_q;
-      for (int i = pl->lev_begin[l + 1]; i < pl->lev_begin[l + 2]; ++i)
-        if (B[i].quad == q) kids_q.push_back(i);
+      const std::vector<int>& kids_q = kids[q];
       for (size_t c0 = 0; c0 < kids_q.size(); c0 += npi) {
         int cnt = (int)std::min<size_t>(npi, kids_q.size() - c0);
         int pbeg = (int)cp_child.size();
@@ -796,8 +817,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
           cp_child.push_back(kids_q[c0 + c]);
           cp_parent.push_back(B[kids_q[c0 + c]].parent);
         }
-        add_items(up_items, q, pbeg, cnt, 0, pl->P[l + 1], pl->P[l]);
-        add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1]);
+        add_items(up_items, q, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up);
+        add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1], ntw_down);
       }
     }
     gu.count = (int)up_items.size() - gu.first;

@@ -277,124 +277,65 @@ constexpr int TR_THREADS = 256;
 
 enum { OUT_ATOMIC = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2 };
 
-template <bool REV, int MODE>
-__global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const TransItem* __restrict__ items,
-                                                          const int* __restrict__ psrc,
-                                                          const int* __restrict__ pdst,
-                                                          const int64_t* __restrict__ pcoff,
-                                                          const TableRef* __restrict__ tabs,
-                                                          const double2* __restrict__ tdata,
-                                                          const double2* __restrict__ src, double2* __restrict__ dst,
-                                                          double* __restrict__ contrib, int64_t cstride, int r) {
-  extern __shared__ double lds_d[];
-  __shared__ int64_t s_off[64];
-  const TransItem it = items[blockIdx.x];
+// LDS layout of an item: the table as three zero-padded vectors Tr, Ti, -Ti of
+// trans_table_stride(nt) doubles each (value n at index kTabPad + n), then the
+// source coefficients, one row of Ms4 = Ms rounded up to 4 per pair (zeros
+// past Ms), so that the real and the imaginary halves of the contraction
+// index k each fill whole 4-deep MFMA steps.
+constexpr int kTabPad = 4;
+__host__ __device__ inline int trans_table_stride(int nt) { return (nt + 2 * kTabPad + 1) & ~1; }
+__host__ __device__ inline int round4(int m) { return (m + 3) & ~3; }
+
+// The contraction of one wave: NT row tiles of 16 rows of the real-embedded
+// operator against one 16-column tile of pairs. Row r of the operator is
+// (rim, p) = (r >= Md, r mod Md), column k = (kim, m) with the halves padded
+// to Ms4; its entry is Tr, Ti or -Ti at table index 2Pd - p + m (forward) or
+// p + 2Ps - m (transpose). Each lane holds one address per row tile and half,
+// so every operand element is one LDS read and the k-loop has no branches.
+template <bool REV, int MODE, int NT>
+__device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, const double* lds_d, int ntp,
+                                   const double2* s_s, int ntile, int rt_lo, int rt_stride, const int* __restrict__ pdst,
+                                   const int64_t* __restrict__ pcoff, double2* __restrict__ dst,
+                                   double* __restrict__ contrib, int64_t cstride, int r) {
   const int Ps = it.Ps, Pd = it.Pd;
-  const int Ms = 2 * Ps + 1, Md = 2 * Pd + 1;
-  const int nt = 2 * (Ps + Pd) + 1;           // table length
-  const int nrt = (2 * Md + 15) / 16;
-  const int nks = (2 * Ms + 3) / 4;
-  const int npi = trans_pairs_per_item(Ps, Pd);
-  double* s_tr = lds_d;
-  double* s_ti = lds_d + nt;
-  double2* s_s = (double2*)(lds_d + 2 * ((nt + 1) / 2) * 2);  // 16-byte aligned
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  // Every global load of the prologue is issued in one of two rounds: the
-  // pairs' coefficient offsets and the table first, then all source rows.
-  if (tid < npi) s_off[tid] = tid < it.npairs ? tv.coff[psrc[it.pbeg + tid]] : -1;
-  const TableRef tr = tabs[it.table];
-  const double2* T = tdata + tr.off + tr.half - (Ps + Pd);  // T[0] = t[-(Ps + Pd)]
-  for (int i = tid; i < nt; i += TR_THREADS) {
-    double2 v = T[i];
-    s_tr[i] = v.x;
-    s_ti[i] = v.y;
-  }
-  __syncthreads();
-  // source coefficients, flattened (pair, order) so consecutive lanes read
-  // consecutive coefficients of a row; four loads in flight per lane
-  const bool reflect_in = it.image && !REV;
-  const double2* Sr = src + (int64_t)r * tv.ctot;
-  const int tot = npi * Ms;
-  for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
-    double2 v[4];
-    int ev[4];
+  const int Ms4 = round4(2 * Ps + 1), Md = 2 * Pd + 1;
+  const int lane = threadIdx.x & 63, lrow = lane & 15, lk = lane >> 4;
+  int a_re[NT], a_im[NT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * TR_THREADS;
-      ev[u] = e;
-      v[u] = cmk(0.0, 0.0);
-      if (e < tot) {
-        const int c = e / Ms, m = e - c * Ms;
-        const int64_t off = s_off[c];
-        if (off >= 0) {
-          if (reflect_in) {
-            v[u] = Sr[off + Ms - 1 - m];
-            if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
-          } else {
-            v[u] = Sr[off + m];
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (ev[u] < tot) s_s[ev[u]] = v[u];
-  }
-  __syncthreads();
-  int ntile, rt_lo, rt_stride, rt_cnt;
-  const int rt_end = min(nrt, it.rt_base + 32);
-  if (npi == 64) {
-    ntile = wave;
-    rt_lo = it.rt_base;
-    rt_stride = 1;
-    rt_cnt = min(rt_end - rt_lo, 8);
-  } else {
-    ntile = 0;
-    rt_lo = it.rt_base + wave;
-    rt_stride = 4;
-    rt_cnt = rt_lo < rt_end ? min((rt_end - rt_lo + 3) / 4, 8) : 0;
-  }
-  if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
-  const int lrow = lane & 15, lk = lane >> 4;
-  const double2* Scol = s_s + (ntile * 16 + lrow) * Ms;
-  // row-dependent parts of the operator index, per row tile of this lane
-  int tb[8];
-  bool rimj[8], rowok[8];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NT; ++j) {
     const int row = (rt_lo + j * rt_stride) * 16 + lrow;
-    rowok[j] = (j < rt_cnt) && row < 2 * Md;
-    rimj[j] = row >= Md;
-    const int p = rimj[j] ? row - Md : row;
-    tb[j] = REV ? (p + 2 * Ps) : (2 * Pd - p);
+    const bool ok = row < 2 * Md;  // rows past the operator compute garbage that is never stored
+    const bool rim = ok && row >= Md;
+    const int p = ok ? (rim ? row - Md : row) : 0;
+    const int tb = kTabPad + (REV ? p + 2 * Ps : 2 * Pd - p) + (REV ? -lk : lk);
+    a_re[j] = (rim ? ntp : 0) + tb;      // Tr (rim == kim) or Ti
+    a_im[j] = (rim ? 0 : 2 * ntp) + tb;  // Tr or -Ti
   }
-  d4 acc[8];
+  const double* Bcol = (const double*)(s_s + (ntile * 16 + lrow) * Ms4) + 2 * lk;
+  d4 acc[NT];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < NT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int nks = Ms4 / 4;
+  // real half of k, then the imaginary half
+#pragma unroll 2
   for (int ks = 0; ks < nks; ++ks) {
-    const int k = 4 * ks + lk;
-    double b = 0.0;
-    int mk = -1;
-    bool kim = false;
-    if (k < Ms) {
-      b = Scol[k].x;
-      mk = k;
-    } else if (k < 2 * Ms) {
-      b = Scol[k - Ms].y;
-      mk = k - Ms;
-      kim = true;
-    }
+    const int kk = REV ? -4 * ks : 4 * ks;
+    const double b = Bcol[8 * ks];
+    double a[NT];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (j < rt_cnt) {
-        double a = 0.0;
-        if (rowok[j] && mk >= 0) {
-          const int tix = REV ? tb[j] - mk : tb[j] + mk;
-          a = (rimj[j] == kim) ? s_tr[tix] : (rimj[j] ? s_ti[tix] : -s_ti[tix]);
-        }
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
-      }
-    }
+    for (int j = 0; j < NT; ++j) a[j] = lds_d[a_re[j] + kk];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b, acc[j], 0, 0, 0);
+  }
+#pragma unroll 2
+  for (int ks = 0; ks < nks; ++ks) {
+    const int kk = REV ? -4 * ks : 4 * ks;
+    const double b = Bcol[8 * ks + 1];
+    double a[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) a[j] = lds_d[a_im[j] + kk];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b, acc[j], 0, 0, 0);
   }
   const int col = ntile * 16 + lrow;
   if (col >= it.npairs) return;
@@ -404,8 +345,7 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   double* crow = CONTRIB ? contrib + (int64_t)r * cstride + pcoff[pair] : nullptr;
   const bool reflect_out = REV && it.image;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    if (j >= rt_cnt) continue;
+  for (int j = 0; j < NT; ++j) {
     const int rt = rt_lo + j * rt_stride;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -431,6 +371,95 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
       }
     }
   }
+}
+
+template <bool REV, int MODE>
+__global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const TransItem* __restrict__ items,
+                                                          const int* __restrict__ psrc,
+                                                          const int* __restrict__ pdst,
+                                                          const int64_t* __restrict__ pcoff,
+                                                          const TableRef* __restrict__ tabs,
+                                                          const double2* __restrict__ tdata,
+                                                          const double2* __restrict__ src, double2* __restrict__ dst,
+                                                          double* __restrict__ contrib, int64_t cstride, int r) {
+  extern __shared__ double lds_d[];
+  __shared__ int64_t s_off[64];
+  const TransItem it = items[blockIdx.x];
+  const int Ps = it.Ps, Pd = it.Pd;
+  const int Ms = 2 * Ps + 1, Ms4 = round4(Ms), Md = 2 * Pd + 1;
+  const int nt = 2 * (Ps + Pd) + 1;  // table length
+  const int ntp = trans_table_stride(nt);
+  const int nrt = (2 * Md + 15) / 16;
+  const int npi = trans_pairs_per_item(Ps, Pd);
+  double2* s_s = (double2*)(lds_d + 3 * ntp);  // 16-byte aligned: ntp is even
+  const int tid = threadIdx.x, wave = tid >> 6;
+  // Every global load of the prologue is issued in one of two rounds: the
+  // pairs' coefficient offsets and the table first, then all source rows.
+  if (tid < npi) s_off[tid] = tid < it.npairs ? tv.coff[psrc[it.pbeg + tid]] : -1;
+  const TableRef tr = tabs[it.table];
+  const double2* T = tdata + tr.off + tr.half - (Ps + Pd);  // T[0] = t[-(Ps + Pd)]
+  for (int i = tid; i < ntp; i += TR_THREADS) {
+    const int n = i - kTabPad;
+    const double2 v = (n >= 0 && n < nt) ? T[n] : cmk(0.0, 0.0);
+    lds_d[i] = v.x;
+    lds_d[ntp + i] = v.y;
+    lds_d[2 * ntp + i] = -v.y;
+  }
+  __syncthreads();
+  // source coefficients, flattened (pair, order) so consecutive lanes read
+  // consecutive coefficients of a row; four loads in flight per lane
+  const bool reflect_in = it.image && !REV;
+  const double2* Sr = src + (int64_t)r * tv.ctot;
+  const int tot = npi * Ms4;
+  for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * TR_THREADS;
+      v[u] = cmk(0.0, 0.0);
+      if (e < tot) {
+        const int c = e / Ms4, m = e - c * Ms4;
+        const int64_t off = s_off[c];
+        if (off >= 0 && m < Ms) {
+          if (reflect_in) {
+            v[u] = Sr[off + Ms - 1 - m];
+            if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
+          } else {
+            v[u] = Sr[off + m];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
+  }
+  __syncthreads();
+  // wave -> (column tile, row tiles): with 64 pairs per item each wave takes a
+  // column tile and it.ntw consecutive row tiles; with 16, the waves split up
+  // to 4 it.ntw row tiles with stride 4
+  int ntile, rt_lo, rt_stride, rt_cnt;
+  if (npi == 64) {
+    ntile = wave;
+    rt_lo = it.rt_base;
+    rt_stride = 1;
+    rt_cnt = min(nrt - rt_lo, it.ntw);
+  } else {
+    ntile = 0;
+    rt_lo = it.rt_base + wave;
+    rt_stride = 4;
+    rt_cnt = rt_lo < nrt ? min((nrt - rt_lo + 3) / 4, it.ntw) : 0;
+  }
+  if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
+#define HFMM_TILES(N)                                                                                           \
+  case N:                                                                                                       \
+    trans_tiles<REV, MODE, N>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r); \
+    break;
+  switch (rt_cnt) {
+    HFMM_TILES(1) HFMM_TILES(2) HFMM_TILES(3) HFMM_TILES(4) HFMM_TILES(5) HFMM_TILES(6) HFMM_TILES(7)
+    default: trans_tiles<REV, MODE, 8>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r);
+  }
+#undef HFMM_TILES
 }
 
 // beta_b = sum of the contribution rows listed for box b (CSR), plain store.
@@ -859,12 +888,12 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
   hipLaunchKernelGGL(k_l2p, dim3(nl), dim3(WAVE), l2p_lds_bytes(P), s, tv, leaves, nl, P, beta, us, conj_w, pref,
                      accumulate);
 }
-// LDS bytes of a translation item: the table (real and imaginary parts) and
-// the source-coefficient tile.
+// LDS bytes of a translation item: the padded table (real, imaginary and
+// negated imaginary parts) and the padded source-coefficient tile.
 size_t trans_lds_bytes(int Ps, int Pd) {
-  int nt = 2 * (Ps + Pd) + 1;
-  int npi = trans_pairs_per_item(Ps, Pd);
-  return sizeof(double) * (size_t)(4 * ((nt + 1) / 2)) + sizeof(double2) * (size_t)npi * (2 * Ps + 1);
+  const int ntp = trans_table_stride(2 * (Ps + Pd) + 1);
+  const int npi = trans_pairs_per_item(Ps, Pd);
+  return sizeof(double) * (size_t)(3 * ntp) + sizeof(double2) * (size_t)npi * round4(2 * Ps + 1);
 }
 
 template <bool REV, int MODE>
