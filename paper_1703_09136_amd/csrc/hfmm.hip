@@ -252,6 +252,7 @@ struct hfmm_plan_s {
   DevBuf<int> leaves;  // leaf boxes, ascending level
   int nleaves = 0;
   std::vector<int> leaf_lev;  // leaves of level l: [leaf_lev[l], leaf_lev[l + 1])
+  int leaf_pmax = 0;          // largest expansion order among the leaves
   // batched translations: item groups sharing (Ps, Pd), per level
   struct Group {
     int first = 0, count = 0, Ps = 0, Pd = 0;
@@ -836,6 +837,9 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       pl->leaf_lev[B[i].level + 1] = (int)leaves.size();
     }
   for (int l = 1; l <= pl->nlev; ++l) pl->leaf_lev[l] = std::max(pl->leaf_lev[l], pl->leaf_lev[l - 1]);
+  pl->leaf_pmax = 0;
+  for (int l = 0; l < pl->nlev; ++l)
+    if (pl->leaf_lev[l + 1] > pl->leaf_lev[l]) pl->leaf_pmax = std::max(pl->leaf_pmax, pl->P[l]);
 
   // ---- direct lists, grouped by target leaf, source ranges merged
   auto leaves_under = [&](int b, std::vector<int>& outv) {
@@ -1181,18 +1185,18 @@ struct Marker {
   }
 };
 
-// P2M (or L2P^T) over the leaves of level l.
-void launch_p2m_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, int l, const double2* qs, double2* alpha,
-                      int conj_w, double2 pref) {
-  const int b0 = pl->leaf_lev[l], b1 = pl->leaf_lev[l + 1];
-  launch_p2m(s, tv, pl->leaves.p + b0, b1 - b0, tv.P[l], qs, alpha, conj_w, pref);
+// P2M (or L2P^T) over all leaves of levels >= 2, one launch (leaves are in
+// level order, coarse first).
+void launch_p2m_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* qs, double2* alpha,
+                    int conj_w, double2 pref) {
+  const int b0 = pl->leaf_lev[std::min(2, pl->nlev)], b1 = pl->leaf_lev[pl->nlev];
+  launch_p2m(s, tv, pl->leaves.p + b0, b1 - b0, pl->leaf_pmax, qs, alpha, conj_w, pref);
 }
 
-// L2P (or P2M^T) over the leaves of level l; the first writer of u.
-void launch_l2p_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, int l, const double2* beta, double2* us,
-                      int conj_w, double2 pref) {
-  const int b0 = pl->leaf_lev[l], b1 = pl->leaf_lev[l + 1];
-  launch_l2p(s, tv, pl->leaves.p + b0, b1 - b0, tv.P[l], beta, us, conj_w, pref, 0);
+// L2P (or P2M^T) over all leaves, one launch; the first writer of u.
+void launch_l2p_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* beta, double2* us, int conj_w,
+                    double2 pref) {
+  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, beta, us, conj_w, pref, 0);
 }
 
 // One level of child -> parent (up) or parent -> child (down) translations.
@@ -1225,7 +1229,7 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
   TreeView tv = pl->view(nrhs);
   // parents accumulate their children's translated multipoles
   launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
-  for (int l = 2; l < pl->nlev; ++l) launch_p2m_level(pl, tv, s, l, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
+  launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
   mark();
   for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0);
   mark();
@@ -1233,7 +1237,7 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
   mark();
   for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0);
   mark();
-  for (int l = 0; l < pl->nlev; ++l) launch_l2p_level(pl, tv, s, l, pl->beta.p, us, 0, cmk(0.0, 0.25));
+  launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25));
   mark();
   launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, qs, us);
   mark();
@@ -1247,7 +1251,7 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   TreeView tv = pl->view(nrhs);
   // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}; parents accumulate
   launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
-  for (int l = 2; l < pl->nlev; ++l) launch_p2m_level(pl, tv, s, l, vs, pl->beta.p, 1, cmk(0.0, 0.25));
+  launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
   // L2L^T, finest parents first: beta'(parent) += T^T beta'(child)
   for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
   // M2L^T, reduced by source box
@@ -1255,7 +1259,7 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
   for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1);
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
-  for (int l = 0; l < pl->nlev; ++l) launch_l2p_level(pl, tv, s, l, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
+  launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
   // the direct parts are symmetric
   launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, vs, ws);
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,

@@ -53,28 +53,31 @@ __global__ void k_scatter(int n, int nrhs, const int* __restrict__ perm, const d
 
 // ------------------------------------------------------------------ P2M
 // alpha_p = sum_j q_j J_p(k rho_j) e^{-i p theta_j}, p in [-P, P] (Eq. multi_coeff).
-// One wave per leaf, a lane per point. Each lane walks the backward Bessel
+// One wave per leaf (one launch for all levels, the order read per leaf), a
+// lane per point. Each lane walks the backward Bessel
 // recurrence once and parks V_{n,j} = J_n(k rho_j) w_j^n (w = e^{-i theta}) for a
 // chunk of P2M_CH orders in LDS; the chunk is then reduced over the points
 // for every right-hand side, giving alpha_n = sum q V and, through
 // J_{-n} = (-1)^n J_n, alpha_{-n} = (-1)^n sum q conj(V). The coefficients
 // accumulate in LDS and are stored once. With conj_w the phase is
 // e^{+i p theta} and the result is scaled by pref: the transpose of L2P.
-constexpr int P2M_CH = 16;  // orders per reduction chunk
+constexpr int P2M_CH = 8;   // orders per reduction chunk
 constexpr int P2M_RB = 4;   // right-hand sides per pass
 constexpr int P2M_VS = WAVE + 1;  // padded row of the V tile
+constexpr int P2M_PARTS = WAVE / P2M_CH;  // lanes that share one order in the reduction
 
-__global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict__ leaves, int nleaves, int P,
+__global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict__ leaves, int nleaves, int rb,
                                               const double2* __restrict__ qs, double2* __restrict__ alpha,
                                               int conj_w, double2 pref) {
   extern __shared__ double2 lds_c[];
   double2* s_V = lds_c;                     // [P2M_CH][P2M_VS]
-  double2* s_q = s_V + P2M_CH * P2M_VS;     // [P2M_RB][WAVE]
-  double2* s_a = s_q + P2M_RB * WAVE;       // [P2M_RB][2P + 1]
+  double2* s_q = s_V + P2M_CH * P2M_VS;     // [rb][WAVE]
+  double2* s_a = s_q + rb * WAVE;           // [rb][2P + 1]
   const int li = blockIdx.x;
   if (li >= nleaves) return;
   const int b = leaves[li];
   const int lane = threadIdx.x;
+  const int P = tv.P[tv.level[b]];
   const int M = 2 * P + 1;
   const int2 pr = tv.prange[b];
   const double2 c = tv.ctr[b];
@@ -87,10 +90,10 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
   }
   for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
   const int nstart = miller_start(tv.k * rmax, P);
-  // reduction role of this lane: order slot t of the chunk, point quarter part
+  // reduction role of this lane: order slot t of the chunk, point block part
   const int t_red = lane & (P2M_CH - 1), part = lane / P2M_CH;
-  for (int r0 = 0; r0 < tv.nrhs; r0 += P2M_RB) {
-    const int nr = min(P2M_RB, tv.nrhs - r0);
+  for (int r0 = 0; r0 < tv.nrhs; r0 += rb) {
+    const int nr = min(rb, tv.nrhs - r0);
     for (int e = lane; e < nr * M; e += WAVE) s_a[e] = cmk(0.0, 0.0);
     for (int j0 = pr.x; j0 < pr.y; j0 += WAVE) {
       const int j = j0 + lane;
@@ -131,19 +134,20 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
           if (rr >= nr) break;
           double2 sp = cmk(0.0, 0.0), sm = cmk(0.0, 0.0);
           if (n >= 0) {
-            const double2* V = s_V + t_red * P2M_VS + part * (WAVE / 4);
-            const double2* Q = s_q + rr * WAVE + part * (WAVE / 4);
-#pragma unroll 4
-            for (int i = 0; i < WAVE / 4; ++i) {
+            const double2* V = s_V + t_red * P2M_VS + part * (WAVE / P2M_PARTS);
+            const double2* Q = s_q + rr * WAVE + part * (WAVE / P2M_PARTS);
+#pragma unroll
+            for (int i = 0; i < WAVE / P2M_PARTS; ++i) {
               const double2 v = V[i], q = Q[i];
               sp = cadd(sp, cmul(q, v));
               sm = cadd(sm, cmul(q, cconj(v)));
             }
           }
-          sp = cadd(sp, shfl_xor_c(sp, P2M_CH));
-          sp = cadd(sp, shfl_xor_c(sp, 2 * P2M_CH));
-          sm = cadd(sm, shfl_xor_c(sm, P2M_CH));
-          sm = cadd(sm, shfl_xor_c(sm, 2 * P2M_CH));
+#pragma unroll
+          for (int m = P2M_CH; m < WAVE; m <<= 1) {
+            sp = cadd(sp, shfl_xor_c(sp, m));
+            sm = cadd(sm, shfl_xor_c(sm, m));
+          }
           if (part == 0 && n >= 0) {
             double2* a = s_a + rr * M + P;
             a[n] = cadd(a[n], cmul(pref, sp));
@@ -161,8 +165,8 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
   }
 }
 
-size_t p2m_lds_bytes(int P) {
-  return sizeof(double2) * (size_t)(P2M_CH * P2M_VS + P2M_RB * WAVE + P2M_RB * (2 * P + 1));
+size_t p2m_lds_bytes(int Pmax, int rb) {
+  return sizeof(double2) * (size_t)(P2M_CH * P2M_VS + rb * WAVE + rb * (2 * Pmax + 1));
 }
 
 // ------------------------------------------------------------------ L2P
@@ -173,15 +177,17 @@ size_t p2m_lds_bytes(int P) {
 // transpose of P2M, used by the adjoint.
 constexpr int L2P_RB = 4;
 
-__global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict__ leaves, int nleaves, int P,
+__global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict__ leaves, int nleaves, int rb,
                                               const double2* __restrict__ beta, double2* __restrict__ us,
                                               int conj_w, double2 pref, int accumulate) {
-  extern __shared__ double2 lds_c[];  // [L2P_RB][2P + 1]
+  extern __shared__ double2 lds_c[];  // [rb][2P + 1]
   const int li = blockIdx.x;
   if (li >= nleaves) return;
   const int b = leaves[li];
   const int lane = threadIdx.x;
-  const bool has_local = tv.level[b] >= 2;
+  const int lev = tv.level[b];
+  const bool has_local = lev >= 2;
+  const int P = tv.P[lev];
   const int M = 2 * P + 1;
   const int2 pr = tv.prange[b];
   const double2 c = tv.ctr[b];
@@ -196,8 +202,8 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
     for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
     nstart = miller_start(tv.k * rmax, P);
   }
-  for (int r0 = 0; r0 < tv.nrhs; r0 += L2P_RB) {
-    const int nr = min(L2P_RB, tv.nrhs - r0);
+  for (int r0 = 0; r0 < tv.nrhs; r0 += rb) {
+    const int nr = min(rb, tv.nrhs - r0);
     if (has_local) {
       for (int e = lane; e < nr * M; e += WAVE) {
         const int rr = e / M;
@@ -254,7 +260,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
   }
 }
 
-size_t l2p_lds_bytes(int P) { return sizeof(double2) * (size_t)(L2P_RB * (2 * P + 1)); }
+size_t l2p_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * (2 * Pmax + 1)); }
 
 // ------------------------------------------------------------------ batched translations on MFMA
 // For one table t (t[n], n = m - p, m in [-Ps, Ps] source orders, p in
@@ -876,17 +882,20 @@ void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const doubl
   int64_t tot = (int64_t)n * nrhs;
   hipLaunchKernelGGL(k_scatter, dim3(blocks(tot, 256)), dim3(256), 0, s, n, nrhs, perm, src, dst, cj);
 }
-void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* qs,
+void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* qs,
                 double2* alpha, int conj_w, double2 pref) {
   if (nl <= 0) return;
-  // at most 53 KiB (P = 255): within the default dynamic LDS limit
-  hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(WAVE), p2m_lds_bytes(P), s, tv, leaves, nl, P, qs, alpha, conj_w, pref);
+  // at most 37 KiB (Pmax = 255): within the default dynamic LDS limit
+  const int rb = min(P2M_RB, tv.nrhs);
+  hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(WAVE), p2m_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, qs, alpha, conj_w,
+                     pref);
 }
-void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* beta,
+void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
                 double2* us, int conj_w, double2 pref, int accumulate) {
   if (nl <= 0) return;
-  hipLaunchKernelGGL(k_l2p, dim3(nl), dim3(WAVE), l2p_lds_bytes(P), s, tv, leaves, nl, P, beta, us, conj_w, pref,
-                     accumulate);
+  const int rb = min(L2P_RB, tv.nrhs);
+  hipLaunchKernelGGL(k_l2p, dim3(nl), dim3(WAVE), l2p_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, beta, us, conj_w,
+                     pref, accumulate);
 }
 // LDS bytes of a translation item: the padded table (real, imaginary and
 // negated imaginary parts) and the padded source-coefficient tile.

@@ -7,10 +7,11 @@ namespace hfmm {
 
 void launch_gather(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_in);
 void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_out);
-// P2M and L2P over leaves of one level (expansion order P).
-void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* qs,
+// P2M and L2P over a list of leaves; each block reads its leaf's order, Pmax
+// bounds the orders of the list (sizes the LDS).
+void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* qs,
                 double2* alpha, int conj_w, double2 pref);
-void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int P, const double2* beta,
+void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
                 double2* us, int conj_w, double2 pref, int accumulate);
 // Batched translation contraction (M2L, M2M, L2L and transposes) for items
 // sharing (Ps, Pd). With contrib != NULL each pair writes its own contribution

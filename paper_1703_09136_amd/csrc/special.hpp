@@ -51,19 +51,12 @@ __host__ __device__ inline void miller_norm(double x, int nstart, double& inv_s,
 // Pass 2 as an explicit walk: value() is the normalised J_n at the current
 // index n (starting at nstart); step() moves to n - 1.
 struct MillerWalk {
-  double tx, j, jp1, inv_s, sc;
-  int n, left;
+  double tx, j, jp1, inv_s;
+  int n, left;  // rescalings still ahead
   __host__ __device__ MillerWalk(double x, int nstart, double inv_s_, int nres)
-      : tx(2.0 / x), j(0x1p-900), jp1(0.0), inv_s(inv_s_), sc(0.0), n(nstart), left(nres) {
-    sc = scale();
-  }
-  // factor from the current scale to the final one: kRescaleBy^left / S
-  __host__ __device__ double scale() const {
-    double f = inv_s;
-    for (int r = 0; r < left; ++r) f *= kRescaleBy;
-    return f;
-  }
-  __host__ __device__ double value() const { return j * sc; }
+      : tx(2.0 / x), j(0x1p-900), jp1(0.0), inv_s(inv_s_), n(nstart), left(nres) {}
+  // J_n = j kRescaleBy^left / S, the power applied exactly by ldexp
+  __host__ __device__ double value() const { return ldexp(j * inv_s, -700 * left); }
   __host__ __device__ void step() {
     double jm1 = ((double)n * tx) * j - jp1;
     jp1 = j;
@@ -72,10 +65,10 @@ struct MillerWalk {
     if (fabs(j) > kRescaleHi) {
       j *= kRescaleBy; jp1 *= kRescaleBy;
       --left;
-      sc = scale();
     }
   }
 };
+static_assert(kRescaleBy == 0x1p-700, "MillerWalk::value applies the rescale factor as 2^-700");
 
 // Pass 2: calls f(n, J_n) for n = nmax down to 0 with normalised values.
 template <class F>
