@@ -142,9 +142,9 @@ def main():
     if dominant == "m2l":
         work = info["flops_m2l"]
     else:
-        # flops of one free-space pair: H0 by its ascending series (about 16
-        # terms x 4 flops + logarithm ~ 20) + distance (~10) + complex MAC (8)
-        work = info["p2p_pairs"] * 102.0
+        # flops of the direct part as the plan evaluates it (series length by
+        # item class, logarithm, complex multiply-adds)
+        work = info["flops_p2p"]
     dom_s = stage_avg[dominant] / 1e3
     achieved = work / dom_s / 1e12
     roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,

@@ -88,8 +88,14 @@ typedef struct {
   int64_t image_tables;     /* heterogeneous translation tables generated */
   double flops_m2l;         /* algorithmic flops of one apply, per RHS */
   double flops_updown;      /* P2M + M2M + L2L + L2P */
-  double flops_p2p;         /* direct pairs (H0 cost counted as 1 pair) */
+  double flops_p2p;         /* free-space direct part as evaluated: per H0
+                               value 4M (series of M terms, by item class)
+                               + 36 (logarithm, distance, assembly) + 8 per
+                               complex multiply-add */
   double plan_seconds;
+  int64_t p2p_evals;        /* H0 evaluations per apply and right-hand side:
+                               each cross-leaf pair once, same-leaf pairs
+                               in both orders */
 } hfmm_info_t;
 
 /* Default options. */

@@ -43,7 +43,7 @@ class Info(ctypes.Structure):
                 ("p2p_pairs", ctypes.c_int64), ("interface_pairs", ctypes.c_int64),
                 ("image_tables", ctypes.c_int64), ("flops_m2l", ctypes.c_double),
                 ("flops_updown", ctypes.c_double), ("flops_p2p", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double)]
+                ("plan_seconds", ctypes.c_double), ("p2p_evals", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "order"}

@@ -137,7 +137,8 @@ struct Rule {
   bool ok = true;
 };
 constexpr size_t kMaxPanels = 100000;
-constexpr int kItemSources = 2048;   // sources per direct work item
+constexpr int kItemSources = 2048;   // at most this many sources per direct work item
+constexpr int kItemPairs = 16384;    // and about this many pairs
 // per-translation truncation bound as a fraction of the requested tolerance
 #ifndef HFMM_ORDER_SAFETY
 #define HFMM_ORDER_SAFETY 0.5
@@ -275,7 +276,10 @@ struct hfmm_plan_s {
   DevBuf<TableRef> tabs;
   DevBuf<double2> tdata;
   std::vector<int> m2m_tab, l2l_tab;  // per parent level: index of 4 consecutive tables
-  DevBuf<int> p2p_ptr, p2p_items, p2p_atomic;
+  DevBuf<int> p2p_ptr, p2p_items, p2p_sym;
+  bool p2p_symmetric = false;  // cross items evaluate each pair once
+  int64_t p2p_evals = 0;       // H0 evaluations per apply
+  double p2p_flops = 0.0;      // their flops (series terms by class)
   int p2p_cls_ptr[kH0Classes + 2] = {0};  // items of series class c: [p2p_cls_ptr[c], p2p_cls_ptr[c + 1])
   DevBuf<int2> p2p_rng;
   int np2p_items = 0;
@@ -319,7 +323,7 @@ struct hfmm_plan_s {
     red_ptr.release(); red_pairs.release(); redT_ptr.release(); redT_pairs.release(); cp_child.release();
     cp_parent.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
-    p2p_items.release(); p2p_atomic.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
+    p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release();
   }
 };
@@ -917,48 +921,99 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     while (c < kH0Classes && zmax > kH0ClassZmax[c]) ++c;
     return c;
   };
+  // Split every leaf's merged ranges at its own points: the part before the
+  // leaf, the leaf itself, and the part after it. The direct-pair relation is
+  // symmetric (leaf T lists leaf S exactly when S lists T), so the pairs of T
+  // with the leaves after it are evaluated once, in T's cross items, and the
+  // parts before are dropped. The plan checks the symmetry leaf pair by leaf
+  // pair and otherwise keeps every ordered pair in one-sided items.
+  const int nl = (int)leaves.size();
+  std::vector<std::vector<int2>> before(nl), self_r(nl), after(nl);
+  for (int li = 0; li < nl; ++li) {
+    const int tb = B[leaves[li]].begin, te = B[leaves[li]].end;
+    for (const int2& rg : u_per[li]) {
+      if (rg.x < std::min(rg.y, tb)) before[li].push_back(make_int2(rg.x, std::min(rg.y, tb)));
+      if (std::max(rg.x, tb) < std::min(rg.y, te)) self_r[li].push_back(make_int2(std::max(rg.x, tb), std::min(rg.y, te)));
+      if (std::max(rg.x, te) < rg.y) after[li].push_back(make_int2(std::max(rg.x, te), rg.y));
+    }
+  }
+  bool symmetric = true;
+  {
+    std::vector<std::pair<int, int>> fwd, rev;  // (earlier leaf, later leaf)
+    for (int li = 0; li < nl; ++li) {
+      for (const int2& r : after[li])
+        for (int j = r.x; j < r.y;) {
+          const int lj = leaf_at[j];
+          if (lj < 0) { symmetric = false; break; }
+          fwd.emplace_back(li, lj);
+          j = B[leaves[lj]].end;
+        }
+      for (const int2& r : before[li])
+        for (int j = r.x; j < r.y;) {
+          const int lj = leaf_at[j];
+          if (lj < 0) { symmetric = false; break; }
+          rev.emplace_back(lj, li);
+          j = B[leaves[lj]].end;
+        }
+    }
+    std::sort(fwd.begin(), fwd.end());
+    std::sort(rev.begin(), rev.end());
+    symmetric = symmetric && fwd == rev;
+  }
+  pl->p2p_symmetric = symmetric;
   // direct work items: a target leaf, one series class, at most kItemSources
-  // sources; a leaf whose sources span several items accumulates atomically.
-  // Largest first.
+  // sources; cross items (sym) when the relation is symmetric. Per class,
+  // largest first.
   struct Item {
     int leaf;
-    int atomic;
+    int sym;
     int cls;
     int64_t cost;
     std::vector<int2> r;
   };
   std::vector<Item> items;
-  for (size_t li = 0; li < leaves.size(); ++li) {
-    size_t first = items.size();
+  auto add_ranges = [&](int li, const std::vector<int2>& rs, int sym) {
+    const size_t first = items.size();
+    // about kItemPairs pairs per item, so that no single wave dominates a launch
+    const int nt_leaf = B[leaves[li]].end - B[leaves[li]].begin;
+    const int cap = std::max(64, std::min(kItemSources, (kItemPairs / std::max(nt_leaf, 1)) & ~63));
     std::vector<int2> by_cls[kH0Classes + 1];
-    for (const int2& rg : u_per[li]) by_cls[series_class(leaf_bb[li], range_bb(rg))].push_back(rg);
+    for (const int2& rg : rs) by_cls[series_class(leaf_bb[li], range_bb(rg))].push_back(rg);
     for (int c = 0; c <= kH0Classes; ++c) {
-      Item cur{leaves[li], 0, c, 0, {}};
+      Item cur{leaves[li], sym, c, 0, {}};
       int cur_n = 0;
       for (const int2& rg : by_cls[c]) {
         int a = rg.x;
         while (a < rg.y) {
-          int take = std::min(rg.y - a, kItemSources - cur_n);
+          int take = std::min(rg.y - a, cap - cur_n);
           cur.r.push_back(make_int2(a, a + take));
           cur_n += take;
           a += take;
-          if (cur_n == kItemSources) {
+          if (cur_n == cap) {
             items.push_back(cur);
-            cur = Item{leaves[li], 0, c, 0, {}};
+            cur = Item{leaves[li], sym, c, 0, {}};
             cur_n = 0;
           }
         }
       }
       if (cur_n > 0) items.push_back(cur);
     }
-    int nt = B[leaves[li]].end - B[leaves[li]].begin;
+    const int nt = B[leaves[li]].end - B[leaves[li]].begin;
     for (size_t it = first; it < items.size(); ++it) {
-      items[it].atomic = (items.size() - first) > 1;
       int64_t ns = 0;
       for (auto& r : items[it].r) ns += r.y - r.x;
       const int c = items[it].cls;
-      // per pair: the two series chains plus about 24 operations of logarithm and update
-      items[it].cost = ns * nt * (2 * kH0ClassTerms[c < kH0Classes ? c : kH0Classes - 1] + 24);
+      // per pair: the two series chains plus about 24 operations of logarithm
+      // and update, and 10 more for the reverse sum of a cross item
+      items[it].cost = ns * nt * (2 * kH0ClassTerms[c < kH0Classes ? c : kH0Classes - 1] + 24 + (sym ? 10 : 0));
+    }
+  };
+  for (int li = 0; li < nl; ++li) {
+    if (symmetric) {
+      add_ranges(li, self_r[li], 0);
+      add_ranges(li, after[li], 1);
+    } else {
+      add_ranges(li, u_per[li], 0);
     }
   }
   std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
@@ -967,14 +1022,27 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   for (int c = 0; c <= kH0Classes + 1; ++c) pl->p2p_cls_ptr[c] = 0;
   for (auto& it : items) ++pl->p2p_cls_ptr[it.cls + 1];
   for (int c = 1; c <= kH0Classes + 1; ++c) pl->p2p_cls_ptr[c] += pl->p2p_cls_ptr[c - 1];
-  std::vector<int> p2p_ptr(1, 0), p2p_items, p2p_atomic, if_ptr(1, 0), if_leaves;
+  std::vector<int> p2p_ptr(1, 0), p2p_items, p2p_sym, if_ptr(1, 0), if_leaves;
   std::vector<int2> p2p_rng, if_rng;
+  int64_t p2p_evals = 0;
+  double p2p_flops = 0.0;
   for (auto& it : items) {
     p2p_items.push_back(it.leaf);
-    p2p_atomic.push_back(it.atomic);
+    p2p_sym.push_back(it.sym);
     p2p_rng.insert(p2p_rng.end(), it.r.begin(), it.r.end());
     p2p_ptr.push_back((int)p2p_rng.size());
+    int64_t ns = 0;
+    for (auto& r : it.r) ns += r.y - r.x;
+    const int64_t ev = ns * (B[it.leaf].end - B[it.leaf].begin);
+    p2p_evals += ev;
+    // flops of one evaluation: two Horner chains of M terms (4M), the
+    // logarithm (26), distance and assembly (10), and a complex multiply-add
+    // per direction (8 each)
+    const int M = kH0ClassTerms[it.cls < kH0Classes ? it.cls : kH0Classes - 1];
+    p2p_flops += (double)ev * (4.0 * M + 36.0 + (it.sym ? 16.0 : 8.0));
   }
+  pl->p2p_evals = p2p_evals;
+  pl->p2p_flops = p2p_flops;
   for (size_t li = 0; li < leaves.size(); ++li) {
     if (!i_per[li].empty()) {
       if_leaves.push_back(leaves[li]);
@@ -1085,7 +1153,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_pairs, red_pairs) UP(redT_ptr, redT_ptr)
   UP(redT_pairs, redT_pairs) UP(cp_child, cp_child) UP(cp_parent, cp_parent) UP(up_items, up_items)
   UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
-  UP(p2p_items, p2p_items) UP(p2p_atomic, p2p_atomic) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
+  UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
   DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
   DevBuf<int> d_fhref, d_fbsgn, d_fbref, d_cpbeg, d_imgref;
@@ -1160,7 +1228,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     if (l >= 3) fud += 2.0 * 8.0 * m * (2.0 * pl->P[l - 1] + 1);     // M2M + L2L
   }
   inf.flops_updown = fud;
-  inf.flops_p2p = (double)np2p;
+  inf.flops_p2p = pl->p2p_flops;
+  inf.p2p_evals = pl->p2p_evals;
   inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   *out = pl;
   return HFMM_OK;
@@ -1239,7 +1308,7 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
   mark();
   launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25));
   mark();
-  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, qs, us);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, qs, us);
   mark();
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, qs, us);
@@ -1261,7 +1330,7 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
   launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
   // the direct parts are symmetric
-  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_atomic.p, vs, ws);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, vs, ws);
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, vs, ws);
 }

@@ -502,31 +502,49 @@ __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
 
 // ------------------------------------------------------------------ P2P (free space)
 // u_i += (i/4) sum_{j in U(i), j != i} q_j H0^(1)(k |x_i - x_j|). One wave per
-// target leaf; when the leaf holds fewer than 64 points several lanes share a
-// target and split its sources, then combine by shuffles.
-// Sources are staged through LDS 64 at a time; RB right-hand sides share each
-// H0 evaluation (right-hand sides r0 .. r0+RB-1 in this launch). Each staged
-// chunk takes the shortest series that covers its largest pair distance,
-// bounded from the bounding boxes of the targets and of the chunk.
+// work item: a target leaf against source ranges. When the leaf holds fewer
+// than 64 points several lanes share a target and split its sources, then
+// combine by shuffles. Sources are staged through LDS P2P_CS at a time; RB
+// right-hand sides share each H0 evaluation (right-hand sides r0 .. r0+RB-1).
+// Each item uses the shortest series that covers its largest pair distance.
+//
+// H0(k |x_i - x_j|) is symmetric and so is the set of direct pairs, so a
+// cross item (sources that follow the target leaf in point order) evaluates
+// each pair once and also adds q_i H_ij into u_j: those sums collect in LDS,
+// each lane starting its sweep of the chunk at a different source so that
+// lanes seldom add to the same entry at once, and go to u once per chunk.
+// Self items (a leaf with itself) take every ordered pair. All output is
+// added atomically: a point receives from its own items and from the cross
+// items of the leaves before it.
 
-// One staged chunk for one lane: sources jj = sub, sub + g, ... of cnt, four
-// per step; jself is the target's own index within the chunk (if any).
-// z = (k r / 2)^2; dropped terms get a harmless z = 1 and weight 0.
-template <int RB, int M, bool LARGE>
-__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, double2 xi, double qk2,
-                                 const double2* s_x, const double2 (*s_q)[WAVE], double2 acc[RB]) {
-  for (int jj = sub; jj < cnt; jj += 4 * g) {
+// One staged chunk for one lane: the sources of residue class sub mod g in
+// [0, cnt), four per step; jself is the target's own index within the chunk
+// (self items). z = (k r / 2)^2; dropped terms get a harmless z = 1 and
+// weight 0.
+constexpr int P2P_CS = 128;  // sources per staged chunk
+
+template <int RB, int M, bool LARGE, bool SYM>
+__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, double2 xi, const double2* qi,
+                                 double qk2, const double2* s_x, const double2 (*s_q)[P2P_CS], double2 acc[RB],
+                                 double2 (*s_acc)[P2P_CS]) {
+  const int K = (cnt - sub + g - 1) / g;  // sources of this lane's class
+  const int r0 = K > 0 ? rot % K : 0;
+  for (int k0 = 0; k0 < K; k0 += 4) {
     // loads first (clamped index, no branches), then the arithmetic
     double2 xj[4], qv[4][RB];
     bool use[4];
+    int jc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int jl = jj + u * g;
-      use[u] = jl < cnt && jl != jself;
-      const int jc = min(jl, cnt - 1);
-      xj[u] = s_x[jc];
+      const int k = k0 + u;
+      int kr = k + r0;
+      if (kr >= K) kr -= K;
+      const int jl = sub + g * (k < K ? kr : 0);
+      use[u] = k < K && jl != jself;
+      jc[u] = min(jl, cnt - 1);
+      xj[u] = s_x[jc[u]];
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) qv[u][rr] = s_q[rr][jc];
+      for (int rr = 0; rr < RB; ++rr) qv[u][rr] = s_q[rr][jc[u]];
     }
     double z[4];
 #pragma unroll
@@ -543,18 +561,31 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, double2 xi,
       const double2 hw = cmk(h[u].x * w, h[u].y * w);
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(hw, qv[u][rr]));
+      if (SYM && use[u]) {
+#pragma unroll
+        for (int rr = 0; rr < RB; ++rr) {
+          const double2 t = cmul(hw, qi[rr]);
+          atomicAdd(&s_acc[rr][jc[u]].x, t.x);
+          atomicAdd(&s_acc[rr][jc[u]].y, t.y);
+        }
+      }
     }
   }
 }
 
 // One work item: the target leaf b against source ranges [e0, e1) of rng.
-template <int RB, int M, bool LARGE>
+template <int RB, int M, bool LARGE, bool SYM>
 __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const int2* __restrict__ rng,
-                                bool atomic, const double2* __restrict__ qs, double2* __restrict__ us, int r0,
-                                double2* s_x, double2 (*s_q)[WAVE]) {
+                                const double2* __restrict__ qs, double2* __restrict__ us, int r0, double2* s_x,
+                                double2 (*s_q)[P2P_CS], double2 (*s_acc)[P2P_CS]) {
   const int lane = threadIdx.x;
   const int2 pr = tv.prange[b];
   const double qk2 = 0.25 * tv.k * tv.k;
+  if (SYM) {
+    for (int l = lane; l < P2P_CS; l += WAVE)
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr) s_acc[rr][l] = cmk(0.0, 0.0);
+  }
   // targets in chunks of 32 (two lanes per target), the remainder in a chunk of
   // the next power of two with more lanes per target
   for (int c0 = pr.x, csz = 0; c0 < pr.y; c0 += csz) {
@@ -570,22 +601,42 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
     const int i = c0 + ti;
     const bool valid = ti < nt;
     const double2 xi = valid ? tv.pts[i] : cmk(0, 0);
+    double2 qi[RB];
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr)
+      qi[rr] = (SYM && valid && r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + i] : cmk(0, 0);
     double2 acc[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk(0, 0);
     for (int e = e0; e < e1; ++e) {
       const int2 sr = rng[e];
-      for (int j0 = sr.x; j0 < sr.y; j0 += WAVE) {
-        const int cnt = min(WAVE, sr.y - j0);
+      for (int j0 = sr.x; j0 < sr.y; j0 += P2P_CS) {
+        const int cnt = min(P2P_CS, sr.y - j0);
         __syncthreads();
-        if (lane < cnt) {
-          s_x[lane] = tv.pts[j0 + lane];
+        for (int l = lane; l < cnt; l += WAVE) {
+          s_x[l] = tv.pts[j0 + l];
 #pragma unroll
           for (int rr = 0; rr < RB; ++rr)
-            s_q[rr][lane] = (r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + j0 + lane] : cmk(0, 0);
+            s_q[rr][l] = (r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + j0 + l] : cmk(0, 0);
         }
         __syncthreads();
-        if (valid) p2p_chunk<RB, M, LARGE>(sub, g, cnt, i - j0, xi, qk2, s_x, s_q, acc);
+        if (valid) p2p_chunk<RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, xi, qi, qk2, s_x, s_q, acc, s_acc);
+        if (SYM) {
+          // the chunk's sums of q_i H_ij go to u_j
+          __syncthreads();
+          for (int l = lane; l < cnt; l += WAVE) {
+#pragma unroll
+            for (int rr = 0; rr < RB; ++rr) {
+              if (r0 + rr < tv.nrhs) {
+                const double2 a = s_acc[rr][l];
+                const int64_t idx = (int64_t)(r0 + rr) * tv.n + j0 + l;
+                unsafeAtomicAdd(&us[idx].x, -0.25 * a.y);  // (i/4) a
+                unsafeAtomicAdd(&us[idx].y, 0.25 * a.x);
+              }
+              s_acc[rr][l] = cmk(0.0, 0.0);
+            }
+          }
+        }
       }
     }
 #pragma unroll
@@ -596,32 +647,31 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
       for (int rr = 0; rr < RB; ++rr)
         if (r0 + rr < tv.nrhs) {
           const int64_t idx = (int64_t)(r0 + rr) * tv.n + i;
-          const double2 v = cmk(-0.25 * acc[rr].y, 0.25 * acc[rr].x);  // (i/4) acc
-          if (atomic) {
-            unsafeAtomicAdd(&us[idx].x, v.x);
-            unsafeAtomicAdd(&us[idx].y, v.y);
-          } else {
-            us[idx] = cadd(us[idx], v);
-          }
+          unsafeAtomicAdd(&us[idx].x, -0.25 * acc[rr].y);  // (i/4) acc
+          unsafeAtomicAdd(&us[idx].y, 0.25 * acc[rr].x);
         }
   }
 }
 
 // One launch per series class (the host bounds every pair distance of an item
 // and sorts the items by class), so each kernel holds only its own
-// coefficients in scalar registers.
+// coefficients in scalar registers; sym[li] marks cross items.
 template <int RB, int CLS>
 __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const int* __restrict__ ptr, const int2* __restrict__ rng,
-                                              const int* __restrict__ atomic, const double2* __restrict__ qs,
+                                              const int* __restrict__ sym, const double2* __restrict__ qs,
                                               double2* __restrict__ us, int r0) {
-  __shared__ double2 s_x[WAVE];
-  __shared__ double2 s_q[RB][WAVE];
+  __shared__ double2 s_x[P2P_CS];
+  __shared__ double2 s_q[RB][P2P_CS];
+  __shared__ double2 s_acc[RB][P2P_CS];
   const int li = blockIdx.x;
   if (li >= nleaves) return;
   constexpr int M = kH0ClassTerms[CLS < kH0Classes ? CLS : kH0Classes - 1];
-  p2p_item<RB, M, (CLS >= kH0Classes)>(tv, leaves[li], ptr[li], ptr[li + 1], rng, atomic[li] != 0, qs, us, r0,
-                                        s_x, s_q);
+  constexpr bool LARGE = CLS >= kH0Classes;
+  if (sym[li])
+    p2p_item<RB, M, LARGE, true>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
+  else
+    p2p_item<RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
 }
 
 // ------------------------------------------------------------------ near-interface direct
@@ -954,20 +1004,20 @@ void launch_fill_zero(hipStream_t s, double2* p, int64_t n) {
 }
 template <int CLS>
 static void p2p_class(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr, const int2* rng,
-                      const int* atomic, const double2* qs, double2* us) {
+                      const int* sym, const double2* qs, double2* us) {
   if (nl <= 0) return;
   if (tv.nrhs == 1) {
-    hipLaunchKernelGGL((k_p2p<1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, 0);
+    hipLaunchKernelGGL((k_p2p<1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, 0);
     return;
   }
   for (int r0 = 0; r0 < tv.nrhs; r0 += 4)
-    hipLaunchKernelGGL((k_p2p<4, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, atomic, qs, us, r0);
+    hipLaunchKernelGGL((k_p2p<4, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, r0);
 }
 
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
-                const int2* rng, const int* atomic, const double2* qs, double2* us) {
+                const int2* rng, const int* sym, const double2* qs, double2* us) {
 #define HFMM_P2P(C)                                                                                       \
-  p2p_class<C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng, atomic + cls_ptr[C], \
+  p2p_class<C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng, sym + cls_ptr[C], \
                qs, us)
   HFMM_P2P(0); HFMM_P2P(1); HFMM_P2P(2); HFMM_P2P(3); HFMM_P2P(4); HFMM_P2P(5);
 #undef HFMM_P2P
