@@ -132,13 +132,21 @@ hfmm_status_t hfmm_apply(hfmm_plan_t plan, const double *q, double *u, int32_t n
 
 /*
  * w = A^H v, the conjugate transpose, and optionally the gradient of
- * Re <v, A q> with respect to the source coordinates.
- *   v        device complex [nrhs][n].
+ * Re <v, A q> with respect to the source coordinates (the vector-Jacobian
+ * product of u = A q for a real loss with dL/du = v in PyTorch's convention).
+ * The stages run transposed in reverse order; A^H v = conj(A^T conj(v)).
+ *   v        device complex [nrhs][n], user point order.
  *   w        device complex [nrhs][n], written.
  *   q        device complex [nrhs][n] or NULL (needed only for grad_xy).
  *   grad_xy  device [n][2] doubles or NULL: grad_xy[j] =
- *            sum_r Re( sum_i conj(v_ri) q_rj dA_ij/d(x_j, y_j) ), targets held
- *            fixed (the gradient of Re <v, A q> in the source positions).
+ *            sum_r Re( q_rj sum_i conj(v_ri) dA_ij/d(x_j, y_j) ), targets held
+ *            fixed; the free i = j term stays excluded. Far field by the
+ *            ladder relations of the cylindrical waves applied to the adjoint
+ *            multipole coefficients, direct pairs by H_1^(1), near-interface
+ *            pairs by the same Sommerfeld rule as the apply.
+ * Errors: HFMM_ERR_INVALID_ARG for NULL plan, v or w, nrhs < 1, or grad_xy
+ * without q; HFMM_ERR_NO_MEMORY / HFMM_ERR_DEVICE from the workspace or the
+ * launches. Buffers must not overlap.
  */
 hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t plan, const double *v, double *w, int32_t nrhs,
                                  const double *q, double *grad_xy, hfmm_stream_t stream);

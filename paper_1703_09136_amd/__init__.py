@@ -205,19 +205,30 @@ def _autograd():
     import torch
 
     class HFMMApply(torch.autograd.Function):
-        """u = A q with the hand-written adjoint as its backward (grad_q = A^H grad_u)."""
+        """u = A(points) q with the hand-written adjoint as its backward:
+        grad_q = A^H grad_u and, when ``points`` requires grad, the gradient in
+        the source coordinates (targets held fixed) from hfmm_apply_adjoint.
+        The plan's tree stays frozen; ``points`` is the tensor the plan was built
+        from (it only carries the autograd edge)."""
 
         @staticmethod
-        def forward(ctx, q, plan):
+        def forward(ctx, q, points, plan):
             ctx.plan = plan
+            ctx.save_for_backward(q)
             return plan.apply(q)
 
         @staticmethod
         def backward(ctx, g):
-            return ctx.plan.apply_adjoint(g.contiguous()), None
+            (q,) = ctx.saved_tensors
+            if ctx.needs_input_grad[1]:
+                w, gxy = ctx.plan.apply_adjoint(g.contiguous(), q=q.detach(), grad_xy=True)
+                return w, gxy, None
+            return ctx.plan.apply_adjoint(g.contiguous()), None, None
 
     return HFMMApply
 
 
-def hfmm_apply_autograd(q, plan):
-    return _autograd().apply(q, plan)
+def hfmm_apply_autograd(q, plan, points=None):
+    """u = plan.apply(q) differentiable in q and, if ``points`` (the plan's
+    points, [n][2] float64) requires grad, in the source coordinates."""
+    return _autograd().apply(q, points, plan)

@@ -55,6 +55,8 @@ struct DevBuf {
     if (count == 0) return hipSuccess;
     return hipMalloc((void**)&p, count * sizeof(T));
   }
+  // grow only: keeps the buffer when it already holds count elements
+  hipError_t ensure(size_t count) { return n >= count && p ? hipSuccess : alloc(count); }
   hipError_t upload(const std::vector<T>& v, hipStream_t s) {
     hipError_t e = alloc(v.size());
     if (e != hipSuccess || v.empty()) return e;
@@ -290,6 +292,7 @@ struct hfmm_plan_s {
   int nq = 0;
   int ws_nrhs = 0;
   DevBuf<double2> qs, us, alpha, beta;
+  DevBuf<double2> gq, gs;  // coordinate gradient: sorted q, per-point (d/dx, d/dy)
   hfmm_info_t info{};
   // stage timing
   bool prof_on = false;
@@ -324,7 +327,7 @@ struct hfmm_plan_s {
     cp_parent.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
-    qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release();
+    qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release(); gq.release(); gs.release();
   }
 };
 
@@ -1400,14 +1403,29 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
   if (!pl || !v || !w) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, v or w");
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   if (grad_xy && !q) return fail(HFMM_ERR_INVALID_ARG, "grad_xy requested without q");
-  if (grad_xy) return fail(HFMM_ERR_UNSUPPORTED, "coordinate gradients are not available in this build");
   hipStream_t s = (hipStream_t)stream_;
   hfmm_status_t st = ensure_workspace(pl, nrhs);
   if (st != HFMM_OK) return st;
+  if (grad_xy) {
+    HIP_TRY(pl->gq.ensure((size_t)pl->n * nrhs));
+    HIP_TRY(pl->gs.ensure((size_t)pl->n));
+  }
   // A^H v = conj(A^T conj(v))
   launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)v, pl->qs.p, 1);
   transpose_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p);
   launch_scatter(s, pl->n, nrhs, pl->perm.p, pl->us.p, (double2*)w, 1);
+  if (grad_xy) {
+    // g_j = Re(q_j sum_i conj(v_i) dA_ij/dx_j): the transposed pipeline has
+    // left the adjoint multipole coefficients in alpha and conj(v) in qs
+    TreeView tv = pl->view(nrhs);
+    launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)q, pl->gq.p, 0);
+    launch_l2p_grad(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, pl->alpha.p, pl->gq.p, pl->gs.p);
+    launch_p2p_grad(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, pl->qs.p,
+                    pl->gq.p, pl->gs.p);
+    launch_iface_grad(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p,
+                      pl->qky.p, pl->qkx.p, pl->qs.p, pl->gq.p, pl->gs.p);
+    launch_scatter_grad(s, pl->n, pl->perm.p, pl->gs.p, (double2*)grad_xy);
+  }
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }

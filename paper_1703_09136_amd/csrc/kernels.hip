@@ -674,6 +674,197 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
     p2p_item<RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
 }
 
+// ------------------------------------------------------------------ source-coordinate gradient
+// The gradient of L = Re sum_i conj(v_i) (A q)_i with respect to the source
+// coordinates x_j, targets held fixed: g_j = Re(q_j sum_i vs_i dA_ij/dx_j)
+// with vs = conj(v). The transposed pipeline has left alpha', the adjoint
+// multipole coefficients of every box, so at a leaf the far field seen by a
+// source is w_j = sum_p alpha'_p f_p(x_j), f_p = J_p(k rho) e^{-i p theta}.
+// The ladder relations of the cylindrical waves (from J_p' and
+// (p/x) J_p = (J_{p-1} + J_{p+1})/2) give
+//   d f_p/dx = (k/2)(f_{p-1} - f_{p+1}),  d f_p/dy = -(ik/2)(f_{p-1} + f_{p+1}),
+// so dw/dx = sum_m (k/2)(a_{m+1} - a_{m-1}) f_m and
+//    dw/dy = -(ik/2) sum_m (a_{m+1} + a_{m-1}) f_m,  m in [-P-1, P+1].
+// gs[j] = (sum_r Re(q_rj dw_r/dx), sum_r Re(q_rj dw_r/dy)), stored (first
+// writer); leaves without a local expansion store zero.
+__global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __restrict__ leaves, int nleaves, int rb,
+                                                   const double2* __restrict__ alpha, const double2* __restrict__ qs,
+                                                   double2* __restrict__ gs) {
+  extern __shared__ double2 lds_c[];  // [rb][2P + 5]: a_m at P + 2 + m, zero for |m| > P
+  const int li = blockIdx.x;
+  if (li >= nleaves) return;
+  const int b = leaves[li];
+  const int lane = threadIdx.x;
+  const int lev = tv.level[b];
+  const bool has_local = lev >= 2;
+  const int P = tv.P[lev], Pg = P + 1, S = 2 * P + 5;
+  const int2 pr = tv.prange[b];
+  const double2 c = tv.ctr[b];
+  const int64_t cb = tv.coff[b];
+  const double hk = 0.5 * tv.k;
+  int nstart = 0;
+  if (has_local) {
+    double rmax = 0.0;
+    for (int j = pr.x + lane; j < pr.y; j += WAVE) {
+      double2 p = tv.pts[j];
+      rmax = fmax(rmax, hypot(p.x - c.x, p.y - c.y));
+    }
+    for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
+    nstart = miller_start(tv.k * rmax, Pg);
+  }
+  for (int r0 = 0; r0 < tv.nrhs; r0 += rb) {
+    const int nr = min(rb, tv.nrhs - r0);
+    if (has_local) {
+      for (int e = lane; e < nr * S; e += WAVE) {
+        const int rr = e / S, m = e - rr * S - (P + 2);
+        lds_c[e] = (m >= -P && m <= P) ? alpha[(int64_t)(r0 + rr) * tv.ctot + cb + P + m] : cmk(0.0, 0.0);
+      }
+      __syncthreads();
+    }
+    for (int j = pr.x + lane; j < pr.y; j += WAVE) {
+      double sx = 0.0, sy = 0.0;
+      if (has_local) {
+        double2 gx[L2P_RB], gy[L2P_RB];
+#pragma unroll
+        for (int rr = 0; rr < L2P_RB; ++rr) gx[rr] = gy[rr] = cmk(0.0, 0.0);
+        const double2 p = tv.pts[j];
+        const double dx = p.x - c.x, dy = p.y - c.y;
+        const double rho = hypot(dx, dy);
+        const double x = fmax(tv.k * rho, 1e-100);
+        const double2 w = rho > 0 ? cmk(dx / rho, -dy / rho) : cmk(1, 0);  // e^{-i theta}
+        double sn, cs;
+        sincos((double)Pg * atan2(w.y, w.x), &sn, &cs);
+        double2 wn = cmk(cs, sn);  // w^Pg
+        double inv_s;
+        int nres;
+        miller_norm(x, nstart, inv_s, nres);
+        MillerWalk mw(x, nstart, inv_s, nres);
+        while (mw.n > Pg) mw.step();
+        for (int n = Pg; n >= 0; --n) {
+          const double jn = mw.value();
+          const double2 wc = cconj(wn);
+#pragma unroll
+          for (int rr = 0; rr < L2P_RB; ++rr) {
+            if (rr < nr) {
+              const double2* a = lds_c + rr * S + P + 2;
+              // ladder coefficients at +n and -n
+              const double2 dxp = cscale(csub(a[n + 1], a[n - 1]), hk);
+              const double2 syp = cadd(a[n + 1], a[n - 1]);
+              const double2 dyp = cmk(hk * syp.y, -hk * syp.x);  // -(ik/2) syp
+              double2 tx = cmul(dxp, wn), ty = cmul(dyp, wn);
+              if (n > 0) {
+                const double2 dxm = cscale(csub(a[-n + 1], a[-n - 1]), hk);
+                const double2 sym = cadd(a[-n + 1], a[-n - 1]);
+                const double2 dym = cmk(hk * sym.y, -hk * sym.x);
+                const double2 ux = cmul(dxm, wc), uy = cmul(dym, wc);
+                tx = (n & 1) ? csub(tx, ux) : cadd(tx, ux);
+                ty = (n & 1) ? csub(ty, uy) : cadd(ty, uy);
+              }
+              gx[rr] = cadd(gx[rr], cscale(tx, jn));
+              gy[rr] = cadd(gy[rr], cscale(ty, jn));
+            }
+          }
+          wn = cmul(wn, cconj(w));
+          if (n > 0) mw.step();
+        }
+#pragma unroll
+        for (int rr = 0; rr < L2P_RB; ++rr) {
+          if (rr < nr) {
+            const double2 q = qs[(int64_t)(r0 + rr) * tv.n + j];
+            sx += cmul(q, gx[rr]).x;
+            sy += cmul(q, gy[rr]).x;
+          }
+        }
+      }
+      if (r0 == 0)
+        gs[j] = cmk(sx, sy);
+      else
+        gs[j] = cadd(gs[j], cmk(sx, sy));
+    }
+    if (has_local) __syncthreads();
+  }
+}
+
+size_t l2p_grad_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * (2 * Pmax + 5)); }
+
+// Gradient of the free-space direct part, on the direct work items. With
+// g(r) = d/dr (i/4) H_0^(1)(k r) / r = -(i/4) k H_1^(1)(k r) / r, a pair (i, j)
+// adds Re(g sum_r vs_ri q_rj) (x_j - x_i) to the source j (summed in LDS per
+// staged chunk and flushed atomically) and, in a cross item, where the pair
+// stands for both orders, Re(g sum_r vs_rj q_ri) (x_i - x_j) to i.
+constexpr int GRAD_CS = 64;
+
+__global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __restrict__ leaves, int nitems,
+                                                   const int* __restrict__ ptr, const int2* __restrict__ rng,
+                                                   const int* __restrict__ sym, const double2* __restrict__ vs,
+                                                   const double2* __restrict__ qs, double2* __restrict__ gs) {
+  __shared__ double2 s_x[GRAD_CS];
+  __shared__ double2 s_g[GRAD_CS];
+  const int li = blockIdx.x;
+  if (li >= nitems) return;
+  const int b = leaves[li];
+  const bool both = sym[li] != 0;
+  const int lane = threadIdx.x;
+  const int2 pr = tv.prange[b];
+  const int nrhs = tv.nrhs;
+  for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
+    const int i = c0 + lane;
+    const bool valid = i < pr.y;
+    const double2 xi = valid ? tv.pts[i] : cmk(0, 0);
+    double gix = 0.0, giy = 0.0;
+    for (int e = ptr[li]; e < ptr[li + 1]; ++e) {
+      const int2 sr = rng[e];
+      for (int j0 = sr.x; j0 < sr.y; j0 += GRAD_CS) {
+        const int cnt = min(GRAD_CS, sr.y - j0);
+        __syncthreads();
+        if (lane < cnt) {
+          s_x[lane] = tv.pts[j0 + lane];
+          s_g[lane] = cmk(0.0, 0.0);
+        }
+        __syncthreads();
+        if (valid) {
+          const int rot = lane % cnt;
+          for (int t = 0; t < cnt; ++t) {
+            // lanes start at different sources: the LDS adds seldom collide
+            int jl = t + rot;
+            if (jl >= cnt) jl -= cnt;
+            const int j = j0 + jl;
+            if (j == i) continue;
+            const double2 xj = s_x[jl];
+            const double dx = xj.x - xi.x, dy = xj.y - xi.y;
+            const double r = sqrt(dx * dx + dy * dy);
+            const double2 h1 = hankel1(tv.k * r);
+            const double2 g = cmk(0.25 * tv.k * h1.y / r, -0.25 * tv.k * h1.x / r);  // -(i/4) k H1 / r
+            double2 cij = cmk(0.0, 0.0), cji = cmk(0.0, 0.0);
+            for (int rr = 0; rr < nrhs; ++rr) {
+              const int64_t o = (int64_t)rr * tv.n;
+              cij = cadd(cij, cmul(vs[o + i], qs[o + j]));
+              if (both) cji = cadd(cji, cmul(vs[o + j], qs[o + i]));
+            }
+            const double sj = cmul(g, cij).x;
+            atomicAdd(&s_g[jl].x, sj * dx);
+            atomicAdd(&s_g[jl].y, sj * dy);
+            if (both) {
+              const double si = cmul(g, cji).x;
+              gix -= si * dx;
+              giy -= si * dy;
+            }
+          }
+        }
+        __syncthreads();
+        if (lane < cnt) {
+          unsafeAtomicAdd(&gs[j0 + lane].x, s_g[lane].x);
+          unsafeAtomicAdd(&gs[j0 + lane].y, s_g[lane].y);
+        }
+      }
+    }
+    if (valid && both) {
+      unsafeAtomicAdd(&gs[i].x, gix);
+      unsafeAtomicAdd(&gs[i].y, giy);
+    }
+  }
+}
+
 // ------------------------------------------------------------------ near-interface direct
 // u_i += sum_j q_j G^s(x_i, x_j) for image pairs that are not admissible, with
 // G^s = sum_q c_q exp(ky_q (y_i + y_j) + kx_q (x_i - x_j)) the Sommerfeld
@@ -730,6 +921,76 @@ __global__ void __launch_bounds__(WAVE) k_iface(TreeView tv, const int* __restri
       }
     }
   }
+}
+
+// Gradient of the near-interface part. The rule's nodes come in pairs
+// (kx, -kx) with equal weights, so G^s(x_i, x_j) = G^s(x_j, x_i) node by node
+// and the derivative of sum_j vs_j G^s(x_j, x_i) with respect to the source x_i
+// weights each node term by kx (x) or ky (y). Added into gs[i] as
+// sum_r Re(q_ri d(...)/dx_i); one block per leaf owns its points.
+__global__ void __launch_bounds__(WAVE) k_iface_grad(TreeView tv, const int* __restrict__ leaves, int nleaves,
+                                                     const int* __restrict__ ptr, const int2* __restrict__ rng,
+                                                     int nq, const double2* __restrict__ qc,
+                                                     const double2* __restrict__ qky, const double2* __restrict__ qkx,
+                                                     const double2* __restrict__ vs, const double2* __restrict__ qs,
+                                                     double2* __restrict__ gs) {
+  __shared__ double2 s_c[WAVE], s_ky[WAVE], s_kx[WAVE];
+  int li = blockIdx.x;
+  if (li >= nleaves) return;
+  int b = leaves[li];
+  int lane = threadIdx.x;
+  int2 pr = tv.prange[b];
+  double xref = tv.ctr[b].x;
+  for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
+    int i = c0 + lane;
+    bool valid = i < pr.y;
+    double2 xi = valid ? tv.pts[i] : cmk(0, 0);
+    double sx = 0.0, sy = 0.0;
+    for (int r = 0; r < tv.nrhs; ++r) {
+      double2 ax = cmk(0, 0), ay = cmk(0, 0);
+      for (int e = ptr[li]; e < ptr[li + 1]; ++e) {
+        int2 sr = rng[e];
+        for (int q0 = 0; q0 < nq; q0 += WAVE) {
+          int q = q0 + lane;
+          double2 sq = cmk(0, 0), ky = cmk(0, 0), kx = cmk(0, 0), cq = cmk(0, 0);
+          if (q < nq) {
+            ky = qky[q]; kx = qkx[q]; cq = qc[q];
+            for (int j = sr.x; j < sr.y; ++j) {
+              double2 xj = tv.pts[j];
+              double2 ex = cadd(cscale(ky, xj.y), cscale(kx, -(xj.x - xref)));
+              sq = cadd(sq, cmul(vs[(int64_t)r * tv.n + j], cexp2(ex)));
+            }
+          }
+          __syncthreads();
+          s_c[lane] = cmul(cq, sq);
+          s_ky[lane] = ky;
+          s_kx[lane] = kx;
+          __syncthreads();
+          int qn = min(WAVE, nq - q0);
+          if (valid)
+            for (int qq = 0; qq < qn; ++qq) {
+              double2 ex = cadd(cscale(s_ky[qq], xi.y), cscale(s_kx[qq], xi.x - xref));
+              double2 t = cmul(s_c[qq], cexp2(ex));
+              ax = cadd(ax, cmul(s_kx[qq], t));
+              ay = cadd(ay, cmul(s_ky[qq], t));
+            }
+        }
+      }
+      if (valid) {
+        const double2 q = qs[(int64_t)r * tv.n + i];
+        sx += cmul(q, ax).x;
+        sy += cmul(q, ay).x;
+      }
+    }
+    if (valid) gs[i] = cadd(gs[i], cmk(sx, sy));
+  }
+}
+
+__global__ void k_scatter_grad(int n, const int* __restrict__ perm, const double2* __restrict__ gs,
+                               double2* __restrict__ grad) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  grad[perm[i]] = gs[i];
 }
 
 // ------------------------------------------------------------------ tables
@@ -1041,6 +1302,30 @@ void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const doub
   if (!ncombo) return;
   ImageTableArgs a{med, ncombo, X, Y, dip, send, pbeg, panels, refs, glx, glw, tdata};
   hipLaunchKernelGGL(k_table_image, dim3(ncombo), dim3(TB_THREADS), 0, s, a);
+}
+
+
+void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* alpha,
+                     const double2* qs, double2* gs) {
+  if (nl <= 0) return;
+  const int rb = min(L2P_RB, tv.nrhs);
+  hipLaunchKernelGGL(k_l2p_grad, dim3(nl), dim3(WAVE), l2p_grad_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, alpha,
+                     qs, gs);
+}
+void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
+                     const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs) {
+  if (nitems <= 0) return;
+  hipLaunchKernelGGL(k_p2p_grad, dim3(nitems), dim3(WAVE), 0, s, tv, items, nitems, ptr, rng, sym, vs, qs, gs);
+}
+void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
+                       int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,
+                       const double2* qs, double2* gs) {
+  if (nl <= 0 || nq <= 0) return;
+  hipLaunchKernelGGL(k_iface_grad, dim3(nl), dim3(WAVE), 0, s, tv, leaves, nl, ptr, rng, nq, qc, qky, qkx, vs, qs,
+                     gs);
+}
+void launch_scatter_grad(hipStream_t s, int n, const int* perm, const double2* gs, double2* grad) {
+  hipLaunchKernelGGL(k_scatter_grad, dim3(blocks(n, 256)), dim3(256), 0, s, n, perm, gs, grad);
 }
 
 }  // namespace hfmm

@@ -45,4 +45,16 @@ void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const doub
                         const double* dip, const double* send, const int* pbeg, const Panel* panels,
                         const TableRef* refs, const double* glx, const double* glw, double2* tdata);
 
+// Source-coordinate gradient (see kernels.hip): far field from the adjoint
+// multipole coefficients (stores gs), then the direct and near-interface
+// parts (add into gs), then gs to the caller's order as [n][2] doubles.
+void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* alpha,
+                     const double2* qs, double2* gs);
+void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
+                     const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs);
+void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
+                       int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,
+                       const double2* qs, double2* gs);
+void launch_scatter_grad(hipStream_t s, int n, const int* perm, const double2* gs, double2* grad);
+
 }  // namespace hfmm

@@ -15,6 +15,7 @@
 
 #include "common.hpp"
 #include "h0_cheb.hpp"
+#include "h1_cheb.hpp"
 
 namespace hfmm {
 
@@ -250,6 +251,68 @@ __device__ inline void hankel0_x4(const double z[4], double2 h[4]) {
     }
   }
 }
+
+// H_1^(1)(x) = J_1 + i Y_1 for x > 0 (coordinate gradients of the direct
+// part: d/dr H_0^(1)(k r) = -k H_1^(1)(k r)). For x <= 6 the ascending series
+// (A&S 9.1.10, 9.1.11) in z = x^2/4:
+//   J_1 = (x/2) sum_m a_m z^m,  a_m = (-1)^m / (m! (m+1)!),
+//   Y_1 = (2/pi)(ln(x/2) + gamma) J_1 - 2/(pi x) - (x/(2 pi)) sum_m b_m z^m,
+//   b_m = (H_m + H_{m+1}) a_m (harmonic numbers),
+// 21 terms (first dropped term below 2^-56 at z = 9); beyond, the
+// modulus-phase form sqrt(2/(pi x)) F(1/x) e^{i(x - 3 pi/4)} with F from
+// h1_cheb.hpp.
+struct H1Series {
+  double a[kSeriesTerms];
+  double b[kSeriesTerms];
+  constexpr H1Series() : a(), b() {
+    double am = 1.0, hm = 0.0;  // a_0 = 1, H_0 = 0
+    for (int m = 0; m < kSeriesTerms; ++m) {
+      if (m > 0) {
+        am = am * (-1.0 / ((double)m * (double)(m + 1)));
+        hm += 1.0 / (double)m;
+      }
+      a[m] = am;
+      b[m] = (2.0 * hm + 1.0 / (double)(m + 1)) * am;  // (H_m + H_{m+1}) a_m
+    }
+  }
+};
+constexpr H1Series kH1{};
+
+__host__ __device__ inline double2 hankel1_large(double x) {
+  const double t = 2.0 * kH1ChebX0 / x - 1.0;
+  const double t2 = 2.0 * t;
+  double br1 = 0.0, br2 = 0.0, bi1 = 0.0, bi2 = 0.0;
+#pragma unroll
+  for (int k = kH1ChebN - 1; k >= 1; --k) {
+    double br = fma(t2, br1, kH1ChebRe[k] - br2);
+    double bi = fma(t2, bi1, kH1ChebIm[k] - bi2);
+    br2 = br1; br1 = br;
+    bi2 = bi1; bi1 = bi;
+  }
+  double fr = fma(t, br1, kH1ChebRe[0] - br2);
+  double fi = fma(t, bi1, kH1ChebIm[0] - bi2);
+  double s, c;
+  sincos(x - 2.35619449019234492885, &s, &c);
+  double a = sqrt(0.63661977236758134308 / x);
+  return cmk(a * (fr * c - fi * s), a * (fr * s + fi * c));
+}
+
+__host__ __device__ inline double2 hankel1_series(double x) {
+  const double z = 0.25 * x * x;
+  double sa = kH1.a[20], sb = kH1.b[20];
+#pragma unroll
+  for (int m = 19; m >= 0; --m) {
+    sa = fma(sa, z, kH1.a[m]);
+    sb = fma(sb, z, kH1.b[m]);
+  }
+  const double j1 = 0.5 * x * sa;
+  const double two_over_pi = 0.63661977236758134308;
+  const double euler = 0.57721566490153286061;
+  const double y1 = two_over_pi * ((0.5 * log(z) + euler) * j1 - 1.0 / x) - (0.5 / 3.14159265358979323846) * x * sb;
+  return cmk(j1, y1);
+}
+
+__host__ __device__ inline double2 hankel1(double x) { return x <= 6.0 ? hankel1_series(x) : hankel1_large(x); }
 
 // Series classes of the pair loops: terms and the largest z each covers.
 constexpr int kH0Classes = 5;

@@ -321,3 +321,56 @@ def test_planted_mistake_in_sigma_breaks_continuity():
     u2 = oracle.layer_field(m, 2, x, 0.0, x0, y0)[0]
     assert abs(true_u1 - u2) < 1e-11 * abs(u2)
     assert abs(wrong_u1 - u2) > 1e-4 * abs(u2)
+
+
+# ---------------------------------------------------------------- gradient
+def _loss_moved_source(media, xy, q, v, j, axis, h):
+    """Re <v, A(targets fixed, source j moved by h along axis) q>."""
+    xs = xy[:, 0].copy()
+    ys = media.to_frame(xy[:, 1]).copy()
+    xt, yt = xs.copy(), ys.copy()
+    if axis == 0:
+        xs[j] += h
+    else:
+        ys[j] += h
+    u = oracle.free_matvec(media.k1, xt, yt, xs, ys, q, target_ids=np.arange(xs.size), workers=1)
+    u = u + oracle.scattered_matvec(media, xt, yt, xs, ys, q, workers=1)
+    return float(np.real(np.vdot(v, u)))
+
+
+@pytest.mark.parametrize("k,ifs", [((8 * np.pi, 12 * np.pi), (0.0,)),
+                                   ((2 * np.pi * 8, 2 * np.pi * 12, 2 * np.pi * 10), (0.5, 0.0))])
+def test_source_gradient_matches_central_differences(k, ifs):
+    """The analytic source gradient against central differences of the matvec
+    itself (targets fixed), free and scattered parts together."""
+    media = Media(k, ifs)
+    rng = np.random.default_rng([1703, 9136, 71])
+    n = 24
+    xy = np.column_stack([rng.uniform(0, 0.6, n), ifs[0] + rng.uniform(0.02, 0.4, n)])
+    q = rng.normal(size=n) + 1j * rng.normal(size=n)
+    v = rng.normal(size=n) + 1j * rng.normal(size=n)
+    g = oracle.source_gradient(media, xy, q, v)
+    h = 1e-6
+    for j, axis in [(0, 0), (3, 1), (7, 0), (11, 1), (19, 0), (23, 1)]:
+        fd = (_loss_moved_source(media, xy, q, v, j, axis, h) -
+              _loss_moved_source(media, xy, q, v, j, axis, -h)) / (2 * h)
+        assert abs(fd - g[j, axis]) <= 2e-6 * max(1.0, abs(fd)), (j, axis, fd, g[j, axis])
+
+
+def test_planted_sign_error_in_scattered_gradient_is_caught():
+    """A sign error in the scattered part of the gradient must show against
+    central differences."""
+    from oracle import gradient as og
+    media = Media((8 * np.pi, 12 * np.pi), (0.0,))
+    rng = np.random.default_rng([1703, 9136, 72])
+    n = 16
+    xy = np.column_stack([rng.uniform(0, 0.5, n), rng.uniform(0.02, 0.3, n)])
+    q = rng.normal(size=n) + 1j * rng.normal(size=n)
+    v = rng.normal(size=n) + 1j * rng.normal(size=n)
+    y = media.to_frame(xy[:, 1])
+    bad = og.free_source_gradient(media.k1, xy[:, 0], y, q, v) - og.scattered_source_gradient(media, xy[:, 0], y, q, v)
+    good = oracle.source_gradient(media, xy, q, v)
+    j, h = 5, 1e-6
+    fd = (_loss_moved_source(media, xy, q, v, j, 1, h) - _loss_moved_source(media, xy, q, v, j, 1, -h)) / (2 * h)
+    assert abs(fd - good[j, 1]) <= 2e-6 * max(1.0, abs(fd))
+    assert abs(fd - bad[j, 1]) > 1e-3 * max(1.0, abs(fd))
