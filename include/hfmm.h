@@ -56,12 +56,17 @@ typedef enum {
 } hfmm_status_t;
 
 enum { HFMM_SELF_SCATTERED = 0, HFMM_SELF_NONE = 1 };
-enum { HFMM_FP64 = 0 };
+/* Arithmetic of the hot stages. HFMM_FP64: everything in double precision.
+ * HFMM_FP32 (mixed): the free-space direct pairs (H0 series, logarithm,
+ * per-item sums) run in single precision, pair differences rounded from FP64;
+ * tables, expansions, translations and the accumulation of u stay FP64. The
+ * result then carries about 1e-7 relative error on top of the tolerance. */
+enum { HFMM_FP64 = 0, HFMM_FP32 = 1 };
 
 typedef struct {
   int32_t struct_size;      /* sizeof(hfmm_options_t) */
   int32_t leaf_size;        /* max points per leaf box; default 64 */
-  int32_t precision;        /* HFMM_FP64 */
+  int32_t precision;        /* HFMM_FP64 (default) or HFMM_FP32 */
   int32_t self_term;        /* HFMM_SELF_SCATTERED (default) or HFMM_SELF_NONE */
   int32_t interface_refine; /* 1 (default): refine boxes touching the bottom
                                row until every image pair is admissible;

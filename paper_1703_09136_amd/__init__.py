@@ -8,9 +8,9 @@ to another implementation.
 Entry points mirror the C interface (include/hfmm.h):
   Plan(k, interfaces, points, tol, ...)   -> hfmm_plan
   Plan.apply(q)                           -> hfmm_apply          (u = A q)
-  Plan.apply_adjoint(v)                   -> hfmm_apply_adjoint  (w = A^H v)
+  Plan.apply_adjoint(v, q, grad_xy)       -> hfmm_apply_adjoint  (w = A^H v, source-coordinate gradient)
   Plan.info()                             -> hfmm_plan_info
-  HFMMApply.apply(q, plan)                -> autograd: forward A q, backward A^H g
+  hfmm_apply_autograd(q, plan, points)    -> autograd: forward A q, backward A^H g and d/d points
 """
 from __future__ import annotations
 
@@ -29,6 +29,7 @@ EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoin
            "hfmm_profile_enable", "hfmm_profile_read", "hfmm_stage_name",
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message")
 NSTAGES = 9
+HFMM_FP64, HFMM_FP32 = 0, 1
 
 
 class Options(ctypes.Structure):

@@ -36,6 +36,21 @@ __host__ __device__ inline double2 cexp2(double2 a) {
   return cmk(e * c, e * s);
 }
 __host__ __device__ inline double2 clog2(double2 a) { return cmk(log(cabs2(a)), atan2(a.y, a.x)); }
+// Integer literals mean double precision.
+__host__ __device__ inline double2 cmk(int r, int i) { return make_double2(r, i); }
+// The same for single precision (float2), used by the FP32 near field.
+__host__ __device__ inline float2 cmk(float r, float i) { return make_float2(r, i); }
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// complex type of a real type
+template <typename T> struct cplx_of;
+template <> struct cplx_of<double> { using type = double2; };
+template <> struct cplx_of<float> { using type = float2; };
+template <typename T> using cplx_t = typename cplx_of<T>::type;
+template <typename T> __host__ __device__ inline cplx_t<T> to_cplx(double2 v) { return cmk((T)v.x, (T)v.y); }
+
 // Principal square root (Re >= 0); the sign of a zero imaginary part is kept.
 __host__ __device__ inline double2 csqrt2(double2 a) {
   double r = cabs2(a);

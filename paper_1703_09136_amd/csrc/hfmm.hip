@@ -253,6 +253,7 @@ struct hfmm_plan_s {
   DevBuf<int2> prange;
   DevBuf<int64_t> coff;
   DevBuf<int> leaves;  // leaf boxes, ascending level
+  int precision = HFMM_FP64;  // HFMM_FP64 or HFMM_FP32 (near field in single precision)
   int nleaves = 0;
   std::vector<int> leaf_lev;  // leaves of level l: [leaf_lev[l], leaf_lev[l + 1])
   int leaf_pmax = 0;          // largest expansion order among the leaves
@@ -439,7 +440,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     o = *opts;
   }
   if (o.leaf_size < 1 || o.leaf_size > 4096) return fail(HFMM_ERR_INVALID_ARG, "leaf_size out of range");
-  if (o.precision != HFMM_FP64) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_FP64 is available");
+  if (o.precision != HFMM_FP64 && o.precision != HFMM_FP32)
+    return fail(HFMM_ERR_UNSUPPORTED, "precision must be HFMM_FP64 or HFMM_FP32");
   if (o.self_term != HFMM_SELF_SCATTERED) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_SELF_SCATTERED is available");
   if (o.max_level < 2 || o.max_level > KEY_BITS) return fail(HFMM_ERR_INVALID_ARG, "max_level out of range");
   if (!(o.leaf_kb == 0.0 || (o.leaf_kb >= 0.25 && std::isfinite(o.leaf_kb))))
@@ -461,6 +463,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     delete pl;
     return s;
   };
+  pl->precision = o.precision;
   pl->n = (int)n;
   pl->tol = tol;
   pl->opt = o;
@@ -1311,7 +1314,8 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
   mark();
   launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25));
   mark();
-  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, qs, us);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, qs, us,
+             pl->precision == HFMM_FP32);
   mark();
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, qs, us);
@@ -1333,7 +1337,8 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
   launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
   // the direct parts are symmetric
-  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, vs, ws);
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, vs, ws,
+             pl->precision == HFMM_FP32);
   launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
                pl->qkx.p, vs, ws);
 }

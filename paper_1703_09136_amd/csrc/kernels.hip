@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
         if (rr < nr) s_q[rr * WAVE + lane] = valid ? qs[(int64_t)(r0 + rr) * tv.n + j] : cmk(0.0, 0.0);
       const double rho = hypot(dx, dy);
       const double x = fmax(tv.k * rho, 1e-100);
-      const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1, 0);
+      const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1.0, 0.0);
       double sn, cs;
       sincos((double)P * atan2(w.y, w.x), &sn, &cs);
       double2 wn = cmk(cs, sn);  // w^P
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
         const double dx = p.x - c.x, dy = p.y - c.y;
         const double rho = hypot(dx, dy);
         const double x = fmax(tv.k * rho, 1e-100);
-        const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1, 0);
+        const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1.0, 0.0);
         double sn, cs;
         sincos((double)P * atan2(w.y, w.x), &sn, &cs);
         double2 wn = cmk(cs, sn);  // w^P
@@ -520,18 +520,28 @@ __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
 // One staged chunk for one lane: the sources of residue class sub mod g in
 // [0, cnt), four per step; jself is the target's own index within the chunk
 // (self items). z = (k r / 2)^2; dropped terms get a harmless z = 1 and
-// weight 0.
+// weight 0. T is the arithmetic precision (pair differences are taken in
+// FP64 and then rounded).
 constexpr int P2P_CS = 128;  // sources per staged chunk
 
-template <int RB, int M, bool LARGE, bool SYM>
-__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, double2 xi, const double2* qi,
-                                 double qk2, const double2* s_x, const double2 (*s_q)[P2P_CS], double2 acc[RB],
-                                 double2 (*s_acc)[P2P_CS]) {
+// In a cross item the reverse sums q_i H_ij go to s_acc[j]: at one step the
+// lanes of a residue class hold distinct rotations, so when every class has
+// at least as many sources as the chunk has targets (own == true) no two
+// lanes touch one entry in one instruction and a plain read-add-write is
+// exact (the wave's LDS operations execute in order). FP32 takes that path
+// (its LDS atomic adds measured far slower); FP64 keeps the no-return atomic
+// adds, which do not wait for the LDS and measured faster there.
+template <typename T, int RB, int M, bool LARGE, bool SYM>
+__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, bool own, double2 xi,
+                                 const cplx_t<T>* qi, T qk2, const double2* s_x, const cplx_t<T> (*s_q)[P2P_CS],
+                                 cplx_t<T> acc[RB], cplx_t<T> (*s_acc)[P2P_CS]) {
+  using C = cplx_t<T>;
   const int K = (cnt - sub + g - 1) / g;  // sources of this lane's class
   const int r0 = K > 0 ? rot % K : 0;
   for (int k0 = 0; k0 < K; k0 += 4) {
     // loads first (clamped index, no branches), then the arithmetic
-    double2 xj[4], qv[4][RB];
+    double2 xj[4];
+    C qv[4][RB];
     bool use[4];
     int jc[4];
 #pragma unroll
@@ -546,27 +556,31 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, do
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) qv[u][rr] = s_q[rr][jc[u]];
     }
-    double z[4];
+    T z[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double dx = xi.x - xj[u].x, dy = xi.y - xj[u].y;
-      const double zz = qk2 * (dx * dx + dy * dy);
-      z[u] = use[u] ? zz : 1.0;
+      const T dx = (T)(xi.x - xj[u].x), dy = (T)(xi.y - xj[u].y);
+      const T zz = qk2 * (dx * dx + dy * dy);
+      z[u] = use[u] ? zz : (T)1.0;
     }
-    double2 h[4];
-    hankel0_x4<M, LARGE>(z, h);
+    T hr[4], hi[4];
+    hankel0_x4<T, M, LARGE>(z, hr, hi);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double w = use[u] ? 1.0 : 0.0;
-      const double2 hw = cmk(h[u].x * w, h[u].y * w);
+      const T w = use[u] ? (T)1.0 : (T)0.0;
+      const C hw = cmk(hr[u] * w, hi[u] * w);
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(hw, qv[u][rr]));
       if (SYM && use[u]) {
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
-          const double2 t = cmul(hw, qi[rr]);
-          atomicAdd(&s_acc[rr][jc[u]].x, t.x);
-          atomicAdd(&s_acc[rr][jc[u]].y, t.y);
+          const C t = cmul(hw, qi[rr]);
+          if (sizeof(T) == 4 && own) {
+            s_acc[rr][jc[u]] = cadd(s_acc[rr][jc[u]], t);
+          } else {
+            atomicAdd(&s_acc[rr][jc[u]].x, t.x);
+            atomicAdd(&s_acc[rr][jc[u]].y, t.y);
+          }
         }
       }
     }
@@ -574,17 +588,19 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, do
 }
 
 // One work item: the target leaf b against source ranges [e0, e1) of rng.
-template <int RB, int M, bool LARGE, bool SYM>
+// Sums run in T; each item adds its (i/4) sums into the FP64 output.
+template <typename T, int RB, int M, bool LARGE, bool SYM>
 __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const int2* __restrict__ rng,
                                 const double2* __restrict__ qs, double2* __restrict__ us, int r0, double2* s_x,
-                                double2 (*s_q)[P2P_CS], double2 (*s_acc)[P2P_CS]) {
+                                cplx_t<T> (*s_q)[P2P_CS], cplx_t<T> (*s_acc)[P2P_CS]) {
+  using C = cplx_t<T>;
   const int lane = threadIdx.x;
   const int2 pr = tv.prange[b];
-  const double qk2 = 0.25 * tv.k * tv.k;
+  const T qk2 = (T)(0.25 * tv.k * tv.k);
   if (SYM) {
     for (int l = lane; l < P2P_CS; l += WAVE)
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) s_acc[rr][l] = cmk(0.0, 0.0);
+      for (int rr = 0; rr < RB; ++rr) s_acc[rr][l] = cmk((T)0, (T)0);
   }
   // targets in chunks of 32 (two lanes per target), the remainder in a chunk of
   // the next power of two with more lanes per target
@@ -600,14 +616,14 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
     const int ti = lane / g, sub = lane % g;
     const int i = c0 + ti;
     const bool valid = ti < nt;
-    const double2 xi = valid ? tv.pts[i] : cmk(0, 0);
-    double2 qi[RB];
+    const double2 xi = valid ? tv.pts[i] : cmk(0.0, 0.0);
+    C qi[RB];
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr)
-      qi[rr] = (SYM && valid && r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + i] : cmk(0, 0);
-    double2 acc[RB];
+      qi[rr] = (SYM && valid && r0 + rr < tv.nrhs) ? to_cplx<T>(qs[(int64_t)(r0 + rr) * tv.n + i]) : cmk((T)0, (T)0);
+    C acc[RB];
 #pragma unroll
-    for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk(0, 0);
+    for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk((T)0, (T)0);
     for (int e = e0; e < e1; ++e) {
       const int2 sr = rng[e];
       for (int j0 = sr.x; j0 < sr.y; j0 += P2P_CS) {
@@ -617,10 +633,13 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
           s_x[l] = tv.pts[j0 + l];
 #pragma unroll
           for (int rr = 0; rr < RB; ++rr)
-            s_q[rr][l] = (r0 + rr < tv.nrhs) ? qs[(int64_t)(r0 + rr) * tv.n + j0 + l] : cmk(0, 0);
+            s_q[rr][l] = (r0 + rr < tv.nrhs) ? to_cplx<T>(qs[(int64_t)(r0 + rr) * tv.n + j0 + l]) : cmk((T)0, (T)0);
         }
         __syncthreads();
-        if (valid) p2p_chunk<RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, xi, qi, qk2, s_x, s_q, acc, s_acc);
+        const bool own = nt <= cnt / g;  // every class holds >= nt sources
+        if (valid)
+          p2p_chunk<T, RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, own, xi, qi, qk2, s_x, s_q, acc,
+                                          s_acc);
         if (SYM) {
           // the chunk's sums of q_i H_ij go to u_j
           __syncthreads();
@@ -628,12 +647,12 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
               if (r0 + rr < tv.nrhs) {
-                const double2 a = s_acc[rr][l];
+                const C a = s_acc[rr][l];
                 const int64_t idx = (int64_t)(r0 + rr) * tv.n + j0 + l;
-                unsafeAtomicAdd(&us[idx].x, -0.25 * a.y);  // (i/4) a
-                unsafeAtomicAdd(&us[idx].y, 0.25 * a.x);
+                unsafeAtomicAdd(&us[idx].x, -0.25 * (double)a.y);  // (i/4) a
+                unsafeAtomicAdd(&us[idx].y, 0.25 * (double)a.x);
               }
-              s_acc[rr][l] = cmk(0.0, 0.0);
+              s_acc[rr][l] = cmk((T)0, (T)0);
             }
           }
         }
@@ -641,14 +660,17 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
     }
 #pragma unroll
     for (int rr = 0; rr < RB; ++rr)
-      for (int m = 1; m < g; m <<= 1) acc[rr] = cadd(acc[rr], shfl_xor_c(acc[rr], m));
+      for (int m = 1; m < g; m <<= 1) {
+        acc[rr].x += __shfl_xor(acc[rr].x, m, WAVE);
+        acc[rr].y += __shfl_xor(acc[rr].y, m, WAVE);
+      }
     if (valid && sub == 0)
 #pragma unroll
       for (int rr = 0; rr < RB; ++rr)
         if (r0 + rr < tv.nrhs) {
           const int64_t idx = (int64_t)(r0 + rr) * tv.n + i;
-          unsafeAtomicAdd(&us[idx].x, -0.25 * acc[rr].y);  // (i/4) acc
-          unsafeAtomicAdd(&us[idx].y, 0.25 * acc[rr].x);
+          unsafeAtomicAdd(&us[idx].x, -0.25 * (double)acc[rr].y);  // (i/4) acc
+          unsafeAtomicAdd(&us[idx].y, 0.25 * (double)acc[rr].x);
         }
   }
 }
@@ -656,22 +678,24 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
 // One launch per series class (the host bounds every pair distance of an item
 // and sorts the items by class), so each kernel holds only its own
 // coefficients in scalar registers; sym[li] marks cross items.
-template <int RB, int CLS>
+template <typename T, int RB, int CLS>
 __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const int* __restrict__ ptr, const int2* __restrict__ rng,
                                               const int* __restrict__ sym, const double2* __restrict__ qs,
                                               double2* __restrict__ us, int r0) {
+  using C = cplx_t<T>;
   __shared__ double2 s_x[P2P_CS];
-  __shared__ double2 s_q[RB][P2P_CS];
-  __shared__ double2 s_acc[RB][P2P_CS];
+  __shared__ C s_q[RB][P2P_CS];
+  __shared__ C s_acc[RB][P2P_CS];
   const int li = blockIdx.x;
   if (li >= nleaves) return;
-  constexpr int M = kH0ClassTerms[CLS < kH0Classes ? CLS : kH0Classes - 1];
+  constexpr int CL = CLS < kH0Classes ? CLS : kH0Classes - 1;
+  constexpr int M = sizeof(T) == 8 ? kH0ClassTerms[CL] : kH0ClassTermsF32[CL];
   constexpr bool LARGE = CLS >= kH0Classes;
   if (sym[li])
-    p2p_item<RB, M, LARGE, true>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
+    p2p_item<T, RB, M, LARGE, true>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
   else
-    p2p_item<RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
+    p2p_item<T, RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
 }
 
 // ------------------------------------------------------------------ source-coordinate gradient
@@ -1263,23 +1287,27 @@ void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, 
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fill_zero, dim3(blocks(n, 256)), dim3(256), 0, s, p, n);
 }
-template <int CLS>
+template <typename T, int CLS>
 static void p2p_class(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr, const int2* rng,
                       const int* sym, const double2* qs, double2* us) {
   if (nl <= 0) return;
   if (tv.nrhs == 1) {
-    hipLaunchKernelGGL((k_p2p<1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, 0);
+    hipLaunchKernelGGL((k_p2p<T, 1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, 0);
     return;
   }
   for (int r0 = 0; r0 < tv.nrhs; r0 += 4)
-    hipLaunchKernelGGL((k_p2p<4, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, r0);
+    hipLaunchKernelGGL((k_p2p<T, 4, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, r0);
 }
 
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
-                const int2* rng, const int* sym, const double2* qs, double2* us) {
-#define HFMM_P2P(C)                                                                                       \
-  p2p_class<C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng, sym + cls_ptr[C], \
-               qs, us)
+                const int2* rng, const int* sym, const double2* qs, double2* us, int fp32) {
+#define HFMM_P2P(C)                                                                                             \
+  if (fp32)                                                                                                     \
+    p2p_class<float, C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng,       \
+                        sym + cls_ptr[C], qs, us);                                                             \
+  else                                                                                                          \
+    p2p_class<double, C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng,      \
+                         sym + cls_ptr[C], qs, us)
   HFMM_P2P(0); HFMM_P2P(1); HFMM_P2P(2); HFMM_P2P(3); HFMM_P2P(4); HFMM_P2P(5);
 #undef HFMM_P2P
   static_assert(kH0Classes == 5, "one launch per class and one for the large-argument class");

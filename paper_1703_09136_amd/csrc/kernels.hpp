@@ -32,9 +32,9 @@ void launch_fill_zero(hipStream_t s, double2* p, int64_t n);
 // the longest series with the large-argument form for x > 6. cls_ptr is a
 // host array of kH0Classes + 2 entries. sym[i] marks a cross item whose pairs
 // are evaluated once and added to both points; the output is accumulated
-// atomically.
+// atomically. fp32: pair arithmetic and per-item sums in single precision.
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
-                const int2* rng, const int* sym, const double2* qs, double2* us);
+                const int2* rng, const int* sym, const double2* qs, double2* us, int fp32);
 void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                   int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* qs, double2* us);
 void launch_table_hankel(hipStream_t s, int ntab, const double* dx, const double* dy, const TableRef* refs, double k,

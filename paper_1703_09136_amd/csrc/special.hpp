@@ -224,30 +224,72 @@ __device__ inline double fma_uniform(double a, double b, double c) {
   return r;
 }
 
-template <int M, bool LARGE>
-__device__ inline void hankel0_x4(const double z[4], double2 h[4]) {
-  double j[4], s[4];
+// The same in FP32 (near field of the mixed-precision plans): one VOP3 FMA
+// with the coefficient in a scalar register, and ln z by the reduction above
+// with five atanh terms (relative remainder below 2^-26).
+__device__ inline float fma_uniform(float a, float b, float c) {
+  float r;
+  asm("v_fma_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
+__device__ inline float log_pos(float z) {
+  int e;
+  float m = frexpf(z, &e);  // m in [1/2, 1)
+  if (m < 0.70710678f) {
+    m *= 2.0f;
+    e -= 1;
+  }
+  const float num = m - 1.0f, den = m + 1.0f;
+  float r = __builtin_amdgcn_rcpf(den);
+  r = fmaf(r, fmaf(-den, r, 1.0f), r);
+  float sq = num * r;
+  sq = fmaf(r, fmaf(-sq, den, num), sq);
+  const float s2 = sq * sq;
+  float p = 1.0f / 9.0f;
+  p = fmaf(p, s2, 1.0f / 7.0f);
+  p = fmaf(p, s2, 1.0f / 5.0f);
+  p = fmaf(p, s2, 1.0f / 3.0f);
+  const float ln_m = 2.0f * fmaf(sq * s2, p, sq);
+  const float ln2_hi = 0x1.62e4p-1f;  // 8 trailing zero bits
+  const float ln2_lo = 0x1.7f7d1cp-20f;
+  const float de = (float)e;
+  return fmaf(de, ln2_hi, fmaf(de, ln2_lo, ln_m));
+}
+
+// Four values of H_0^(1) at once from z_u = x_u^2/4, in the precision T,
+// by the ascending series with M terms and the four Horner chains
+// interleaved. M is chosen by the caller from a bound on z: the first dropped
+// term max(|c_M|, |d_M|) z^M stays below the precision's half-ulp for
+// z <= the class bound (from the closed forms of c_M and d_M). With LARGE,
+// entries with z > 9 (x > 6) take the FP64 large-argument form.
+template <typename T, int M, bool LARGE>
+__device__ inline void hankel0_x4(const T z[4], T hr[4], T hi[4]) {
+  T j[4], s[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    j[u] = kH0.c[M - 1];
-    s[u] = kH0.d[M - 1];
+    j[u] = (T)kH0.c[M - 1];
+    s[u] = (T)kH0.d[M - 1];
   }
 #pragma unroll
   for (int m = M - 2; m >= 0; --m) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      j[u] = fma_uniform(j[u], z[u], kH0.c[m]);
-      s[u] = fma_uniform(s[u], z[u], kH0.d[m]);
+      j[u] = fma_uniform(j[u], z[u], (T)kH0.c[m]);
+      s[u] = fma_uniform(s[u], z[u], (T)kH0.d[m]);
     }
   }
-  const double two_over_pi = 0.63661977236758134308;
-  const double euler = 0.57721566490153286061;
+  const T two_over_pi = (T)0.63661977236758134308;
+  const T euler = (T)0.57721566490153286061;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    if (!LARGE || z[u] <= 9.0) {
-      h[u] = cmk(j[u], two_over_pi * ((0.5 * log_pos(z[u]) + euler) * j[u] + s[u]));
+    if (!LARGE || z[u] <= (T)9.0) {
+      hr[u] = j[u];
+      hi[u] = two_over_pi * (((T)0.5 * log_pos(z[u]) + euler) * j[u] + s[u]);
     } else {
-      h[u] = hankel0_large_call(2.0 * sqrt(z[u]));
+      const double2 h = hankel0_large_call(2.0 * sqrt((double)z[u]));
+      hr[u] = (T)h.x;
+      hi[u] = (T)h.y;
     }
   }
 }
@@ -314,9 +356,11 @@ __host__ __device__ inline double2 hankel1_series(double x) {
 
 __host__ __device__ inline double2 hankel1(double x) { return x <= 6.0 ? hankel1_series(x) : hankel1_large(x); }
 
-// Series classes of the pair loops: terms and the largest z each covers.
+// Series classes of the pair loops: the largest z each covers and the terms
+// it takes in FP64 (remainder below 2^-56) and in FP32 (below 2^-26).
 constexpr int kH0Classes = 5;
-constexpr int kH0ClassTerms[kH0Classes] = {8, 10, 12, 15, 20};
 constexpr double kH0ClassZmax[kH0Classes] = {0.0976, 0.3797, 1.0021, 2.8639, 9.0};
+constexpr int kH0ClassTerms[kH0Classes] = {8, 10, 12, 15, 20};
+constexpr int kH0ClassTermsF32[kH0Classes] = {5, 6, 8, 10, 14};
 
 }  // namespace hfmm
