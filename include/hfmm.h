@@ -156,6 +156,38 @@ hfmm_status_t hfmm_apply(hfmm_plan_t plan, const double *q, double *u, int32_t n
 hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t plan, const double *v, double *w, int32_t nrhs,
                                  const double *q, double *grad_xy, hfmm_stream_t stream);
 
+/*
+ * Batches of independent geometries (same medium, tolerance and options):
+ * one plan per geometry, applied together so that small geometries share
+ * the GPU with large ones.
+ *   hfmm_plan_batch  builds nplans plans from n[g] points at the device
+ *                    pointers points[g] (host arrays of nplans entries); the
+ *                    batch owns the plans. Synchronises like hfmm_plan.
+ *   hfmm_apply_batch u[g] = A_g q[g] for every g, q and u host arrays of
+ *                    device pointers ([nrhs][n[g]] complex each), stream
+ *                    ordered on stream: the plans run on up to four internal
+ *                    streams (default priority) forked from and joined back
+ *                    to stream.
+ *   hfmm_batch_graph with enable != 0, hfmm_apply_batch captures its launches
+ *                    into a HIP graph on the first call for a set of
+ *                    (q, u, nrhs, stream) and replays the graph on later calls
+ *                    with the same set (stage profiling is switched off).
+ *   hfmm_batch_plan  the g-th plan (owned by the batch), e.g. for its info
+ *                    or adjoint.
+ * Errors: HFMM_ERR_INVALID_ARG for NULL arrays, entries or nrhs < 1; the
+ * plan errors of hfmm_plan / hfmm_apply; HFMM_ERR_DEVICE for stream, event or
+ * graph failures.
+ */
+typedef struct hfmm_batch_s *hfmm_batch_t;
+hfmm_status_t hfmm_plan_batch(hfmm_batch_t *out, int32_t nplans, int32_t layers, const double *wavenumbers,
+                              const double *interfaces, const int64_t *n, const double *const *points,
+                              double tol, const hfmm_options_t *opts, hfmm_stream_t stream);
+hfmm_status_t hfmm_apply_batch(hfmm_batch_t batch, const double *const *q, double *const *u, int32_t nrhs,
+                               hfmm_stream_t stream);
+hfmm_status_t hfmm_batch_graph(hfmm_batch_t batch, int32_t enable);
+hfmm_status_t hfmm_batch_plan(hfmm_batch_t batch, int32_t g, hfmm_plan_t *out);
+void hfmm_batch_destroy(hfmm_batch_t batch);
+
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 

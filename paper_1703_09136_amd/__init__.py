@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "HFMM_OK", 1: "HFMM_ERR_INVALID_ARG", 2: "HFMM_ERR_DOMAIN", 3
 # every symbol declared in include/hfmm.h
 EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoint", "hfmm_plan_info",
            "hfmm_profile_enable", "hfmm_profile_read", "hfmm_stage_name",
-           "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message")
+           "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
+           "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy")
 NSTAGES = 9
 HFMM_FP64, HFMM_FP32 = 0, 1
 
@@ -94,6 +95,18 @@ def load(path: str | None = None):
     lib.hfmm_status_string.restype = ctypes.c_char_p
     lib.hfmm_last_error_message.argtypes = []
     lib.hfmm_last_error_message.restype = ctypes.c_char_p
+    pp = ctypes.POINTER(vp)
+    lib.hfmm_plan_batch.argtypes = [pp, i32, i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), ctypes.POINTER(i64), pp,
+                                    dbl, ctypes.POINTER(Options), vp]
+    lib.hfmm_plan_batch.restype = ctypes.c_int
+    lib.hfmm_apply_batch.argtypes = [vp, pp, pp, i32, vp]
+    lib.hfmm_apply_batch.restype = ctypes.c_int
+    lib.hfmm_batch_graph.argtypes = [vp, i32]
+    lib.hfmm_batch_graph.restype = ctypes.c_int
+    lib.hfmm_batch_plan.argtypes = [vp, i32, pp]
+    lib.hfmm_batch_plan.restype = ctypes.c_int
+    lib.hfmm_batch_destroy.argtypes = [vp]
+    lib.hfmm_batch_destroy.restype = None
     _lib = lib
     return lib
 
@@ -193,6 +206,78 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.hfmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent geometries in one medium, applied together (hfmm_plan_batch).
+
+    ``points`` is a list of float64 CUDA tensors (n_g, 2). apply() takes a list
+    of complex128 right-hand sides (nrhs, n_g) and returns the list of results.
+    graph(True) makes repeated applies with the same tensors replay a captured
+    HIP graph; that needs a stream other than the legacy null stream."""
+
+    def __init__(self, k, interfaces, points, tol=1e-8, stream=None, **options):
+        import torch
+        lib = load()
+        k = [float(v) for v in k]
+        interfaces = [float(v) for v in interfaces]
+        pts = []
+        for p in points:
+            if not (p.is_cuda and p.dtype == torch.float64 and p.dim() == 2 and p.shape[1] == 2):
+                raise TypeError("points must be float64 CUDA tensors of shape (n, 2)")
+            pts.append(p.contiguous())
+        self._pts = pts
+        self.ns = [int(p.shape[0]) for p in pts]
+        G = len(pts)
+        kk = (ctypes.c_double * len(k))(*k)
+        ii = (ctypes.c_double * max(1, len(interfaces)))(*(interfaces or [0.0]))
+        nn = (ctypes.c_int64 * G)(*self.ns)
+        pp = (ctypes.c_void_p * G)(*[p.data_ptr() for p in pts])
+        opts = default_options(**options)
+        h = ctypes.c_void_p()
+        _check(lib.hfmm_plan_batch(ctypes.byref(h), G, len(k), kk, ii, nn, pp, float(tol), ctypes.byref(opts),
+                                   _stream_ptr(stream)))
+        self._h = h
+        self._lib = lib
+
+    def __len__(self):
+        return len(self.ns)
+
+    def graph(self, enable=True):
+        _check(self._lib.hfmm_batch_graph(self._h, 1 if enable else 0))
+
+    def apply(self, qs, outs=None, stream=None):
+        import torch
+        G = len(self.ns)
+        if len(qs) != G:
+            raise ValueError("one right-hand side tensor per geometry")
+        q2 = [_as_rhs(q, n, "q") for q, n in zip(qs, self.ns)]
+        nrhs = q2[0].shape[0]
+        if any(q.shape[0] != nrhs for q in q2):
+            raise ValueError("every geometry needs the same number of right-hand sides")
+        us = outs if outs is not None else [torch.empty_like(q) for q in q2]
+        qa = (ctypes.c_void_p * G)(*[q.data_ptr() for q in q2])
+        ua = (ctypes.c_void_p * G)(*[u.data_ptr() for u in us])
+        _check(self._lib.hfmm_apply_batch(self._h, qa, ua, nrhs, _stream_ptr(stream)))
+        return us
+
+    def info(self, g):
+        h = ctypes.c_void_p()
+        _check(self._lib.hfmm_batch_plan(self._h, int(g), ctypes.byref(h)))
+        inf = Info()
+        _check(self._lib.hfmm_plan_info(h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hfmm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

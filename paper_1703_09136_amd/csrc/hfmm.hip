@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -334,6 +335,21 @@ struct hfmm_plan_s {
 
 namespace {
 
+// Right-hand sides per pass through the pipeline: the M2L contribution rows
+// (one per pair and right-hand side) stay within kContribBudget bytes per
+// plan. HFMM_RHS_CHUNK in the environment caps the pass size further
+// (diagnostics and tests).
+constexpr double kContribBudget = 512.0 * 1024 * 1024;
+int rhs_chunk(hfmm_plan_t pl, int nrhs) {
+  const double per_rhs = 8.0 * (double)std::max<int64_t>(pl->cstride, 1);
+  int c = std::max(1, std::min(nrhs, (int)std::max(1.0, kContribBudget / per_rhs)));
+  if (const char* env = std::getenv("HFMM_RHS_CHUNK")) {
+    const int cap = std::atoi(env);
+    if (cap >= 1) c = std::min(c, cap);
+  }
+  return c;
+}
+
 hfmm_status_t ensure_workspace(hfmm_plan_t pl, int nrhs) {
   if (pl->ws_nrhs >= nrhs) return HFMM_OK;
   HIP_TRY(pl->qs.alloc((size_t)pl->n * nrhs));
@@ -377,6 +393,13 @@ int choose_order(double k, double b, double eps, int& status) {
 }
 
 }  // namespace
+
+namespace hfmm {
+// Workspace for nrhs right-hand sides, allocated ahead of a graph capture.
+hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs) { return ensure_workspace(pl, rhs_chunk(pl, nrhs)); }
+int64_t plan_points(hfmm_plan_t pl) { return pl->n; }
+hfmm_status_t report(hfmm_status_t st, const std::string& msg) { return fail(st, msg); }
+}  // namespace hfmm
 
 extern "C" {
 
@@ -457,6 +480,10 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   if (layers == 3 && !(interfaces[0] > interfaces[1]))
     return fail(HFMM_ERR_INVALID_ARG, "interfaces must be strictly decreasing");
 
+  {
+    const hipError_t e = init_kernel_attributes();
+    if (e != hipSuccess) return fail(HFMM_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
+  }
   hfmm_plan_t pl = new hfmm_plan_s();
   auto bail = [&](hfmm_status_t s) {
     pl->release_all();
@@ -1351,20 +1378,26 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
   if (!pl || !q || !u) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, q or u");
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   hipStream_t s = (hipStream_t)stream_;
-  hfmm_status_t st = ensure_workspace(pl, nrhs);
+  const int chunk = rhs_chunk(pl, nrhs);
+  hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
   Marker mark;
   mark.s = s;
-  if (pl->prof_on) {
+  if (pl->prof_on && chunk == nrhs) {  // stage timing covers single-pass applies
     pl->prof_pending.emplace_back();
     mark.ev = &pl->prof_pending.back();
   }
-  mark();
-  launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)q, pl->qs.p, 0);
-  mark();
-  forward_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p, mark);
-  launch_scatter(s, pl->n, nrhs, pl->perm.p, pl->us.p, (double2*)u, 0);
-  mark();
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int nc = std::min(chunk, nrhs - r0);
+    const double2* qc = (const double2*)q + (int64_t)r0 * pl->n;
+    double2* uc = (double2*)u + (int64_t)r0 * pl->n;
+    mark();
+    launch_gather(s, pl->n, nc, pl->perm.p, qc, pl->qs.p, 0);
+    mark();
+    forward_pipeline(pl, nc, s, pl->qs.p, pl->us.p, mark);
+    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, uc, 0);
+    mark();
+  }
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }
@@ -1409,28 +1442,34 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   if (grad_xy && !q) return fail(HFMM_ERR_INVALID_ARG, "grad_xy requested without q");
   hipStream_t s = (hipStream_t)stream_;
-  hfmm_status_t st = ensure_workspace(pl, nrhs);
+  const int chunk = rhs_chunk(pl, nrhs);
+  hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
   if (grad_xy) {
-    HIP_TRY(pl->gq.ensure((size_t)pl->n * nrhs));
+    HIP_TRY(pl->gq.ensure((size_t)pl->n * chunk));
     HIP_TRY(pl->gs.ensure((size_t)pl->n));
   }
-  // A^H v = conj(A^T conj(v))
-  launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)v, pl->qs.p, 1);
-  transpose_pipeline(pl, nrhs, s, pl->qs.p, pl->us.p);
-  launch_scatter(s, pl->n, nrhs, pl->perm.p, pl->us.p, (double2*)w, 1);
-  if (grad_xy) {
-    // g_j = Re(q_j sum_i conj(v_i) dA_ij/dx_j): the transposed pipeline has
-    // left the adjoint multipole coefficients in alpha and conj(v) in qs
-    TreeView tv = pl->view(nrhs);
-    launch_gather(s, pl->n, nrhs, pl->perm.p, (const double2*)q, pl->gq.p, 0);
-    launch_l2p_grad(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, pl->alpha.p, pl->gq.p, pl->gs.p);
-    launch_p2p_grad(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, pl->qs.p,
-                    pl->gq.p, pl->gs.p);
-    launch_iface_grad(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p,
-                      pl->qky.p, pl->qkx.p, pl->qs.p, pl->gq.p, pl->gs.p);
-    launch_scatter_grad(s, pl->n, pl->perm.p, pl->gs.p, (double2*)grad_xy);
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int nc = std::min(chunk, nrhs - r0);
+    const int64_t off = (int64_t)r0 * pl->n;
+    // A^H v = conj(A^T conj(v))
+    launch_gather(s, pl->n, nc, pl->perm.p, (const double2*)v + off, pl->qs.p, 1);
+    transpose_pipeline(pl, nc, s, pl->qs.p, pl->us.p);
+    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, (double2*)w + off, 1);
+    if (grad_xy) {
+      // g_j = Re(q_j sum_i conj(v_i) dA_ij/dx_j): the transposed pipeline has
+      // left the adjoint multipole coefficients in alpha and conj(v) in qs;
+      // later chunks add to the first one's sums
+      TreeView tv = pl->view(nc);
+      launch_gather(s, pl->n, nc, pl->perm.p, (const double2*)q + off, pl->gq.p, 0);
+      launch_l2p_grad(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, pl->alpha.p, pl->gq.p, pl->gs.p, r0 > 0);
+      launch_p2p_grad(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, pl->qs.p,
+                      pl->gq.p, pl->gs.p);
+      launch_iface_grad(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p,
+                        pl->qky.p, pl->qkx.p, pl->qs.p, pl->gq.p, pl->gs.p);
+    }
   }
+  if (grad_xy) launch_scatter_grad(s, pl->n, pl->perm.p, pl->gs.p, (double2*)grad_xy);
   HIP_TRY(hipGetLastError());
   return HFMM_OK;
 }

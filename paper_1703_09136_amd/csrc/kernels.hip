@@ -387,9 +387,10 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
                                                           const TableRef* __restrict__ tabs,
                                                           const double2* __restrict__ tdata,
                                                           const double2* __restrict__ src, double2* __restrict__ dst,
-                                                          double* __restrict__ contrib, int64_t cstride, int r) {
+                                                          double* __restrict__ contrib, int64_t cstride) {
   extern __shared__ double lds_d[];
   __shared__ int64_t s_off[64];
+  const int r = blockIdx.y;  // right-hand side
   const TransItem it = items[blockIdx.x];
   const int Ps = it.Ps, Pd = it.Pd;
   const int Ms = 2 * Ps + 1, Ms4 = round4(Ms), Md = 2 * Pd + 1;
@@ -682,8 +683,9 @@ template <typename T, int RB, int CLS>
 __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const int* __restrict__ ptr, const int2* __restrict__ rng,
                                               const int* __restrict__ sym, const double2* __restrict__ qs,
-                                              double2* __restrict__ us, int r0) {
+                                              double2* __restrict__ us) {
   using C = cplx_t<T>;
+  const int r0 = blockIdx.y * RB;  // first right-hand side of this block
   __shared__ double2 s_x[P2P_CS];
   __shared__ C s_q[RB][P2P_CS];
   __shared__ C s_acc[RB][P2P_CS];
@@ -710,10 +712,10 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
 // so dw/dx = sum_m (k/2)(a_{m+1} - a_{m-1}) f_m and
 //    dw/dy = -(ik/2) sum_m (a_{m+1} + a_{m-1}) f_m,  m in [-P-1, P+1].
 // gs[j] = (sum_r Re(q_rj dw_r/dx), sum_r Re(q_rj dw_r/dy)), stored (first
-// writer); leaves without a local expansion store zero.
+// writer, or added with add); leaves without a local expansion store zero.
 __global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __restrict__ leaves, int nleaves, int rb,
                                                    const double2* __restrict__ alpha, const double2* __restrict__ qs,
-                                                   double2* __restrict__ gs) {
+                                                   double2* __restrict__ gs, int add) {
   extern __shared__ double2 lds_c[];  // [rb][2P + 5]: a_m at P + 2 + m, zero for |m| > P
   const int li = blockIdx.x;
   if (li >= nleaves) return;
@@ -800,7 +802,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __res
           }
         }
       }
-      if (r0 == 0)
+      if (r0 == 0 && !add)
         gs[j] = cmk(sx, sy);
       else
         gs[j] = cadd(gs[j], cmk(sx, sy));
@@ -1240,23 +1242,33 @@ size_t trans_lds_bytes(int Ps, int Pd) {
   return sizeof(double) * (size_t)(3 * ntp) + sizeof(double2) * (size_t)npi * round4(2 * Ps + 1);
 }
 
+// Dynamic LDS limit of the translation kernels: the CU's 160 KiB less each
+// kernel's static LDS. Called when a plan is built (before any launch or
+// graph capture); returns the first HIP error.
+template <bool REV, int MODE>
+static hipError_t trans_lds_limit() {
+  const void* f = (const void*)k_trans_mfma<REV, MODE>;
+  hipFuncAttributes fa;
+  hipError_t e = hipFuncGetAttributes(&fa, f);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
+}
+
+hipError_t init_kernel_attributes() {
+  const hipError_t es[6] = {trans_lds_limit<false, OUT_ATOMIC>(), trans_lds_limit<false, OUT_CONTRIB>(),
+                            trans_lds_limit<false, OUT_EXCLUSIVE>(), trans_lds_limit<true, OUT_ATOMIC>(),
+                            trans_lds_limit<true, OUT_CONTRIB>(), trans_lds_limit<true, OUT_EXCLUSIVE>()};
+  for (hipError_t e : es)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
+}
+
 template <bool REV, int MODE>
 static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, size_t lds,
                       const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
                       const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    // the CU's 160 KiB less the kernel's static LDS; a failure here is left
-    // for the caller's hipGetLastError check
-    const void* f = (const void*)k_trans_mfma<REV, MODE>;
-    hipFuncAttributes fa;
-    if (hipFuncGetAttributes(&fa, f) == hipSuccess)
-      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
-    attr_done = true;
-  }
-  for (int r = 0; r < tv.nrhs; ++r)
-    hipLaunchKernelGGL((k_trans_mfma<REV, MODE>), dim3(nitems), dim3(TR_THREADS), lds, s, tv, items, psrc, pdst,
-                       pcoff, tabs, tdata, src, dst, contrib, cstride, r);
+  hipLaunchKernelGGL((k_trans_mfma<REV, MODE>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items, psrc,
+                     pdst, pcoff, tabs, tdata, src, dst, contrib, cstride);
 }
 
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
@@ -1292,11 +1304,11 @@ static void p2p_class(hipStream_t s, const TreeView& tv, const int* items, int n
                       const int* sym, const double2* qs, double2* us) {
   if (nl <= 0) return;
   if (tv.nrhs == 1) {
-    hipLaunchKernelGGL((k_p2p<T, 1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, 0);
+    hipLaunchKernelGGL((k_p2p<T, 1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us);
     return;
   }
-  for (int r0 = 0; r0 < tv.nrhs; r0 += 4)
-    hipLaunchKernelGGL((k_p2p<T, 4, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us, r0);
+  hipLaunchKernelGGL((k_p2p<T, 4, CLS>), dim3(nl, (tv.nrhs + 3) / 4), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym,
+                     qs, us);
 }
 
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
@@ -1334,11 +1346,11 @@ void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const doub
 
 
 void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* alpha,
-                     const double2* qs, double2* gs) {
+                     const double2* qs, double2* gs, int add) {
   if (nl <= 0) return;
   const int rb = min(L2P_RB, tv.nrhs);
   hipLaunchKernelGGL(k_l2p_grad, dim3(nl), dim3(WAVE), l2p_grad_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, alpha,
-                     qs, gs);
+                     qs, gs, add);
 }
 void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
                      const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs) {

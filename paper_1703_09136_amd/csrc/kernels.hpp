@@ -7,6 +7,10 @@ namespace hfmm {
 
 void launch_gather(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_in);
 void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_out);
+// Kernel attributes that must be set before launches (and before any graph
+// capture): the dynamic LDS limit of the translation kernels.
+hipError_t init_kernel_attributes();
+
 // P2M and L2P over a list of leaves; each block reads its leaf's order, Pmax
 // bounds the orders of the list (sizes the LDS).
 void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* qs,
@@ -49,7 +53,7 @@ void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const doub
 // multipole coefficients (stores gs), then the direct and near-interface
 // parts (add into gs), then gs to the caller's order as [n][2] doubles.
 void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* alpha,
-                     const double2* qs, double2* gs);
+                     const double2* qs, double2* gs, int add);
 void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
                      const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs);
 void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
