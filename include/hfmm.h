@@ -77,9 +77,8 @@ typedef struct {
                                direct pairs at small k1 r: a box is split
                                while k1 times its side exceeds leaf_kb and it
                                holds more than leaf_size / 4 points, or
-                               exceeds 2 leaf_kb and holds two or more
-                               (default 1.5; 0 turns the bound off). Must be
-                               0 or >= 0.25. */
+                               exceeds 2 leaf_kb (default 1.5; 0 turns the
+                               bound off). Must be 0 or >= 0.25. */
 } hfmm_options_t;
 
 typedef struct {

@@ -568,12 +568,14 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       bool split = cnt > o.leaf_size;
       // wavelength bound: wide leaves leave direct pairs at large k1 r. Up to
       // twice the bound, boxes holding a quarter of a leaf or less stay whole
-      // (their pairs are few); beyond it every box with two points splits.
+      // (their pairs are few); beyond it every box splits, a lone point
+      // included, so that no leaf takes a wide neighbour subtree into its
+      // direct lists (nor a near-interface image pair that is not admissible).
       if (o.leaf_kb > 0.0 && k * b > o.leaf_kb) {
-        if (cnt > std::max(1, o.leaf_size / 4) || (k * b > 2.0 * o.leaf_kb && cnt > 1)) split = true;
+        if (cnt > std::max(1, o.leaf_size / 4) || k * b > 2.0 * o.leaf_kb) split = true;
       }
       // bottom-row boxes whose own image pair is not admissible (2 y0 < b)
-      if (o.interface_refine && B[bi].iy == 0 && 2.0 * ymin < b && cnt > 4) split = true;
+      if (o.interface_refine && B[bi].iy == 0 && 2.0 * ymin < b && cnt > 1) split = true;
       if (l >= maxl) split = false;
       if (!split) continue;
       any = true;

@@ -53,8 +53,8 @@ __global__ void k_scatter(int n, int nrhs, const int* __restrict__ perm, const d
 
 // ------------------------------------------------------------------ P2M
 // alpha_p = sum_j q_j J_p(k rho_j) e^{-i p theta_j}, p in [-P, P] (Eq. multi_coeff).
-// One wave per leaf (one launch for all levels, the order read per leaf), a
-// lane per point. Each lane walks the backward Bessel
+// One wave per leaf and group of up to P2M_RB right-hand sides (grid y; one
+// launch for all levels, the order read per leaf), a lane per point. Each lane walks the backward Bessel
 // recurrence once and parks V_{n,j} = J_n(k rho_j) w_j^n (w = e^{-i theta}) for a
 // chunk of P2M_CH orders in LDS; the chunk is then reduced over the points
 // for every right-hand side, giving alpha_n = sum q V and, through
@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
   const int nstart = miller_start(tv.k * rmax, P);
   // reduction role of this lane: order slot t of the chunk, point block part
   const int t_red = lane & (P2M_CH - 1), part = lane / P2M_CH;
-  for (int r0 = 0; r0 < tv.nrhs; r0 += rb) {
+  {  // right-hand sides r0 .. r0 + rb - 1 (grid y)
+    const int r0 = blockIdx.y * rb;
     const int nr = min(rb, tv.nrhs - r0);
     for (int e = lane; e < nr * M; e += WAVE) s_a[e] = cmk(0.0, 0.0);
     for (int j0 = pr.x; j0 < pr.y; j0 += WAVE) {
@@ -171,9 +172,9 @@ size_t p2m_lds_bytes(int Pmax, int rb) {
 
 // ------------------------------------------------------------------ L2P
 // u_i (+)= pref * sum_p beta_p J_p(k r_i) e^{i p theta_i} (local expansion,
-// Section 3.2). One wave per leaf, a lane per point; the leaf's coefficients
-// for up to L2P_RB right-hand sides are staged in LDS and one recurrence walk
-// serves all of them. With conj_w the phase is e^{-i p theta_i}: the
+// Section 3.2). One wave per leaf and group of up to L2P_RB right-hand sides
+// (grid y), a lane per point; the group's coefficients are staged in LDS and
+// one recurrence walk serves all of them. With conj_w the phase is e^{-i p theta_i}: the
 // transpose of P2M, used by the adjoint.
 constexpr int L2P_RB = 4;
 
@@ -202,7 +203,8 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
     for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
     nstart = miller_start(tv.k * rmax, P);
   }
-  for (int r0 = 0; r0 < tv.nrhs; r0 += rb) {
+  {  // right-hand sides r0 .. r0 + rb - 1 (grid y)
+    const int r0 = blockIdx.y * rb;
     const int nr = min(rb, tv.nrhs - r0);
     if (has_local) {
       for (int e = lane; e < nr * M; e += WAVE) {
@@ -470,7 +472,7 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
 }
 
 // beta_b = sum of the contribution rows listed for box b (CSR), plain store.
-// One wave per box; a lane per order.
+// One wave per box and right-hand side (grid y); a lane per order.
 __global__ void __launch_bounds__(WAVE) k_reduce_contrib(TreeView tv, const int* __restrict__ boxes, int nb,
                                                          const int* __restrict__ ptr, const int* __restrict__ pairs,
                                                          const int64_t* __restrict__ pcoff,
@@ -482,7 +484,8 @@ __global__ void __launch_bounds__(WAVE) k_reduce_contrib(TreeView tv, const int*
   int P = tv.P[tv.level[b]];
   int M = 2 * P + 1;
   int e0 = ptr[wi], e1 = ptr[wi + 1];
-  for (int r = 0; r < tv.nrhs; ++r) {
+  {  // right-hand side r (grid y)
+    const int r = blockIdx.y;
     const double* cr = contrib + (int64_t)r * cstride;
     for (int p = threadIdx.x; p < M; p += WAVE) {
       double re = 0.0, im = 0.0;
@@ -1224,14 +1227,16 @@ void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
   if (nl <= 0) return;
   // at most 37 KiB (Pmax = 255): within the default dynamic LDS limit
   const int rb = min(P2M_RB, tv.nrhs);
-  hipLaunchKernelGGL(k_p2m, dim3(nl), dim3(WAVE), p2m_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, qs, alpha, conj_w,
+  hipLaunchKernelGGL(k_p2m, dim3(nl, (tv.nrhs + rb - 1) / rb), dim3(WAVE), p2m_lds_bytes(Pmax, rb), s, tv, leaves,
+                     nl, rb, qs, alpha, conj_w,
                      pref);
 }
 void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
                 double2* us, int conj_w, double2 pref, int accumulate) {
   if (nl <= 0) return;
   const int rb = min(L2P_RB, tv.nrhs);
-  hipLaunchKernelGGL(k_l2p, dim3(nl), dim3(WAVE), l2p_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, beta, us, conj_w,
+  hipLaunchKernelGGL(k_l2p, dim3(nl, (tv.nrhs + rb - 1) / rb), dim3(WAVE), l2p_lds_bytes(Pmax, rb), s, tv, leaves,
+                     nl, rb, beta, us, conj_w,
                      pref, accumulate);
 }
 // LDS bytes of a translation item: the padded table (real, imaginary and
@@ -1292,7 +1297,8 @@ void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, 
                            const int* pairs, const int64_t* pcoff, const double* contrib, int64_t cstride,
                            double2* dst) {
   if (nb)
-    hipLaunchKernelGGL(k_reduce_contrib, dim3(nb), dim3(WAVE), 0, s, tv, boxes, nb, ptr, pairs, pcoff, contrib,
+    hipLaunchKernelGGL(k_reduce_contrib, dim3(nb, tv.nrhs), dim3(WAVE), 0, s, tv, boxes, nb, ptr, pairs, pcoff,
+                       contrib,
                        cstride, dst);
 }
 
