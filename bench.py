@@ -7,11 +7,16 @@ synthetic inputs, see workloads.three_layer_ellipses).
 
 A step is one hfmm_apply (u = A q) with q and u resident in device memory;
 the plan (tree, lists, tables) is built before the timed region. Prints one
-JSON line. With --gpus other than 1 it exits: this build runs on one GPU.
+JSON line. Besides the headline number it reports the mixed-precision plan
+(near field in FP32) with its error, the adjoint with and without coordinate
+gradients, the batched workload (32 geometries x 256 right-hand sides), the
+roofline of the dominant kernel and the CPU oracle on a bounded sample.
+With --gpus other than 1 it exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,9 +28,38 @@ sys.path.insert(0, ROOT)
 METRIC = "H-FMM matvecs/sec at N=1e6, 3 layers, rel err 1e-8 (FP64) vs mixed; adjoint s"
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_p2p_three_layer_n1e6.txt")
+KERNEL_SOURCES = ["kernels.hip", "special.hpp", "common.hpp", "h0_cheb.hpp"]
 
 
-def cpu_baseline_sample(w, seconds_budget=20.0):
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1703_09136_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic():
+    """HBM bytes per apply of the near-field kernels from the profiler counters
+    recorded in profiles/, or None when missing or taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["p2p_bytes_per_apply"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline_sample(w):
     """The oracle on a bounded sample of the same matvec, extrapolated to one full matvec.
 
     Free part: a few complete target rows (all N sources). Scattered part: the
@@ -59,12 +93,90 @@ def cpu_baseline_sample(w, seconds_budget=20.0):
             "seconds_per_matvec_extrapolated": per_matvec}
 
 
+def timed(torch, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def extras(hf, torch, np, w, plan, pts, q, u, args, golden):
+    """Adjoint timings and the mixed-precision plan on the same workload."""
+    v = torch.randn_like(q)
+    plan.apply_adjoint(v)
+    nadj = max(1, args.steps // 4)
+    adj_ms = timed(torch, lambda: plan.apply_adjoint(v), nadj)
+    plan.apply_adjoint(v, q=q, grad_xy=True)
+    adj_grad_ms = timed(torch, lambda: plan.apply_adjoint(v, q=q, grad_xy=True), nadj)
+    plan32 = hf.Plan(w.k, w.interfaces, pts, tol=w.tol, leaf_size=w.leaf, precision=hf.HFMM_FP32)
+    for _ in range(args.warmup):
+        plan32.apply(q, out=u)
+    ms32 = timed(torch, lambda: plan32.apply(q, out=u), args.steps)
+    err32 = None
+    if golden is not None:
+        err32 = float(np.linalg.norm(u.cpu().numpy()[:, golden["targets"]] - golden["u"]) /
+                      np.linalg.norm(golden["u"]))
+    plan32.close()
+    mixed = {"precision": "fp32 near field (H0 series, logarithm, per-item sums), fp64 elsewhere",
+             "value": 1e3 / ms32, "unit": "matvecs/s", "ms_per_step": ms32, "rel_err_vs_oracle": err32}
+    return adj_ms / 1e3, adj_grad_ms / 1e3, mixed
+
+
+def batched(hf, torch, args):
+    """32 three-layer geometries, N_g = round(2^U(12,18)), 256 right-hand sides
+    each (strengths drawn on the device from a seeded generator), applied as one
+    batch replayed from a HIP graph."""
+    import workloads
+    dev = torch.device("cuda:0")
+    geos = workloads.batched_geometries(nrhs=1)
+    pts = [torch.tensor(g.xy, dtype=torch.float64, device=dev) for g in geos]
+    ns = [g.n for g in geos]
+    t0 = time.time()
+    b = hf.Batch(workloads.THREE_LAYER_K, workloads.THREE_LAYER_IF, pts, tol=1e-8, leaf_size=64)
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1703 * 9136 + 4)
+    nrhs = args.batch_rhs
+    qs = [torch.randn((nrhs, n), dtype=torch.complex128, device=dev, generator=gen) for n in ns]
+    us = [torch.empty_like(t) for t in qs]
+    s = torch.cuda.Stream()
+    b.graph(True)
+    with torch.cuda.stream(s):
+        b.apply(qs, outs=us, stream=s)
+    s.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 2
+    with torch.cuda.stream(s):
+        e0.record(s)
+        for _ in range(reps):
+            b.apply(qs, outs=us, stream=s)
+        e1.record(s)
+    s.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    b.close()
+    return {"workload": "32 three-layer geometries of 2^U(12,18) points (%d in all), %d right-hand sides each"
+                        % (sum(ns), nrhs),
+            "value": len(ns) * nrhs / ms * 1e3, "unit": "matvecs/s (geometry x right-hand side)",
+            "ms_per_batch": ms, "point_rhs_per_s": sum(ns) * nrhs / ms * 1e3, "plan_s": plan_s,
+            "graph": True}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the adjoint, mixed-precision and batched legs (profiling runs)")
+    ap.add_argument("--batch-rhs", type=int, default=256)
     ap.add_argument("--n", type=int, default=1_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -91,6 +203,9 @@ def main():
     info = plan.info()
     print("plan: %.2f s %s" % (plan_s, json.dumps(info)), file=sys.stderr, flush=True)
     u = torch.empty_like(q)
+    # a plain copy of known size (16 B per point each way): it calibrates the
+    # HBM byte counters of the profiler runs
+    q.clone()
     for _ in range(args.warmup):
         plan.apply(q, out=u)
     torch.cuda.synchronize()
@@ -99,85 +214,48 @@ def main():
     # timed region: K matvecs, stage events recorded on the same stream
     plan.profile(True)
     plan.profile_read()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        plan.apply(q, out=u)
-    end.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
+    ms = timed(torch, lambda: plan.apply(q, out=u), args.steps)
     stages, napplies = plan.profile_read()
     plan.profile(False)
-    ms = total_ms / args.steps
     stage_avg = {k: v / max(napplies, 1) for k, v in stages.items()}
     print("stage ms per apply: %s" % json.dumps({k: round(v, 4) for k, v in stage_avg.items()}),
           file=sys.stderr, flush=True)
 
     # accuracy on the oracle's target subset, when the stored values are present
     err = None
+    golden = None
     gpath = os.path.join(ROOT, "tests", "golden", "three_layer_oracle.npz")
     if args.n == 1_000_000 and os.path.exists(gpath):
-        g = np.load(gpath)
-        uu = u.cpu().numpy()[:, g["targets"]]
-        err = float(np.linalg.norm(uu - g["u"]) / np.linalg.norm(g["u"]))
+        golden = np.load(gpath)
+        err = float(np.linalg.norm(u.cpu().numpy()[:, golden["targets"]] - golden["u"]) /
+                    np.linalg.norm(golden["u"]))
 
-    # adjoint seconds
-    v = torch.randn_like(q)
-    plan.apply_adjoint(v)
-    torch.cuda.synchronize()
-    a0 = torch.cuda.Event(enable_timing=True)
-    a1 = torch.cuda.Event(enable_timing=True)
-    a0.record()
-    nadj = max(1, args.steps // 4)
-    for _ in range(nadj):
-        plan.apply_adjoint(v)
-    a1.record()
-    torch.cuda.synchronize()
-    adj_s = a0.elapsed_time(a1) / nadj / 1e3
-    # the full backward: A^H v and the source-coordinate gradient
-    plan.apply_adjoint(v, q=q, grad_xy=True)
-    torch.cuda.synchronize()
-    a0.record()
-    for _ in range(nadj):
-        plan.apply_adjoint(v, q=q, grad_xy=True)
-    a1.record()
-    torch.cuda.synchronize()
-    adj_grad_s = a0.elapsed_time(a1) / nadj / 1e3
-
-    # mixed precision: the near field in FP32, the rest FP64
-    plan32 = hf.Plan(w.k, w.interfaces, pts, tol=w.tol, leaf_size=w.leaf, precision=hf.HFMM_FP32)
-    for _ in range(args.warmup):
-        plan32.apply(q, out=u)
-    torch.cuda.synchronize()
-    a0.record()
-    for _ in range(args.steps):
-        plan32.apply(q, out=u)
-    a1.record()
-    torch.cuda.synchronize()
-    ms32 = a0.elapsed_time(a1) / args.steps
-    err32 = None
-    if args.n == 1_000_000 and os.path.exists(gpath):
-        err32 = float(np.linalg.norm(u.cpu().numpy()[:, g["targets"]] - g["u"]) / np.linalg.norm(g["u"]))
-    plan32.close()
-    mixed = {"precision": "fp32 near field (H0 series, logarithm, per-item sums), fp64 elsewhere",
-             "value": 1e3 / ms32, "unit": "matvecs/s", "ms_per_step": ms32, "rel_err_vs_oracle": err32}
-    print("mixed: %s" % json.dumps(mixed), file=sys.stderr, flush=True)
-
-    # roofline of the dominant stage
-    dominant = max(("m2l", "p2p"), key=lambda s: stage_avg[s])
+    # roofline of the dominant stage (the near field or M2L), its time from the
+    # HIP events recorded on the apply stream around its launches
+    dominant = max(("m2l", "p2p"), key=lambda k: stage_avg[k])
     if dominant == "m2l":
         work = info["flops_m2l"]
+        kname = "k_trans_mfma + k_reduce_contrib (M2L)"
+        traffic = None
     else:
         # flops of the direct part as the plan evaluates it (series length by
         # item class, logarithm, complex multiply-adds)
         work = info["flops_p2p"]
+        kname = "k_p2p (six series-class launches per apply)"
+        traffic = stored_traffic()
     dom_s = stage_avg[dominant] / 1e3
     achieved = work / dom_s / 1e12
-    roofline = {"bound": "alu", "kernel": dominant, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+    roofline = {"bound": "alu", "kernel": kname, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()}}
+
+    adj_s = adj_grad_s = mixed = batch = None
+    if not args.no_extras:
+        adj_s, adj_grad_s, mixed = extras(hf, torch, np, w, plan, pts, q, u, args, golden)
+        print("mixed: %s" % json.dumps(mixed), file=sys.stderr, flush=True)
+        batch = batched(hf, torch, args)
+        print("batched: %s" % json.dumps(batch), file=sys.stderr, flush=True)
+    plan.close()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -191,7 +269,7 @@ def main():
                       % w.n, "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
                       "parallelism": "single GPU"},
            "rel_err_vs_oracle": err, "adjoint_s": adj_s, "adjoint_with_coordinate_grad_s": adj_grad_s,
-           "mixed": mixed, "plan_s": plan_s,
+           "mixed": mixed, "batched": batch, "plan_s": plan_s,
            "levels": info["levels"], "orders": info["order"],
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
