@@ -528,17 +528,14 @@ __global__ void k_fill_zero(double2* __restrict__ p, int64_t n) {
 // FP64 and then rounded).
 constexpr int P2P_CS = 128;  // sources per staged chunk
 
-// In a cross item the reverse sums q_i H_ij go to s_acc[j]: at one step the
-// lanes of a residue class hold distinct rotations, so when every class has
-// at least as many sources as the chunk has targets (own == true) no two
-// lanes touch one entry in one instruction and a plain read-add-write is
-// exact (the wave's LDS operations execute in order). FP32 takes that path
-// (its LDS atomic adds measured far slower); FP64 keeps the no-return atomic
-// adds, which do not wait for the LDS and measured faster there.
+// In a cross item the reverse sums q_i H_ij go to s_acc[j], kept in FP64 for
+// both precisions and added with the no-return FP64 LDS atomics, which do not
+// wait for the LDS (FP32 LDS atomics and plain read-add-writes measured
+// several times slower).
 template <typename T, int RB, int M, bool LARGE, bool SYM>
-__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, bool own, double2 xi,
-                                 const cplx_t<T>* qi, T qk2, const double2* s_x, const cplx_t<T> (*s_q)[P2P_CS],
-                                 cplx_t<T> acc[RB], cplx_t<T> (*s_acc)[P2P_CS]) {
+__device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, double2 xi, const cplx_t<T>* qi,
+                                 T qk2, const double2* s_x, const cplx_t<T> (*s_q)[P2P_CS], cplx_t<T> acc[RB],
+                                 double2 (*s_acc)[P2P_CS]) {
   using C = cplx_t<T>;
   const int K = (cnt - sub + g - 1) / g;  // sources of this lane's class
   const int r0 = K > 0 ? rot % K : 0;
@@ -579,12 +576,8 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, bo
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
           const C t = cmul(hw, qi[rr]);
-          if (sizeof(T) == 4 && own) {
-            s_acc[rr][jc[u]] = cadd(s_acc[rr][jc[u]], t);
-          } else {
-            atomicAdd(&s_acc[rr][jc[u]].x, t.x);
-            atomicAdd(&s_acc[rr][jc[u]].y, t.y);
-          }
+          atomicAdd(&s_acc[rr][jc[u]].x, (double)t.x);
+          atomicAdd(&s_acc[rr][jc[u]].y, (double)t.y);
         }
       }
     }
@@ -596,7 +589,7 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, bo
 template <typename T, int RB, int M, bool LARGE, bool SYM>
 __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const int2* __restrict__ rng,
                                 const double2* __restrict__ qs, double2* __restrict__ us, int r0, double2* s_x,
-                                cplx_t<T> (*s_q)[P2P_CS], cplx_t<T> (*s_acc)[P2P_CS]) {
+                                cplx_t<T> (*s_q)[P2P_CS], double2 (*s_acc)[P2P_CS]) {
   using C = cplx_t<T>;
   const int lane = threadIdx.x;
   const int2 pr = tv.prange[b];
@@ -604,7 +597,7 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
   if (SYM) {
     for (int l = lane; l < P2P_CS; l += WAVE)
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) s_acc[rr][l] = cmk((T)0, (T)0);
+      for (int rr = 0; rr < RB; ++rr) s_acc[rr][l] = cmk(0.0, 0.0);
   }
   // targets in chunks of 32 (two lanes per target), the remainder in a chunk of
   // the next power of two with more lanes per target
@@ -640,10 +633,8 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
             s_q[rr][l] = (r0 + rr < tv.nrhs) ? to_cplx<T>(qs[(int64_t)(r0 + rr) * tv.n + j0 + l]) : cmk((T)0, (T)0);
         }
         __syncthreads();
-        const bool own = nt <= cnt / g;  // every class holds >= nt sources
         if (valid)
-          p2p_chunk<T, RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, own, xi, qi, qk2, s_x, s_q, acc,
-                                          s_acc);
+          p2p_chunk<T, RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, xi, qi, qk2, s_x, s_q, acc, s_acc);
         if (SYM) {
           // the chunk's sums of q_i H_ij go to u_j
           __syncthreads();
@@ -651,12 +642,12 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
               if (r0 + rr < tv.nrhs) {
-                const C a = s_acc[rr][l];
+                const double2 a = s_acc[rr][l];
                 const int64_t idx = (int64_t)(r0 + rr) * tv.n + j0 + l;
-                unsafeAtomicAdd(&us[idx].x, -0.25 * (double)a.y);  // (i/4) a
-                unsafeAtomicAdd(&us[idx].y, 0.25 * (double)a.x);
+                unsafeAtomicAdd(&us[idx].x, -0.25 * a.y);  // (i/4) a
+                unsafeAtomicAdd(&us[idx].y, 0.25 * a.x);
               }
-              s_acc[rr][l] = cmk((T)0, (T)0);
+              s_acc[rr][l] = cmk(0.0, 0.0);
             }
           }
         }
@@ -691,7 +682,7 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
   const int r0 = blockIdx.y * RB;  // first right-hand side of this block
   __shared__ double2 s_x[P2P_CS];
   __shared__ C s_q[RB][P2P_CS];
-  __shared__ C s_acc[RB][P2P_CS];
+  __shared__ double2 s_acc[RB][P2P_CS];
   const int li = blockIdx.x;
   if (li >= nleaves) return;
   constexpr int CL = CLS < kH0Classes ? CLS : kH0Classes - 1;
