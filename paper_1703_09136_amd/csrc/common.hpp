@@ -126,10 +126,13 @@ struct Panel {
   int32_t pad;
 };
 
-// Pairs per translation item: 64 (four 16-column MFMA tiles, one per wave) when
-// both expansions fit 64 coefficients, else 16 (the waves split the rows).
+// Pairs per translation item: one 16-column MFMA tile; the four waves of the
+// block split its row tiles. (Larger items, 32 or 64 pairs sharing the staged
+// table, measured slower: their source tiles cut the blocks per CU.)
 __host__ __device__ inline int trans_pairs_per_item(int Ps, int Pd) {
-  return (2 * Ps + 1 <= 64 && 2 * Pd + 1 <= 64) ? 64 : 16;
+  (void)Ps;
+  (void)Pd;
+  return 16;
 }
 
 // A work item of the batched translation contraction: one translation table
@@ -148,10 +151,12 @@ struct TransItem {
   int32_t ntw;
 };
 
-// Row tiles one item covers: ntw per wave, the four waves side by side (64
-// pairs per item) or interleaved over rows (16 pairs per item).
+// Row tiles one item covers: ntw per wave, the four waves interleaved over
+// the rows.
 __host__ __device__ inline int trans_rows_per_item(int Ps, int Pd, int ntw) {
-  return trans_pairs_per_item(Ps, Pd) == 64 ? ntw : 4 * ntw;
+  (void)Ps;
+  (void)Pd;
+  return 4 * ntw;
 }
 
 

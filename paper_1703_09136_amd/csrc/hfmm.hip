@@ -260,7 +260,7 @@ struct hfmm_plan_s {
   int leaf_pmax = 0;          // largest expansion order among the leaves
   // batched translations: item groups sharing (Ps, Pd), per level
   struct Group {
-    int first = 0, count = 0, Ps = 0, Pd = 0;
+    int first = 0, count = 0, Ps = 0, Pd = 0, ntw = 8;  // ntw: row tiles per wave of the items
   };
   // M2L: items, (source, target) pair arrays, contribution row offsets, and the
   // per-box lists of pairs for the reduction by target (forward) / by source
@@ -749,10 +749,13 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     for (int rt = 0; rt < nrt; rt += step) items.push_back(TransItem{table, pbeg, cnt, image, rt, Ps, Pd, ntw});
   };
   // row tiles per wave for a launch of `batches` pair batches: the most (up to
-  // 8, the longest MFMA chains) that still give about four blocks per CU
+  // 8, the longest MFMA chains, and no more than the rows need) that still
+  // give about four blocks per CU
   auto choose_ntw = [](int64_t batches, int Ps, int Pd) {
     const int nrt = (2 * (2 * Pd + 1) + 15) / 16;
-    for (int ntw = 8; ntw > 1; ntw /= 2) {
+    int ntw = 8;
+    while (ntw > 1 && trans_rows_per_item(Ps, Pd, ntw / 2) >= nrt) ntw /= 2;
+    for (; ntw > 1; ntw = (ntw + 1) / 2) {
       const int step = trans_rows_per_item(Ps, Pd, ntw);
       if (batches * ((nrt + step - 1) / step) >= 1024) return ntw;
     }
@@ -771,6 +774,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     for (size_t id = 0; id < pairs_of.size(); ++id)
       if (table_level[id] == l) batches += ((int64_t)pairs_of[id].size() + npi - 1) / npi;
     const int ntw = choose_ntw(batches, pl->P[l], pl->P[l]);
+    g.ntw = ntw;
     for (size_t id = 0; id < pairs_of.size(); ++id) {
       if (table_level[id] != l) continue;
       auto& v = pairs_of[id];
@@ -848,6 +852,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     for (int q = 0; q < 4; ++q) batches += ((int64_t)kids[q].size() + npi - 1) / npi;
     const int ntw_up = choose_ntw(batches, pl->P[l + 1], pl->P[l]);
     const int ntw_down = choose_ntw(batches, pl->P[l], pl->P[l + 1]);
+    gu.ntw = ntw_up;
+    gd.ntw = ntw_down;
     for (int q = 0; q < 4; ++q) {
       const std::vector<int>& kids_q = kids[q];
       for (size_t c0 = 0; c0 < kids_q.size(); c0 += npi) {
@@ -1314,7 +1320,7 @@ void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, in
   const int* pdst = up ? pl->cp_parent.p : pl->cp_child.p;
   // a child has one parent: parent -> child writes never collide
   launch_trans(s, tv, items, g.count, g.Ps, g.Pd, psrc, pdst, nullptr, tabs4, pl->tdata.p, src, dst, nullptr, 0, rev,
-               up ? 0 : 1);
+               up ? 0 : 1, g.ntw);
 }
 
 // All M2L items (forward: source -> target; transpose: target -> source) into
@@ -1324,7 +1330,7 @@ void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
   const int* pdst = rev ? pl->m2l_psrc.p : pl->m2l_pdst.p;
   for (const auto& g : pl->m2l_groups)
     launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, psrc, pdst, pl->m2l_pcoff.p, pl->tabs.p,
-                 pl->tdata.p, src, nullptr, pl->contrib.p, pl->cstride, rev, 0);
+                 pl->tdata.p, src, nullptr, pl->contrib.p, pl->cstride, rev, 0, g.ntw);
   launch_reduce_contrib(s, tv, pl->red_boxes.p, pl->nred_boxes, rev ? pl->redT_ptr.p : pl->red_ptr.p,
                         rev ? pl->redT_pairs.p : pl->red_pairs.p, pl->m2l_pcoff.p, pl->contrib.p, pl->cstride, dst);
 }

@@ -381,7 +381,10 @@ __device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, cons
   }
 }
 
-template <bool REV, int MODE>
+// NTMAX bounds the row tiles per wave of the launch: the register allocation
+// is that of the largest instantiated case, so launches with few row tiles use
+// a variant with NTMAX = 2 and more waves fit a SIMD.
+template <bool REV, int MODE, int NTMAX>
 __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const TransItem* __restrict__ items,
                                                           const int* __restrict__ psrc,
                                                           const int* __restrict__ pdst,
@@ -444,29 +447,26 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
       if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
   }
   __syncthreads();
-  // wave -> (column tile, row tiles): with 64 pairs per item each wave takes a
-  // column tile and it.ntw consecutive row tiles; with 16, the waves split up
-  // to 4 it.ntw row tiles with stride 4
-  int ntile, rt_lo, rt_stride, rt_cnt;
-  if (npi == 64) {
-    ntile = wave;
-    rt_lo = it.rt_base;
-    rt_stride = 1;
-    rt_cnt = min(nrt - rt_lo, it.ntw);
-  } else {
-    ntile = 0;
-    rt_lo = it.rt_base + wave;
-    rt_stride = 4;
-    rt_cnt = rt_lo < nrt ? min((nrt - rt_lo + 3) / 4, it.ntw) : 0;
-  }
+  // wave -> row tiles: the four waves split up to 4 it.ntw row tiles of the
+  // item's single column tile with stride 4
+  const int ntile = 0;
+  const int rt_lo = it.rt_base + wave, rt_stride = 4;
+  const int rt_cnt = rt_lo < nrt ? min((nrt - rt_lo + 3) / 4, it.ntw) : 0;
   if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
 #define HFMM_TILES(N)                                                                                           \
   case N:                                                                                                       \
     trans_tiles<REV, MODE, N>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r); \
     break;
-  switch (rt_cnt) {
-    HFMM_TILES(1) HFMM_TILES(2) HFMM_TILES(3) HFMM_TILES(4) HFMM_TILES(5) HFMM_TILES(6) HFMM_TILES(7)
-    default: trans_tiles<REV, MODE, 8>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r);
+  if (NTMAX <= 2) {
+    switch (rt_cnt) {
+      HFMM_TILES(1)
+      default: trans_tiles<REV, MODE, 2>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r);
+    }
+  } else {
+    switch (rt_cnt) {
+      HFMM_TILES(1) HFMM_TILES(2) HFMM_TILES(3) HFMM_TILES(4) HFMM_TILES(5) HFMM_TILES(6) HFMM_TILES(7)
+      default: trans_tiles<REV, MODE, 8>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r);
+    }
   }
 #undef HFMM_TILES
 }
@@ -1241,13 +1241,19 @@ size_t trans_lds_bytes(int Ps, int Pd) {
 // Dynamic LDS limit of the translation kernels: the CU's 160 KiB less each
 // kernel's static LDS. Called when a plan is built (before any launch or
 // graph capture); returns the first HIP error.
-template <bool REV, int MODE>
-static hipError_t trans_lds_limit() {
-  const void* f = (const void*)k_trans_mfma<REV, MODE>;
+template <bool REV, int MODE, int NTMAX>
+static hipError_t trans_lds_limit_one() {
+  const void* f = (const void*)k_trans_mfma<REV, MODE, NTMAX>;
   hipFuncAttributes fa;
   hipError_t e = hipFuncGetAttributes(&fa, f);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)fa.sharedSizeBytes);
+}
+
+template <bool REV, int MODE>
+static hipError_t trans_lds_limit() {
+  const hipError_t e = trans_lds_limit_one<REV, MODE, 2>();
+  return e != hipSuccess ? e : trans_lds_limit_one<REV, MODE, 8>();
 }
 
 hipError_t init_kernel_attributes() {
@@ -1260,20 +1266,25 @@ hipError_t init_kernel_attributes() {
 }
 
 template <bool REV, int MODE>
-static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, size_t lds,
+static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, size_t lds, int ntw,
                       const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
                       const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride) {
-  hipLaunchKernelGGL((k_trans_mfma<REV, MODE>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items, psrc,
-                     pdst, pcoff, tabs, tdata, src, dst, contrib, cstride);
+  if (ntw <= 2)
+    hipLaunchKernelGGL((k_trans_mfma<REV, MODE, 2>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items,
+                       psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride);
+  else
+    hipLaunchKernelGGL((k_trans_mfma<REV, MODE, 8>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items,
+                       psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride);
 }
 
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
                   const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
-                  int exclusive) {
+                  int exclusive, int ntw) {
   if (nitems <= 0) return;
   const size_t lds = trans_lds_bytes(Ps, Pd);
-#define HFMM_TRANS(R, M) trans_one<R, M>(s, tv, items, nitems, lds, psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride)
+#define HFMM_TRANS(R, M) \
+  trans_one<R, M>(s, tv, items, nitems, lds, ntw, psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride)
   if (contrib) {
     if (rev) HFMM_TRANS(true, OUT_CONTRIB); else HFMM_TRANS(false, OUT_CONTRIB);
   } else if (exclusive) {

@@ -22,10 +22,11 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
 // row at pcoff[pair] (plane stride cstride per right-hand side); otherwise the
 // result is added into dst of the pair's target box, atomically unless
 // exclusive says that no two pairs of the launch share a target box.
+// ntw: the row tiles per wave of the items (their largest value).
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
                   const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
-                  int exclusive);
+                  int exclusive, int ntw);
 void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
                            const int* pairs, const int64_t* pcoff, const double* contrib, int64_t cstride,
                            double2* dst);
