@@ -28,6 +28,17 @@ __host__ __device__ inline double2 cdiv(double2 a, double2 b) {
   double r = b.x / b.y, den = b.x * r + b.y;
   return cmk((a.x * r + a.y) / den, (a.y * r - a.x) / den);
 }
+// w^n for n >= 0 by repeated squaring (|w| = 1 here: the error grows with the
+// number of squarings, about log2 n roundings).
+__host__ __device__ inline double2 cpowi(double2 w, int n) {
+  double2 r = cmk(1.0, 0.0);
+  while (n > 0) {
+    if (n & 1) r = cmul(r, w);
+    w = cmul(w, w);
+    n >>= 1;
+  }
+  return r;
+}
 __host__ __device__ inline double cabs2(double2 a) { return hypot(a.x, a.y); }
 __host__ __device__ inline double2 cexp2(double2 a) {
   double e = exp(a.x);

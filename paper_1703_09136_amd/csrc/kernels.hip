@@ -53,26 +53,30 @@ __global__ void k_scatter(int n, int nrhs, const int* __restrict__ perm, const d
 
 // ------------------------------------------------------------------ P2M
 // alpha_p = sum_j q_j J_p(k rho_j) e^{-i p theta_j}, p in [-P, P] (Eq. multi_coeff).
-// One wave per leaf and group of up to P2M_RB right-hand sides (grid y; one
-// launch for all levels, the order read per leaf), a lane per point. Each lane walks the backward Bessel
-// recurrence once and parks V_{n,j} = J_n(k rho_j) w_j^n (w = e^{-i theta}) for a
-// chunk of P2M_CH orders in LDS; the chunk is then reduced over the points
-// for every right-hand side, giving alpha_n = sum q V and, through
-// J_{-n} = (-1)^n J_n, alpha_{-n} = (-1)^n sum q conj(V). The coefficients
+// One wave per leaf and group of up to RB right-hand sides (grid y; one
+// launch for all levels, the order read per leaf), a lane per point. Each lane
+// walks the backward Bessel recurrence once and parks V_{n,j} = J_n(k rho_j)
+// w_j^n (w = e^{-i theta}) for a chunk of P2M_CH orders in LDS; the chunk is
+// then reduced over the points for every right-hand side, giving
+// alpha_n = sum q V and, through J_{-n} = (-1)^n J_n,
+// alpha_{-n} = (-1)^n sum q conj(V). Both come from the four real sums
+// A = sum q.x v.x, B = sum q.y v.y, C = sum q.x v.y, D = sum q.y v.x:
+// sum q V = (A - B, C + D), sum q conj(V) = (A + B, D - C). The coefficients
 // accumulate in LDS and are stored once. With conj_w the phase is
 // e^{+i p theta} and the result is scaled by pref: the transpose of L2P.
 constexpr int P2M_CH = 8;   // orders per reduction chunk
-constexpr int P2M_RB = 4;   // right-hand sides per pass
+constexpr int P2M_RB = 4;   // right-hand sides per pass (several right-hand sides)
 constexpr int P2M_VS = WAVE + 1;  // padded row of the V tile
 constexpr int P2M_PARTS = WAVE / P2M_CH;  // lanes that share one order in the reduction
 
-__global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict__ leaves, int nleaves, int rb,
+template <int RB>
+__global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const double2* __restrict__ qs, double2* __restrict__ alpha,
                                               int conj_w, double2 pref) {
   extern __shared__ double2 lds_c[];
   double2* s_V = lds_c;                     // [P2M_CH][P2M_VS]
-  double2* s_q = s_V + P2M_CH * P2M_VS;     // [rb][WAVE]
-  double2* s_a = s_q + rb * WAVE;           // [rb][2P + 1]
+  double2* s_q = s_V + P2M_CH * P2M_VS;     // [RB][WAVE]
+  double2* s_a = s_q + RB * WAVE;           // [RB][2P + 1]
   const int li = blockIdx.x;
   if (li >= nleaves) return;
   const int b = leaves[li];
@@ -89,80 +93,82 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
     rmax = fmax(rmax, hypot(p.x - c.x, p.y - c.y));
   }
   for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
-  const int nstart = miller_start(tv.k * rmax, P);
+  const int nstart = miller_start_expansion(tv.k * rmax, P);
   // reduction role of this lane: order slot t of the chunk, point block part
   const int t_red = lane & (P2M_CH - 1), part = lane / P2M_CH;
-  {  // right-hand sides r0 .. r0 + rb - 1 (grid y)
-    const int r0 = blockIdx.y * rb;
-    const int nr = min(rb, tv.nrhs - r0);
-    for (int e = lane; e < nr * M; e += WAVE) s_a[e] = cmk(0.0, 0.0);
-    for (int j0 = pr.x; j0 < pr.y; j0 += WAVE) {
-      const int j = j0 + lane;
-      const bool valid = j < pr.y;
-      double dx = 0, dy = 0;
-      if (valid) {
-        double2 p = tv.pts[j];
-        dx = p.x - c.x;
-        dy = p.y - c.y;
+  const int r0 = blockIdx.y * RB;  // right-hand sides r0 .. r0 + nr - 1
+  const int nr = min(RB, tv.nrhs - r0);
+  for (int e = lane; e < nr * M; e += WAVE) s_a[e] = cmk(0.0, 0.0);
+  for (int j0 = pr.x; j0 < pr.y; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool valid = j < pr.y;
+    double dx = 0, dy = 0;
+    if (valid) {
+      double2 p = tv.pts[j];
+      dx = p.x - c.x;
+      dy = p.y - c.y;
+    }
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr)
+      if (rr < nr) s_q[rr * WAVE + lane] = valid ? qs[(int64_t)(r0 + rr) * tv.n + j] : cmk(0.0, 0.0);
+    const double rho = hypot(dx, dy);
+    const double x = fmax(tv.k * rho, 1e-100);
+    const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1.0, 0.0);
+    double2 wn = cpowi(w, P);
+    double inv_s;
+    int nres;
+    miller_norm(x, nstart, inv_s, nres);
+    MillerWalk mw(x, nstart, inv_s, nres);
+    while (mw.n > P) mw.step();
+    for (int nh = P; nh >= 0; nh -= P2M_CH) {
+#pragma unroll
+      for (int t = 0; t < P2M_CH; ++t) {
+        if (nh - t >= 0) {
+          s_V[t * P2M_VS + lane] = cscale(wn, valid ? mw.value() : 0.0);
+          wn = cmul(wn, cconj(w));
+          if (mw.n > 0) mw.step();
+        }
       }
+      __syncthreads();
+      const int n = nh - t_red;
 #pragma unroll
-      for (int rr = 0; rr < P2M_RB; ++rr)
-        if (rr < nr) s_q[rr * WAVE + lane] = valid ? qs[(int64_t)(r0 + rr) * tv.n + j] : cmk(0.0, 0.0);
-      const double rho = hypot(dx, dy);
-      const double x = fmax(tv.k * rho, 1e-100);
-      const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1.0, 0.0);
-      double sn, cs;
-      sincos((double)P * atan2(w.y, w.x), &sn, &cs);
-      double2 wn = cmk(cs, sn);  // w^P
-      double inv_s;
-      int nres;
-      miller_norm(x, nstart, inv_s, nres);
-      MillerWalk mw(x, nstart, inv_s, nres);
-      while (mw.n > P) mw.step();
-      for (int nh = P; nh >= 0; nh -= P2M_CH) {
+      for (int rr = 0; rr < RB; ++rr) {
+        if (rr >= nr) break;
+        double A = 0.0, B = 0.0, C = 0.0, D = 0.0;
+        if (n >= 0) {
+          const double2* V = s_V + t_red * P2M_VS + part * (WAVE / P2M_PARTS);
+          const double2* Q = s_q + rr * WAVE + part * (WAVE / P2M_PARTS);
 #pragma unroll
-        for (int t = 0; t < P2M_CH; ++t) {
-          if (nh - t >= 0) {
-            s_V[t * P2M_VS + lane] = cscale(wn, valid ? mw.value() : 0.0);
-            wn = cmul(wn, cconj(w));
-            if (mw.n > 0) mw.step();
+          for (int i = 0; i < WAVE / P2M_PARTS; ++i) {
+            const double2 v = V[i], q = Q[i];
+            A = fma(q.x, v.x, A);
+            B = fma(q.y, v.y, B);
+            C = fma(q.x, v.y, C);
+            D = fma(q.y, v.x, D);
           }
         }
-        __syncthreads();
-        const int n = nh - t_red;
 #pragma unroll
-        for (int rr = 0; rr < P2M_RB; ++rr) {
-          if (rr >= nr) break;
-          double2 sp = cmk(0.0, 0.0), sm = cmk(0.0, 0.0);
-          if (n >= 0) {
-            const double2* V = s_V + t_red * P2M_VS + part * (WAVE / P2M_PARTS);
-            const double2* Q = s_q + rr * WAVE + part * (WAVE / P2M_PARTS);
-#pragma unroll
-            for (int i = 0; i < WAVE / P2M_PARTS; ++i) {
-              const double2 v = V[i], q = Q[i];
-              sp = cadd(sp, cmul(q, v));
-              sm = cadd(sm, cmul(q, cconj(v)));
-            }
-          }
-#pragma unroll
-          for (int m = P2M_CH; m < WAVE; m <<= 1) {
-            sp = cadd(sp, shfl_xor_c(sp, m));
-            sm = cadd(sm, shfl_xor_c(sm, m));
-          }
-          if (part == 0 && n >= 0) {
-            double2* a = s_a + rr * M + P;
-            a[n] = cadd(a[n], cmul(pref, sp));
-            if (n > 0) a[-n] = cadd(a[-n], cmul(pref, (n & 1) ? cscale(sm, -1.0) : sm));
+        for (int m = P2M_CH; m < WAVE; m <<= 1) {
+          A += __shfl_xor(A, m, WAVE);
+          B += __shfl_xor(B, m, WAVE);
+          C += __shfl_xor(C, m, WAVE);
+          D += __shfl_xor(D, m, WAVE);
+        }
+        if (part == 0 && n >= 0) {
+          double2* a = s_a + rr * M + P;
+          a[n] = cadd(a[n], cmul(pref, cmk(A - B, C + D)));
+          if (n > 0) {
+            const double2 sm = cmk(A + B, D - C);
+            a[-n] = cadd(a[-n], cmul(pref, (n & 1) ? cscale(sm, -1.0) : sm));
           }
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
-    for (int e = lane; e < nr * M; e += WAVE) {
-      const int rr = e / M;
-      alpha[(int64_t)(r0 + rr) * tv.ctot + cb + (e - rr * M)] = s_a[e];
-    }
-    __syncthreads();
+  }
+  for (int e = lane; e < nr * M; e += WAVE) {
+    const int rr = e / M;
+    alpha[(int64_t)(r0 + rr) * tv.ctot + cb + (e - rr * M)] = s_a[e];
   }
 }
 
@@ -172,16 +178,21 @@ size_t p2m_lds_bytes(int Pmax, int rb) {
 
 // ------------------------------------------------------------------ L2P
 // u_i (+)= pref * sum_p beta_p J_p(k r_i) e^{i p theta_i} (local expansion,
-// Section 3.2). One wave per leaf and group of up to L2P_RB right-hand sides
-// (grid y), a lane per point; the group's coefficients are staged in LDS and
-// one recurrence walk serves all of them. With conj_w the phase is e^{-i p theta_i}: the
-// transpose of P2M, used by the adjoint.
+// Section 3.2). One wave per leaf and group of up to RB right-hand sides
+// (grid y), a lane per point; one recurrence walk serves the whole group.
+// With w = e^{i theta}, a_n = beta_n and b_n = (-1)^n beta_{-n}, the orders
+// +n and -n together give J_n (a_n w^n + b_n conj(w^n)); with
+// s = a + b, d = a - b and (J_n w^n) = (c, e) this is
+// (s.x c - d.y e, d.x e + s.y c), four multiply-adds per order. The group's
+// s_n and d_n (b_0 = 0) are staged in LDS. With conj_w the phase is
+// e^{-i p theta_i}: the transpose of P2M, used by the adjoint.
 constexpr int L2P_RB = 4;
 
-__global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict__ leaves, int nleaves, int rb,
+template <int RB>
+__global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const double2* __restrict__ beta, double2* __restrict__ us,
                                               int conj_w, double2 pref, int accumulate) {
-  extern __shared__ double2 lds_c[];  // [rb][2P + 1]
+  extern __shared__ double2 lds_c[];  // [RB][P + 1][s, d]
   const int li = blockIdx.x;
   if (li >= nleaves) return;
   const int b = leaves[li];
@@ -189,10 +200,11 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
   const int lev = tv.level[b];
   const bool has_local = lev >= 2;
   const int P = tv.P[lev];
-  const int M = 2 * P + 1;
   const int2 pr = tv.prange[b];
   const double2 c = tv.ctr[b];
   const int64_t cb = tv.coff[b];
+  const int r0 = blockIdx.y * RB;  // right-hand sides r0 .. r0 + nr - 1
+  const int nr = min(RB, tv.nrhs - r0);
   int nstart = 0;
   if (has_local) {
     double rmax = 0.0;
@@ -201,68 +213,60 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
       rmax = fmax(rmax, hypot(p.x - c.x, p.y - c.y));
     }
     for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
-    nstart = miller_start(tv.k * rmax, P);
+    nstart = miller_start_expansion(tv.k * rmax, P);
+    for (int e = lane; e < nr * (P + 1); e += WAVE) {
+      const int rr = e / (P + 1), n = e - rr * (P + 1);
+      const double2* bt = beta + (int64_t)(r0 + rr) * tv.ctot + cb + P;
+      const double2 an = bt[n];
+      double2 bn = n > 0 ? bt[-n] : cmk(0.0, 0.0);
+      if (n & 1) bn = cscale(bn, -1.0);
+      lds_c[2 * e] = cadd(an, bn);
+      lds_c[2 * e + 1] = csub(an, bn);
+    }
+    __syncthreads();
   }
-  {  // right-hand sides r0 .. r0 + rb - 1 (grid y)
-    const int r0 = blockIdx.y * rb;
-    const int nr = min(rb, tv.nrhs - r0);
+  for (int j = pr.x + lane; j < pr.y; j += WAVE) {
+    double2 acc[RB];
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) acc[rr] = cmk(0.0, 0.0);
     if (has_local) {
-      for (int e = lane; e < nr * M; e += WAVE) {
-        const int rr = e / M;
-        lds_c[e] = beta[(int64_t)(r0 + rr) * tv.ctot + cb + (e - rr * M)];
-      }
-      __syncthreads();
-    }
-    for (int j = pr.x + lane; j < pr.y; j += WAVE) {
-      double2 acc[L2P_RB];
+      const double2 p = tv.pts[j];
+      const double dx = p.x - c.x, dy = p.y - c.y;
+      const double rho = hypot(dx, dy);
+      const double x = fmax(tv.k * rho, 1e-100);
+      const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1.0, 0.0);
+      double2 wn = cpowi(w, P);
+      double inv_s;
+      int nres;
+      miller_norm(x, nstart, inv_s, nres);
+      MillerWalk mw(x, nstart, inv_s, nres);
+      while (mw.n > P) mw.step();
+      for (int n = P; n >= 0; --n) {
+        const double2 jw = cscale(wn, mw.value());
 #pragma unroll
-      for (int rr = 0; rr < L2P_RB; ++rr) acc[rr] = cmk(0.0, 0.0);
-      if (has_local) {
-        const double2 p = tv.pts[j];
-        const double dx = p.x - c.x, dy = p.y - c.y;
-        const double rho = hypot(dx, dy);
-        const double x = fmax(tv.k * rho, 1e-100);
-        const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1.0, 0.0);
-        double sn, cs;
-        sincos((double)P * atan2(w.y, w.x), &sn, &cs);
-        double2 wn = cmk(cs, sn);  // w^P
-        double inv_s;
-        int nres;
-        miller_norm(x, nstart, inv_s, nres);
-        MillerWalk mw(x, nstart, inv_s, nres);
-        while (mw.n > P) mw.step();
-        for (int n = P; n >= 0; --n) {
-          const double jn = mw.value();
-#pragma unroll
-          for (int rr = 0; rr < L2P_RB; ++rr) {
-            if (rr < nr) {
-              const double2* bt = lds_c + rr * M + P;
-              double2 t = cmul(bt[n], wn);
-              if (n > 0) {
-                const double2 tm = cmul(bt[-n], cconj(wn));
-                t = (n & 1) ? csub(t, tm) : cadd(t, tm);
-              }
-              acc[rr] = cadd(acc[rr], cscale(t, jn));
-            }
+        for (int rr = 0; rr < RB; ++rr) {
+          if (rr < nr) {
+            const double2 sn = lds_c[2 * (rr * (P + 1) + n)], dn = lds_c[2 * (rr * (P + 1) + n) + 1];
+            acc[rr].x = fma(sn.x, jw.x, fma(-dn.y, jw.y, acc[rr].x));
+            acc[rr].y = fma(dn.x, jw.y, fma(sn.y, jw.x, acc[rr].y));
           }
-          wn = cmul(wn, cconj(w));
-          if (n > 0) mw.step();
         }
-      }
-#pragma unroll
-      for (int rr = 0; rr < L2P_RB; ++rr) {
-        if (rr < nr) {
-          const int64_t idx = (int64_t)(r0 + rr) * tv.n + j;
-          const double2 v = cmul(pref, acc[rr]);
-          us[idx] = accumulate ? cadd(us[idx], v) : v;
-        }
+        wn = cmul(wn, cconj(w));
+        if (n > 0) mw.step();
       }
     }
-    if (has_local) __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr) {
+      if (rr < nr) {
+        const int64_t idx = (int64_t)(r0 + rr) * tv.n + j;
+        const double2 v = cmul(pref, acc[rr]);
+        us[idx] = accumulate ? cadd(us[idx], v) : v;
+      }
+    }
   }
 }
 
-size_t l2p_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * (2 * Pmax + 1)); }
+size_t l2p_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * 2 * (Pmax + 1)); }
 
 // ------------------------------------------------------------------ batched translations on MFMA
 // For one table t (t[n], n = m - p, m in [-Ps, Ps] source orders, p in
@@ -730,7 +734,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __res
       rmax = fmax(rmax, hypot(p.x - c.x, p.y - c.y));
     }
     for (int m = 1; m < WAVE; m <<= 1) rmax = fmax(rmax, __shfl_xor(rmax, m, WAVE));
-    nstart = miller_start(tv.k * rmax, Pg);
+    nstart = miller_start_expansion(tv.k * rmax, Pg);
   }
   for (int r0 = 0; r0 < tv.nrhs; r0 += rb) {
     const int nr = min(rb, tv.nrhs - r0);
@@ -752,9 +756,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __res
         const double rho = hypot(dx, dy);
         const double x = fmax(tv.k * rho, 1e-100);
         const double2 w = rho > 0 ? cmk(dx / rho, -dy / rho) : cmk(1, 0);  // e^{-i theta}
-        double sn, cs;
-        sincos((double)Pg * atan2(w.y, w.x), &sn, &cs);
-        double2 wn = cmk(cs, sn);  // w^Pg
+        double2 wn = cpowi(w, Pg);
         double inv_s;
         int nres;
         miller_norm(x, nstart, inv_s, nres);
@@ -1217,18 +1219,22 @@ void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
                 double2* alpha, int conj_w, double2 pref) {
   if (nl <= 0) return;
   // at most 37 KiB (Pmax = 255): within the default dynamic LDS limit
-  const int rb = min(P2M_RB, tv.nrhs);
-  hipLaunchKernelGGL(k_p2m, dim3(nl, (tv.nrhs + rb - 1) / rb), dim3(WAVE), p2m_lds_bytes(Pmax, rb), s, tv, leaves,
-                     nl, rb, qs, alpha, conj_w,
-                     pref);
+  if (tv.nrhs == 1)
+    hipLaunchKernelGGL(k_p2m<1>, dim3(nl, 1), dim3(WAVE), p2m_lds_bytes(Pmax, 1), s, tv, leaves, nl, qs, alpha,
+                       conj_w, pref);
+  else
+    hipLaunchKernelGGL(k_p2m<P2M_RB>, dim3(nl, (tv.nrhs + P2M_RB - 1) / P2M_RB), dim3(WAVE),
+                       p2m_lds_bytes(Pmax, P2M_RB), s, tv, leaves, nl, qs, alpha, conj_w, pref);
 }
 void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
                 double2* us, int conj_w, double2 pref, int accumulate) {
   if (nl <= 0) return;
-  const int rb = min(L2P_RB, tv.nrhs);
-  hipLaunchKernelGGL(k_l2p, dim3(nl, (tv.nrhs + rb - 1) / rb), dim3(WAVE), l2p_lds_bytes(Pmax, rb), s, tv, leaves,
-                     nl, rb, beta, us, conj_w,
-                     pref, accumulate);
+  if (tv.nrhs == 1)
+    hipLaunchKernelGGL(k_l2p<1>, dim3(nl, 1), dim3(WAVE), l2p_lds_bytes(Pmax, 1), s, tv, leaves, nl, beta, us,
+                       conj_w, pref, accumulate);
+  else
+    hipLaunchKernelGGL(k_l2p<L2P_RB>, dim3(nl, (tv.nrhs + L2P_RB - 1) / L2P_RB), dim3(WAVE),
+                       l2p_lds_bytes(Pmax, L2P_RB), s, tv, leaves, nl, beta, us, conj_w, pref, accumulate);
 }
 // LDS bytes of a translation item: the padded table (real, imaginary and
 // negated imaginary parts) and the padded source-coefficient tile.

@@ -24,6 +24,27 @@ __host__ __device__ inline int miller_start(double x, int nmax) {
   return (int)(m + 20.0 + 12.0 * cbrt(m + 1.0));
 }
 
+// Start index for the expansions at a leaf, orders 0..nmax at arguments up to
+// x, when nmax is well above x (nmax >= 2x + 2; otherwise the general start
+// above). For m >= nmax > x the ratio J_{m+1}(x) / J_m(x) is at most
+// x / (2(m + 1) - x): the continued fraction of the ratio, every later ratio
+// being below one. A backward walk started at N computes
+// J_n - (J_{N+1} / Y_{N+1}) Y_n up to normalisation, a relative error of
+// (J_{N+1} Y_n) / (Y_{N+1} J_n); at large order J_m Y_m ~ -1 / (pi m), so at
+// n = nmax (the worst order) it is about (J_{N+1} / J_nmax)^2 (N + 1) / nmax.
+// The start is two past the index where the bound of J_{N+1} / J_nmax falls
+// below 1e-10, so that this error stays under 1e-19.
+__host__ __device__ inline int miller_start_expansion(double x, int nmax) {
+  if (!((double)nmax >= 2.0 * x + 2.0)) return miller_start(x, nmax);
+  double r = 1.0;  // bound of J_m / J_nmax
+  int m = nmax;
+  while (r > 1e-10) {
+    r *= x / (2.0 * (double)(m + 1) - x);
+    ++m;
+  }
+  return m + 1;
+}
+
 constexpr double kRescaleHi = 0x1p+700;   // rescale when |J| exceeds this
 constexpr double kRescaleBy = 0x1p-700;
 
