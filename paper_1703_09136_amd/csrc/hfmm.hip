@@ -296,6 +296,9 @@ struct hfmm_plan_s {
   DevBuf<double2> qs, us, alpha, beta;
   DevBuf<double2> gq, gs;  // coordinate gradient: sorted q, per-point (d/dx, d/dy)
   hfmm_info_t info{};
+  // the near field runs on a stream of its own, beside the far-field chain
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // stage timing
   bool prof_on = false;
   std::vector<std::vector<hipEvent_t>> prof_pending;
@@ -330,6 +333,11 @@ struct hfmm_plan_s {
     tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release(); gq.release(); gs.release();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
+    ev_fork = ev_join = nullptr;
+    side = nullptr;
   }
 };
 
@@ -490,6 +498,15 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     delete pl;
     return s;
   };
+  {
+    hipError_t e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      fail(HFMM_ERR_DEVICE, std::string("plan stream: ") + hipGetErrorString(e));
+      return bail(HFMM_ERR_DEVICE);
+    }
+  }
   pl->precision = o.precision;
   pl->n = (int)n;
   pl->tol = tol;
@@ -1303,10 +1320,11 @@ void launch_p2m_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
   launch_p2m(s, tv, pl->leaves.p + b0, b1 - b0, pl->leaf_pmax, qs, alpha, conj_w, pref);
 }
 
-// L2P (or P2M^T) over all leaves, one launch; the first writer of u.
+// L2P (or P2M^T) over all leaves, one launch: stores u, or adds atomically
+// (accumulate = 2) while the near field adds into it.
 void launch_l2p_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* beta, double2* us, int conj_w,
-                    double2 pref) {
-  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, beta, us, conj_w, pref, 0);
+                    double2 pref, int accumulate) {
+  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, beta, us, conj_w, pref, accumulate);
 }
 
 // One level of child -> parent (up) or parent -> child (down) translations.
@@ -1335,8 +1353,47 @@ void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
                         rev ? pl->redT_pairs.p : pl->red_pairs.p, pl->m2l_pcoff.p, pl->contrib.p, pl->cstride, dst);
 }
 
-void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
+// The direct parts (free-space pairs and near-interface pairs) add into us
+// atomically.
+void launch_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* qs, double2* us, Marker* mark) {
+  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, qs, us,
+             pl->precision == HFMM_FP32);
+  if (mark) (*mark)();
+  launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
+               pl->qkx.p, qs, us);
+  if (mark) (*mark)();
+}
+
+// Fork: us is cleared and the near field starts on the plan's side stream
+// while the far-field chain runs on s; every writer of us then adds
+// atomically. join() makes s wait for the side stream.
+hipError_t fork_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* qs, double2* us) {
+  launch_fill_zero(s, us, (int64_t)tv.nrhs * pl->n);
+  hipError_t e = hipEventRecord(pl->ev_fork, s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(pl->side, pl->ev_fork, 0);
+  if (e != hipSuccess) return e;
+  launch_near(pl, tv, pl->side, qs, us, nullptr);
+  return hipEventRecord(pl->ev_join, pl->side);
+}
+hipError_t join_near(hfmm_plan_t pl, hipStream_t s) { return hipStreamWaitEvent(s, pl->ev_join, 0); }
+
+// Whether s is being captured into a graph (or its state is unknown). A
+// capture keeps every stage on s: the fork onto the side stream is not used
+// there (a batch capture, which already forks per plan, crashed in the
+// runtime with it).
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
+
+// With stage timing on (mark.ev set) the stages run one after another on s.
+hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
   TreeView tv = pl->view(nrhs);
+  const bool overlap = mark.ev == nullptr && !capturing(s);
+  if (overlap) {
+    const hipError_t e = fork_near(pl, tv, s, qs, us);
+    if (e != hipSuccess) return e;
+  }
   // parents accumulate their children's translated multipoles
   launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
   launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
@@ -1347,19 +1404,22 @@ void forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs
   mark();
   for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0);
   mark();
-  launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25));
+  launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25), overlap ? 2 : 0);
   mark();
-  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, qs, us,
-             pl->precision == HFMM_FP32);
-  mark();
-  launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
-               pl->qkx.p, qs, us);
-  mark();
+  if (overlap) return join_near(pl, s);
+  launch_near(pl, tv, s, qs, us, &mark);
+  return hipSuccess;
 }
 
 // w_sorted = A^T v_sorted through the transposes of the stages, in reverse order.
-void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* vs, double2* ws) {
+hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* vs, double2* ws) {
   TreeView tv = pl->view(nrhs);
+  // the direct parts are symmetric: the same near field, beside the far field
+  const bool overlap = !capturing(s);
+  if (overlap) {
+    const hipError_t e = fork_near(pl, tv, s, vs, ws);
+    if (e != hipSuccess) return e;
+  }
   // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}; parents accumulate
   launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
   launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
@@ -1370,12 +1430,10 @@ void transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* 
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
   for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1);
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
-  launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0));
-  // the direct parts are symmetric
-  launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, vs, ws,
-             pl->precision == HFMM_FP32);
-  launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
-               pl->qkx.p, vs, ws);
+  launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0), overlap ? 2 : 0);
+  if (overlap) return join_near(pl, s);
+  launch_near(pl, tv, s, vs, ws, nullptr);
+  return hipSuccess;
 }
 
 }  // namespace
@@ -1402,7 +1460,7 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
     mark();
     launch_gather(s, pl->n, nc, pl->perm.p, qc, pl->qs.p, 0);
     mark();
-    forward_pipeline(pl, nc, s, pl->qs.p, pl->us.p, mark);
+    HIP_TRY(forward_pipeline(pl, nc, s, pl->qs.p, pl->us.p, mark));
     launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, uc, 0);
     mark();
   }
@@ -1462,7 +1520,7 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
     const int64_t off = (int64_t)r0 * pl->n;
     // A^H v = conj(A^T conj(v))
     launch_gather(s, pl->n, nc, pl->perm.p, (const double2*)v + off, pl->qs.p, 1);
-    transpose_pipeline(pl, nc, s, pl->qs.p, pl->us.p);
+    HIP_TRY(transpose_pipeline(pl, nc, s, pl->qs.p, pl->us.p));
     launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, (double2*)w + off, 1);
     if (grad_xy) {
       // g_j = Re(q_j sum_i conj(v_i) dA_ij/dx_j): the transposed pipeline has

@@ -260,7 +260,12 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
       if (rr < nr) {
         const int64_t idx = (int64_t)(r0 + rr) * tv.n + j;
         const double2 v = cmul(pref, acc[rr]);
-        us[idx] = accumulate ? cadd(us[idx], v) : v;
+        if (accumulate == 2) {
+          unsafeAtomicAdd(&us[idx].x, v.x);
+          unsafeAtomicAdd(&us[idx].y, v.y);
+        } else {
+          us[idx] = accumulate ? cadd(us[idx], v) : v;
+        }
       }
     }
   }
@@ -937,9 +942,10 @@ __global__ void __launch_bounds__(WAVE) k_iface(TreeView tv, const int* __restri
             }
         }
       }
-      if (valid) {
+      if (valid) {  // other writers of us may run at the same time
         int64_t idx = (int64_t)r * tv.n + i;
-        us[idx] = cadd(us[idx], acc);
+        unsafeAtomicAdd(&us[idx].x, acc.x);
+        unsafeAtomicAdd(&us[idx].y, acc.y);
       }
     }
   }

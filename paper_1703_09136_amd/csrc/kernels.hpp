@@ -12,7 +12,8 @@ void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const doubl
 hipError_t init_kernel_attributes();
 
 // P2M and L2P over a list of leaves; each block reads its leaf's order, Pmax
-// bounds the orders of the list (sizes the LDS).
+// bounds the orders of the list (sizes the LDS). L2P stores into us
+// (accumulate = 0), adds with a read-modify-write (1) or adds atomically (2).
 void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* qs,
                 double2* alpha, int conj_w, double2 pref);
 void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
