@@ -544,7 +544,7 @@ constexpr int P2P_CS = 128;  // sources per staged chunk
 template <typename T, int RB, int M, bool LARGE, bool SYM>
 __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, double2 xi, const cplx_t<T>* qi,
                                  T qk2, const double2* s_x, const cplx_t<T> (*s_q)[P2P_CS], cplx_t<T> acc[RB],
-                                 double2 (*s_acc)[P2P_CS]) {
+                                 double2 (*s_acc)[P2P_CS], const double2* s_ln) {
   using C = cplx_t<T>;
   const int K = (cnt - sub + g - 1) / g;  // sources of this lane's class
   const int r0 = K > 0 ? rot % K : 0;
@@ -574,13 +574,16 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, do
       z[u] = use[u] ? zz : (T)1.0;
     }
     T hr[4], hi[4];
-    hankel0_x4<T, M, LARGE>(z, hr, hi);
+    hankel0_x4<T, M, LARGE>(z, hr, hi, s_ln);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const T w = use[u] ? (T)1.0 : (T)0.0;
       const C hw = cmk(hr[u] * w, hi[u] * w);
 #pragma unroll
-      for (int rr = 0; rr < RB; ++rr) acc[rr] = cadd(acc[rr], cmul(hw, qv[u][rr]));
+      for (int rr = 0; rr < RB; ++rr) {
+        acc[rr].x = fma(hw.x, qv[u][rr].x, fma(-hw.y, qv[u][rr].y, acc[rr].x));
+        acc[rr].y = fma(hw.x, qv[u][rr].y, fma(hw.y, qv[u][rr].x, acc[rr].y));
+      }
       if (SYM && use[u]) {
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
@@ -598,7 +601,7 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, do
 template <typename T, int RB, int M, bool LARGE, bool SYM>
 __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const int2* __restrict__ rng,
                                 const double2* __restrict__ qs, double2* __restrict__ us, int r0, double2* s_x,
-                                cplx_t<T> (*s_q)[P2P_CS], double2 (*s_acc)[P2P_CS]) {
+                                cplx_t<T> (*s_q)[P2P_CS], double2 (*s_acc)[P2P_CS], const double2* s_ln) {
   using C = cplx_t<T>;
   const int lane = threadIdx.x;
   const int2 pr = tv.prange[b];
@@ -643,7 +646,8 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
         }
         __syncthreads();
         if (valid)
-          p2p_chunk<T, RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, xi, qi, qk2, s_x, s_q, acc, s_acc);
+          p2p_chunk<T, RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, xi, qi, qk2, s_x, s_q, acc, s_acc,
+                                          s_ln);
         if (SYM) {
           // the chunk's sums of q_i H_ij go to u_j
           __syncthreads();
@@ -692,15 +696,18 @@ __global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict
   __shared__ double2 s_x[P2P_CS];
   __shared__ C s_q[RB][P2P_CS];
   __shared__ double2 s_acc[RB][P2P_CS];
+  __shared__ double2 s_ln[1 << kLogTabBits];  // logarithm bins (FP64)
   const int li = blockIdx.x;
   if (li >= nleaves) return;
+  if (sizeof(T) == 8)  // the first chunk's barrier orders these stores before any use
+    for (int l = threadIdx.x; l < (1 << kLogTabBits); l += WAVE) s_ln[l] = cmk(kLogTab[l][0], kLogTab[l][1]);
   constexpr int CL = CLS < kH0Classes ? CLS : kH0Classes - 1;
   constexpr int M = sizeof(T) == 8 ? kH0ClassTerms[CL] : kH0ClassTermsF32[CL];
   constexpr bool LARGE = CLS >= kH0Classes;
   if (sym[li])
-    p2p_item<T, RB, M, LARGE, true>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
+    p2p_item<T, RB, M, LARGE, true>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc, s_ln);
   else
-    p2p_item<T, RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc);
+    p2p_item<T, RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc, s_ln);
 }
 
 // ------------------------------------------------------------------ source-coordinate gradient

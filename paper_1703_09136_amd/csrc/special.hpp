@@ -16,6 +16,7 @@
 #include "common.hpp"
 #include "h0_cheb.hpp"
 #include "h1_cheb.hpp"
+#include "log_table.hpp"
 
 namespace hfmm {
 
@@ -278,14 +279,38 @@ __device__ inline float log_pos(float z) {
   return fmaf(de, ln2_hi, fmaf(de, ln2_lo, ln_m));
 }
 
+// ln z for z > 0 (normal) from the mantissa bins of log_table.hpp, tab[i] =
+// {a_i, -ln a_i} (staged in LDS by the caller): with z = 2^e m, m in [1, 2)
+// in bin i, ln z = e ln 2 - ln a_i + ln(1 + r), r = m a_i - 1 (one fused
+// multiply-add, |r| <= 2^-7), and ln(1 + r) = r - r^2/2 + ... + r^7/7 (the
+// first dropped term is below 2^-59). ln 2 is split so that e ln2_hi is exact.
+__device__ inline double log_tab(double z, const double2* tab) {
+  int e;
+  const double m = 2.0 * frexp(z, &e);  // [1, 2), z = 2^(e - 1) m
+  const int i = (__double2hiint(m) >> (20 - kLogTabBits)) & ((1 << kLogTabBits) - 1);
+  const double2 t = tab[i];
+  const double r = fma(m, t.x, -1.0);
+  double w = fma(r, 1.0 / 7.0, -1.0 / 6.0);
+  w = fma_uniform(w, r, 1.0 / 5.0);
+  w = fma_uniform(w, r, -0.25);
+  w = fma_uniform(w, r, 1.0 / 3.0);
+  w = fma_uniform(w, r, -0.5);
+  const double p = fma(w, r * r, r);
+  const double ln2_hi = 0x1.62e42fefa3800p-1;
+  const double ln2_lo = 0x1.ef35793c76730p-45;
+  const double de = (double)(e - 1);
+  return fma(de, ln2_hi, fma(de, ln2_lo, t.y) + p);
+}
+
 // Four values of H_0^(1) at once from z_u = x_u^2/4, in the precision T,
 // by the ascending series with M terms and the four Horner chains
 // interleaved. M is chosen by the caller from a bound on z: the first dropped
 // term max(|c_M|, |d_M|) z^M stays below the precision's half-ulp for
 // z <= the class bound (from the closed forms of c_M and d_M). With LARGE,
-// entries with z > 9 (x > 6) take the FP64 large-argument form.
+// entries with z > 9 (x > 6) take the FP64 large-argument form. In FP64 the
+// logarithm takes the bin table ltab (LDS).
 template <typename T, int M, bool LARGE>
-__device__ inline void hankel0_x4(const T z[4], T hr[4], T hi[4]) {
+__device__ inline void hankel0_x4(const T z[4], T hr[4], T hi[4], const double2* ltab) {
   T j[4], s[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -306,7 +331,12 @@ __device__ inline void hankel0_x4(const T z[4], T hr[4], T hi[4]) {
   for (int u = 0; u < 4; ++u) {
     if (!LARGE || z[u] <= (T)9.0) {
       hr[u] = j[u];
-      hi[u] = two_over_pi * (((T)0.5 * log_pos(z[u]) + euler) * j[u] + s[u]);
+      T lz;
+      if constexpr (sizeof(T) == 8)
+        lz = log_tab(z[u], ltab);
+      else
+        lz = log_pos(z[u]);
+      hi[u] = two_over_pi * (((T)0.5 * lz + euler) * j[u] + s[u]);
     } else {
       const double2 h = hankel0_large_call(2.0 * sqrt((double)z[u]));
       hr[u] = (T)h.x;
