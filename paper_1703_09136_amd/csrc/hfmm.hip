@@ -266,10 +266,13 @@ struct hfmm_plan_s {
   // per-box lists of pairs for the reduction by target (forward) / by source
   DevBuf<TransItem> m2l_items;
   DevBuf<int> m2l_psrc, m2l_pdst;
-  DevBuf<int64_t> m2l_pcoff;
+  DevBuf<int64_t> m2l_pcoff, m2l_pcoffT;  // row offsets: grouped by target box / by source box
   std::vector<Group> m2l_groups;
   int64_t cstride = 0;  // contribution doubles per right-hand side
-  DevBuf<int> red_boxes, red_ptr, red_pairs, redT_ptr, redT_pairs;
+  // reductions: boxes of levels >= 2, pair counts per box (CSR) by target and
+  // by source, and where each box's rows begin
+  DevBuf<int> red_boxes, red_ptr, redT_ptr;
+  DevBuf<int64_t> red_beg, redT_beg;
   int nred_boxes = 0;
   // M2M / L2L: (child, parent) pairs grouped by parent level and quadrant;
   // items shaped child -> parent (up) and parent -> child (down), by parent level
@@ -327,8 +330,8 @@ struct hfmm_plan_s {
   void release_all() {
     pts.release(); ctr.release(); perm.release(); level.release(); parent.release(); quad.release();
     child.release(); prange.release(); coff.release(); leaves.release();
-    m2l_items.release(); m2l_psrc.release(); m2l_pdst.release(); m2l_pcoff.release(); red_boxes.release();
-    red_ptr.release(); red_pairs.release(); redT_ptr.release(); redT_pairs.release(); cp_child.release();
+    m2l_items.release(); m2l_psrc.release(); m2l_pdst.release(); m2l_pcoff.release(); m2l_pcoffT.release();
+    red_boxes.release(); red_ptr.release(); red_beg.release(); redT_ptr.release(); redT_beg.release(); cp_child.release();
     cp_parent.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
@@ -758,7 +761,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   // batched M2L items: per level, per table, batches of up to 64 pairs (16 when
   // 2P+1 > 64), and groups of row tiles of the real-embedded operator (ntw per
   // wave). Each pair owns a contribution row of 2(2P+1) doubles, reduced per
-  // box afterwards.
+  // box afterwards: the rows of one target box are contiguous (and, for the
+  // transpose, those of one source box).
   auto add_items = [](std::vector<TransItem>& items, int table, int pbeg, int cnt, int image, int Ps, int Pd,
                       int ntw) {
     const int nrt = (2 * (2 * Pd + 1) + 15) / 16;
@@ -801,7 +805,6 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         for (int c = 0; c < cnt; ++c) {
           m2l_psrc.push_back(v[c0 + c].first);
           m2l_pdst.push_back(v[c0 + c].second);
-          m2l_pcoff.push_back(cstride);
           cstride += 2 * (2 * pl->P[l] + 1);
         }
         add_items(m2l_items, (int)id, pbeg, cnt, table_image[id], pl->P[l], pl->P[l], ntw);
@@ -811,21 +814,30 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     if (g.count) pl->m2l_groups.push_back(g);
   }
   pl->cstride = cstride;
-  // per-box pair lists for the reductions (by target, and by source for the transpose)
-  std::vector<int> red_boxes, red_ptr(1, 0), red_pairs, redT_ptr(1, 0), redT_pairs;
+  // contribution rows in box order, by target (forward) and by source
+  // (transpose), and the per-box counts and first rows for the reductions
+  std::vector<int> red_boxes, red_ptr(1, 0), redT_ptr(1, 0);
+  std::vector<int64_t> red_beg, redT_beg, m2l_pcoffT;
   {
     std::vector<std::vector<int>> as_t(nb), as_s(nb);
     for (int i = 0; i < (int)m2l_psrc.size(); ++i) {
       as_t[m2l_pdst[i]].push_back(i);
       as_s[m2l_psrc[i]].push_back(i);
     }
+    m2l_pcoff.assign(m2l_psrc.size(), 0);
+    m2l_pcoffT.assign(m2l_psrc.size(), 0);
+    int64_t of = 0, ofT = 0;
     for (int i = pl->lev_begin[std::min(2, pl->nlev)]; i < nb; ++i) {
+      const int64_t row = 2 * (2 * pl->P[B[i].level] + 1);
       red_boxes.push_back(i);
-      red_pairs.insert(red_pairs.end(), as_t[i].begin(), as_t[i].end());
-      red_ptr.push_back((int)red_pairs.size());
-      redT_pairs.insert(redT_pairs.end(), as_s[i].begin(), as_s[i].end());
-      redT_ptr.push_back((int)redT_pairs.size());
+      red_beg.push_back(of);
+      for (int pr : as_t[i]) { m2l_pcoff[pr] = of; of += row; }
+      red_ptr.push_back(red_ptr.back() + (int)as_t[i].size());
+      redT_beg.push_back(ofT);
+      for (int pr : as_s[i]) { m2l_pcoffT[pr] = ofT; ofT += row; }
+      redT_ptr.push_back(redT_ptr.back() + (int)as_s[i].size());
     }
+    if (of != cstride || ofT != cstride) return bail(fail(HFMM_ERR_DEVICE, "internal: contribution rows"));
   }
   // M2M / L2L tables per parent level l (children at l + 1), quadrant order
   std::vector<double> fb_dx, fb_dy;
@@ -1207,9 +1219,9 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
   UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
   UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves)
-  UP(m2l_items, m2l_items) UP(m2l_psrc, m2l_psrc) UP(m2l_pdst, m2l_pdst) UP(m2l_pcoff, m2l_pcoff)
-  UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_pairs, red_pairs) UP(redT_ptr, redT_ptr)
-  UP(redT_pairs, redT_pairs) UP(cp_child, cp_child) UP(cp_parent, cp_parent) UP(up_items, up_items)
+  UP(m2l_items, m2l_items) UP(m2l_psrc, m2l_psrc) UP(m2l_pdst, m2l_pdst) UP(m2l_pcoff, m2l_pcoff) UP(m2l_pcoffT, m2l_pcoffT)
+  UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_beg, red_beg) UP(redT_ptr, redT_ptr)
+  UP(redT_beg, redT_beg) UP(cp_child, cp_child) UP(cp_parent, cp_parent) UP(up_items, up_items)
   UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
   UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
@@ -1347,10 +1359,11 @@ void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
   const int* psrc = rev ? pl->m2l_pdst.p : pl->m2l_psrc.p;
   const int* pdst = rev ? pl->m2l_psrc.p : pl->m2l_pdst.p;
   for (const auto& g : pl->m2l_groups)
-    launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, psrc, pdst, pl->m2l_pcoff.p, pl->tabs.p,
-                 pl->tdata.p, src, nullptr, pl->contrib.p, pl->cstride, rev, 0, g.ntw);
+    launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, psrc, pdst,
+                 rev ? pl->m2l_pcoffT.p : pl->m2l_pcoff.p, pl->tabs.p, pl->tdata.p, src, nullptr, pl->contrib.p,
+                 pl->cstride, rev, 0, g.ntw);
   launch_reduce_contrib(s, tv, pl->red_boxes.p, pl->nred_boxes, rev ? pl->redT_ptr.p : pl->red_ptr.p,
-                        rev ? pl->redT_pairs.p : pl->red_pairs.p, pl->m2l_pcoff.p, pl->contrib.p, pl->cstride, dst);
+                        rev ? pl->redT_beg.p : pl->red_beg.p, pl->contrib.p, pl->cstride, dst);
 }
 
 // The direct parts (free-space pairs and near-interface pairs) add into us

@@ -480,31 +480,36 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
 #undef HFMM_TILES
 }
 
-// beta_b = sum of the contribution rows listed for box b (CSR), plain store.
-// One wave per box and right-hand side (grid y); a lane per order.
-__global__ void __launch_bounds__(WAVE) k_reduce_contrib(TreeView tv, const int* __restrict__ boxes, int nb,
-                                                         const int* __restrict__ ptr, const int* __restrict__ pairs,
-                                                         const int64_t* __restrict__ pcoff,
-                                                         const double* __restrict__ contrib, int64_t cstride,
-                                                         double2* __restrict__ dst) {
-  int wi = blockIdx.x;
+// beta_b = sum of the contribution rows of box b, plain store. The box's
+// ptr[wi + 1] - ptr[wi] rows lie one after another from beg[wi] (each 2M
+// doubles: the real parts, then the imaginary parts). One block per box and
+// right-hand side (grid y), a thread per double of the row; four partial sums
+// keep several loads in flight.
+constexpr int RED_THREADS = 128;
+__global__ void __launch_bounds__(RED_THREADS) k_reduce_contrib(TreeView tv, const int* __restrict__ boxes, int nb,
+                                                                const int* __restrict__ ptr,
+                                                                const int64_t* __restrict__ beg,
+                                                                const double* __restrict__ contrib, int64_t cstride,
+                                                                double2* __restrict__ dst) {
+  const int wi = blockIdx.x;
   if (wi >= nb) return;
-  int b = boxes[wi];
-  int P = tv.P[tv.level[b]];
-  int M = 2 * P + 1;
-  int e0 = ptr[wi], e1 = ptr[wi + 1];
-  {  // right-hand side r (grid y)
-    const int r = blockIdx.y;
-    const double* cr = contrib + (int64_t)r * cstride;
-    for (int p = threadIdx.x; p < M; p += WAVE) {
-      double re = 0.0, im = 0.0;
-      for (int e = e0; e < e1; ++e) {
-        const double* row = cr + pcoff[pairs[e]];
-        re += row[p];
-        im += row[M + p];
-      }
-      dst[(int64_t)r * tv.ctot + tv.coff[b] + p] = cmk(re, im);
+  const int b = boxes[wi];
+  const int M = 2 * tv.P[tv.level[b]] + 1, W = 2 * M;
+  const int cnt = ptr[wi + 1] - ptr[wi];
+  const int r = blockIdx.y;
+  const double* rows = contrib + (int64_t)r * cstride + beg[wi];
+  double* out = (double*)(dst + (int64_t)r * tv.ctot + tv.coff[b]);
+  for (int t = threadIdx.x; t < W; t += RED_THREADS) {
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+    int e = 0;
+    for (; e + 4 <= cnt; e += 4) {
+      v0 += rows[(int64_t)e * W + t];
+      v1 += rows[(int64_t)(e + 1) * W + t];
+      v2 += rows[(int64_t)(e + 2) * W + t];
+      v3 += rows[(int64_t)(e + 3) * W + t];
     }
+    for (; e < cnt; ++e) v0 += rows[(int64_t)e * W + t];
+    out[t < M ? 2 * t : 2 * (t - M) + 1] = (v0 + v1) + (v2 + v3);
   }
 }
 
@@ -1315,11 +1320,9 @@ void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int
 }
 
 void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
-                           const int* pairs, const int64_t* pcoff, const double* contrib, int64_t cstride,
-                           double2* dst) {
+                           const int64_t* beg, const double* contrib, int64_t cstride, double2* dst) {
   if (nb)
-    hipLaunchKernelGGL(k_reduce_contrib, dim3(nb, tv.nrhs), dim3(WAVE), 0, s, tv, boxes, nb, ptr, pairs, pcoff,
-                       contrib,
+    hipLaunchKernelGGL(k_reduce_contrib, dim3(nb, tv.nrhs), dim3(RED_THREADS), 0, s, tv, boxes, nb, ptr, beg, contrib,
                        cstride, dst);
 }
 

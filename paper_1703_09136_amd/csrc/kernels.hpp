@@ -28,9 +28,10 @@ void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int
                   const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
                   int exclusive, int ntw);
+// dst(box) = sum of its contribution rows: ptr[w + 1] - ptr[w] rows from
+// row offset beg[w] for boxes[w].
 void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
-                           const int* pairs, const int64_t* pcoff, const double* contrib, int64_t cstride,
-                           double2* dst);
+                           const int64_t* beg, const double* contrib, int64_t cstride, double2* dst);
 size_t trans_lds_bytes(int Ps, int Pd);
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n);
 // Free-space direct pairs. Items are sorted by H0 series class: items
