@@ -1379,7 +1379,9 @@ void launch_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double
 
 // Fork: us is cleared and the near field starts on the plan's side stream
 // while the far-field chain runs on s; every writer of us then adds
-// atomically. join() makes s wait for the side stream.
+// atomically. join() makes s wait for the side stream. The fork comes after
+// P2M: P2M is on the far field's critical path and alone fills the GPU, and
+// measured faster that way than with the near field beside it.
 hipError_t fork_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* qs, double2* us) {
   launch_fill_zero(s, us, (int64_t)tv.nrhs * pl->n);
   hipError_t e = hipEventRecord(pl->ev_fork, s);
@@ -1403,14 +1405,14 @@ bool capturing(hipStream_t s) {
 hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
   TreeView tv = pl->view(nrhs);
   const bool overlap = mark.ev == nullptr && !capturing(s);
-  if (overlap) {
-    const hipError_t e = fork_near(pl, tv, s, qs, us);
-    if (e != hipSuccess) return e;
-  }
   // parents accumulate their children's translated multipoles
   launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
   launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
   mark();
+  if (overlap) {
+    const hipError_t e = fork_near(pl, tv, s, qs, us);
+    if (e != hipSuccess) return e;
+  }
   for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0);
   mark();
   launch_m2l_all(pl, tv, s, pl->alpha.p, pl->beta.p, 0);
@@ -1429,13 +1431,13 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
   TreeView tv = pl->view(nrhs);
   // the direct parts are symmetric: the same near field, beside the far field
   const bool overlap = !capturing(s);
+  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}; parents accumulate
+  launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
+  launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
   if (overlap) {
     const hipError_t e = fork_near(pl, tv, s, vs, ws);
     if (e != hipSuccess) return e;
   }
-  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}; parents accumulate
-  launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
-  launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
   // L2L^T, finest parents first: beta'(parent) += T^T beta'(child)
   for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
   // M2L^T, reduced by source box
