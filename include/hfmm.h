@@ -94,7 +94,7 @@ typedef struct {
   double flops_updown;      /* P2M + M2M + L2L + L2P */
   double flops_p2p;         /* free-space direct part as evaluated: per H0
                                value 4M (series of M terms, by item class)
-                               + 36 (logarithm, distance, assembly) + 8 per
+                               + 32 (logarithm, distance, assembly) + 8 per
                                complex multiply-add */
   double plan_seconds;
   int64_t p2p_evals;        /* H0 evaluations per apply and right-hand side:

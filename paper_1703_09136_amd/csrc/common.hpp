@@ -153,13 +153,19 @@ __host__ __device__ inline int trans_pairs_per_item(int Ps, int Pd) {
 // number of row tiles per wave (1..8); image marks heterogeneous M2L tables
 // (reflected source coefficients).
 struct TransItem {
-  int32_t table;
+  int32_t table;  // M2M / L2L: quadrant, an index into the launch's four tables
   int32_t pbeg;
   int32_t npairs;
   int32_t image;
   int32_t rt_base;
   int32_t Ps, Pd;
   int32_t ntw;
+  int64_t toff;  // M2L: offset of t[-(Ps + Pd)] in the table data (-1: by quadrant)
+};
+// The four tables of an M2M or L2L launch (offsets of t[-(Ps + Pd)]), passed
+// by value.
+struct Toff4 {
+  int64_t v[4];
 };
 
 // Row tiles one item covers: ntw per wave, the four waves interleaved over

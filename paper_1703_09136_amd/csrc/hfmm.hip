@@ -265,7 +265,7 @@ struct hfmm_plan_s {
   // M2L: items, (source, target) pair arrays, contribution row offsets, and the
   // per-box lists of pairs for the reduction by target (forward) / by source
   DevBuf<TransItem> m2l_items;
-  DevBuf<int> m2l_psrc, m2l_pdst;
+  DevBuf<int64_t> m2l_soff, m2l_toff;  // coefficient offsets of each pair's source / target box
   DevBuf<int64_t> m2l_pcoff, m2l_pcoffT;  // row offsets: grouped by target box / by source box
   std::vector<Group> m2l_groups;
   int64_t cstride = 0;  // contribution doubles per right-hand side
@@ -276,7 +276,8 @@ struct hfmm_plan_s {
   int nred_boxes = 0;
   // M2M / L2L: (child, parent) pairs grouped by parent level and quadrant;
   // items shaped child -> parent (up) and parent -> child (down), by parent level
-  DevBuf<int> cp_child, cp_parent;
+  DevBuf<int64_t> cp_child, cp_parent;  // coefficient offsets of each pair's child / parent box
+  std::vector<Toff4> m2m_q4, l2l_q4;      // per parent level: the four tables' offsets
   DevBuf<TransItem> up_items, down_items;
   std::vector<Group> up_groups, down_groups;
   DevBuf<double> contrib;
@@ -330,7 +331,7 @@ struct hfmm_plan_s {
   void release_all() {
     pts.release(); ctr.release(); perm.release(); level.release(); parent.release(); quad.release();
     child.release(); prange.release(); coff.release(); leaves.release();
-    m2l_items.release(); m2l_psrc.release(); m2l_pdst.release(); m2l_pcoff.release(); m2l_pcoffT.release();
+    m2l_items.release(); m2l_soff.release(); m2l_toff.release(); m2l_pcoff.release(); m2l_pcoffT.release();
     red_boxes.release(); red_ptr.release(); red_beg.release(); redT_ptr.release(); redT_beg.release(); cp_child.release();
     cp_parent.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
@@ -764,10 +765,11 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   // box afterwards: the rows of one target box are contiguous (and, for the
   // transpose, those of one source box).
   auto add_items = [](std::vector<TransItem>& items, int table, int pbeg, int cnt, int image, int Ps, int Pd,
-                      int ntw) {
+                      int ntw, int64_t toff) {
     const int nrt = (2 * (2 * Pd + 1) + 15) / 16;
     const int step = trans_rows_per_item(Ps, Pd, ntw);
-    for (int rt = 0; rt < nrt; rt += step) items.push_back(TransItem{table, pbeg, cnt, image, rt, Ps, Pd, ntw});
+    for (int rt = 0; rt < nrt; rt += step)
+      items.push_back(TransItem{table, pbeg, cnt, image, rt, Ps, Pd, ntw, toff});
   };
   // row tiles per wave for a launch of `batches` pair batches: the most (up to
   // 8, the longest MFMA chains, and no more than the rows need) that still
@@ -807,7 +809,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
           m2l_pdst.push_back(v[c0 + c].second);
           cstride += 2 * (2 * pl->P[l] + 1);
         }
-        add_items(m2l_items, (int)id, pbeg, cnt, table_image[id], pl->P[l], pl->P[l], ntw);
+        add_items(m2l_items, (int)id, pbeg, cnt, table_image[id], pl->P[l], pl->P[l], ntw,
+                  tabs[id].off + tabs[id].half - 2 * pl->P[l]);
       }
     }
     g.count = (int)m2l_items.size() - g.first;
@@ -844,6 +847,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<int> fb_sgn, fb_ref;
   pl->m2m_tab.assign(pl->nlev, -1);
   pl->l2l_tab.assign(pl->nlev, -1);
+  pl->m2m_q4.assign(pl->nlev, Toff4{});
+  pl->l2l_q4.assign(pl->nlev, Toff4{});
   for (int l = 2; l + 1 < pl->nlev; ++l) {
     double bc = pl->bsize[l + 1];
     for (int pass = 0; pass < 2; ++pass) {
@@ -856,6 +861,9 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         fb_ref.push_back(id);
       }
       (pass == 0 ? pl->m2m_tab : pl->l2l_tab)[l] = base;
+      Toff4 q4{};
+      for (int q = 0; q < 4; ++q) q4.v[q] = tabs[base + q].off + tabs[base + q].half - (pl->P[l] + pl->P[l + 1]);
+      (pass == 0 ? pl->m2m_q4 : pl->l2l_q4)[l] = q4;
     }
   }
 
@@ -892,8 +900,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
           cp_child.push_back(kids_q[c0 + c]);
           cp_parent.push_back(B[kids_q[c0 + c]].parent);
         }
-        add_items(up_items, q, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up);
-        add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1], ntw_down);
+        add_items(up_items, q, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
+        add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1], ntw_down, -1);
       }
     }
     gu.count = (int)up_items.size() - gu.first;
@@ -1106,10 +1114,10 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     const int64_t ev = ns * (B[it.leaf].end - B[it.leaf].begin);
     p2p_evals += ev;
     // flops of one evaluation: two Horner chains of M terms (4M), the
-    // logarithm (26), distance and assembly (10), and a complex multiply-add
-    // per direction (8 each)
+    // table logarithm (21), distance and assembly (11), and a complex
+    // multiply-add per direction (8 each)
     const int M = kH0ClassTerms[it.cls < kH0Classes ? it.cls : kH0Classes - 1];
-    p2p_flops += (double)ev * (4.0 * M + 36.0 + (it.sym ? 16.0 : 8.0));
+    p2p_flops += (double)ev * (4.0 * M + 32.0 + (it.sym ? 16.0 : 8.0));
   }
   pl->p2p_evals = p2p_evals;
   pl->p2p_flops = p2p_flops;
@@ -1214,14 +1222,22 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     for (int q = 0; q < 4; ++q) hchild[4 * i + q] = B[i].child[q];
     hpr[i] = make_int2(B[i].begin, B[i].end);
   }
+  // pair lists as coefficient offsets of their boxes
+  auto offsets_of = [&](const std::vector<int>& boxes_of_pairs) {
+    std::vector<int64_t> o(boxes_of_pairs.size());
+    for (size_t i = 0; i < o.size(); ++i) o[i] = coff[boxes_of_pairs[i]];
+    return o;
+  };
+  const std::vector<int64_t> m2l_soff = offsets_of(m2l_psrc), m2l_toff = offsets_of(m2l_pdst);
+  const std::vector<int64_t> cp_child_off = offsets_of(cp_child), cp_parent_off = offsets_of(cp_parent);
   hipError_t e = hipSuccess;
 #define UP(buf, vec)                                  \
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
   UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
   UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves)
-  UP(m2l_items, m2l_items) UP(m2l_psrc, m2l_psrc) UP(m2l_pdst, m2l_pdst) UP(m2l_pcoff, m2l_pcoff) UP(m2l_pcoffT, m2l_pcoffT)
+  UP(m2l_items, m2l_items) UP(m2l_soff, m2l_soff) UP(m2l_toff, m2l_toff) UP(m2l_pcoff, m2l_pcoff) UP(m2l_pcoffT, m2l_pcoffT)
   UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_beg, red_beg) UP(redT_ptr, redT_ptr)
-  UP(redT_beg, redT_beg) UP(cp_child, cp_child) UP(cp_parent, cp_parent) UP(up_items, up_items)
+  UP(redT_beg, redT_beg) UP(cp_child, cp_child_off) UP(cp_parent, cp_parent_off) UP(up_items, up_items)
   UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
   UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
@@ -1344,23 +1360,23 @@ void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, in
                   const double2* src, double2* dst, int rev) {
   const hfmm_plan_s::Group& g = up ? pl->up_groups[l] : pl->down_groups[l];
   if (!g.count) return;
-  const TableRef* tabs4 = pl->tabs.p + (m2m_tables ? pl->m2m_tab[l] : pl->l2l_tab[l]);
+  const Toff4& q4 = m2m_tables ? pl->m2m_q4[l] : pl->l2l_q4[l];
   const TransItem* items = (up ? pl->up_items.p : pl->down_items.p) + g.first;
-  const int* psrc = up ? pl->cp_child.p : pl->cp_parent.p;
-  const int* pdst = up ? pl->cp_parent.p : pl->cp_child.p;
+  const int64_t* soff = up ? pl->cp_child.p : pl->cp_parent.p;
+  const int64_t* doff = up ? pl->cp_parent.p : pl->cp_child.p;
   // a child has one parent: parent -> child writes never collide
-  launch_trans(s, tv, items, g.count, g.Ps, g.Pd, psrc, pdst, nullptr, tabs4, pl->tdata.p, src, dst, nullptr, 0, rev,
+  launch_trans(s, tv, items, g.count, g.Ps, g.Pd, soff, doff, nullptr, q4, pl->tdata.p, src, dst, nullptr, 0, rev,
                up ? 0 : 1, g.ntw);
 }
 
 // All M2L items (forward: source -> target; transpose: target -> source) into
 // the per-pair contribution rows, then the per-box reduction into dst.
 void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* src, double2* dst, int rev) {
-  const int* psrc = rev ? pl->m2l_pdst.p : pl->m2l_psrc.p;
-  const int* pdst = rev ? pl->m2l_psrc.p : pl->m2l_pdst.p;
+  const int64_t* soff = rev ? pl->m2l_toff.p : pl->m2l_soff.p;
+  const int64_t* doff = rev ? pl->m2l_soff.p : pl->m2l_toff.p;
   for (const auto& g : pl->m2l_groups)
-    launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, psrc, pdst,
-                 rev ? pl->m2l_pcoffT.p : pl->m2l_pcoff.p, pl->tabs.p, pl->tdata.p, src, nullptr, pl->contrib.p,
+    launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, soff, doff,
+                 rev ? pl->m2l_pcoffT.p : pl->m2l_pcoff.p, Toff4{}, pl->tdata.p, src, nullptr, pl->contrib.p,
                  pl->cstride, rev, 0, g.ntw);
   launch_reduce_contrib(s, tv, pl->red_boxes.p, pl->nred_boxes, rev ? pl->redT_ptr.p : pl->red_ptr.p,
                         rev ? pl->redT_beg.p : pl->red_beg.p, pl->contrib.p, pl->cstride, dst);

@@ -311,12 +311,49 @@ __host__ __device__ inline int round4(int m) { return (m + 3) & ~3; }
 // so every operand element is one LDS read and the k-loop has no branches.
 template <bool REV, int MODE, int NT>
 __device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, const double* lds_d, int ntp,
-                                   const double2* s_s, int ntile, int rt_lo, int rt_stride, const int* __restrict__ pdst,
-                                   const int64_t* __restrict__ pcoff, double2* __restrict__ dst,
-                                   double* __restrict__ contrib, int64_t cstride, int r) {
+                                   const double2* s_s, int ntile, int rt_lo, int rt_stride,
+                                   const int64_t* __restrict__ doff, const int64_t* __restrict__ pcoff,
+                                   double2* __restrict__ dst, double* __restrict__ contrib, int64_t cstride, int r) {
   const int Ps = it.Ps, Pd = it.Pd;
   const int Ms4 = round4(2 * Ps + 1), Md = 2 * Pd + 1;
   const int lane = threadIdx.x & 63, lrow = lane & 15, lk = lane >> 4;
+  constexpr bool CONTRIB = MODE == OUT_CONTRIB;
+  // output slots of this lane: D[row][col] of a 16x16x4 FP64 tile sits in
+  // lane col + 16 (row % 4), register row / 4; idx is the double within the
+  // target's coefficients (or contribution row), neg the reflection's sign
+  const int col = ntile * 16 + lrow;
+  const bool col_ok = col < it.npairs;
+  const int pair = it.pbeg + (col_ok ? col : 0);
+  const bool reflect_out = REV && it.image;
+  auto slot = [&](int j, int i, int& idx, bool& neg) {
+    const int row = (rt_lo + j * rt_stride) * 16 + 4 * i + lk;
+    if (row >= 2 * Md) return false;
+    const bool rim = row >= Md;
+    const int p = rim ? row - Md : row;
+    int po = p;
+    neg = false;
+    if (reflect_out) {
+      po = Md - 1 - p;
+      neg = ((p + Pd) & 1) != 0;
+    }
+    idx = CONTRIB ? (rim ? Md : 0) + po : 2 * po + (rim ? 1 : 0);
+    return true;
+  };
+  double* outd = CONTRIB ? contrib + (int64_t)r * cstride + pcoff[pair]
+                         : (double*)(dst + (int64_t)r * tv.ctot + doff[pair]);
+  // exclusive targets: their current values are read before the contraction
+  constexpr bool PREFETCH = MODE == OUT_EXCLUSIVE && NT <= 2;
+  double old[PREFETCH ? NT : 1][4];
+  if (PREFETCH) {
+#pragma unroll
+    for (int j = 0; j < (PREFETCH ? NT : 1); ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int idx;
+        bool neg;
+        old[j][i] = (col_ok && slot(j, i, idx, neg)) ? outd[idx] : 0.0;
+      }
+  }
   int a_re[NT], a_im[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
@@ -354,38 +391,21 @@ __device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, cons
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b, acc[j], 0, 0, 0);
   }
-  const int col = ntile * 16 + lrow;
-  if (col >= it.npairs) return;
-  const int pair = it.pbeg + col;
-  constexpr bool CONTRIB = MODE == OUT_CONTRIB;
-  double2* out = CONTRIB ? nullptr : dst + (int64_t)r * tv.ctot + tv.coff[pdst[pair]];
-  double* crow = CONTRIB ? contrib + (int64_t)r * cstride + pcoff[pair] : nullptr;
-  const bool reflect_out = REV && it.image;
+  if (!col_ok) return;
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
-    const int rt = rt_lo + j * rt_stride;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      // D[row][col] of a 16x16x4 FP64 tile sits in lane col + 16 (row % 4), register row / 4
-      const int row = rt * 16 + 4 * i + lk;
-      if (row >= 2 * Md) continue;
-      const bool rim = row >= Md;
-      const int p = rim ? row - Md : row;
-      double v = acc[j][i];
-      int po = p;
-      if (reflect_out) {
-        po = Md - 1 - p;
-        if ((p + Pd) & 1) v = -v;
-      }
-      if (CONTRIB) {
-        crow[(rim ? Md : 0) + po] = v;
-      } else {
-        double* o = rim ? &out[po].y : &out[po].x;
-        if (MODE == OUT_EXCLUSIVE)
-          *o += v;
-        else
-          unsafeAtomicAdd(o, v);
-      }
+      int idx;
+      bool neg;
+      if (!slot(j, i, idx, neg)) continue;
+      const double v = neg ? -acc[j][i] : acc[j][i];
+      if (CONTRIB)
+        outd[idx] = v;
+      else if (MODE == OUT_EXCLUSIVE)
+        outd[idx] = (PREFETCH ? old[PREFETCH ? j : 0][i] : outd[idx]) + v;
+      else
+        unsafeAtomicAdd(&outd[idx], v);
     }
   }
 }
@@ -395,10 +415,9 @@ __device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, cons
 // a variant with NTMAX = 2 and more waves fit a SIMD.
 template <bool REV, int MODE, int NTMAX>
 __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const TransItem* __restrict__ items,
-                                                          const int* __restrict__ psrc,
-                                                          const int* __restrict__ pdst,
-                                                          const int64_t* __restrict__ pcoff,
-                                                          const TableRef* __restrict__ tabs,
+                                                          const int64_t* __restrict__ soff,
+                                                          const int64_t* __restrict__ doff,
+                                                          const int64_t* __restrict__ pcoff, Toff4 q4,
                                                           const double2* __restrict__ tdata,
                                                           const double2* __restrict__ src, double2* __restrict__ dst,
                                                           double* __restrict__ contrib, int64_t cstride) {
@@ -416,9 +435,8 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   const int tid = threadIdx.x, wave = tid >> 6;
   // Every global load of the prologue is issued in one of two rounds: the
   // pairs' coefficient offsets and the table first, then all source rows.
-  if (tid < npi) s_off[tid] = tid < it.npairs ? tv.coff[psrc[it.pbeg + tid]] : -1;
-  const TableRef tr = tabs[it.table];
-  const double2* T = tdata + tr.off + tr.half - (Ps + Pd);  // T[0] = t[-(Ps + Pd)]
+  if (tid < npi) s_off[tid] = tid < it.npairs ? soff[it.pbeg + tid] : -1;
+  const double2* T = tdata + (it.toff >= 0 ? it.toff : q4.v[it.table & 3]);  // T[0] = t[-(Ps + Pd)]
   for (int i = tid; i < ntp; i += TR_THREADS) {
     const int n = i - kTabPad;
     const double2 v = (n >= 0 && n < nt) ? T[n] : cmk(0.0, 0.0);
@@ -464,17 +482,17 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
 #define HFMM_TILES(N)                                                                                           \
   case N:                                                                                                       \
-    trans_tiles<REV, MODE, N>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r); \
+    trans_tiles<REV, MODE, N>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, doff, pcoff, dst, contrib, cstride, r); \
     break;
   if (NTMAX <= 2) {
     switch (rt_cnt) {
       HFMM_TILES(1)
-      default: trans_tiles<REV, MODE, 2>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r);
+      default: trans_tiles<REV, MODE, 2>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, doff, pcoff, dst, contrib, cstride, r);
     }
   } else {
     switch (rt_cnt) {
       HFMM_TILES(1) HFMM_TILES(2) HFMM_TILES(3) HFMM_TILES(4) HFMM_TILES(5) HFMM_TILES(6) HFMM_TILES(7)
-      default: trans_tiles<REV, MODE, 8>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, pdst, pcoff, dst, contrib, cstride, r);
+      default: trans_tiles<REV, MODE, 8>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, doff, pcoff, dst, contrib, cstride, r);
     }
   }
 #undef HFMM_TILES
@@ -1291,24 +1309,24 @@ hipError_t init_kernel_attributes() {
 
 template <bool REV, int MODE>
 static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, size_t lds, int ntw,
-                      const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
+                      const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
                       const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride) {
   if (ntw <= 2)
     hipLaunchKernelGGL((k_trans_mfma<REV, MODE, 2>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items,
-                       psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride);
+                       soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride);
   else
     hipLaunchKernelGGL((k_trans_mfma<REV, MODE, 8>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items,
-                       psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride);
+                       soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride);
 }
 
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
-                  const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
+                  const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
                   int exclusive, int ntw) {
   if (nitems <= 0) return;
   const size_t lds = trans_lds_bytes(Ps, Pd);
 #define HFMM_TRANS(R, M) \
-  trans_one<R, M>(s, tv, items, nitems, lds, ntw, psrc, pdst, pcoff, tabs, tdata, src, dst, contrib, cstride)
+  trans_one<R, M>(s, tv, items, nitems, lds, ntw, soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride)
   if (contrib) {
     if (rev) HFMM_TRANS(true, OUT_CONTRIB); else HFMM_TRANS(false, OUT_CONTRIB);
   } else if (exclusive) {

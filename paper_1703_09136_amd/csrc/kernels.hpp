@@ -23,9 +23,12 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
 // row at pcoff[pair] (plane stride cstride per right-hand side); otherwise the
 // result is added into dst of the pair's target box, atomically unless
 // exclusive says that no two pairs of the launch share a target box.
-// ntw: the row tiles per wave of the items (their largest value).
+// soff / doff: per pair, the coefficient offsets of its source and target
+// boxes. The table of an item is at item.toff in tdata, or (toff < 0) at
+// q4.v[item.table]. ntw: the row tiles per wave of the items (their largest
+// value).
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
-                  const int* psrc, const int* pdst, const int64_t* pcoff, const TableRef* tabs,
+                  const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
                   int exclusive, int ntw);
 // dst(box) = sum of its contribution rows: ptr[w + 1] - ptr[w] rows from
