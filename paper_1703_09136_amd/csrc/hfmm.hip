@@ -277,6 +277,7 @@ struct hfmm_plan_s {
   // M2M / L2L: (child, parent) pairs grouped by parent level and quadrant;
   // items shaped child -> parent (up) and parent -> child (down), by parent level
   DevBuf<int64_t> cp_child, cp_parent;  // coefficient offsets of each pair's child / parent box
+  DevBuf<int64_t> up_doff, up_soff4;     // child -> parent: parent offsets, and their four children's (-1: none)
   std::vector<Toff4> m2m_q4, l2l_q4;      // per parent level: the four tables' offsets
   DevBuf<TransItem> up_items, down_items;
   std::vector<Group> up_groups, down_groups;
@@ -333,7 +334,7 @@ struct hfmm_plan_s {
     child.release(); prange.release(); coff.release(); leaves.release();
     m2l_items.release(); m2l_soff.release(); m2l_toff.release(); m2l_pcoff.release(); m2l_pcoffT.release();
     red_boxes.release(); red_ptr.release(); red_beg.release(); redT_ptr.release(); redT_beg.release(); cp_child.release();
-    cp_parent.release(); up_items.release(); down_items.release(); contrib.release();
+    cp_parent.release(); up_doff.release(); up_soff4.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release(); gq.release(); gs.release();
@@ -868,10 +869,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
 
   // (child, parent) pairs per parent level l >= 2 and quadrant q, with items
-  // shaped child -> parent ("up": M2M, transposed L2L) and parent -> child
-  // ("down": L2L, transposed M2M); the table of an item is the quadrant, taken
-  // relative to the level's four M2M or L2L tables at launch.
+  // shaped parent -> child ("down": L2L, transposed M2M); the table of an item
+  // is the quadrant, taken from the level's four M2M or L2L tables at launch.
+  // Child -> parent ("up": M2M, transposed L2L) items list 16 parents each and
+  // gather their four children.
   std::vector<int> cp_child, cp_parent;
+  std::vector<int64_t> up_doff_h, up_soff4_h;
   std::vector<TransItem> up_items, down_items;
   pl->up_groups.assign(pl->nlev, {});
   pl->down_groups.assign(pl->nlev, {});
@@ -883,14 +886,26 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     gu.Ps = gd.Pd = pl->P[l + 1];
     gu.Pd = gd.Ps = pl->P[l];
     const int npi = trans_pairs_per_item(pl->P[l + 1], pl->P[l]);
-    std::vector<int> kids[4];
+    std::vector<int> kids[4], parents;
     for (int i = pl->lev_begin[l + 1]; i < pl->lev_begin[l + 2]; ++i) kids[B[i].quad].push_back(i);
+    for (int i = pl->lev_begin[l]; i < pl->lev_begin[l + 1]; ++i)
+      if (!B[i].leaf) parents.push_back(i);
     int64_t batches = 0;
     for (int q = 0; q < 4; ++q) batches += ((int64_t)kids[q].size() + npi - 1) / npi;
-    const int ntw_up = choose_ntw(batches, pl->P[l + 1], pl->P[l]);
+    const int ntw_up = choose_ntw(((int64_t)parents.size() + npi - 1) / npi, pl->P[l + 1], pl->P[l]);
     const int ntw_down = choose_ntw(batches, pl->P[l], pl->P[l + 1]);
     gu.ntw = ntw_up;
     gd.ntw = ntw_down;
+    for (size_t c0 = 0; c0 < parents.size(); c0 += npi) {
+      const int cnt = (int)std::min<size_t>(npi, parents.size() - c0);
+      const int pbeg = (int)up_doff_h.size();
+      for (int c = 0; c < cnt; ++c) {
+        const Box& par = B[parents[c0 + c]];
+        up_doff_h.push_back(coff[parents[c0 + c]]);
+        for (int q = 0; q < 4; ++q) up_soff4_h.push_back(par.child[q] >= 0 ? coff[par.child[q]] : -1);
+      }
+      add_items(up_items, 0, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
+    }
     for (int q = 0; q < 4; ++q) {
       const std::vector<int>& kids_q = kids[q];
       for (size_t c0 = 0; c0 < kids_q.size(); c0 += npi) {
@@ -900,7 +915,6 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
           cp_child.push_back(kids_q[c0 + c]);
           cp_parent.push_back(B[kids_q[c0 + c]].parent);
         }
-        add_items(up_items, q, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
         add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1], ntw_down, -1);
       }
     }
@@ -1237,7 +1251,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves)
   UP(m2l_items, m2l_items) UP(m2l_soff, m2l_soff) UP(m2l_toff, m2l_toff) UP(m2l_pcoff, m2l_pcoff) UP(m2l_pcoffT, m2l_pcoffT)
   UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_beg, red_beg) UP(redT_ptr, redT_ptr)
-  UP(redT_beg, redT_beg) UP(cp_child, cp_child_off) UP(cp_parent, cp_parent_off) UP(up_items, up_items)
+  UP(redT_beg, redT_beg) UP(cp_child, cp_child_off) UP(cp_parent, cp_parent_off) UP(up_doff, up_doff_h) UP(up_soff4, up_soff4_h) UP(up_items, up_items)
   UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
   UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
@@ -1362,11 +1376,12 @@ void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, in
   if (!g.count) return;
   const Toff4& q4 = m2m_tables ? pl->m2m_q4[l] : pl->l2l_q4[l];
   const TransItem* items = (up ? pl->up_items.p : pl->down_items.p) + g.first;
-  const int64_t* soff = up ? pl->cp_child.p : pl->cp_parent.p;
-  const int64_t* doff = up ? pl->cp_parent.p : pl->cp_child.p;
-  // a child has one parent: parent -> child writes never collide
+  const int64_t* soff = up ? pl->up_soff4.p : pl->cp_parent.p;
+  const int64_t* doff = up ? pl->up_doff.p : pl->cp_child.p;
+  // a child has one parent, and up items gather a parent's children: no two
+  // pairs of a launch write the same box
   launch_trans(s, tv, items, g.count, g.Ps, g.Pd, soff, doff, nullptr, q4, pl->tdata.p, src, dst, nullptr, 0, rev,
-               up ? 0 : 1, g.ntw);
+               up ? 1 : 0, g.ntw);
 }
 
 // All M2L items (forward: source -> target; transpose: target -> source) into
@@ -1421,8 +1436,8 @@ bool capturing(hipStream_t s) {
 hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
   TreeView tv = pl->view(nrhs);
   const bool overlap = mark.ev == nullptr && !capturing(s);
-  // parents accumulate their children's translated multipoles
-  launch_fill_zero(s, pl->alpha.p, (int64_t)nrhs * pl->ctot);
+  // P2M stores the leaves' multipoles, M2M each parent's (every box of levels
+  // >= 2 is one or the other)
   launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
   mark();
   if (overlap) {
@@ -1447,14 +1462,14 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
   TreeView tv = pl->view(nrhs);
   // the direct parts are symmetric: the same near field, beside the far field
   const bool overlap = !capturing(s);
-  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i}; parents accumulate
-  launch_fill_zero(s, pl->beta.p, (int64_t)nrhs * pl->ctot);
+  // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i} at the leaves, then
+  // the parents' sums (stored, as in the forward pass)
   launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
   if (overlap) {
     const hipError_t e = fork_near(pl, tv, s, vs, ws);
     if (e != hipSuccess) return e;
   }
-  // L2L^T, finest parents first: beta'(parent) += T^T beta'(child)
+  // L2L^T, finest parents first: beta'(parent) = sum over its children of T^T beta'(child)
   for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
   // M2L^T, reduced by source box
   launch_m2l_all(pl, tv, s, pl->beta.p, pl->alpha.p, 1);

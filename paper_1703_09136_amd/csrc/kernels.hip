@@ -51,6 +51,12 @@ __global__ void k_scatter(int n, int nrhs, const int* __restrict__ perm, const d
   dst[(int64_t)r * n + perm[i]] = conj_out ? cconj(v) : v;
 }
 
+// The far-field kernels form a chain of short, latency-bound launches that
+// share the GPU with the near field (a stream of its own): their waves take
+// the highest issue priority within a SIMD (s_setprio), so that the near
+// field's long arithmetic runs fill the cycles they leave.
+__device__ inline void far_field_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // ------------------------------------------------------------------ P2M
 // alpha_p = sum_j q_j J_p(k rho_j) e^{-i p theta_j}, p in [-P, P] (Eq. multi_coeff).
 // One wave per leaf and group of up to RB right-hand sides (grid y; one
@@ -195,6 +201,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
   extern __shared__ double2 lds_c[];  // [RB][P + 1][s, d]
   const int li = blockIdx.x;
   if (li >= nleaves) return;
+  far_field_priority();
   const int b = leaves[li];
   const int lane = threadIdx.x;
   const int lev = tv.level[b];
@@ -283,16 +290,21 @@ size_t l2p_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * 
 // of 4, columns = 16 pairs per wave. Operator tiles are expanded from the
 // Toeplitz vector in LDS on the fly. Image pairs use the reflected source
 // coefficients abar_m = (-1)^m alpha_{-m}; in the transpose the reflection
-// moves to the output. The result either goes to a per-pair contribution row
-// (reduced per box afterwards), is added atomically into the target box, or,
-// when every target box of the launch receives exactly one pair (parent to
-// child), is added with a plain read-modify-write.
+// moves to the output. Three output modes:
+//  * contribution rows (M2L): each pair writes its own row, reduced per box
+//    afterwards;
+//  * exclusive (parent to child): every target box of the launch receives
+//    exactly one pair and the result is added with a read-modify-write;
+//  * four-quadrant gather (child to parent): the 16 columns are parents and
+//    the contraction runs over the four child quadrants in turn, each with its
+//    table, so that k spans the stacked children; a missing child is a zero
+//    column. Each parent receives its whole sum at once and is stored.
 // This one kernel runs M2L (free and heterogeneous), M2M, L2L and their
 // transposes.
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int TR_THREADS = 256;
 
-enum { OUT_ATOMIC = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2 };
+enum { OUT_GATHER4 = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2 };
 
 // LDS layout of an item: the table as three zero-padded vectors Tr, Ti, -Ti of
 // trans_table_stride(nt) doubles each (value n at index kTabPad + n), then the
@@ -304,56 +316,17 @@ __host__ __device__ inline int trans_table_stride(int nt) { return (nt + 2 * kTa
 __host__ __device__ inline int round4(int m) { return (m + 3) & ~3; }
 
 // The contraction of one wave: NT row tiles of 16 rows of the real-embedded
-// operator against one 16-column tile of pairs. Row r of the operator is
-// (rim, p) = (r >= Md, r mod Md), column k = (kim, m) with the halves padded
-// to Ms4; its entry is Tr, Ti or -Ti at table index 2Pd - p + m (forward) or
-// p + 2Ps - m (transpose). Each lane holds one address per row tile and half,
-// so every operand element is one LDS read and the k-loop has no branches.
-template <bool REV, int MODE, int NT>
-__device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, const double* lds_d, int ntp,
-                                   const double2* s_s, int ntile, int rt_lo, int rt_stride,
-                                   const int64_t* __restrict__ doff, const int64_t* __restrict__ pcoff,
-                                   double2* __restrict__ dst, double* __restrict__ contrib, int64_t cstride, int r) {
-  const int Ps = it.Ps, Pd = it.Pd;
+// operator against one 16-column tile of pairs, added into acc. Row r of the
+// operator is (rim, p) = (r >= Md, r mod Md), column k = (kim, m) with the
+// halves padded to Ms4; its entry is Tr, Ti or -Ti at table index 2Pd - p + m
+// (forward) or p + 2Ps - m (transpose). Each lane holds one address per row
+// tile and half, so every operand element is one LDS read and the k-loop has
+// no branches.
+template <bool REV, int NT>
+__device__ inline void trans_contract(d4* acc, const double* lds_d, int ntp, const double2* s_s, int Ps, int Pd,
+                                      int rt_lo, int rt_stride) {
   const int Ms4 = round4(2 * Ps + 1), Md = 2 * Pd + 1;
   const int lane = threadIdx.x & 63, lrow = lane & 15, lk = lane >> 4;
-  constexpr bool CONTRIB = MODE == OUT_CONTRIB;
-  // output slots of this lane: D[row][col] of a 16x16x4 FP64 tile sits in
-  // lane col + 16 (row % 4), register row / 4; idx is the double within the
-  // target's coefficients (or contribution row), neg the reflection's sign
-  const int col = ntile * 16 + lrow;
-  const bool col_ok = col < it.npairs;
-  const int pair = it.pbeg + (col_ok ? col : 0);
-  const bool reflect_out = REV && it.image;
-  auto slot = [&](int j, int i, int& idx, bool& neg) {
-    const int row = (rt_lo + j * rt_stride) * 16 + 4 * i + lk;
-    if (row >= 2 * Md) return false;
-    const bool rim = row >= Md;
-    const int p = rim ? row - Md : row;
-    int po = p;
-    neg = false;
-    if (reflect_out) {
-      po = Md - 1 - p;
-      neg = ((p + Pd) & 1) != 0;
-    }
-    idx = CONTRIB ? (rim ? Md : 0) + po : 2 * po + (rim ? 1 : 0);
-    return true;
-  };
-  double* outd = CONTRIB ? contrib + (int64_t)r * cstride + pcoff[pair]
-                         : (double*)(dst + (int64_t)r * tv.ctot + doff[pair]);
-  // exclusive targets: their current values are read before the contraction
-  constexpr bool PREFETCH = MODE == OUT_EXCLUSIVE && NT <= 2;
-  double old[PREFETCH ? NT : 1][4];
-  if (PREFETCH) {
-#pragma unroll
-    for (int j = 0; j < (PREFETCH ? NT : 1); ++j)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int idx;
-        bool neg;
-        old[j][i] = (col_ok && slot(j, i, idx, neg)) ? outd[idx] : 0.0;
-      }
-  }
   int a_re[NT], a_im[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
@@ -365,10 +338,7 @@ __device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, cons
     a_re[j] = (rim ? ntp : 0) + tb;      // Tr (rim == kim) or Ti
     a_im[j] = (rim ? 0 : 2 * ntp) + tb;  // Tr or -Ti
   }
-  const double* Bcol = (const double*)(s_s + (ntile * 16 + lrow) * Ms4) + 2 * lk;
-  d4 acc[NT];
-#pragma unroll
-  for (int j = 0; j < NT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  const double* Bcol = (const double*)(s_s + lrow * Ms4) + 2 * lk;
   const int nks = Ms4 / 4;
   // real half of k, then the imaginary half
 #pragma unroll 2
@@ -391,21 +361,49 @@ __device__ inline void trans_tiles(const TreeView& tv, const TransItem& it, cons
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b, acc[j], 0, 0, 0);
   }
-  if (!col_ok) return;
+}
+
+// Output slot of operator row `row` for this lane's column: D[row][col] of a
+// 16x16x4 FP64 tile sits in lane col + 16 (row % 4), register row / 4. False
+// past the operator's rows; idx is the double within the target's
+// coefficients (real and imaginary parts interleaved) or, for a contribution
+// row, within the row (real parts, then imaginary parts); neg is the sign of
+// the output reflection.
+template <bool CONTRIB>
+__device__ inline bool trans_slot(int row, int Md, int Pd, bool reflect_out, int& idx, bool& neg) {
+  if (row >= 2 * Md) return false;
+  const bool rim = row >= Md;
+  const int p = rim ? row - Md : row;
+  int po = p;
+  neg = false;
+  if (reflect_out) {
+    po = Md - 1 - p;
+    neg = ((p + Pd) & 1) != 0;
+  }
+  idx = CONTRIB ? (rim ? Md : 0) + po : 2 * po + (rim ? 1 : 0);
+  return true;
+}
+
+// Store (contribution rows, gathered parents) or add (exclusive targets: old
+// holds their values read before the contraction when PREFETCH, else they are
+// read here).
+template <int MODE, bool PREFETCH, int NT>
+__device__ inline void trans_store(const d4* acc, const double* old, double* outd, int rt_lo, int rt_stride, int Md,
+                                   int Pd, bool reflect_out) {
+  const int lk = (threadIdx.x & 63) >> 4;
 #pragma unroll
   for (int j = 0; j < NT; ++j) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       int idx;
       bool neg;
-      if (!slot(j, i, idx, neg)) continue;
+      const int row = (rt_lo + j * rt_stride) * 16 + 4 * i + lk;
+      if (!trans_slot<MODE == OUT_CONTRIB>(row, Md, Pd, reflect_out, idx, neg)) continue;
       const double v = neg ? -acc[j][i] : acc[j][i];
-      if (CONTRIB)
+      if (MODE != OUT_EXCLUSIVE)
         outd[idx] = v;
-      else if (MODE == OUT_EXCLUSIVE)
-        outd[idx] = (PREFETCH ? old[PREFETCH ? j : 0][i] : outd[idx]) + v;
       else
-        unsafeAtomicAdd(&outd[idx], v);
+        outd[idx] = (PREFETCH ? old[4 * j + i] : outd[idx]) + v;
     }
   }
 }
@@ -423,6 +421,9 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
                                                           double* __restrict__ contrib, int64_t cstride) {
   extern __shared__ double lds_d[];
   __shared__ int64_t s_off[64];
+  far_field_priority();
+  constexpr bool G4 = MODE == OUT_GATHER4;
+  constexpr bool CONTRIB = MODE == OUT_CONTRIB;
   const int r = blockIdx.y;  // right-hand side
   const TransItem it = items[blockIdx.x];
   const int Ps = it.Ps, Pd = it.Pd;
@@ -433,71 +434,113 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   const int npi = trans_pairs_per_item(Ps, Pd);
   double2* s_s = (double2*)(lds_d + 3 * ntp);  // 16-byte aligned: ntp is even
   const int tid = threadIdx.x, wave = tid >> 6;
-  // Every global load of the prologue is issued in one of two rounds: the
-  // pairs' coefficient offsets and the table first, then all source rows.
-  if (tid < npi) s_off[tid] = tid < it.npairs ? soff[it.pbeg + tid] : -1;
-  const double2* T = tdata + (it.toff >= 0 ? it.toff : q4.v[it.table & 3]);  // T[0] = t[-(Ps + Pd)]
-  for (int i = tid; i < ntp; i += TR_THREADS) {
-    const int n = i - kTabPad;
-    const double2 v = (n >= 0 && n < nt) ? T[n] : cmk(0.0, 0.0);
-    lds_d[i] = v.x;
-    lds_d[ntp + i] = v.y;
-    lds_d[2 * ntp + i] = -v.y;
+  // wave -> row tiles: the four waves split up to 4 it.ntw row tiles of the
+  // item's column tile with stride 4
+  const int rt_lo = it.rt_base + wave, rt_stride = 4;
+  const int rt_cnt = rt_lo < nrt ? min((nrt - rt_lo + 3) / 4, it.ntw) : 0;
+  // this lane's column (pair) and output; exclusive targets are read now, so
+  // that the read overlaps the contraction
+  const int lane = tid & 63, lk = lane >> 4;
+  const int col = lane & 15;
+  const bool col_ok = col < it.npairs;
+  const int pair = it.pbeg + (col_ok ? col : 0);
+  const bool reflect_out = REV && it.image;
+  double* outd = CONTRIB ? contrib + (int64_t)r * cstride + pcoff[pair]
+                         : (double*)(dst + (int64_t)r * tv.ctot + doff[pair]);
+  constexpr bool PREFETCH = MODE == OUT_EXCLUSIVE && NTMAX <= 2;
+  double old[PREFETCH ? 4 * NTMAX : 1];
+  if (PREFETCH) {
+#pragma unroll
+    for (int j = 0; j < (PREFETCH ? NTMAX : 1); ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        int idx;
+        bool neg;
+        const int row = (rt_lo + j * rt_stride) * 16 + 4 * i + lk;
+        old[4 * j + i] =
+            (j < rt_cnt && col_ok && trans_slot<false>(row, Md, Pd, reflect_out, idx, neg)) ? outd[idx] : 0.0;
+      }
   }
-  __syncthreads();
-  // source coefficients, flattened (pair, order) so consecutive lanes read
-  // consecutive coefficients of a row; four loads in flight per lane
+  d4 acc[NTMAX];
+#pragma unroll
+  for (int j = 0; j < NTMAX; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
   const bool reflect_in = it.image && !REV;
   const double2* Sr = src + (int64_t)r * tv.ctot;
   const int tot = npi * Ms4;
-  for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
-    double2 v[4];
+  for (int ph = 0; ph < (G4 ? 4 : 1); ++ph) {
+    if (ph > 0) __syncthreads();  // the previous quadrant's operands are no longer read
+    // Every global load of the prologue is issued in one of two rounds: the
+    // pairs' coefficient offsets and the table first, then all source rows.
+    if (tid < npi) s_off[tid] = tid < it.npairs ? soff[G4 ? 4 * (it.pbeg + tid) + ph : it.pbeg + tid] : -1;
+    const double2* T = tdata + (it.toff >= 0 ? it.toff : q4.v[G4 ? ph : (it.table & 3)]);  // T[0] = t[-(Ps + Pd)]
+    for (int i = tid; i < ntp; i += TR_THREADS) {
+      const int n = i - kTabPad;
+      const double2 v = (n >= 0 && n < nt) ? T[n] : cmk(0.0, 0.0);
+      lds_d[i] = v.x;
+      lds_d[ntp + i] = v.y;
+      lds_d[2 * ntp + i] = -v.y;
+    }
+    __syncthreads();
+    // source coefficients, flattened (pair, order) so consecutive lanes read
+    // consecutive coefficients of a row; four loads in flight per lane
+    for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
+      double2 v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = e0 + u * TR_THREADS;
-      v[u] = cmk(0.0, 0.0);
-      if (e < tot) {
-        const int c = e / Ms4, m = e - c * Ms4;
-        const int64_t off = s_off[c];
-        if (off >= 0 && m < Ms) {
-          if (reflect_in) {
-            v[u] = Sr[off + Ms - 1 - m];
-            if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
-          } else {
-            v[u] = Sr[off + m];
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * TR_THREADS;
+        v[u] = cmk(0.0, 0.0);
+        if (e < tot) {
+          const int c = e / Ms4, m = e - c * Ms4;
+          const int64_t off = s_off[c];
+          if (off >= 0 && m < Ms) {
+            if (reflect_in) {
+              v[u] = Sr[off + Ms - 1 - m];
+              if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
+            } else {
+              v[u] = Sr[off + m];
+            }
           }
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
+    }
+    __syncthreads();
+    if (rt_cnt > 0) {
+      if (NTMAX <= 2) {
+        if (rt_cnt == 1)
+          trans_contract<REV, 1>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
+        else
+          trans_contract<REV, (NTMAX < 2 ? NTMAX : 2)>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
+      } else {
+#define HFMM_CONTRACT(N) \
+  case N: trans_contract<REV, N>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride); break;
+        switch (rt_cnt) {
+          HFMM_CONTRACT(1) HFMM_CONTRACT(2) HFMM_CONTRACT(3) HFMM_CONTRACT(4) HFMM_CONTRACT(5) HFMM_CONTRACT(6)
+          HFMM_CONTRACT(7)
+          default: trans_contract<REV, NTMAX>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
+        }
+#undef HFMM_CONTRACT
+      }
+    }
   }
-  __syncthreads();
-  // wave -> row tiles: the four waves split up to 4 it.ntw row tiles of the
-  // item's single column tile with stride 4
-  const int ntile = 0;
-  const int rt_lo = it.rt_base + wave, rt_stride = 4;
-  const int rt_cnt = rt_lo < nrt ? min((nrt - rt_lo + 3) / 4, it.ntw) : 0;
-  if (ntile * 16 >= it.npairs || rt_cnt <= 0) return;
-#define HFMM_TILES(N)                                                                                           \
-  case N:                                                                                                       \
-    trans_tiles<REV, MODE, N>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, doff, pcoff, dst, contrib, cstride, r); \
-    break;
+  if (rt_cnt <= 0 || !col_ok) return;
   if (NTMAX <= 2) {
-    switch (rt_cnt) {
-      HFMM_TILES(1)
-      default: trans_tiles<REV, MODE, 2>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, doff, pcoff, dst, contrib, cstride, r);
-    }
+    if (rt_cnt == 1)
+      trans_store<MODE, PREFETCH, 1>(acc, old, outd, rt_lo, rt_stride, Md, Pd, reflect_out);
+    else
+      trans_store<MODE, PREFETCH, (NTMAX < 2 ? NTMAX : 2)>(acc, old, outd, rt_lo, rt_stride, Md, Pd, reflect_out);
   } else {
+#define HFMM_STORE(N) \
+  case N: trans_store<MODE, PREFETCH, N>(acc, old, outd, rt_lo, rt_stride, Md, Pd, reflect_out); break;
     switch (rt_cnt) {
-      HFMM_TILES(1) HFMM_TILES(2) HFMM_TILES(3) HFMM_TILES(4) HFMM_TILES(5) HFMM_TILES(6) HFMM_TILES(7)
-      default: trans_tiles<REV, MODE, 8>(tv, it, lds_d, ntp, s_s, ntile, rt_lo, rt_stride, doff, pcoff, dst, contrib, cstride, r);
+      HFMM_STORE(1) HFMM_STORE(2) HFMM_STORE(3) HFMM_STORE(4) HFMM_STORE(5) HFMM_STORE(6) HFMM_STORE(7)
+      default: trans_store<MODE, PREFETCH, NTMAX>(acc, old, outd, rt_lo, rt_stride, Md, Pd, reflect_out);
     }
+#undef HFMM_STORE
   }
-#undef HFMM_TILES
 }
-
 // beta_b = sum of the contribution rows of box b, plain store. The box's
 // ptr[wi + 1] - ptr[wi] rows lie one after another from beg[wi] (each 2M
 // doubles: the real parts, then the imaginary parts). One block per box and
@@ -511,6 +554,7 @@ __global__ void __launch_bounds__(RED_THREADS) k_reduce_contrib(TreeView tv, con
                                                                 double2* __restrict__ dst) {
   const int wi = blockIdx.x;
   if (wi >= nb) return;
+  far_field_priority();
   const int b = boxes[wi];
   const int M = 2 * tv.P[tv.level[b]] + 1, W = 2 * M;
   const int cnt = ptr[wi + 1] - ptr[wi];
@@ -1299,8 +1343,8 @@ static hipError_t trans_lds_limit() {
 }
 
 hipError_t init_kernel_attributes() {
-  const hipError_t es[6] = {trans_lds_limit<false, OUT_ATOMIC>(), trans_lds_limit<false, OUT_CONTRIB>(),
-                            trans_lds_limit<false, OUT_EXCLUSIVE>(), trans_lds_limit<true, OUT_ATOMIC>(),
+  const hipError_t es[6] = {trans_lds_limit<false, OUT_GATHER4>(), trans_lds_limit<false, OUT_CONTRIB>(),
+                            trans_lds_limit<false, OUT_EXCLUSIVE>(), trans_lds_limit<true, OUT_GATHER4>(),
                             trans_lds_limit<true, OUT_CONTRIB>(), trans_lds_limit<true, OUT_EXCLUSIVE>()};
   for (hipError_t e : es)
     if (e != hipSuccess) return e;
@@ -1322,17 +1366,17 @@ static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items,
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
                   const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
-                  int exclusive, int ntw) {
+                  int gather4, int ntw) {
   if (nitems <= 0) return;
   const size_t lds = trans_lds_bytes(Ps, Pd);
 #define HFMM_TRANS(R, M) \
   trans_one<R, M>(s, tv, items, nitems, lds, ntw, soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride)
   if (contrib) {
     if (rev) HFMM_TRANS(true, OUT_CONTRIB); else HFMM_TRANS(false, OUT_CONTRIB);
-  } else if (exclusive) {
-    if (rev) HFMM_TRANS(true, OUT_EXCLUSIVE); else HFMM_TRANS(false, OUT_EXCLUSIVE);
+  } else if (gather4) {
+    if (rev) HFMM_TRANS(true, OUT_GATHER4); else HFMM_TRANS(false, OUT_GATHER4);
   } else {
-    if (rev) HFMM_TRANS(true, OUT_ATOMIC); else HFMM_TRANS(false, OUT_ATOMIC);
+    if (rev) HFMM_TRANS(true, OUT_EXCLUSIVE); else HFMM_TRANS(false, OUT_EXCLUSIVE);
   }
 #undef HFMM_TRANS
 }

@@ -21,16 +21,17 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
 // Batched translation contraction (M2L, M2M, L2L and transposes) for items
 // sharing (Ps, Pd). With contrib != NULL each pair writes its own contribution
 // row at pcoff[pair] (plane stride cstride per right-hand side); otherwise the
-// result is added into dst of the pair's target box, atomically unless
-// exclusive says that no two pairs of the launch share a target box.
-// soff / doff: per pair, the coefficient offsets of its source and target
-// boxes. The table of an item is at item.toff in tdata, or (toff < 0) at
-// q4.v[item.table]. ntw: the row tiles per wave of the items (their largest
-// value).
+// result is added into dst of the pair's target box, which no other pair of
+// the launch targets. Without gather4 a pair is (source, target): soff / doff
+// hold the coefficient offsets of its boxes, and the table of an item is at
+// item.toff in tdata or (toff < 0) at q4.v[item.table]. With gather4 (child
+// to parent) a "pair" is a parent: doff its offset, soff[4 pair + q] that of
+// its child in quadrant q (-1: none), translated with the table at q4.v[q].
+// ntw: the row tiles per wave of the items (their largest value).
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
                   const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
-                  int exclusive, int ntw);
+                  int gather4, int ntw);
 // dst(box) = sum of its contribution rows: ptr[w + 1] - ptr[w] rows from
 // row offset beg[w] for boxes[w].
 void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
