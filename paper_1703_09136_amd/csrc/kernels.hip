@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
     for (int rr = 0; rr < RB; ++rr)
       if (rr < nr) s_q[rr * WAVE + lane] = valid ? qs[(int64_t)(r0 + rr) * tv.n + j] : cmk(0.0, 0.0);
     const double rho = hypot(dx, dy);
-    const double x = fmax(tv.k * rho, 1e-100);
+    const double x = fmax(tv.k * rho, kTinyX), s1 = tv.k * rho < kTinyX ? tv.k * rho / kTinyX : 1.0;
     const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? dy : -dy) / rho) : cmk(1.0, 0.0);
     double2 wn = cpowi(w, P);
     double inv_s;
@@ -130,7 +130,8 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
 #pragma unroll
       for (int t = 0; t < P2M_CH; ++t) {
         if (nh - t >= 0) {
-          s_V[t * P2M_VS + lane] = cscale(wn, valid ? mw.value() : 0.0);
+          const double jv = nh - t == 1 ? s1 * mw.value() : mw.value();
+          s_V[t * P2M_VS + lane] = cscale(wn, valid ? jv : 0.0);
           wn = cmul(wn, cconj(w));
           if (mw.n > 0) mw.step();
         }
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
       const double2 p = tv.pts[j];
       const double dx = p.x - c.x, dy = p.y - c.y;
       const double rho = hypot(dx, dy);
-      const double x = fmax(tv.k * rho, 1e-100);
+      const double x = fmax(tv.k * rho, kTinyX), s1 = tv.k * rho < kTinyX ? tv.k * rho / kTinyX : 1.0;
       const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1.0, 0.0);
       double2 wn = cpowi(w, P);
       double inv_s;
@@ -249,7 +250,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
       MillerWalk mw(x, nstart, inv_s, nres);
       while (mw.n > P) mw.step();
       for (int n = P; n >= 0; --n) {
-        const double2 jw = cscale(wn, mw.value());
+        const double2 jw = cscale(wn, n == 1 ? s1 * mw.value() : mw.value());
 #pragma unroll
         for (int rr = 0; rr < RB; ++rr) {
           if (rr < nr) {
@@ -833,7 +834,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __res
         const double2 p = tv.pts[j];
         const double dx = p.x - c.x, dy = p.y - c.y;
         const double rho = hypot(dx, dy);
-        const double x = fmax(tv.k * rho, 1e-100);
+        const double x = fmax(tv.k * rho, kTinyX), s1 = tv.k * rho < kTinyX ? tv.k * rho / kTinyX : 1.0;
         const double2 w = rho > 0 ? cmk(dx / rho, -dy / rho) : cmk(1, 0);  // e^{-i theta}
         double2 wn = cpowi(w, Pg);
         double inv_s;
@@ -842,7 +843,7 @@ __global__ void __launch_bounds__(WAVE) k_l2p_grad(TreeView tv, const int* __res
         MillerWalk mw(x, nstart, inv_s, nres);
         while (mw.n > Pg) mw.step();
         for (int n = Pg; n >= 0; --n) {
-          const double jn = mw.value();
+          const double jn = n == 1 ? s1 * mw.value() : mw.value();
           const double2 wc = cconj(wn);
 #pragma unroll
           for (int rr = 0; rr < L2P_RB; ++rr) {

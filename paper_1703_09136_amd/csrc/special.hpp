@@ -20,9 +20,13 @@
 
 namespace hfmm {
 
+// Start indices of the backward recurrence are multiples of 4 (the passes
+// below take four steps at a time).
+__host__ __device__ inline int miller_round(int n) { return (n + 3) & ~3; }
+
 __host__ __device__ inline int miller_start(double x, int nmax) {
   double m = fmax((double)nmax, x);
-  return (int)(m + 20.0 + 12.0 * cbrt(m + 1.0));
+  return miller_round((int)(m + 20.0 + 12.0 * cbrt(m + 1.0)));
 }
 
 // Start index for the expansions at a leaf, orders 0..nmax at arguments up to
@@ -43,25 +47,39 @@ __host__ __device__ inline int miller_start_expansion(double x, int nmax) {
     r *= x / (2.0 * (double)(m + 1) - x);
     ++m;
   }
-  return m + 1;
+  return miller_round(m + 1);
 }
 
 constexpr double kRescaleHi = 0x1p+700;   // rescale when |J| exceeds this
 constexpr double kRescaleBy = 0x1p-700;
+// Arguments below kTinyX are raised to it: then J_n(x) = J_n(kTinyX) to
+// 1.3e-19 absolutely for n != 1, and J_1(x) = (x / kTinyX) J_1(kTinyX) to a
+// relative 1e-19 (the ascending series' second terms), which callers apply.
+// It bounds the growth of the backward sequence, at most 2 n / x per step:
+// below 2^41 for the starts used here (n < 1100), so four steps between
+// rescaling checks stay far from overflow.
+constexpr double kTinyX = 1e-9;
 
-// Pass 1: normalisation of the backward sequence. Returns 1/S in the final
-// scale and the number of rescalings performed. The recurrence factor is
-// n * (2/x); every pass below uses this same arithmetic so that the passes
-// rescale at the same indices.
+// Pass 1: normalisation of the backward sequence, S = J_0 + 2 sum J_{2k}
+// unnormalised, four steps at a time (nstart a multiple of 4, x >= kTinyX).
+// Returns 1/S in the final scale and the number of rescalings performed. The
+// recurrence is j_{n-1} = fma(n (2/x), j_n, -j_{n+1}), rescaled whenever a new
+// index is a multiple of 4 and |j| exceeds kRescaleHi; the walk below uses
+// this same arithmetic so that both passes rescale at the same indices.
 __host__ __device__ inline void miller_norm(double x, int nstart, double& inv_s, int& nres) {
   const double tx = 2.0 / x;
   double jp1 = 0.0, j = 0x1p-900, s = 0.0;
   nres = 0;
-  for (int n = nstart; n >= 1; --n) {
-    if ((n & 1) == 0) s += 2.0 * j;
-    double jm1 = ((double)n * tx) * j - jp1;
-    jp1 = j;
-    j = jm1;
+  double dn = (double)nstart;
+  for (int n = nstart; n >= 4; n -= 4) {  // j = j_n, jp1 = j_{n+1}, n even
+    const double a = fma(dn * tx, j, -jp1);          // j_{n-1}
+    const double b = fma((dn - 1.0) * tx, a, -j);    // j_{n-2}
+    const double c = fma((dn - 2.0) * tx, b, -a);    // j_{n-3}
+    const double d = fma((dn - 3.0) * tx, c, -b);    // j_{n-4}
+    s += 2.0 * (j + b);
+    jp1 = c;
+    j = d;
+    dn -= 4.0;
     if (fabs(j) > kRescaleHi) {
       j *= kRescaleBy; jp1 *= kRescaleBy; s *= kRescaleBy;
       ++nres;
@@ -74,18 +92,19 @@ __host__ __device__ inline void miller_norm(double x, int nstart, double& inv_s,
 // Pass 2 as an explicit walk: value() is the normalised J_n at the current
 // index n (starting at nstart); step() moves to n - 1.
 struct MillerWalk {
-  double tx, j, jp1, inv_s;
+  double tx, j, jp1, inv_s, dn;
   int n, left;  // rescalings still ahead
   __host__ __device__ MillerWalk(double x, int nstart, double inv_s_, int nres)
-      : tx(2.0 / x), j(0x1p-900), jp1(0.0), inv_s(inv_s_), n(nstart), left(nres) {}
+      : tx(2.0 / x), j(0x1p-900), jp1(0.0), inv_s(inv_s_), dn((double)nstart), n(nstart), left(nres) {}
   // J_n = j kRescaleBy^left / S, the power applied exactly by ldexp
   __host__ __device__ double value() const { return ldexp(j * inv_s, -700 * left); }
   __host__ __device__ void step() {
-    double jm1 = ((double)n * tx) * j - jp1;
+    const double jm1 = fma(dn * tx, j, -jp1);
     jp1 = j;
     j = jm1;
     --n;
-    if (fabs(j) > kRescaleHi) {
+    dn -= 1.0;
+    if ((n & 3) == 0 && fabs(j) > kRescaleHi) {
       j *= kRescaleBy; jp1 *= kRescaleBy;
       --left;
     }
@@ -111,11 +130,12 @@ __host__ __device__ inline void bessel_j_each(double x, int nmax, F f) {
     for (int n = nmax; n >= 0; --n) f(n, n == 0 ? 1.0 : 0.0);
     return;
   }
-  int ns = miller_start(x, nmax);
+  const double xr = fmax(x, kTinyX), s1 = x < kTinyX ? x / kTinyX : 1.0;
+  int ns = miller_start(xr, nmax);
   double inv_s;
   int nres;
-  miller_norm(x, ns, inv_s, nres);
-  miller_emit(x, ns, nmax, inv_s, nres, f);
+  miller_norm(xr, ns, inv_s, nres);
+  miller_emit(xr, ns, nmax, inv_s, nres, [&](int n, double v) { f(n, n == 1 ? s1 * v : v); });
 }
 
 // Coefficients of the ascending series in z = x^2/4 (A&S 9.1.12, 9.1.13):
