@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhfmm.so")
-SOURCES = ["hfmm.hip", "kernels.hip", "batch.hip"]
+SOURCES = ["hfmm.hip", "kernels.hip", "p2p.hip", "batch.hip"]
 ARCH = os.environ.get("HFMM_OFFLOAD_ARCH", "gfx950")
 
 
