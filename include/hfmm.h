@@ -79,6 +79,17 @@ typedef struct {
                                holds more than leaf_size / 4 points, or
                                exceeds 2 leaf_kb (default 1.5; 0 turns the
                                bound off). Must be 0 or >= 0.25. */
+  int32_t top_level;        /* coarsest level of the expansions: multipole-
+                               to-local pairs of coarser levels are split into
+                               their children's pairs at this level, and the
+                               passes up and down stop there. 2 is the
+                               classical choice (every level that can hold a
+                               separated pair); 0 (default) takes the
+                               deepest level whose
+                               boxes form at most 4096 ordered pairs and
+                               which no leaf lies above. Must be 0 or >= 2;
+                               it is lowered to the shallowest leaf level. */
+  int32_t reserved0;
 } hfmm_options_t;
 
 typedef struct {
@@ -100,6 +111,8 @@ typedef struct {
   int64_t p2p_evals;        /* H0 evaluations per apply and right-hand side:
                                each cross-leaf pair once, same-leaf pairs
                                in both orders */
+  int32_t top_level;        /* coarsest level of the expansions in use */
+  int32_t reserved0;
 } hfmm_info_t;
 
 /* Default options. */

@@ -36,7 +36,7 @@ HFMM_FP64, HFMM_FP32 = 0, 1
 class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("self_term", ctypes.c_int32), ("interface_refine", ctypes.c_int32), ("max_level", ctypes.c_int32),
-                ("leaf_kb", ctypes.c_double)]
+                ("leaf_kb", ctypes.c_double), ("top_level", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -45,10 +45,11 @@ class Info(ctypes.Structure):
                 ("p2p_pairs", ctypes.c_int64), ("interface_pairs", ctypes.c_int64),
                 ("image_tables", ctypes.c_int64), ("flops_m2l", ctypes.c_double),
                 ("flops_updown", ctypes.c_double), ("flops_p2p", ctypes.c_double),
-                ("plan_seconds", ctypes.c_double), ("p2p_evals", ctypes.c_int64)]
+                ("plan_seconds", ctypes.c_double), ("p2p_evals", ctypes.c_int64),
+                ("top_level", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "order"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("order", "reserved0")}
         d["order"] = [int(self.order[i]) for i in range(self.levels)]
         return d
 
@@ -120,8 +121,11 @@ def default_options(**kw) -> Options:
     lib = load()
     o = Options()
     lib.hfmm_default_options(ctypes.byref(o))
+    kinds = dict(Options._fields_)
     for key, val in kw.items():
-        setattr(o, key, int(val))
+        if key not in kinds:
+            raise TypeError("unknown option %r" % key)
+        setattr(o, key, float(val) if kinds[key] is ctypes.c_double else int(val))
     return o
 
 

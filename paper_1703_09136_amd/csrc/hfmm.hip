@@ -242,6 +242,7 @@ struct hfmm_plan_s {
   double tol = 0.0;
   hfmm_options_t opt{};
   int nlev = 0;
+  int top = 2;  // coarsest level of the expansions
   double S = 1.0, x0 = 0.0, y0 = 0.0;
   int P[HFMM_MAX_LEVELS] = {0};
   double bsize[HFMM_MAX_LEVELS] = {0};
@@ -482,6 +483,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   if (o.max_level < 2 || o.max_level > KEY_BITS) return fail(HFMM_ERR_INVALID_ARG, "max_level out of range");
   if (!(o.leaf_kb == 0.0 || (o.leaf_kb >= 0.25 && std::isfinite(o.leaf_kb))))
     return fail(HFMM_ERR_INVALID_ARG, "leaf_kb must be 0 or a finite value >= 0.25");
+  if (o.top_level != 0 && (o.top_level < 2 || o.top_level > KEY_BITS))
+    return fail(HFMM_ERR_INVALID_ARG, "top_level must be 0 or in [2, 30]");
   for (int i = 0; i < layers; ++i)
     if (!(wavenumbers[i] > 0.0) || !std::isfinite(wavenumbers[i]))
       return fail(HFMM_ERR_UNSUPPORTED, "wavenumbers must be finite and > 0");
@@ -655,6 +658,29 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
   pl->ctot = ctot;
 
+  // ---- coarsest level of the expansions. Starting the multipole-to-local
+  // pairs at a finer level than 2 splits the coarse levels' few pairs (of the
+  // highest orders, whose launches are latency bound) into more pairs of a
+  // lower order at that level; the automatic choice keeps every pair of boxes
+  // of the top level below kTopPairs. No leaf may lie above it.
+  {
+    constexpr int64_t kTopPairs = 4096;
+    int minleaf = pl->nlev;
+    for (int i = 0; i < nb; ++i)
+      if (B[i].leaf) minleaf = std::min(minleaf, B[i].level);
+    int top = 2;
+    if (o.top_level >= 2) {
+      top = o.top_level;
+    } else {
+      for (int l = 3; l < pl->nlev; ++l) {
+        const int64_t nbl = pl->lev_begin[l + 1] - pl->lev_begin[l];
+        if (nbl * nbl > kTopPairs) break;
+        top = l;
+      }
+    }
+    pl->top = std::max(2, std::min(top, std::min(minleaf, pl->nlev - 1)));
+  }
+
   // ---- interaction lists
   struct PairL { int t, s; };
   std::vector<PairL> fv, iv, fu, iu;
@@ -672,7 +698,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   while (!stack.empty()) {
     PairL pr = stack.back();
     stack.pop_back();
-    if (!adjacent(pr.t, pr.s)) {
+    if (!adjacent(pr.t, pr.s) && B[pr.t].level >= pl->top) {
       fv.push_back(pr);
     } else if (B[pr.t].leaf || B[pr.s].leaf) {
       fu.push_back(pr);
@@ -689,7 +715,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     stack.pop_back();
     int l = B[pr.t].level;
     double b = pl->bsize[l];
-    bool adm = l >= 2 && (B[pr.t].iy + B[pr.s].iy >= 1 || 2.0 * ymin >= b);
+    bool adm = l >= pl->top && (B[pr.t].iy + B[pr.s].iy >= 1 || 2.0 * ymin >= b);
     if (adm) {
       iv.push_back(pr);
     } else if (B[pr.t].leaf || B[pr.s].leaf) {
@@ -850,7 +876,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->l2l_tab.assign(pl->nlev, -1);
   pl->m2m_q4.assign(pl->nlev, Toff4{});
   pl->l2l_q4.assign(pl->nlev, Toff4{});
-  for (int l = 2; l + 1 < pl->nlev; ++l) {
+  for (int l = pl->top; l + 1 < pl->nlev; ++l) {
     double bc = pl->bsize[l + 1];
     for (int pass = 0; pass < 2; ++pass) {
       int base = (int)tabs.size();
@@ -878,7 +904,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<TransItem> up_items, down_items;
   pl->up_groups.assign(pl->nlev, {});
   pl->down_groups.assign(pl->nlev, {});
-  for (int l = 2; l + 1 < pl->nlev; ++l) {
+  for (int l = pl->top; l + 1 < pl->nlev; ++l) {
     auto& gu = pl->up_groups[l];
     auto& gd = pl->down_groups[l];
     gu.first = (int)up_items.size();
@@ -1325,11 +1351,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     if (l < 2) continue;
     double m = 2.0 * pl->P[l] + 1;
     if (B[i].leaf) fud += 2.0 * (B[i].end - B[i].begin) * m * 8.0;  // P2M + L2P MACs
-    if (l >= 3) fud += 2.0 * 8.0 * m * (2.0 * pl->P[l - 1] + 1);     // M2M + L2L
+    if (l > pl->top) fud += 2.0 * 8.0 * m * (2.0 * pl->P[l - 1] + 1);  // M2M + L2L
   }
   inf.flops_updown = fud;
   inf.flops_p2p = pl->p2p_flops;
   inf.p2p_evals = pl->p2p_evals;
+  inf.top_level = pl->top;
   inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   *out = pl;
   return HFMM_OK;
@@ -1444,11 +1471,11 @@ hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const doubl
     const hipError_t e = fork_near(pl, tv, s, qs, us);
     if (e != hipSuccess) return e;
   }
-  for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0);
+  for (int l = pl->nlev - 2; l >= pl->top; --l) launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0);
   mark();
   launch_m2l_all(pl, tv, s, pl->alpha.p, pl->beta.p, 0);
   mark();
-  for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0);
+  for (int l = pl->top; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0);
   mark();
   launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25), overlap ? 2 : 0);
   mark();
@@ -1470,11 +1497,11 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
     if (e != hipSuccess) return e;
   }
   // L2L^T, finest parents first: beta'(parent) = sum over its children of T^T beta'(child)
-  for (int l = pl->nlev - 2; l >= 2; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
+  for (int l = pl->nlev - 2; l >= pl->top; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
   // M2L^T, reduced by source box
   launch_m2l_all(pl, tv, s, pl->beta.p, pl->alpha.p, 1);
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
-  for (int l = 2; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1);
+  for (int l = pl->top; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1);
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
   launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0), overlap ? 2 : 0);
   if (overlap) return join_near(pl, s);

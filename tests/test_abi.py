@@ -58,6 +58,9 @@ def _plan(lib, layers, k, ifs, n, tol, opts=None, points=1):
     (dict(opts=dict(leaf_size=0)), 1),
     (dict(opts=dict(precision=7)), 3),
     (dict(opts=dict(max_level=1)), 1),
+    (dict(opts=dict(top_level=1)), 1),
+    (dict(opts=dict(top_level=31)), 1),
+    (dict(opts=dict(leaf_kb=0.1)), 1),
 ])
 def test_plan_rejects_bad_arguments(case, expected):
     lib = hf.load()

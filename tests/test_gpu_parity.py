@@ -45,13 +45,18 @@ def test_one_leaf_plan_is_the_direct_sum(gpu_lib):
     assert e < 1e-12
 
 
-def test_two_layer_n1024_full_tree(gpu_lib):
+@pytest.mark.parametrize("top_level", [0, 2, 3])
+def test_two_layer_n1024_full_tree(gpu_lib, top_level):
+    """top_level 2: every separated pair at its coarsest level (M2M and L2L on
+    every level); 0: the automatic top level; 3: in between."""
     w = workloads.two_layer_uniform()
-    plan, u = run(gpu_lib, w, 1e-10, leaf_size=32)
+    plan, u = run(gpu_lib, w, 1e-10, leaf_size=32, top_level=top_level)
     inf = plan.info()
     e = rel(u, ref_apply(w))
-    print("two-layer N=1024 E =", e, inf)
+    print("two-layer N=1024 top_level %d E =" % top_level, e, inf)
     assert inf["m2l_pairs"] > 0 and inf["image_pairs"] > 0
+    if top_level:
+        assert inf["top_level"] == top_level
     assert e < 1e-10
 
 
