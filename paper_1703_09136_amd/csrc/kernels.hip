@@ -307,13 +307,9 @@ enum { OUT_GATHER4 = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2 };
 
 // LDS layout of an item: the table as three zero-padded vectors Tr, Ti, -Ti of
 // trans_table_stride(nt) doubles each (value n at index kTabPad + n), then the
-// source coefficients of one chunk of orders, a row per pair. The orders run
-// over Ms4 = Ms rounded up to 4 (zeros past Ms), so that the real and the
-// imaginary halves of the contraction index k each fill whole 4-deep MFMA
-// steps, in chunks of at most TR_KC orders: the coarse levels' long rows
-// (P up to a few hundred) then need no more LDS than the leaves' and their
-// blocks still fit beside other work.
-constexpr int TR_KC = 64;
+// source coefficients, one row of Ms4 = Ms rounded up to 4 per pair (zeros
+// past Ms), so that the real and the imaginary halves of the contraction
+// index k each fill whole 4-deep MFMA steps.
 constexpr int kTabPad = 4;
 __host__ __device__ inline int trans_table_stride(int nt) { return (nt + 2 * kTabPad + 1) & ~1; }
 __host__ __device__ inline int round4(int m) { return (m + 3) & ~3; }
@@ -326,9 +322,9 @@ __host__ __device__ inline int round4(int m) { return (m + 3) & ~3; }
 // tile and half, so every operand element is one LDS read and the k-loop has
 // no branches.
 template <bool REV, int NT>
-__device__ inline void trans_contract(d4* acc, const double* lds_d, int ntp, const double2* s_s, int rs, int m0,
-                                      int Ps, int Pd, int rt_lo, int rt_stride) {
-  const int Md = 2 * Pd + 1;
+__device__ inline void trans_contract(d4* acc, const double* lds_d, int ntp, const double2* s_s, int Ps, int Pd,
+                                      int rt_lo, int rt_stride) {
+  const int Ms4 = round4(2 * Ps + 1), Md = 2 * Pd + 1;
   const int lane = threadIdx.x & 63, lrow = lane & 15, lk = lane >> 4;
   int a_re[NT], a_im[NT];
 #pragma unroll
@@ -341,14 +337,12 @@ __device__ inline void trans_contract(d4* acc, const double* lds_d, int ntp, con
     a_re[j] = (rim ? ntp : 0) + tb;      // Tr (rim == kim) or Ti
     a_im[j] = (rim ? 0 : 2 * ntp) + tb;  // Tr or -Ti
   }
-  // the chunk's orders m0 .. m0 + rs - 1, a row of rs per pair
-  const double* Bcol = (const double*)(s_s + lrow * rs) + 2 * lk;
-  const int nks = rs / 4;
-  const int kb = REV ? -m0 : m0;
+  const double* Bcol = (const double*)(s_s + lrow * Ms4) + 2 * lk;
+  const int nks = Ms4 / 4;
   // real half of k, then the imaginary half
 #pragma unroll 2
   for (int ks = 0; ks < nks; ++ks) {
-    const int kk = kb + (REV ? -4 * ks : 4 * ks);
+    const int kk = REV ? -4 * ks : 4 * ks;
     const double b = Bcol[8 * ks];
     double a[NT];
 #pragma unroll
@@ -358,7 +352,7 @@ __device__ inline void trans_contract(d4* acc, const double* lds_d, int ntp, con
   }
 #pragma unroll 2
   for (int ks = 0; ks < nks; ++ks) {
-    const int kk = kb + (REV ? -4 * ks : 4 * ks);
+    const int kk = REV ? -4 * ks : 4 * ks;
     const double b = Bcol[8 * ks + 1];
     double a[NT];
 #pragma unroll
@@ -471,10 +465,12 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   for (int j = 0; j < NTMAX; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
   const bool reflect_in = it.image && !REV;
   const double2* Sr = src + (int64_t)r * tv.ctot;
+  const int tot = npi * Ms4;
+#pragma unroll 1
   for (int ph = 0; ph < (G4 ? 4 : 1); ++ph) {
     if (ph > 0) __syncthreads();  // the previous quadrant's operands are no longer read
     // Every global load of the prologue is issued in one of two rounds: the
-    // pairs' coefficient offsets and the table first, then the source rows.
+    // pairs' coefficient offsets and the table first, then all source rows.
     if (tid < npi) s_off[tid] = tid < it.npairs ? soff[G4 ? 4 * (it.pbeg + tid) + ph : it.pbeg + tid] : -1;
     const double2* T = tdata + (it.toff >= 0 ? it.toff : q4.v[G4 ? ph : (it.table & 3)]);  // T[0] = t[-(Ps + Pd)]
     for (int i = tid; i < ntp; i += TR_THREADS) {
@@ -485,54 +481,49 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
       lds_d[2 * ntp + i] = -v.y;
     }
     __syncthreads();
-    for (int m0 = 0; m0 < Ms4; m0 += TR_KC) {
-      if (m0 > 0) __syncthreads();  // the previous chunk is no longer read
-      const int rs = min(TR_KC, Ms4 - m0);  // orders of this chunk (a multiple of 4)
-      const int tot = npi * rs;
-      // source coefficients, flattened (pair, order) so consecutive lanes read
-      // consecutive coefficients of a row; four loads in flight per lane
-      for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
-        double2 v[4];
+    // source coefficients, flattened (pair, order) so consecutive lanes read
+    // consecutive coefficients of a row; four loads in flight per lane
+    for (int e0 = tid; e0 < tot; e0 += 4 * TR_THREADS) {
+      double2 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int e = e0 + u * TR_THREADS;
-          v[u] = cmk(0.0, 0.0);
-          if (e < tot) {
-            const int c = e / rs, m = m0 + (e - c * rs);
-            const int64_t off = s_off[c];
-            if (off >= 0 && m < Ms) {
-              if (reflect_in) {
-                v[u] = Sr[off + Ms - 1 - m];
-                if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
-              } else {
-                v[u] = Sr[off + m];
-              }
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * TR_THREADS;
+        v[u] = cmk(0.0, 0.0);
+        if (e < tot) {
+          const int c = e / Ms4, m = e - c * Ms4;
+          const int64_t off = s_off[c];
+          if (off >= 0 && m < Ms) {
+            if (reflect_in) {
+              v[u] = Sr[off + Ms - 1 - m];
+              if ((m + Ps) & 1) v[u] = cscale(v[u], -1.0);
+            } else {
+              v[u] = Sr[off + m];
             }
           }
         }
+      }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
-      }
-      __syncthreads();
-      if (rt_cnt > 0) {
-        if (NTMAX <= 2) {
-          if (rt_cnt == 1)
-            trans_contract<REV, 1>(acc, lds_d, ntp, s_s, rs, m0, Ps, Pd, rt_lo, rt_stride);
-          else
-            trans_contract<REV, (NTMAX < 2 ? NTMAX : 2)>(acc, lds_d, ntp, s_s, rs, m0, Ps, Pd, rt_lo, rt_stride);
-        } else {
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
+    }
+    __syncthreads();
+    if (rt_cnt > 0) {
+      if (NTMAX <= 2) {
+        if (rt_cnt == 1)
+          trans_contract<REV, 1>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
+        else
+          trans_contract<REV, (NTMAX < 2 ? NTMAX : 2)>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
+      } else {
 #define HFMM_CONTRACT(N) \
-    case N: trans_contract<REV, N>(acc, lds_d, ntp, s_s, rs, m0, Ps, Pd, rt_lo, rt_stride); break;
-          switch (rt_cnt) {
-            HFMM_CONTRACT(1) HFMM_CONTRACT(2) HFMM_CONTRACT(3) HFMM_CONTRACT(4) HFMM_CONTRACT(5) HFMM_CONTRACT(6)
-            HFMM_CONTRACT(7)
-            default: trans_contract<REV, NTMAX>(acc, lds_d, ntp, s_s, rs, m0, Ps, Pd, rt_lo, rt_stride);
-          }
-#undef HFMM_CONTRACT
+  case N: trans_contract<REV, N>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride); break;
+        switch (rt_cnt) {
+          HFMM_CONTRACT(1) HFMM_CONTRACT(2) HFMM_CONTRACT(3) HFMM_CONTRACT(4) HFMM_CONTRACT(5) HFMM_CONTRACT(6)
+          HFMM_CONTRACT(7)
+          default: trans_contract<REV, NTMAX>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
         }
+#undef HFMM_CONTRACT
       }
-    }  // chunks
+    }
   }
   if (rt_cnt <= 0 || !col_ok) return;
   if (NTMAX <= 2) {
@@ -1133,7 +1124,7 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
 size_t trans_lds_bytes(int Ps, int Pd) {
   const int ntp = trans_table_stride(2 * (Ps + Pd) + 1);
   const int npi = trans_pairs_per_item(Ps, Pd);
-  return sizeof(double) * (size_t)(3 * ntp) + sizeof(double2) * (size_t)npi * std::min(TR_KC, round4(2 * Ps + 1));
+  return sizeof(double) * (size_t)(3 * ntp) + sizeof(double2) * (size_t)npi * round4(2 * Ps + 1);
 }
 
 // Dynamic LDS limit of the translation kernels: the CU's 160 KiB less each
