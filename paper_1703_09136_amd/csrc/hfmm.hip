@@ -259,7 +259,8 @@ struct hfmm_plan_s {
   int nleaves = 0;
   std::vector<int> leaf_lev;  // leaves of level l: [leaf_lev[l], leaf_lev[l + 1])
   int leaf_pmax = 0;          // largest expansion order among the leaves
-  // batched translations: item groups sharing (Ps, Pd), per level
+  // batched translations: item groups, one launch each (M2M / L2L: per level;
+  // M2L: runs of consecutive levels); Ps, Pd: the largest orders of the items
   struct Group {
     int first = 0, count = 0, Ps = 0, Pd = 0, ntw = 8;  // ntw: row tiles per wave of the items
   };
@@ -841,7 +842,23 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       }
     }
     g.count = (int)m2l_items.size() - g.first;
-    if (g.count) pl->m2l_groups.push_back(g);
+    if (!g.count) continue;
+    // Consecutive levels share one launch where that costs little, which
+    // removes the drain at the end of each launch. A launch reserves the LDS
+    // of its largest order, so a level joins the launch before it when that
+    // LDS is at most 1.25 times its own, or when the level alone has under
+    // four blocks per CU and so cannot fill the GPU by itself. Both use the
+    // same kernel instantiation (ntw up to 2, or more).
+    if (!pl->m2l_groups.empty()) {
+      auto& run = pl->m2l_groups.back();
+      const double lds_ratio = (double)trans_lds_bytes(run.Ps, run.Pd) / (double)trans_lds_bytes(g.Ps, g.Pd);
+      if ((run.ntw <= 2) == (g.ntw <= 2) && g.Ps <= run.Ps && g.Pd <= run.Pd &&
+          (lds_ratio <= 1.25 || g.count < 1024)) {
+        run.count += g.count;
+        continue;
+      }
+    }
+    pl->m2l_groups.push_back(g);
   }
   pl->cstride = cstride;
   // contribution rows in box order, by target (forward) and by source
