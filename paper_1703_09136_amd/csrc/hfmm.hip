@@ -150,6 +150,12 @@ constexpr double kOrderSafety = HFMM_ORDER_SAFETY;
 // largest expansion order: the batched M2L keeps a 16-pair operand tile of
 // 2P+1 coefficients and the 4P+1 table entries in LDS
 constexpr int kMaxOrder = 255;
+// Launch shaping: the CUs of the GPU (MI355X: 256), the LDS of one CU, and the
+// most dynamic LDS a translation block may take (the CU's less the kernel's
+// static offsets).
+constexpr int64_t kNumCu = 256;
+constexpr size_t kCuLds = 160 * 1024;
+constexpr size_t kSplitLdsMax = kCuLds - 1024;
 
 Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
   Rule r;
@@ -263,6 +269,7 @@ struct hfmm_plan_s {
   // M2L: runs of consecutive levels); Ps, Pd: the largest orders of the items
   struct Group {
     int first = 0, count = 0, Ps = 0, Pd = 0, ntw = 8;  // ntw: row tiles per wave of the items
+    int split = 0;  // M2M gather: a quadrant per wave, one row tile per item
   };
   // M2L: items, (source, target) pair arrays, contribution row offsets, and the
   // per-box lists of pairs for the reduction by target (forward) / by source
@@ -935,10 +942,21 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       if (!B[i].leaf) parents.push_back(i);
     int64_t batches = 0;
     for (int q = 0; q < 4; ++q) batches += ((int64_t)kids[q].size() + npi - 1) / npi;
-    const int ntw_up = choose_ntw(((int64_t)parents.size() + npi - 1) / npi, pl->P[l + 1], pl->P[l]);
+    const int64_t pbatches = ((int64_t)parents.size() + npi - 1) / npi;
+    const int ntw_up = choose_ntw(pbatches, pl->P[l + 1], pl->P[l]);
     const int ntw_down = choose_ntw(batches, pl->P[l], pl->P[l + 1]);
     gu.ntw = ntw_up;
     gd.ntw = ntw_down;
+    // The gather with a quadrant per wave where its blocks (one per parent
+    // batch and row tile) all fit on the GPU at once: such small launches are
+    // bound by each block's chain of quadrants, which the split form runs
+    // side by side. Its LDS (four tables and source tiles) must fit a CU.
+    {
+      const size_t lds_split = trans_lds_bytes_split(pl->P[l + 1], pl->P[l]);
+      const int nrt_up = (2 * (2 * pl->P[l] + 1) + 15) / 16;
+      const int64_t per_cu = lds_split <= kSplitLdsMax ? (int64_t)(kCuLds / lds_split) : 0;
+      gu.split = per_cu > 0 && pbatches * nrt_up <= kNumCu * per_cu;
+    }
     for (size_t c0 = 0; c0 < parents.size(); c0 += npi) {
       const int cnt = (int)std::min<size_t>(npi, parents.size() - c0);
       const int pbeg = (int)up_doff_h.size();
@@ -947,7 +965,13 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         up_doff_h.push_back(coff[parents[c0 + c]]);
         for (int q = 0; q < 4; ++q) up_soff4_h.push_back(par.child[q] >= 0 ? coff[par.child[q]] : -1);
       }
-      add_items(up_items, 0, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
+      if (gu.split) {
+        const int nrt_up = (2 * (2 * pl->P[l] + 1) + 15) / 16;
+        for (int rt = 0; rt < nrt_up; ++rt)
+          up_items.push_back(TransItem{0, pbeg, cnt, 0, rt, pl->P[l + 1], pl->P[l], 1, -1});
+      } else {
+        add_items(up_items, 0, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
+      }
     }
     for (int q = 0; q < 4; ++q) {
       const std::vector<int>& kids_q = kids[q];
@@ -1425,7 +1449,7 @@ void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, in
   // a child has one parent, and up items gather a parent's children: no two
   // pairs of a launch write the same box
   launch_trans(s, tv, items, g.count, g.Ps, g.Pd, soff, doff, nullptr, q4, pl->tdata.p, src, dst, nullptr, 0, rev,
-               up ? 1 : 0, g.ntw);
+               up ? (g.split ? 2 : 1) : 0, g.ntw);
 }
 
 // All M2L items (forward: source -> target; transpose: target -> source) into

@@ -297,13 +297,18 @@ size_t l2p_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * 
 //  * four-quadrant gather (child to parent): the 16 columns are parents and
 //    the contraction runs over the four child quadrants in turn, each with its
 //    table, so that k spans the stacked children; a missing child is a zero
-//    column. Each parent receives its whole sum at once and is stored.
+//    column. Each parent receives its whole sum at once and is stored;
+//  * split four-quadrant gather (child to parent, launches too small to fill
+//    the GPU): an item is one row tile, and wave q contracts child quadrant q
+//    with its own table and source tile, all four staged at once; the four
+//    partial tiles are added through LDS and stored. Each SIMD's MFMA chain
+//    is a quarter of the in-turn form's, and the four rounds of loads are one.
 // This one kernel runs M2L (free and heterogeneous), M2M, L2L and their
 // transposes.
 typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int TR_THREADS = 256;
 
-enum { OUT_GATHER4 = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2 };
+enum { OUT_GATHER4 = 0, OUT_CONTRIB = 1, OUT_EXCLUSIVE = 2, OUT_GATHER4_SPLIT = 3 };
 
 // LDS layout of an item: the table as three zero-padded vectors Tr, Ti, -Ti of
 // trans_table_stride(nt) doubles each (value n at index kTabPad + n), then the
@@ -422,6 +427,7 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   __shared__ int64_t s_off[64];
   far_field_priority();
   constexpr bool G4 = MODE == OUT_GATHER4;
+  constexpr bool GS = MODE == OUT_GATHER4_SPLIT;  // quadrant per wave
   constexpr bool CONTRIB = MODE == OUT_CONTRIB;
   const int r = blockIdx.y;  // right-hand side
   const TransItem it = items[blockIdx.x];
@@ -431,12 +437,13 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   const int ntp = trans_table_stride(nt);
   const int nrt = (2 * Md + 15) / 16;
   const int npi = trans_pairs_per_item(Ps, Pd);
-  double2* s_s = (double2*)(lds_d + 3 * ntp);  // 16-byte aligned: ntp is even
+  // split gather: the four quadrants' tables, then their source tiles
+  double2* s_s = (double2*)(lds_d + (GS ? 4 : 1) * 3 * ntp);  // 16-byte aligned: ntp is even
   const int tid = threadIdx.x, wave = tid >> 6;
   // wave -> row tiles: the four waves split up to 4 it.ntw row tiles of the
-  // item's column tile with stride 4
-  const int rt_lo = it.rt_base + wave, rt_stride = 4;
-  const int rt_cnt = rt_lo < nrt ? min((nrt - rt_lo + 3) / 4, it.ntw) : 0;
+  // item's column tile with stride 4 (split gather: all take tile rt_base)
+  const int rt_lo = it.rt_base + (GS ? 0 : wave), rt_stride = 4;
+  const int rt_cnt = rt_lo < nrt ? (GS ? 1 : min((nrt - rt_lo + 3) / 4, it.ntw)) : 0;
   // this lane's column (pair) and output; exclusive targets are read now, so
   // that the read overlaps the contraction
   const int lane = tid & 63, lk = lane >> 4;
@@ -465,20 +472,30 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
   for (int j = 0; j < NTMAX; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
   const bool reflect_in = it.image && !REV;
   const double2* Sr = src + (int64_t)r * tv.ctot;
-  const int tot = npi * Ms4;
+  const int tot = (GS ? 4 : 1) * npi * Ms4;
 #pragma unroll 1
   for (int ph = 0; ph < (G4 ? 4 : 1); ++ph) {
     if (ph > 0) __syncthreads();  // the previous quadrant's operands are no longer read
     // Every global load of the prologue is issued in one of two rounds: the
     // pairs' coefficient offsets and the table first, then all source rows.
-    if (tid < npi) s_off[tid] = tid < it.npairs ? soff[G4 ? 4 * (it.pbeg + tid) + ph : it.pbeg + tid] : -1;
-    const double2* T = tdata + (it.toff >= 0 ? it.toff : q4.v[G4 ? ph : (it.table & 3)]);  // T[0] = t[-(Ps + Pd)]
-    for (int i = tid; i < ntp; i += TR_THREADS) {
-      const int n = i - kTabPad;
+    if (GS) {  // s_off[q npi + c]: quadrant q of parent c
+      if (tid < 4 * npi) {
+        const int q = tid / npi, c = tid - q * npi;
+        s_off[tid] = c < it.npairs ? soff[4 * (it.pbeg + c) + q] : -1;
+      }
+    } else if (tid < npi) {
+      s_off[tid] = tid < it.npairs ? soff[G4 ? 4 * (it.pbeg + tid) + ph : it.pbeg + tid] : -1;
+    }
+    for (int i = tid; i < (GS ? 4 : 1) * ntp; i += TR_THREADS) {
+      const int q = GS ? i / ntp : 0, j = i - q * ntp;
+      // T[0] = t[-(Ps + Pd)]
+      const double2* T = tdata + (it.toff >= 0 ? it.toff : q4.v[GS ? q : G4 ? ph : (it.table & 3)]);
+      const int n = j - kTabPad;
       const double2 v = (n >= 0 && n < nt) ? T[n] : cmk(0.0, 0.0);
-      lds_d[i] = v.x;
-      lds_d[ntp + i] = v.y;
-      lds_d[2 * ntp + i] = -v.y;
+      double* L = lds_d + 3 * ntp * q;
+      L[j] = v.x;
+      L[ntp + j] = v.y;
+      L[2 * ntp + j] = -v.y;
     }
     __syncthreads();
     // source coefficients, flattened (pair, order) so consecutive lanes read
@@ -507,7 +524,10 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
         if (e0 + u * TR_THREADS < tot) s_s[e0 + u * TR_THREADS] = v[u];
     }
     __syncthreads();
-    if (rt_cnt > 0) {
+    if (GS) {
+      if (rt_cnt > 0)
+        trans_contract<REV, 1>(acc, lds_d + 3 * ntp * wave, ntp, s_s + npi * Ms4 * wave, Ps, Pd, rt_lo, rt_stride);
+    } else if (rt_cnt > 0) {
       if (NTMAX <= 2) {
         if (rt_cnt == 1)
           trans_contract<REV, 1>(acc, lds_d, ntp, s_s, Ps, Pd, rt_lo, rt_stride);
@@ -524,6 +544,18 @@ __global__ void __launch_bounds__(TR_THREADS) k_trans_mfma(TreeView tv, const Tr
 #undef HFMM_CONTRACT
       }
     }
+  }
+  if (GS) {  // add the four quadrants' tiles (every wave has the same rt_cnt)
+    if (rt_cnt <= 0) return;
+    __syncthreads();  // the source tiles are no longer read
+    double* red = (double*)s_s;  // [wave][4][64]
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[(wave * 4 + i) * 64 + lane] = acc[0][i];
+    __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      acc[0][i] = (red[i * 64 + lane] + red[(4 + i) * 64 + lane]) + (red[(8 + i) * 64 + lane] + red[(12 + i) * 64 + lane]);
   }
   if (rt_cnt <= 0 || !col_ok) return;
   if (NTMAX <= 2) {
@@ -1126,6 +1158,15 @@ size_t trans_lds_bytes(int Ps, int Pd) {
   const int npi = trans_pairs_per_item(Ps, Pd);
   return sizeof(double) * (size_t)(3 * ntp) + sizeof(double2) * (size_t)npi * round4(2 * Ps + 1);
 }
+// The split gather stages four tables and four source tiles; the source area
+// also holds the four waves' partial tiles (4 x 4 x 64 doubles) at the end.
+size_t trans_lds_bytes_split(int Ps, int Pd) {
+  const int ntp = trans_table_stride(2 * (Ps + Pd) + 1);
+  const int npi = trans_pairs_per_item(Ps, Pd);
+  const size_t src = sizeof(double2) * (size_t)(4 * npi) * round4(2 * Ps + 1);
+  const size_t red = sizeof(double) * (size_t)(16 * 64);
+  return sizeof(double) * (size_t)(12 * ntp) + (src > red ? src : red);
+}
 
 // Dynamic LDS limit of the translation kernels: the CU's 160 KiB less each
 // kernel's static LDS. Called when a plan is built (before any launch or
@@ -1146,9 +1187,10 @@ static hipError_t trans_lds_limit() {
 }
 
 hipError_t init_kernel_attributes() {
-  const hipError_t es[6] = {trans_lds_limit<false, OUT_GATHER4>(), trans_lds_limit<false, OUT_CONTRIB>(),
-                            trans_lds_limit<false, OUT_EXCLUSIVE>(), trans_lds_limit<true, OUT_GATHER4>(),
-                            trans_lds_limit<true, OUT_CONTRIB>(), trans_lds_limit<true, OUT_EXCLUSIVE>()};
+  const hipError_t es[8] = {trans_lds_limit<false, OUT_GATHER4>(),          trans_lds_limit<false, OUT_CONTRIB>(),
+                            trans_lds_limit<false, OUT_EXCLUSIVE>(),        trans_lds_limit<true, OUT_GATHER4>(),
+                            trans_lds_limit<true, OUT_CONTRIB>(),           trans_lds_limit<true, OUT_EXCLUSIVE>(),
+                            trans_lds_limit_one<false, OUT_GATHER4_SPLIT, 1>(), trans_lds_limit_one<true, OUT_GATHER4_SPLIT, 1>()};
   for (hipError_t e : es)
     if (e != hipSuccess) return e;
   return hipSuccess;
@@ -1158,7 +1200,10 @@ template <bool REV, int MODE>
 static void trans_one(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, size_t lds, int ntw,
                       const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
                       const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride) {
-  if (ntw <= 2)
+  if (MODE == OUT_GATHER4_SPLIT)
+    hipLaunchKernelGGL((k_trans_mfma<REV, OUT_GATHER4_SPLIT, 1>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv,
+                       items, soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride);
+  else if (ntw <= 2)
     hipLaunchKernelGGL((k_trans_mfma<REV, MODE, 2>), dim3(nitems, tv.nrhs), dim3(TR_THREADS), lds, s, tv, items,
                        soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride);
   else
@@ -1171,11 +1216,13 @@ void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int
                   const double2* tdata, const double2* src, double2* dst, double* contrib, int64_t cstride, int rev,
                   int gather4, int ntw) {
   if (nitems <= 0) return;
-  const size_t lds = trans_lds_bytes(Ps, Pd);
+  const size_t lds = gather4 == 2 ? trans_lds_bytes_split(Ps, Pd) : trans_lds_bytes(Ps, Pd);
 #define HFMM_TRANS(R, M) \
   trans_one<R, M>(s, tv, items, nitems, lds, ntw, soff, doff, pcoff, q4, tdata, src, dst, contrib, cstride)
   if (contrib) {
     if (rev) HFMM_TRANS(true, OUT_CONTRIB); else HFMM_TRANS(false, OUT_CONTRIB);
+  } else if (gather4 == 2) {
+    if (rev) HFMM_TRANS(true, OUT_GATHER4_SPLIT); else HFMM_TRANS(false, OUT_GATHER4_SPLIT);
   } else if (gather4) {
     if (rev) HFMM_TRANS(true, OUT_GATHER4); else HFMM_TRANS(false, OUT_GATHER4);
   } else {

@@ -27,6 +27,9 @@ void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
 // item.toff in tdata or (toff < 0) at q4.v[item.table]. With gather4 (child
 // to parent) a "pair" is a parent: doff its offset, soff[4 pair + q] that of
 // its child in quadrant q (-1: none), translated with the table at q4.v[q].
+// gather4 = 1: the quadrants in turn, items of up to 4 ntw row tiles;
+// gather4 = 2: the split form, items of one row tile each, a quadrant per
+// wave (LDS: trans_lds_bytes_split).
 // ntw: the row tiles per wave of the items (their largest value).
 void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int nitems, int Ps, int Pd,
                   const int64_t* soff, const int64_t* doff, const int64_t* pcoff, const Toff4& q4,
@@ -37,6 +40,7 @@ void launch_trans(hipStream_t s, const TreeView& tv, const TransItem* items, int
 void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, int nb, const int* ptr,
                            const int64_t* beg, const double* contrib, int64_t cstride, double2* dst);
 size_t trans_lds_bytes(int Ps, int Pd);
+size_t trans_lds_bytes_split(int Ps, int Pd);
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n);
 // Free-space direct pairs. Items are sorted by H0 series class: items
 // [cls_ptr[c], cls_ptr[c + 1]) use kH0ClassTerms[c] terms, class kH0Classes
