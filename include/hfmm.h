@@ -205,7 +205,10 @@ hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 
 /*
  * Stage timing (diagnostics). While enabled, every hfmm_apply records HIP
- * events on its stream between its stages. hfmm_profile_read synchronises the
+ * events on its stream between its stages, and the stages of hfmm_apply and
+ * hfmm_apply_adjoint run one after another on that stream (the near field is
+ * not run beside the far field, as during graph capture; results agree with
+ * the overlapped form up to the order of rounding). hfmm_profile_read synchronises the
  * device, writes the accumulated milliseconds per stage and the number of
  * applies into stage_ms[0..HFMM_NSTAGES-1] and *napplies, and clears the
  * accumulators. Stages: see hfmm_stage_name.

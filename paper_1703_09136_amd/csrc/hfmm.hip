@@ -269,7 +269,6 @@ struct hfmm_plan_s {
   // M2L: runs of consecutive levels); Ps, Pd: the largest orders of the items
   struct Group {
     int first = 0, count = 0, Ps = 0, Pd = 0, ntw = 8;  // ntw: row tiles per wave of the items
-    int split = 0;  // M2M gather: a quadrant per wave, one row tile per item
   };
   // M2L: items, (source, target) pair arrays, contribution row offsets, and the
   // per-box lists of pairs for the reduction by target (forward) / by source
@@ -290,6 +289,10 @@ struct hfmm_plan_s {
   std::vector<Toff4> m2m_q4, l2l_q4;      // per parent level: the four tables' offsets
   DevBuf<TransItem> up_items, down_items;
   std::vector<Group> up_groups, down_groups;
+  // small up levels: the same parents as items of the split gather (a child
+  // quadrant per wave, one row tile per item), used when the stages run in
+  // sequence; count 0 where the standard form is kept
+  std::vector<Group> up_split_groups;
   DevBuf<double> contrib;
   DevBuf<TableRef> tabs;
   DevBuf<double2> tdata;
@@ -928,6 +931,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<TransItem> up_items, down_items;
   pl->up_groups.assign(pl->nlev, {});
   pl->down_groups.assign(pl->nlev, {});
+  pl->up_split_groups.assign(pl->nlev, {});
   for (int l = pl->top; l + 1 < pl->nlev; ++l) {
     auto& gu = pl->up_groups[l];
     auto& gd = pl->down_groups[l];
@@ -947,16 +951,20 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     const int ntw_down = choose_ntw(batches, pl->P[l], pl->P[l + 1]);
     gu.ntw = ntw_up;
     gd.ntw = ntw_down;
-    // The gather with a quadrant per wave where its blocks (one per parent
-    // batch and row tile) all fit on the GPU at once: such small launches are
-    // bound by each block's chain of quadrants, which the split form runs
-    // side by side. Its LDS (four tables and source tiles) must fit a CU.
+    // The split gather where its blocks (one per parent batch and row tile)
+    // all fit on the GPU at once: such small launches are bound by each
+    // block's chain of quadrants, which the split form runs side by side. Its
+    // LDS (four tables and source tiles) must fit a CU. Beside the near field
+    // its large blocks wait for LDS, so the overlapped apply keeps the
+    // standard form.
+    const int nrt_up = (2 * (2 * pl->P[l] + 1) + 15) / 16;
+    bool split = false;
     {
       const size_t lds_split = trans_lds_bytes_split(pl->P[l + 1], pl->P[l]);
-      const int nrt_up = (2 * (2 * pl->P[l] + 1) + 15) / 16;
       const int64_t per_cu = lds_split <= kSplitLdsMax ? (int64_t)(kCuLds / lds_split) : 0;
-      gu.split = per_cu > 0 && pbatches * nrt_up <= kNumCu * per_cu;
+      split = per_cu > 0 && pbatches * nrt_up <= kNumCu * per_cu;
     }
+    std::vector<std::pair<int, int>> batch_pairs;  // (pbeg, count) per parent batch
     for (size_t c0 = 0; c0 < parents.size(); c0 += npi) {
       const int cnt = (int)std::min<size_t>(npi, parents.size() - c0);
       const int pbeg = (int)up_doff_h.size();
@@ -965,13 +973,19 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         up_doff_h.push_back(coff[parents[c0 + c]]);
         for (int q = 0; q < 4; ++q) up_soff4_h.push_back(par.child[q] >= 0 ? coff[par.child[q]] : -1);
       }
-      if (gu.split) {
-        const int nrt_up = (2 * (2 * pl->P[l] + 1) + 15) / 16;
+      add_items(up_items, 0, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
+      batch_pairs.emplace_back(pbeg, cnt);
+    }
+    gu.count = (int)up_items.size() - gu.first;
+    if (split) {
+      auto& gs = pl->up_split_groups[l];
+      gs = gu;
+      gs.first = (int)up_items.size();
+      gs.ntw = 1;
+      for (const auto& bp : batch_pairs)
         for (int rt = 0; rt < nrt_up; ++rt)
-          up_items.push_back(TransItem{0, pbeg, cnt, 0, rt, pl->P[l + 1], pl->P[l], 1, -1});
-      } else {
-        add_items(up_items, 0, pbeg, cnt, 0, pl->P[l + 1], pl->P[l], ntw_up, -1);
-      }
+          up_items.push_back(TransItem{0, bp.first, bp.second, 0, rt, pl->P[l + 1], pl->P[l], 1, -1});
+      gs.count = (int)up_items.size() - gs.first;
     }
     for (int q = 0; q < 4; ++q) {
       const std::vector<int>& kids_q = kids[q];
@@ -985,7 +999,6 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         add_items(down_items, q, pbeg, cnt, 0, pl->P[l], pl->P[l + 1], ntw_down, -1);
       }
     }
-    gu.count = (int)up_items.size() - gu.first;
     gd.count = (int)down_items.size() - gd.first;
   }
 
@@ -1437,10 +1450,12 @@ void launch_l2p_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
   launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, beta, us, conj_w, pref, accumulate);
 }
 
-// One level of child -> parent (up) or parent -> child (down) translations.
+// One level of child -> parent (up) or parent -> child (down) translations;
+// in_sequence: nothing runs beside this launch (the split gather may be used).
 void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, int l, bool m2m_tables,
-                  const double2* src, double2* dst, int rev) {
-  const hfmm_plan_s::Group& g = up ? pl->up_groups[l] : pl->down_groups[l];
+                  const double2* src, double2* dst, int rev, bool in_sequence) {
+  const bool split = up && in_sequence && pl->up_split_groups[l].count > 0;
+  const hfmm_plan_s::Group& g = split ? pl->up_split_groups[l] : up ? pl->up_groups[l] : pl->down_groups[l];
   if (!g.count) return;
   const Toff4& q4 = m2m_tables ? pl->m2m_q4[l] : pl->l2l_q4[l];
   const TransItem* items = (up ? pl->up_items.p : pl->down_items.p) + g.first;
@@ -1449,7 +1464,7 @@ void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, in
   // a child has one parent, and up items gather a parent's children: no two
   // pairs of a launch write the same box
   launch_trans(s, tv, items, g.count, g.Ps, g.Pd, soff, doff, nullptr, q4, pl->tdata.p, src, dst, nullptr, 0, rev,
-               up ? (g.split ? 2 : 1) : 0, g.ntw);
+               up ? (split ? 2 : 1) : 0, g.ntw);
 }
 
 // All M2L items (forward: source -> target; transpose: target -> source) into
@@ -1512,11 +1527,13 @@ hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const doubl
     const hipError_t e = fork_near(pl, tv, s, qs, us);
     if (e != hipSuccess) return e;
   }
-  for (int l = pl->nlev - 2; l >= pl->top; --l) launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0);
+  for (int l = pl->nlev - 2; l >= pl->top; --l)
+    launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0, !overlap);
   mark();
   launch_m2l_all(pl, tv, s, pl->alpha.p, pl->beta.p, 0);
   mark();
-  for (int l = pl->top; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0);
+  for (int l = pl->top; l + 1 < pl->nlev; ++l)
+    launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0, !overlap);
   mark();
   launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25), overlap ? 2 : 0);
   mark();
@@ -1529,7 +1546,8 @@ hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const doubl
 hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* vs, double2* ws) {
   TreeView tv = pl->view(nrhs);
   // the direct parts are symmetric: the same near field, beside the far field
-  const bool overlap = !capturing(s);
+  // (in sequence under stage timing or graph capture)
+  const bool overlap = !pl->prof_on && !capturing(s);
   // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i} at the leaves, then
   // the parents' sums (stored, as in the forward pass)
   launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
@@ -1538,11 +1556,13 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
     if (e != hipSuccess) return e;
   }
   // L2L^T, finest parents first: beta'(parent) = sum over its children of T^T beta'(child)
-  for (int l = pl->nlev - 2; l >= pl->top; --l) launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1);
+  for (int l = pl->nlev - 2; l >= pl->top; --l)
+    launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1, !overlap);
   // M2L^T, reduced by source box
   launch_m2l_all(pl, tv, s, pl->beta.p, pl->alpha.p, 1);
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
-  for (int l = pl->top; l + 1 < pl->nlev; ++l) launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1);
+  for (int l = pl->top; l + 1 < pl->nlev; ++l)
+    launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1, !overlap);
   // P2M^T: w_j = sum_p alpha'_p J_p e^{-i p theta_j}
   launch_l2p_all(pl, tv, s, pl->alpha.p, ws, 1, cmk(1.0, 0.0), overlap ? 2 : 0);
   if (overlap) return join_near(pl, s);

@@ -116,3 +116,27 @@ def test_adjoint_is_the_transpose(gpu_lib):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
     ref = np.conj(ref_apply(w, np.conj(v)))   # A symmetric: A^H v = conj(A conj v)
     assert rel(wv, ref) < 1e-10
+
+
+def test_stages_in_sequence_match_overlapped(gpu_lib):
+    """Under stage timing the stages run one after another, the form graph
+    capture also uses (small M2M levels then gather a child quadrant per wave,
+    and the adjoint's small L2L^T levels likewise); forward and adjoint agree
+    with the overlapped applies up to the order of rounding."""
+    import torch
+    w = workloads.three_layer_ellipses(n=20000, seed=17, nrhs=2)
+    plan, u = run(gpu_lib, w, 1e-8, leaf_size=64)
+    q = torch.tensor(w.q, dtype=torch.complex128, device="cuda:0")
+    v = torch.tensor(workloads.complex_normal(workloads.rng_for(1703, 9136, 18), (2, w.n)),
+                     dtype=torch.complex128, device="cuda:0")
+    wv = plan.apply_adjoint(v).cpu().numpy()
+    plan.profile(True)
+    us = plan.apply(q).cpu().numpy()
+    ws = plan.apply_adjoint(v).cpu().numpy()
+    st, napplies = plan.profile_read()
+    plan.profile(False)
+    print("levels", plan.info()["levels"], "orders", plan.info()["order"], "stages ms", st)
+    assert napplies == 1 and st["m2m"] > 0
+    assert rel(us, u) < 1e-13
+    assert rel(ws, wv) < 1e-13
+    plan.close()
