@@ -261,6 +261,7 @@ struct hfmm_plan_s {
   DevBuf<int2> prange;
   DevBuf<int64_t> coff;
   DevBuf<int> leaves;  // leaf boxes, ascending level
+  DevBuf<int> pt_box;  // leaf box of each sorted point
   int precision = HFMM_FP64;  // HFMM_FP64 or HFMM_FP32 (near field in single precision)
   int nleaves = 0;
   std::vector<int> leaf_lev;  // leaves of level l: [leaf_lev[l], leaf_lev[l + 1])
@@ -343,7 +344,7 @@ struct hfmm_plan_s {
   }
   void release_all() {
     pts.release(); ctr.release(); perm.release(); level.release(); parent.release(); quad.release();
-    child.release(); prange.release(); coff.release(); leaves.release();
+    child.release(); prange.release(); coff.release(); leaves.release(); pt_box.release();
     m2l_items.release(); m2l_soff.release(); m2l_toff.release(); m2l_pcoff.release(); m2l_pcoffT.release();
     red_boxes.release(); red_ptr.release(); red_beg.release(); redT_ptr.release(); redT_beg.release(); cp_child.release();
     cp_parent.release(); up_doff.release(); up_soff4.release(); up_items.release(); down_items.release(); contrib.release();
@@ -1013,6 +1014,10 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       pl->leaf_lev[B[i].level + 1] = (int)leaves.size();
     }
   for (int l = 1; l <= pl->nlev; ++l) pl->leaf_lev[l] = std::max(pl->leaf_lev[l], pl->leaf_lev[l - 1]);
+  // the leaves' point ranges partition the sorted points
+  std::vector<int> pt_box_h((size_t)n, 0);
+  for (int x : leaves)
+    for (int j = B[x].begin; j < B[x].end; ++j) pt_box_h[j] = x;
   pl->leaf_pmax = 0;
   for (int l = 0; l < pl->nlev; ++l)
     if (pl->leaf_lev[l + 1] > pl->leaf_lev[l]) pl->leaf_pmax = std::max(pl->leaf_pmax, pl->P[l]);
@@ -1328,7 +1333,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
 #define UP(buf, vec)                                  \
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
   UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
-  UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves)
+  UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves) UP(pt_box, pt_box_h)
   UP(m2l_items, m2l_items) UP(m2l_soff, m2l_soff) UP(m2l_toff, m2l_toff) UP(m2l_pcoff, m2l_pcoff) UP(m2l_pcoffT, m2l_pcoffT)
   UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_beg, red_beg) UP(redT_ptr, redT_ptr)
   UP(redT_beg, redT_beg) UP(cp_child, cp_child_off) UP(cp_parent, cp_parent_off) UP(up_doff, up_doff_h) UP(up_soff4, up_soff4_h) UP(up_items, up_items)
@@ -1447,7 +1452,7 @@ void launch_p2m_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
 // (accumulate = 2) while the near field adds into it.
 void launch_l2p_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* beta, double2* us, int conj_w,
                     double2 pref, int accumulate) {
-  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, beta, us, conj_w, pref, accumulate);
+  launch_l2p(s, tv, pl->leaves.p, pl->nleaves, pl->pt_box.p, pl->leaf_pmax, beta, us, conj_w, pref, accumulate);
 }
 
 // One level of child -> parent (up) or parent -> child (down) translations;

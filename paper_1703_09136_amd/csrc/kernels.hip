@@ -279,6 +279,87 @@ __global__ void __launch_bounds__(WAVE) k_l2p(TreeView tv, const int* __restrict
 
 size_t l2p_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(rb * 2 * (Pmax + 1)); }
 
+// The same sum for one right-hand side with a lane per point of the sorted
+// order: a wave takes 64 consecutive points, which lie in a few leaves (runs
+// of equal box[j]; leaves average about 35 points, so a wave per leaf leaves
+// about half its lanes idle). The runs' s_n and d_n are staged in LDS,
+// L2P_RUNS runs at a time, and each lane walks the recurrence for its own
+// argument and order.
+constexpr int L2P_RUNS = 4;
+__global__ void __launch_bounds__(WAVE) k_l2p_flat(TreeView tv, const int* __restrict__ pt_box, int Pmax,
+                                                   const double2* __restrict__ beta, double2* __restrict__ us,
+                                                   int conj_w, double2 pref, int accumulate) {
+  extern __shared__ double2 lds_c[];  // [L2P_RUNS][Pmax + 1][s, d]
+  far_field_priority();
+  const int lane = threadIdx.x;
+  const int j = blockIdx.x * WAVE + lane;
+  const bool valid = j < tv.n;
+  const int b = valid ? pt_box[j] : -1;
+  const int b_prev = __shfl_up(b, 1, WAVE);
+  const uint64_t runs = __ballot(valid && (lane == 0 || b != b_prev));
+  const int nruns = __popcll(runs);
+  // this lane's run: the run heads at or below it, less one
+  const int my_run = valid ? __popcll(runs & (~0ull >> (63 - lane))) - 1 : -1;
+  const int lev = valid ? tv.level[b] : 0;
+  const bool has_local = valid && lev >= 2;
+  const int P = has_local ? tv.P[lev] : 0;
+  double2 acc = cmk(0.0, 0.0);
+  uint64_t heads = runs;
+  for (int g0 = 0; g0 < nruns; g0 += L2P_RUNS) {
+    // stage the coefficients of runs g0 .. g0 + L2P_RUNS - 1 (the wave's
+    // lanes together, one run after another)
+    for (int r = 0; r < L2P_RUNS && g0 + r < nruns; ++r) {
+      const int head = __ffsll((long long)heads) - 1;
+      heads &= heads - 1;
+      const int br = __shfl(b, head, WAVE);
+      const int lr = tv.level[br];
+      if (lr < 2) continue;
+      const int Pr = tv.P[lr];
+      const double2* bt = beta + tv.coff[br] + Pr;
+      for (int n = lane; n <= Pr; n += WAVE) {
+        const double2 an = bt[n];
+        double2 bn = n > 0 ? bt[-n] : cmk(0.0, 0.0);
+        if (n & 1) bn = cscale(bn, -1.0);
+        lds_c[2 * (r * (Pmax + 1) + n)] = cadd(an, bn);
+        lds_c[2 * (r * (Pmax + 1) + n) + 1] = csub(an, bn);
+      }
+    }
+    __syncthreads();
+    if (has_local && my_run >= g0 && my_run < g0 + L2P_RUNS) {
+      const double2* sd = lds_c + 2 * (my_run - g0) * (Pmax + 1);
+      const double2 p = tv.pts[j], c = tv.ctr[b];
+      const double dx = p.x - c.x, dy = p.y - c.y;
+      const double rho = hypot(dx, dy);
+      const double x = fmax(tv.k * rho, kTinyX), s1 = tv.k * rho < kTinyX ? tv.k * rho / kTinyX : 1.0;
+      const double2 w = rho > 0 ? cmk(dx / rho, (conj_w ? -dy : dy) / rho) : cmk(1.0, 0.0);
+      double2 wn = cpowi(w, P);
+      const int nstart = miller_start_expansion(tv.k * rho, P);
+      double inv_s;
+      int nres;
+      miller_norm(x, nstart, inv_s, nres);
+      MillerWalk mw(x, nstart, inv_s, nres);
+      while (mw.n > P) mw.step();
+      for (int n = P; n >= 0; --n) {
+        const double2 jw = cscale(wn, n == 1 ? s1 * mw.value() : mw.value());
+        const double2 sn = sd[2 * n], dn = sd[2 * n + 1];
+        acc.x = fma(sn.x, jw.x, fma(-dn.y, jw.y, acc.x));
+        acc.y = fma(dn.x, jw.y, fma(sn.y, jw.x, acc.y));
+        wn = cmul(wn, cconj(w));
+        if (n > 0) mw.step();
+      }
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
+  const double2 v = cmul(pref, acc);
+  if (accumulate == 2) {
+    unsafeAtomicAdd(&us[j].x, v.x);
+    unsafeAtomicAdd(&us[j].y, v.y);
+  } else {
+    us[j] = accumulate ? cadd(us[j], v) : v;
+  }
+}
+
 // ------------------------------------------------------------------ batched translations on MFMA
 // For one table t (t[n], n = m - p, m in [-Ps, Ps] source orders, p in
 // [-Pd, Pd] target orders) and a batch of (source, target) box pairs using it:
@@ -1141,10 +1222,14 @@ void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, in
     hipLaunchKernelGGL(k_p2m<P2M_RB>, dim3(nl, (tv.nrhs + P2M_RB - 1) / P2M_RB), dim3(WAVE),
                        p2m_lds_bytes(Pmax, P2M_RB), s, tv, leaves, nl, qs, alpha, conj_w, pref);
 }
-void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
-                double2* us, int conj_w, double2 pref, int accumulate) {
+void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* pt_box, int Pmax,
+                const double2* beta, double2* us, int conj_w, double2 pref, int accumulate) {
   if (nl <= 0) return;
-  if (tv.nrhs == 1)
+  if (tv.nrhs == 1 && pt_box)
+    hipLaunchKernelGGL(k_l2p_flat, dim3((tv.n + WAVE - 1) / WAVE), dim3(WAVE),
+                       sizeof(double2) * (size_t)(L2P_RUNS * 2 * (Pmax + 1)), s, tv, pt_box, Pmax, beta, us, conj_w,
+                       pref, accumulate);
+  else if (tv.nrhs == 1)
     hipLaunchKernelGGL(k_l2p<1>, dim3(nl, 1), dim3(WAVE), l2p_lds_bytes(Pmax, 1), s, tv, leaves, nl, beta, us,
                        conj_w, pref, accumulate);
   else

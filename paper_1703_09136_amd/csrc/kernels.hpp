@@ -14,10 +14,12 @@ hipError_t init_kernel_attributes();
 // P2M and L2P over a list of leaves; each block reads its leaf's order, Pmax
 // bounds the orders of the list (sizes the LDS). L2P stores into us
 // (accumulate = 0), adds with a read-modify-write (1) or adds atomically (2).
+// With pt_box (the leaf box of every sorted point, all points in leaves) and
+// one right-hand side, L2P runs a lane per point over the sorted order.
 void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* qs,
                 double2* alpha, int conj_w, double2 pref);
-void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* beta,
-                double2* us, int conj_w, double2 pref, int accumulate);
+void launch_l2p(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* pt_box, int Pmax,
+                const double2* beta, double2* us, int conj_w, double2 pref, int accumulate);
 // Batched translation contraction (M2L, M2M, L2L and transposes) for items
 // sharing (Ps, Pd). With contrib != NULL each pair writes its own contribution
 // row at pcoff[pair] (plane stride cstride per right-hand side); otherwise the
