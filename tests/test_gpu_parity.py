@@ -140,3 +140,25 @@ def test_stages_in_sequence_match_overlapped(gpu_lib):
     assert rel(us, u) < 1e-13
     assert rel(ws, wv) < 1e-13
     plan.close()
+
+
+def test_tiny_leaves_many_per_wave(gpu_lib):
+    """Leaves of a few points: the per-point L2P then finds more than four
+    leaves in most 64-point waves and stages them four at a time; forward
+    against the oracle, adjoint by the dot test."""
+    import torch
+    w = workloads.two_layer_uniform(n=1024, seed=19, nrhs=1)
+    plan, u = run(gpu_lib, w, 1e-10, leaf_size=4)
+    inf = plan.info()
+    print("tiny leaves:", inf)
+    assert inf["leaves"] > w.n / 8 and inf["m2l_pairs"] > 0
+    e = rel(u, ref_apply(w))
+    print("tiny-leaf E =", e)
+    assert e < 1e-10
+    rng = workloads.rng_for(1703, 9136, 20)
+    v = workloads.complex_normal(rng, (w.n,))
+    wv = plan.apply_adjoint(torch.tensor(v, dtype=torch.complex128, device="cuda:0")).cpu().numpy()
+    lhs = np.vdot(v, u.reshape(-1))
+    rhs = np.vdot(wv, w.q.reshape(-1))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    plan.close()
