@@ -130,7 +130,9 @@ def extras(hf, torch, np, w, plan, pts, q, u, args, golden):
 def batched(hf, torch, args):
     """32 three-layer geometries, N_g = round(2^U(12,18)), 256 right-hand sides
     each (strengths drawn on the device from a seeded generator), applied as one
-    batch replayed from a HIP graph."""
+    batch: eagerly (each plan's near field beside its far field, the plans on
+    four streams) and replayed from a HIP graph (the stages of a plan in
+    sequence). `value` is the faster of the two."""
     import workloads
     dev = torch.device("cuda:0")
     geos = workloads.batched_geometries(nrhs=1)
@@ -146,26 +148,31 @@ def batched(hf, torch, args):
     qs = [torch.randn((nrhs, n), dtype=torch.complex128, device=dev, generator=gen) for n in ns]
     us = [torch.empty_like(t) for t in qs]
     s = torch.cuda.Stream()
-    b.graph(True)
-    with torch.cuda.stream(s):
-        b.apply(qs, outs=us, stream=s)
-    s.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    reps = 2
-    with torch.cuda.stream(s):
-        e0.record(s)
-        for _ in range(reps):
-            b.apply(qs, outs=us, stream=s)
-        e1.record(s)
-    s.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    ms = {}
+    for mode in ("eager", "graph"):
+        b.graph(mode == "graph")
+        with torch.cuda.stream(s):
+            b.apply(qs, outs=us, stream=s)  # warm-up (graph: capture and first replay)
+        s.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 2
+        with torch.cuda.stream(s):
+            e0.record(s)
+            for _ in range(reps):
+                b.apply(qs, outs=us, stream=s)
+            e1.record(s)
+        s.synchronize()
+        ms[mode] = e0.elapsed_time(e1) / reps
+        print("batched %s: %.1f ms per batch" % (mode, ms[mode]), file=sys.stderr, flush=True)
     b.close()
+    best = min(ms, key=ms.get)
     return {"workload": "32 three-layer geometries of 2^U(12,18) points (%d in all), %d right-hand sides each"
                         % (sum(ns), nrhs),
-            "value": len(ns) * nrhs / ms * 1e3, "unit": "matvecs/s (geometry x right-hand side)",
-            "ms_per_batch": ms, "point_rhs_per_s": sum(ns) * nrhs / ms * 1e3, "plan_s": plan_s,
-            "graph": True}
+            "value": len(ns) * nrhs / ms[best] * 1e3, "unit": "matvecs/s (geometry x right-hand side)",
+            "ms_per_batch": ms[best], "point_rhs_per_s": sum(ns) * nrhs / ms[best] * 1e3, "plan_s": plan_s,
+            "mode": best, "ms_per_batch_eager": ms["eager"], "ms_per_batch_graph": ms["graph"],
+            "graph_value": len(ns) * nrhs / ms["graph"] * 1e3}
 
 
 def main():
