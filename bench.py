@@ -29,7 +29,8 @@ METRIC = "H-FMM matvecs/sec at N=1e6, 3 layers, rel err 1e-8 (FP64) vs mixed; ad
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_p2p_three_layer_n1e6.txt")
-KERNEL_SOURCES = ["p2p.hip", "special.hpp", "common.hpp", "h0_cheb.hpp", "log_table.hpp"]
+# the near-field kernels and the plan code that sizes their work items
+KERNEL_SOURCES = ["p2p.hip", "special.hpp", "common.hpp", "h0_cheb.hpp", "log_table.hpp", "hfmm.hip"]
 
 
 def kernel_source_hash():

@@ -141,7 +141,10 @@ struct Rule {
 };
 constexpr size_t kMaxPanels = 100000;
 constexpr int kItemSources = 2048;   // at most this many sources per direct work item
-constexpr int kItemPairs = 16384;    // and about this many pairs
+// and about this many pairs, by series class: the longer series have fewer
+// items per launch, so their items are smaller, which spreads each class
+// launch over the GPU instead of ending it with a few long waves
+constexpr int kItemPairs[kH0Classes + 1] = {8192, 8192, 8192, 4096, 2048, 2048};
 // per-translation truncation bound as a fraction of the requested tolerance
 #ifndef HFMM_ORDER_SAFETY
 #define HFMM_ORDER_SAFETY 0.5
@@ -1151,12 +1154,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<Item> items;
   auto add_ranges = [&](int li, const std::vector<int2>& rs, int sym) {
     const size_t first = items.size();
-    // about kItemPairs pairs per item, so that no single wave dominates a launch
+    // about kItemPairs[c] pairs per item, so that no single wave dominates a launch
     const int nt_leaf = B[leaves[li]].end - B[leaves[li]].begin;
-    const int cap = std::max(64, std::min(kItemSources, (kItemPairs / std::max(nt_leaf, 1)) & ~63));
     std::vector<int2> by_cls[kH0Classes + 1];
     for (const int2& rg : rs) by_cls[series_class(leaf_bb[li], range_bb(rg))].push_back(rg);
     for (int c = 0; c <= kH0Classes; ++c) {
+      const int cap = std::max(64, std::min(kItemSources, (kItemPairs[c] / std::max(nt_leaf, 1)) & ~63));
       Item cur{leaves[li], sym, c, 0, {}};
       int cur_n = 0;
       for (const int2& rg : by_cls[c]) {
