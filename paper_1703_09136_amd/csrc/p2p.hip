@@ -35,6 +35,20 @@ __device__ __noinline__ double2 hankel0_large_call(double x) { return hankel0_la
 // FP64 and then rounded).
 constexpr int P2P_CS = 128;  // sources per staged chunk
 
+// Orders a wave's LDS stores before its lanes' later loads. A block runs WPB
+// items, one per wave, each on its own LDS: with one wave a block barrier,
+// with several a wavefront-scope fence (a wave's LDS accesses complete in
+// order) and a barrier to the compiler's reordering.
+template <int WPB>
+__device__ inline void p2p_wave_sync() {
+  if (WPB == 1) {
+    __syncthreads();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // In a cross item the reverse sums q_i H_ij go to s_acc[j], kept in FP64 for
 // both precisions and added with the no-return FP64 LDS atomics, which do not
 // wait for the LDS (FP32 LDS atomics and plain read-add-writes measured
@@ -96,12 +110,12 @@ __device__ inline void p2p_chunk(int sub, int g, int cnt, int jself, int rot, do
 
 // One work item: the target leaf b against source ranges [e0, e1) of rng.
 // Sums run in T; each item adds its (i/4) sums into the FP64 output.
-template <typename T, int RB, int M, bool LARGE, bool SYM>
+template <typename T, int RB, int M, bool LARGE, bool SYM, int WPB>
 __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const int2* __restrict__ rng,
                                 const double2* __restrict__ qs, double2* __restrict__ us, int r0, double2* s_x,
                                 cplx_t<T> (*s_q)[P2P_CS], double2 (*s_acc)[P2P_CS], const double2* s_ln) {
   using C = cplx_t<T>;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & (WAVE - 1);
   const int2 pr = tv.prange[b];
   const T qk2 = (T)(0.25 * tv.k * tv.k);
   if (SYM) {
@@ -135,20 +149,20 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
       const int2 sr = rng[e];
       for (int j0 = sr.x; j0 < sr.y; j0 += P2P_CS) {
         const int cnt = min(P2P_CS, sr.y - j0);
-        __syncthreads();
+        p2p_wave_sync<WPB>();
         for (int l = lane; l < cnt; l += WAVE) {
           s_x[l] = tv.pts[j0 + l];
 #pragma unroll
           for (int rr = 0; rr < RB; ++rr)
             s_q[rr][l] = (r0 + rr < tv.nrhs) ? to_cplx<T>(qs[(int64_t)(r0 + rr) * tv.n + j0 + l]) : cmk((T)0, (T)0);
         }
-        __syncthreads();
+        p2p_wave_sync<WPB>();
         if (valid)
           p2p_chunk<T, RB, M, LARGE, SYM>(sub, g, cnt, SYM ? -1 : i - j0, ti, xi, qi, qk2, s_x, s_q, acc, s_acc,
                                           s_ln);
         if (SYM) {
           // the chunk's sums of q_i H_ij go to u_j
-          __syncthreads();
+          p2p_wave_sync<WPB>();
           for (int l = lane; l < cnt; l += WAVE) {
 #pragma unroll
             for (int rr = 0; rr < RB; ++rr) {
@@ -183,29 +197,41 @@ __device__ inline void p2p_item(const TreeView& tv, int b, int e0, int e1, const
 
 // One launch per series class (the host bounds every pair distance of an item
 // and sorts the items by class), so each kernel holds only its own
-// coefficients in scalar registers; sym[li] marks cross items.
-template <typename T, int RB, int CLS>
-__global__ void __launch_bounds__(WAVE) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
+// coefficients in scalar registers; sym[li] marks cross items. A block runs
+// WPB consecutive items, one per wave. Beside the far-field launches (blocks
+// of four waves) the one-right-hand-side launch uses four-wave blocks: a
+// finished near-field block then frees room that a far-field block can take,
+// where one-wave blocks leave gaps too small for it that the next near-field
+// block fills.
+template <typename T, int RB, int CLS, int WPB>
+__global__ void __launch_bounds__(WAVE * WPB) k_p2p(TreeView tv, const int* __restrict__ leaves, int nleaves,
                                               const int* __restrict__ ptr, const int2* __restrict__ rng,
                                               const int* __restrict__ sym, const double2* __restrict__ qs,
                                               double2* __restrict__ us) {
   using C = cplx_t<T>;
   const int r0 = blockIdx.y * RB;  // first right-hand side of this block
-  __shared__ double2 s_x[P2P_CS];
-  __shared__ C s_q[RB][P2P_CS];
-  __shared__ double2 s_acc[RB][P2P_CS];
+  __shared__ double2 s_xw[WPB][P2P_CS];
+  __shared__ C s_qw[WPB][RB][P2P_CS];
+  __shared__ double2 s_accw[WPB][RB][P2P_CS];
   __shared__ double2 s_ln[1 << kLogTabBits];  // logarithm bins (FP64)
-  const int li = blockIdx.x;
+  if (sizeof(T) == 8)
+    for (int l = threadIdx.x; l < (1 << kLogTabBits); l += WAVE * WPB) s_ln[l] = cmk(kLogTab[l][0], kLogTab[l][1]);
+  __syncthreads();  // the table before any use; every wave of the block is here
+  const int wv = threadIdx.x / WAVE;
+  const int li = blockIdx.x * WPB + wv;
   if (li >= nleaves) return;
-  if (sizeof(T) == 8)  // the first chunk's barrier orders these stores before any use
-    for (int l = threadIdx.x; l < (1 << kLogTabBits); l += WAVE) s_ln[l] = cmk(kLogTab[l][0], kLogTab[l][1]);
+  double2* s_x = s_xw[wv];
+  C(*s_q)[P2P_CS] = s_qw[wv];
+  double2(*s_acc)[P2P_CS] = s_accw[wv];
   constexpr int CL = CLS < kH0Classes ? CLS : kH0Classes - 1;
   constexpr int M = sizeof(T) == 8 ? kH0ClassTerms[CL] : kH0ClassTermsF32[CL];
   constexpr bool LARGE = CLS >= kH0Classes;
   if (sym[li])
-    p2p_item<T, RB, M, LARGE, true>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc, s_ln);
+    p2p_item<T, RB, M, LARGE, true, WPB>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc,
+                                         s_ln);
   else
-    p2p_item<T, RB, M, LARGE, false>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc, s_ln);
+    p2p_item<T, RB, M, LARGE, false, WPB>(tv, leaves[li], ptr[li], ptr[li + 1], rng, qs, us, r0, s_x, s_q, s_acc,
+                                          s_ln);
 }
 
 // ------------------------------------------------------------------ launcher
@@ -214,10 +240,11 @@ static void p2p_class(hipStream_t s, const TreeView& tv, const int* items, int n
                       const int* sym, const double2* qs, double2* us) {
   if (nl <= 0) return;
   if (tv.nrhs == 1) {
-    hipLaunchKernelGGL((k_p2p<T, 1, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, qs, us);
+    hipLaunchKernelGGL((k_p2p<T, 1, CLS, 4>), dim3((nl + 3) / 4), dim3(4 * WAVE), 0, s, tv, items, nl, ptr, rng, sym,
+                       qs, us);
     return;
   }
-  hipLaunchKernelGGL((k_p2p<T, 4, CLS>), dim3(nl, (tv.nrhs + 3) / 4), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym,
+  hipLaunchKernelGGL((k_p2p<T, 4, CLS, 1>), dim3(nl, (tv.nrhs + 3) / 4), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym,
                      qs, us);
 }
 
