@@ -18,7 +18,7 @@ What it computes (Section 2 of the paper):
   (Section 2.3, Eq. multitop), sigma_1 being fixed by the interface system of
   Section 2.3.
 
-Readings taken where the paper is silent (each listed in the design doc):
+Readings taken where the paper is silent:
 
 * two layers with a transmission interface are the three-layer system with
   k3 = k2 (the result does not depend on d);
