@@ -1501,9 +1501,9 @@ void launch_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double
 
 // Fork: us is cleared and the near field starts on the plan's side stream
 // while the far-field chain runs on s; every writer of us then adds
-// atomically. join() makes s wait for the side stream. The fork comes after
-// P2M: P2M is on the far field's critical path and alone fills the GPU, and
-// measured faster that way than with the near field beside it.
+// atomically. join() makes s wait for the side stream. The fork comes first,
+// before P2M: P2M's one-wave blocks fit beside the near field's four-wave
+// blocks, which measured faster than P2M alone followed by the fork.
 hipError_t fork_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* qs, double2* us) {
   launch_fill_zero(s, us, (int64_t)tv.nrhs * pl->n);
   hipError_t e = hipEventRecord(pl->ev_fork, s);
@@ -1527,14 +1527,14 @@ bool capturing(hipStream_t s) {
 hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
   TreeView tv = pl->view(nrhs);
   const bool overlap = mark.ev == nullptr && !capturing(s);
-  // P2M stores the leaves' multipoles, M2M each parent's (every box of levels
-  // >= 2 is one or the other)
-  launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
-  mark();
   if (overlap) {
     const hipError_t e = fork_near(pl, tv, s, qs, us);
     if (e != hipSuccess) return e;
   }
+  // P2M stores the leaves' multipoles, M2M each parent's (every box of levels
+  // >= 2 is one or the other)
+  launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
+  mark();
   for (int l = pl->nlev - 2; l >= pl->top; --l)
     launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0, !overlap);
   mark();
@@ -1558,11 +1558,11 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
   const bool overlap = !pl->prof_on && !capturing(s);
   // L2P^T: beta'_p = (i/4) sum_i v_i J_p e^{i p theta_i} at the leaves, then
   // the parents' sums (stored, as in the forward pass)
-  launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
   if (overlap) {
     const hipError_t e = fork_near(pl, tv, s, vs, ws);
     if (e != hipSuccess) return e;
   }
+  launch_p2m_all(pl, tv, s, vs, pl->beta.p, 1, cmk(0.0, 0.25));
   // L2L^T, finest parents first: beta'(parent) = sum over its children of T^T beta'(child)
   for (int l = pl->nlev - 2; l >= pl->top; --l)
     launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1, !overlap);
