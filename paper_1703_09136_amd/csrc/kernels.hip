@@ -811,12 +811,18 @@ size_t l2p_grad_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(
 // stands for both orders, Re(g sum_r vs_rj q_ri) (x_i - x_j) to i.
 constexpr int GRAD_CS = 64;
 
+// ONE: a single right-hand side, whose v_i and q_i stay in registers and
+// whose sources' q_j and v_j are staged in LDS with their positions (the
+// general form reads them from memory for every pair and right-hand side).
+template <bool ONE>
 __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __restrict__ leaves, int nitems,
                                                    const int* __restrict__ ptr, const int2* __restrict__ rng,
                                                    const int* __restrict__ sym, const double2* __restrict__ vs,
                                                    const double2* __restrict__ qs, double2* __restrict__ gs) {
   __shared__ double2 s_x[GRAD_CS];
   __shared__ double2 s_g[GRAD_CS];
+  __shared__ double2 s_qj[ONE ? GRAD_CS : 1];
+  __shared__ double2 s_vj[ONE ? GRAD_CS : 1];
   const int li = blockIdx.x;
   if (li >= nitems) return;
   const int b = leaves[li];
@@ -828,6 +834,7 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
     const int i = c0 + lane;
     const bool valid = i < pr.y;
     const double2 xi = valid ? tv.pts[i] : cmk(0, 0);
+    const double2 vi = (ONE && valid) ? vs[i] : cmk(0, 0), qi = (ONE && valid) ? qs[i] : cmk(0, 0);
     double gix = 0.0, giy = 0.0;
     for (int e = ptr[li]; e < ptr[li + 1]; ++e) {
       const int2 sr = rng[e];
@@ -837,6 +844,10 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
         if (lane < cnt) {
           s_x[lane] = tv.pts[j0 + lane];
           s_g[lane] = cmk(0.0, 0.0);
+          if (ONE) {
+            s_qj[lane] = qs[j0 + lane];
+            s_vj[lane] = both ? vs[j0 + lane] : cmk(0.0, 0.0);
+          }
         }
         __syncthreads();
         if (valid) {
@@ -853,10 +864,15 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
             const double2 h1 = hankel1(tv.k * r);
             const double2 g = cmk(0.25 * tv.k * h1.y / r, -0.25 * tv.k * h1.x / r);  // -(i/4) k H1 / r
             double2 cij = cmk(0.0, 0.0), cji = cmk(0.0, 0.0);
-            for (int rr = 0; rr < nrhs; ++rr) {
-              const int64_t o = (int64_t)rr * tv.n;
-              cij = cadd(cij, cmul(vs[o + i], qs[o + j]));
-              if (both) cji = cadd(cji, cmul(vs[o + j], qs[o + i]));
+            if (ONE) {
+              cij = cmul(vi, s_qj[jl]);
+              if (both) cji = cmul(s_vj[jl], qi);
+            } else {
+              for (int rr = 0; rr < nrhs; ++rr) {
+                const int64_t o = (int64_t)rr * tv.n;
+                cij = cadd(cij, cmul(vs[o + i], qs[o + j]));
+                if (both) cji = cadd(cji, cmul(vs[o + j], qs[o + i]));
+              }
             }
             const double sj = cmul(g, cij).x;
             atomicAdd(&s_g[jl].x, sj * dx);
@@ -1357,7 +1373,11 @@ void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int n
 void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
                      const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs) {
   if (nitems <= 0) return;
-  hipLaunchKernelGGL(k_p2p_grad, dim3(nitems), dim3(WAVE), 0, s, tv, items, nitems, ptr, rng, sym, vs, qs, gs);
+  if (tv.nrhs == 1)
+    hipLaunchKernelGGL(k_p2p_grad<true>, dim3(nitems), dim3(WAVE), 0, s, tv, items, nitems, ptr, rng, sym, vs, qs, gs);
+  else
+    hipLaunchKernelGGL(k_p2p_grad<false>, dim3(nitems), dim3(WAVE), 0, s, tv, items, nitems, ptr, rng, sym, vs, qs,
+                       gs);
 }
 void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                        int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,

@@ -158,3 +158,25 @@ def test_gradient_central_differences_n2e18(gpu_lib):
     print("central differences: %d coordinates, worst relative difference %.3e" % (checked, worst))
     assert checked >= 48
     assert worst < 1e-4
+
+
+def test_gradient_sums_over_right_hand_sides(gpu_lib):
+    """The gradient of Re sum_r <v_r, A q_r> is the sum of the per-pair terms
+    over r: two right-hand sides at once (the general near-field form) equal
+    the two single ones added (the one-right-hand-side form)."""
+    import torch
+    dev = torch.device("cuda:0")
+    w = workloads.two_layer_uniform(n=1024, seed=86, nrhs=2)
+    pts = torch.tensor(w.xy, dtype=torch.float64, device=dev)
+    plan = gpu_lib.Plan(w.k, w.interfaces, pts, tol=1e-10, leaf_size=32)
+    q = torch.tensor(w.q, dtype=torch.complex128, device=dev)
+    v = torch.tensor(workloads.complex_normal(workloads.rng_for(1703, 9136, 87), (2, w.n)),
+                     dtype=torch.complex128, device=dev)
+    _, g2 = plan.apply_adjoint(v, q=q, grad_xy=True)
+    _, ga = plan.apply_adjoint(v[0:1].contiguous(), q=q[0:1].contiguous(), grad_xy=True)
+    _, gb = plan.apply_adjoint(v[1:2].contiguous(), q=q[1:2].contiguous(), grad_xy=True)
+    g2 = g2.cpu().numpy()
+    gs = (ga + gb).cpu().numpy()
+    print("two right-hand sides vs the sum of single ones:", rel(g2, gs))
+    assert rel(g2, gs) < 1e-12
+    plan.close()
