@@ -1671,7 +1671,7 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
       TreeView tv = pl->view(nc);
       launch_gather(s, pl->n, nc, pl->perm.p, (const double2*)q + off, pl->gq.p, 0);
       launch_l2p_grad(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, pl->alpha.p, pl->gq.p, pl->gs.p, r0 > 0);
-      launch_p2p_grad(s, tv, pl->p2p_items.p, pl->np2p_items, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, pl->qs.p,
+      launch_p2p_grad(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, pl->qs.p,
                       pl->gq.p, pl->gs.p);
       launch_iface_grad(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p,
                         pl->qky.p, pl->qkx.p, pl->qs.p, pl->gq.p, pl->gs.p);

@@ -811,18 +811,47 @@ size_t l2p_grad_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(
 // stands for both orders, Re(g sum_r vs_rj q_ri) (x_i - x_j) to i.
 constexpr int GRAD_CS = 64;
 
+// H1^(1)(x) for x^2/4 within a series class: the series of M terms (the
+// class's H0 term count; the H1 coefficients fall faster, and at each class's
+// largest argument the truncation stays below 2e-18 relative) with the
+// logarithm from the LDS table; LARGE: the large-argument form above x = 6.
+// inv_x = 1/x from the caller, which has the reciprocal of r at hand.
+template <int M, bool LARGE>
+__device__ inline double2 hankel1_class(double x, double inv_x, const double2* ltab) {
+  if (LARGE && x > 6.0) return hankel1_large(x);
+  const double z = 0.25 * x * x;
+  double sa = kH1.a[M - 1], sb = kH1.b[M - 1];
+#pragma unroll
+  for (int m = M - 2; m >= 0; --m) {
+    sa = fma(sa, z, kH1.a[m]);
+    sb = fma(sb, z, kH1.b[m]);
+  }
+  const double j1 = 0.5 * x * sa;
+  const double two_over_pi = 0.63661977236758134308;
+  const double euler = 0.57721566490153286061;
+  const double y1 =
+      two_over_pi * ((0.5 * log_tab(z, ltab) + euler) * j1 - inv_x) - (0.5 / 3.14159265358979323846) * x * sb;
+  return cmk(j1, y1);
+}
+
 // ONE: a single right-hand side, whose v_i and q_i stay in registers and
 // whose sources' q_j and v_j are staged in LDS with their positions (the
 // general form reads them from memory for every pair and right-hand side).
-template <bool ONE>
+// One launch per series class, as for the near field itself.
+template <bool ONE, int CLS>
 __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __restrict__ leaves, int nitems,
                                                    const int* __restrict__ ptr, const int2* __restrict__ rng,
                                                    const int* __restrict__ sym, const double2* __restrict__ vs,
                                                    const double2* __restrict__ qs, double2* __restrict__ gs) {
+  constexpr int M = kH0ClassTerms[CLS < kH0Classes ? CLS : kH0Classes - 1];
+  constexpr bool LARGE = CLS >= kH0Classes;
   __shared__ double2 s_x[GRAD_CS];
   __shared__ double2 s_g[GRAD_CS];
   __shared__ double2 s_qj[ONE ? GRAD_CS : 1];
   __shared__ double2 s_vj[ONE ? GRAD_CS : 1];
+  __shared__ double2 s_ln[1 << kLogTabBits];
+  for (int l = threadIdx.x; l < (1 << kLogTabBits); l += WAVE) s_ln[l] = cmk(kLogTab[l][0], kLogTab[l][1]);
+  __syncthreads();
   const int li = blockIdx.x;
   if (li >= nitems) return;
   const int b = leaves[li];
@@ -830,6 +859,7 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
   const int lane = threadIdx.x;
   const int2 pr = tv.prange[b];
   const int nrhs = tv.nrhs;
+  const double inv_k = 1.0 / tv.k;
   for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
     const int i = c0 + lane;
     const bool valid = i < pr.y;
@@ -851,36 +881,54 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
         }
         __syncthreads();
         if (valid) {
+          // lanes start at different sources, so the LDS adds seldom collide;
+          // four pairs at a time give the series chains room to overlap
           const int rot = lane % cnt;
-          for (int t = 0; t < cnt; ++t) {
-            // lanes start at different sources: the LDS adds seldom collide
-            int jl = t + rot;
-            if (jl >= cnt) jl -= cnt;
-            const int j = j0 + jl;
-            if (j == i) continue;
-            const double2 xj = s_x[jl];
-            const double dx = xj.x - xi.x, dy = xj.y - xi.y;
-            const double r = sqrt(dx * dx + dy * dy);
-            const double2 h1 = hankel1(tv.k * r);
-            const double2 g = cmk(0.25 * tv.k * h1.y / r, -0.25 * tv.k * h1.x / r);  // -(i/4) k H1 / r
-            double2 cij = cmk(0.0, 0.0), cji = cmk(0.0, 0.0);
-            if (ONE) {
-              cij = cmul(vi, s_qj[jl]);
-              if (both) cji = cmul(s_vj[jl], qi);
-            } else {
-              for (int rr = 0; rr < nrhs; ++rr) {
-                const int64_t o = (int64_t)rr * tv.n;
-                cij = cadd(cij, cmul(vs[o + i], qs[o + j]));
-                if (both) cji = cadd(cji, cmul(vs[o + j], qs[o + i]));
-              }
+          for (int t0 = 0; t0 < cnt; t0 += 4) {
+            int jl[4];
+            bool use[4];
+            double dx[4], dy[4], r[4], inv_r[4];
+            double2 h1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              int l = t0 + u + rot;
+              if (l >= cnt) l -= cnt;
+              use[u] = t0 + u < cnt && j0 + l != i;
+              jl[u] = t0 + u < cnt ? l : 0;
+              const double2 xj = s_x[jl[u]];
+              dx[u] = xj.x - xi.x;
+              dy[u] = xj.y - xi.y;
+              r[u] = use[u] ? sqrt(dx[u] * dx[u] + dy[u] * dy[u]) : 1.0;
+              inv_r[u] = 1.0 / r[u];
             }
-            const double sj = cmul(g, cij).x;
-            atomicAdd(&s_g[jl].x, sj * dx);
-            atomicAdd(&s_g[jl].y, sj * dy);
-            if (both) {
-              const double si = cmul(g, cji).x;
-              gix -= si * dx;
-              giy -= si * dy;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) h1[u] = hankel1_class<M, LARGE>(tv.k * r[u], inv_r[u] * inv_k, s_ln);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (!use[u]) continue;
+              // -(i/4) k H1 / r
+              const double kr4 = 0.25 * tv.k * inv_r[u];
+              const double2 g = cmk(kr4 * h1[u].y, -kr4 * h1[u].x);
+              double2 cij = cmk(0.0, 0.0), cji = cmk(0.0, 0.0);
+              if (ONE) {
+                cij = cmul(vi, s_qj[jl[u]]);
+                if (both) cji = cmul(s_vj[jl[u]], qi);
+              } else {
+                const int j = j0 + jl[u];
+                for (int rr = 0; rr < nrhs; ++rr) {
+                  const int64_t o = (int64_t)rr * tv.n;
+                  cij = cadd(cij, cmul(vs[o + i], qs[o + j]));
+                  if (both) cji = cadd(cji, cmul(vs[o + j], qs[o + i]));
+                }
+              }
+              const double sj = cmul(g, cij).x;
+              atomicAdd(&s_g[jl[u]].x, sj * dx[u]);
+              atomicAdd(&s_g[jl[u]].y, sj * dy[u]);
+              if (both) {
+                const double si = cmul(g, cji).x;
+                gix -= si * dx[u];
+                giy -= si * dy[u];
+              }
             }
           }
         }
@@ -1370,14 +1418,24 @@ void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int n
   hipLaunchKernelGGL(k_l2p_grad, dim3(nl), dim3(WAVE), l2p_grad_lds_bytes(Pmax, rb), s, tv, leaves, nl, rb, alpha,
                      qs, gs, add);
 }
-void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
-                     const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs) {
-  if (nitems <= 0) return;
+template <int CLS>
+static void p2p_grad_class(hipStream_t s, const TreeView& tv, const int* items, int nl, const int* ptr,
+                           const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs) {
+  if (nl <= 0) return;
   if (tv.nrhs == 1)
-    hipLaunchKernelGGL(k_p2p_grad<true>, dim3(nitems), dim3(WAVE), 0, s, tv, items, nitems, ptr, rng, sym, vs, qs, gs);
+    hipLaunchKernelGGL((k_p2p_grad<true, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, vs, qs, gs);
   else
-    hipLaunchKernelGGL(k_p2p_grad<false>, dim3(nitems), dim3(WAVE), 0, s, tv, items, nitems, ptr, rng, sym, vs, qs,
-                       gs);
+    hipLaunchKernelGGL((k_p2p_grad<false, CLS>), dim3(nl), dim3(WAVE), 0, s, tv, items, nl, ptr, rng, sym, vs, qs, gs);
+}
+
+void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
+                     const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs) {
+#define HFMM_P2P_GRAD(C)                                                                                          \
+  p2p_grad_class<C>(s, tv, items + cls_ptr[C], cls_ptr[C + 1] - cls_ptr[C], ptr + cls_ptr[C], rng, sym + cls_ptr[C], \
+                    vs, qs, gs)
+  HFMM_P2P_GRAD(0); HFMM_P2P_GRAD(1); HFMM_P2P_GRAD(2); HFMM_P2P_GRAD(3); HFMM_P2P_GRAD(4); HFMM_P2P_GRAD(5);
+#undef HFMM_P2P_GRAD
+  static_assert(kH0Classes == 5, "one launch per class and one for the large-argument class");
 }
 void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                        int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,

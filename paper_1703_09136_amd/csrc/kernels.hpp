@@ -67,7 +67,9 @@ void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const doub
 // parts (add into gs), then gs to the caller's order as [n][2] doubles.
 void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* alpha,
                      const double2* qs, double2* gs, int add);
-void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, int nitems, const int* ptr,
+// Near-field gradient over the direct items, one launch per series class
+// (cls_ptr: host array of kH0Classes + 2 entries, as for launch_p2p).
+void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
                      const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs);
 void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
                        int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,
