@@ -811,27 +811,32 @@ size_t l2p_grad_lds_bytes(int Pmax, int rb) { return sizeof(double2) * (size_t)(
 // stands for both orders, Re(g sum_r vs_rj q_ri) (x_i - x_j) to i.
 constexpr int GRAD_CS = 64;
 
-// H1^(1)(x) for x^2/4 within a series class: the series of M terms (the
-// class's H0 term count; the H1 coefficients fall faster, and at each class's
-// largest argument the truncation stays below 2e-18 relative) with the
-// logarithm from the LDS table; LARGE: the large-argument form above x = 6.
-// inv_x = 1/x from the caller, which has the reciprocal of r at hand.
+// H1^(1)(x) / x from z = x^2/4 within a series class: the series of M terms
+// (the class's H0 term count; the H1 coefficients fall faster, and at each
+// class's largest argument the truncation stays below 2e-18 relative) with
+// the logarithm from the LDS table. J1/x = (1/2) sum a_m z^m and
+// Y1/x = (2/pi)((ln z / 2 + gamma) J1/x - 1/(4z)) - (1/(2 pi)) sum b_m z^m need
+// no square root; LARGE: the large-argument form above x = 6 (z > 9).
 template <int M, bool LARGE>
-__device__ inline double2 hankel1_class(double x, double inv_x, const double2* ltab) {
-  if (LARGE && x > 6.0) return hankel1_large(x);
-  const double z = 0.25 * x * x;
+__device__ inline double2 hankel1_over_x_class(double z, double inv_z, const double2* ltab) {
+  if (LARGE && z > 9.0) {
+    const double x = 2.0 * sqrt(z);
+    const double2 h = hankel1_large(x);
+    const double ix = 1.0 / x;
+    return cmk(h.x * ix, h.y * ix);
+  }
   double sa = kH1.a[M - 1], sb = kH1.b[M - 1];
 #pragma unroll
   for (int m = M - 2; m >= 0; --m) {
     sa = fma(sa, z, kH1.a[m]);
     sb = fma(sb, z, kH1.b[m]);
   }
-  const double j1 = 0.5 * x * sa;
+  const double jx = 0.5 * sa;
   const double two_over_pi = 0.63661977236758134308;
   const double euler = 0.57721566490153286061;
-  const double y1 =
-      two_over_pi * ((0.5 * log_tab(z, ltab) + euler) * j1 - inv_x) - (0.5 / 3.14159265358979323846) * x * sb;
-  return cmk(j1, y1);
+  const double yx =
+      two_over_pi * ((0.5 * log_tab(z, ltab) + euler) * jx - 0.25 * inv_z) - (0.5 / 3.14159265358979323846) * sb;
+  return cmk(jx, yx);
 }
 
 // ONE: a single right-hand side, whose v_i and q_i stay in registers and
@@ -859,7 +864,7 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
   const int lane = threadIdx.x;
   const int2 pr = tv.prange[b];
   const int nrhs = tv.nrhs;
-  const double inv_k = 1.0 / tv.k;
+  const double qk2 = 0.25 * tv.k * tv.k, kk4 = 0.25 * tv.k * tv.k;
   for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
     const int i = c0 + lane;
     const bool valid = i < pr.y;
@@ -887,8 +892,8 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
           for (int t0 = 0; t0 < cnt; t0 += 4) {
             int jl[4];
             bool use[4];
-            double dx[4], dy[4], r[4], inv_r[4];
-            double2 h1[4];
+            double dx[4], dy[4], z[4], inv_z[4];
+            double2 hx[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               int l = t0 + u + rot;
@@ -898,17 +903,16 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
               const double2 xj = s_x[jl[u]];
               dx[u] = xj.x - xi.x;
               dy[u] = xj.y - xi.y;
-              r[u] = use[u] ? sqrt(dx[u] * dx[u] + dy[u] * dy[u]) : 1.0;
-              inv_r[u] = 1.0 / r[u];
+              z[u] = use[u] ? qk2 * (dx[u] * dx[u] + dy[u] * dy[u]) : 1.0;
+              inv_z[u] = 1.0 / z[u];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) h1[u] = hankel1_class<M, LARGE>(tv.k * r[u], inv_r[u] * inv_k, s_ln);
+            for (int u = 0; u < 4; ++u) hx[u] = hankel1_over_x_class<M, LARGE>(z[u], inv_z[u], s_ln);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
               if (!use[u]) continue;
-              // -(i/4) k H1 / r
-              const double kr4 = 0.25 * tv.k * inv_r[u];
-              const double2 g = cmk(kr4 * h1[u].y, -kr4 * h1[u].x);
+              // -(i/4) k H1(k r) / r = -(i/4) k^2 H1(x) / x
+              const double2 g = cmk(kk4 * hx[u].y, -kk4 * hx[u].x);
               double2 cij = cmk(0.0, 0.0), cji = cmk(0.0, 0.0);
               if (ONE) {
                 cij = cmul(vi, s_qj[jl[u]]);
