@@ -865,9 +865,20 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
   const int2 pr = tv.prange[b];
   const int nrhs = tv.nrhs;
   const double qk2 = 0.25 * tv.k * tv.k, kk4 = 0.25 * tv.k * tv.k;
-  for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
-    const int i = c0 + lane;
-    const bool valid = i < pr.y;
+  // targets in chunks of 32 with two lanes each, the remainder in a chunk of
+  // the next power of two with more lanes per target; the g lanes of a
+  // target take every g-th source of a staged chunk
+  for (int c0 = pr.x, csz = 0; c0 < pr.y; c0 += csz) {
+    const int rem = pr.y - c0;
+    csz = 32;
+    if (rem < 32) {
+      csz = 1;
+      while (csz < rem) csz *= 2;
+    }
+    const int g = WAVE / csz;
+    const int ti = lane / g, sub = lane % g;
+    const int i = c0 + ti;
+    const bool valid = ti < min(csz, rem);
     const double2 xi = valid ? tv.pts[i] : cmk(0, 0);
     const double2 vi = (ONE && valid) ? vs[i] : cmk(0, 0), qi = (ONE && valid) ? qs[i] : cmk(0, 0);
     double gix = 0.0, giy = 0.0;
@@ -885,21 +896,23 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
           }
         }
         __syncthreads();
-        if (valid) {
-          // lanes start at different sources, so the LDS adds seldom collide;
-          // four pairs at a time give the series chains room to overlap
-          const int rot = lane % cnt;
-          for (int t0 = 0; t0 < cnt; t0 += 4) {
+        const int K = (cnt - sub + g - 1) / g;  // this lane's sources: sub + g k, k < K
+        if (valid && K > 0) {
+          // targets start at different sources, so the LDS adds seldom
+          // collide; four pairs at a time give the series chains room to overlap
+          const int r0 = ti % K;
+          for (int t0 = 0; t0 < K; t0 += 4) {
             int jl[4];
             bool use[4];
             double dx[4], dy[4], z[4], inv_z[4];
             double2 hx[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-              int l = t0 + u + rot;
-              if (l >= cnt) l -= cnt;
-              use[u] = t0 + u < cnt && j0 + l != i;
-              jl[u] = t0 + u < cnt ? l : 0;
+              const int k = t0 + u;
+              int kr = k + r0;
+              if (kr >= K) kr -= K;
+              jl[u] = sub + g * (k < K ? kr : 0);
+              use[u] = k < K && j0 + jl[u] != i;
               const double2 xj = s_x[jl[u]];
               dx[u] = xj.x - xi.x;
               dy[u] = xj.y - xi.y;
@@ -912,7 +925,7 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
             for (int u = 0; u < 4; ++u) {
               if (!use[u]) continue;
               // -(i/4) k H1(k r) / r = -(i/4) k^2 H1(x) / x
-              const double2 g = cmk(kk4 * hx[u].y, -kk4 * hx[u].x);
+              const double2 gg = cmk(kk4 * hx[u].y, -kk4 * hx[u].x);
               double2 cij = cmk(0.0, 0.0), cji = cmk(0.0, 0.0);
               if (ONE) {
                 cij = cmul(vi, s_qj[jl[u]]);
@@ -925,11 +938,11 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
                   if (both) cji = cadd(cji, cmul(vs[o + j], qs[o + i]));
                 }
               }
-              const double sj = cmul(g, cij).x;
+              const double sj = cmul(gg, cij).x;
               atomicAdd(&s_g[jl[u]].x, sj * dx[u]);
               atomicAdd(&s_g[jl[u]].y, sj * dy[u]);
               if (both) {
-                const double si = cmul(g, cji).x;
+                const double si = cmul(gg, cji).x;
                 gix -= si * dx[u];
                 giy -= si * dy[u];
               }
@@ -943,7 +956,12 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
         }
       }
     }
-    if (valid && both) {
+    // the target's sums over its g lanes (neighbouring lanes)
+    for (int m = 1; m < g; m <<= 1) {
+      gix += __shfl_xor(gix, m, WAVE);
+      giy += __shfl_xor(giy, m, WAVE);
+    }
+    if (valid && both && sub == 0) {
       unsafeAtomicAdd(&gs[i].x, gix);
       unsafeAtomicAdd(&gs[i].y, giy);
     }
