@@ -273,6 +273,7 @@ struct hfmm_plan_s {
   // M2L: runs of consecutive levels); Ps, Pd: the largest orders of the items
   struct Group {
     int first = 0, count = 0, Ps = 0, Pd = 0, ntw = 8;  // ntw: row tiles per wave of the items
+    int max_rhs = 0;  // split gather: the most right-hand sides whose blocks fit the GPU at once
   };
   // M2L: items, (source, target) pair arrays, contribution row offsets, and the
   // per-box lists of pairs for the reduction by target (forward) / by source
@@ -966,10 +967,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     // standard form.
     const int nrt_up = (2 * (2 * pl->P[l] + 1) + 15) / 16;
     bool split = false;
+    int split_rhs = 0;
     {
       const size_t lds_split = trans_lds_bytes_split(pl->P[l + 1], pl->P[l]);
       const int64_t per_cu = lds_split <= kSplitLdsMax ? (int64_t)(kCuLds / lds_split) : 0;
       split = per_cu > 0 && pbatches * nrt_up <= kNumCu * per_cu;
+      if (split) split_rhs = (int)std::min<int64_t>(1 << 20, kNumCu * per_cu / std::max<int64_t>(pbatches * nrt_up, 1));
     }
     std::vector<std::pair<int, int>> batch_pairs;  // (pbeg, count) per parent batch
     for (size_t c0 = 0; c0 < parents.size(); c0 += npi) {
@@ -989,6 +992,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       gs = gu;
       gs.first = (int)up_items.size();
       gs.ntw = 1;
+      gs.max_rhs = split_rhs;
       for (const auto& bp : batch_pairs)
         for (int rt = 0; rt < nrt_up; ++rt)
           up_items.push_back(TransItem{0, bp.first, bp.second, 0, rt, pl->P[l + 1], pl->P[l], 1, -1});
@@ -1465,7 +1469,9 @@ void launch_l2p_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const dou
 // in_sequence: nothing runs beside this launch (the split gather may be used).
 void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, int l, bool m2m_tables,
                   const double2* src, double2* dst, int rev, bool in_sequence) {
-  const bool split = up && in_sequence && pl->up_split_groups[l].count > 0;
+  // the split form while the launch (one block per item and right-hand side)
+  // still fits the GPU at once
+  const bool split = up && in_sequence && pl->up_split_groups[l].count > 0 && tv.nrhs <= pl->up_split_groups[l].max_rhs;
   const hfmm_plan_s::Group& g = split ? pl->up_split_groups[l] : up ? pl->up_groups[l] : pl->down_groups[l];
   if (!g.count) return;
   const Toff4& q4 = m2m_tables ? pl->m2m_q4[l] : pl->l2l_q4[l];
