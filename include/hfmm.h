@@ -55,18 +55,39 @@ typedef enum {
                                above its cap, or out of FP64 range) */
 } hfmm_status_t;
 
+/* Self term of the matrix. HFMM_SELF_SCATTERED (default): A_ii is the
+ * smooth scattered self term G^s(x_i, x_i) (the image of x_i lies 2 y_i away);
+ * HFMM_SELF_NONE: A_ii = 0 (both the free and the scattered i = i term are
+ * left out). The free term i = i is singular and is never included. */
 enum { HFMM_SELF_SCATTERED = 0, HFMM_SELF_NONE = 1 };
-/* Arithmetic of the hot stages. HFMM_FP64: everything in double precision.
- * HFMM_FP32 (mixed): the free-space direct pairs (H0 series, logarithm,
- * per-item sums) run in single precision, pair differences rounded from FP64;
- * tables, expansions, translations and the accumulation of u stay FP64. The
- * result then carries about 1e-7 relative error on top of the tolerance. */
-enum { HFMM_FP64 = 0, HFMM_FP32 = 1 };
+/* Arithmetic of the hot stages.
+ * HFMM_FP64: everything in double precision.
+ * HFMM_FP32 (mixed): the multipole-to-local translations (free and
+ *   heterogeneous) run as complex single-precision contractions on the FP32
+ *   matrix cores on per-level scaled coefficients, and the free-space direct
+ *   pairs (H0 series, logarithm, per-item sums) run in single precision with
+ *   pair differences rounded from FP64. Tables are generated in FP64 and
+ *   rounded once; P2M, M2M, L2L, L2P, the Bessel recurrences and the
+ *   accumulation of u stay FP64.
+ * HFMM_BF16 (mixed): as HFMM_FP32, with the multipole-to-local operands
+ *   (tables and scaled coefficients) rounded to bfloat16 and multiplied on the
+ *   BF16 matrix cores with FP32 accumulation.
+ * The reduced-precision results carry about 1e-7 (FP32) or 1e-3 (BF16)
+ * relative error on top of the tolerance. */
+enum { HFMM_FP64 = 0, HFMM_FP32 = 1, HFMM_BF16 = 2 };
+
+/* Caller-supplied device allocator (e.g. a framework's caching allocator):
+ * alloc returns device memory of at least `bytes` bytes on the current device
+ * (NULL on failure), free releases a pointer alloc returned. Both receive
+ * alloc_ctx. The library releases its buffers only after the work that uses
+ * them has completed. */
+typedef void *(*hfmm_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*hfmm_free_fn)(void *ptr, void *ctx);
 
 typedef struct {
   int32_t struct_size;      /* sizeof(hfmm_options_t) */
   int32_t leaf_size;        /* max points per leaf box; default 64 */
-  int32_t precision;        /* HFMM_FP64 (default) or HFMM_FP32 */
+  int32_t precision;        /* HFMM_FP64 (default), HFMM_FP32 or HFMM_BF16 */
   int32_t self_term;        /* HFMM_SELF_SCATTERED (default) or HFMM_SELF_NONE */
   int32_t interface_refine; /* 1 (default): refine boxes touching the bottom
                                row until every image pair is admissible;
@@ -89,7 +110,21 @@ typedef struct {
                                boxes form at most 4096 ordered pairs and
                                which no leaf lies above. Must be 0 or >= 2;
                                it is lowered to the shallowest leaf level. */
-  int32_t reserved0;
+  int32_t max_nrhs;         /* 0 (default): workspace grows on demand; > 0:
+                               the workspace for this many right-hand sides is
+                               reserved when the plan is built, so that applies
+                               with up to max_nrhs right-hand sides allocate
+                               nothing */
+  int32_t deterministic;    /* 0 (default); 1: bitwise reproducible results
+                               from run to run (stages in sequence on the
+                               caller's stream, every output element summed in
+                               a fixed order; slower) */
+  int32_t order;            /* 0 (default): expansion order per level from
+                               tol; > 0: this order at every level (the
+                               paper's fixed-p experiments), at most 255 */
+  hfmm_alloc_fn alloc;      /* NULL (default): hipMalloc / hipFree */
+  hfmm_free_fn free;        /* must be set together with alloc */
+  void *alloc_ctx;
 } hfmm_options_t;
 
 typedef struct {

@@ -102,20 +102,4 @@ def dense_matrix(media: Media, xy, *, refine=1.0):
     return direct_apply(media, xy, eye, refine=refine, workers=1).T
 
 
-def column(media: Media, xy_targets, x_src, y_src, *, refine=1.0):
-    """A(:, j) for one source at (x_src, y_src) evaluated at the given targets.
-
-    No self exclusion: the caller drops a coincident target if needed.
-    """
-    xy_targets = np.asarray(xy_targets, float)
-    x = xy_targets[:, 0]
-    y = media.to_frame(xy_targets[:, 1])
-    ys = float(media.to_frame(y_src))
-    r = np.hypot(x - x_src, y - ys)
-    free = 0.25j * hankel1(0, media.k1 * r)
-    sc = scattered_matvec(media, x, y, np.array([x_src]), np.array([ys]), np.array([1.0 + 0j]),
-                          refine=refine, workers=1)
-    return free + sc
-
-
-__all__ = ["free_matvec", "direct_apply", "dense_matrix", "column", "_SHARED"]
+__all__ = ["free_matvec", "direct_apply", "dense_matrix", "_SHARED"]

@@ -82,16 +82,26 @@ def scattered_source_gradient(media: Media, x, y, q, v, *, refine: float = 1.0):
     return g
 
 
-def source_gradient(media: Media, xy, q, v, *, refine: float = 1.0):
+def source_gradient(media: Media, xy, q, v, *, refine: float = 1.0, self_term: bool = True):
     """g_j = sum_r Re( q_rj sum_i conj(v_ri) dA_ij/d(x_j, y_j) ) for all j.
 
     xy: (N, 2) in the caller's frame (all points above the top interface);
     q, v: (N,) or (nrhs, N). Returns (N, 2); y derivatives are frame-free.
+    With ``self_term=False`` A has no scattered self term (A_jj = 0): the
+    pair (j, j) is removed, whose derivative in the source point, the target
+    held at x_j, is d/dY G^s(0, 2 y_j) in y and zero in x (G^s is even in X).
     """
     xy = np.asarray(xy, float)
     x = xy[:, 0]
     y = media.to_frame(xy[:, 1])
-    return free_source_gradient(media.k1, x, y, q, v) + scattered_source_gradient(media, x, y, q, v, refine=refine)
+    g = free_source_gradient(media.k1, x, y, q, v) + scattered_source_gradient(media, x, y, q, v, refine=refine)
+    if not self_term:
+        from .sommerfeld import scattered_pairs
+        qq = np.atleast_2d(np.asarray(q, complex))
+        vv = np.atleast_2d(np.asarray(v, complex))
+        dgs = scattered_pairs(media, np.zeros(x.size), 2.0 * y, refine=refine, d_dY=True)
+        g[:, 1] -= np.real((qq * np.conj(vv)).sum(axis=0) * dgs)
+    return g
 
 
 __all__ = ["source_gradient", "free_source_gradient", "scattered_source_gradient"]

@@ -128,12 +128,14 @@ def _sigma_or(media, lam, sigma):
     return complex(sigma) * np.ones_like(lam)
 
 
-def scattered_pairs(media: Media, X, Y, *, sigma=None, refine: float = 1.0):
+def scattered_pairs(media: Media, X, Y, *, sigma=None, refine: float = 1.0, d_dY: bool = False):
     """G^s(X, Y) pair by pair, each with its own contour rule.
 
     X = x - x0, Y = y + y0 > 0 in the interface frame. ``sigma`` overrides
     sigma_1 (a constant or a callable of lambda) for the identity checks.
     G^s = (1/2pi) int_{Gamma+} e^{-g1 Y}/g1 cos(lambda X) sigma_1 d lambda.
+    With ``d_dY`` the derivative in Y (the integrand times -g1), which is the
+    derivative in either height y or y0.
     """
     X = np.atleast_1d(np.asarray(X, dtype=float))
     Y = np.atleast_1d(np.asarray(Y, dtype=float))
@@ -144,6 +146,8 @@ def scattered_pairs(media: Media, X, Y, *, sigma=None, refine: float = 1.0):
         g1 = gamma(lam, k1)
         sig = _sigma_or(media, lam, sigma)
         f = np.exp(-g1 * Y.flat[i]) / g1 * np.cos(lam * X.flat[i]) * sig
+        if d_dY:
+            f = -g1 * f
         out.flat[i] = np.sum(w * f) / (2.0 * np.pi)
     return out
 

@@ -30,13 +30,40 @@ EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoin
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
            "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy")
 NSTAGES = 9
-HFMM_FP64, HFMM_FP32 = 0, 1
+HFMM_FP64, HFMM_FP32, HFMM_BF16 = 0, 1, 2
+HFMM_SELF_SCATTERED, HFMM_SELF_NONE = 0, 1
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("self_term", ctypes.c_int32), ("interface_refine", ctypes.c_int32), ("max_level", ctypes.c_int32),
-                ("leaf_kb", ctypes.c_double), ("top_level", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("leaf_kb", ctypes.c_double), ("top_level", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("order", ctypes.c_int32), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
+
+
+def _torch_alloc(nbytes, ctx):
+    """Device memory for the library from torch's caching allocator (current
+    device and stream); NULL (None) makes the library report HFMM_ERR_NO_MEMORY."""
+    import torch
+    try:
+        return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, ctx):
+    import torch
+    if ptr:
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# kept for the life of the module: the library holds these function pointers
+_TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+_TORCH_FREE = FREE_FN(_torch_free)
 
 
 class Info(ctypes.Structure):
@@ -117,15 +144,20 @@ def _check(status):
         raise HFMMError(status, _lib.hfmm_last_error_message().decode())
 
 
-def default_options(**kw) -> Options:
+def default_options(torch_allocator=False, **kw) -> Options:
+    """hfmm_default_options with the given fields changed; torch_allocator
+    routes the plan's device memory through torch's caching allocator."""
     lib = load()
     o = Options()
     lib.hfmm_default_options(ctypes.byref(o))
     kinds = dict(Options._fields_)
     for key, val in kw.items():
-        if key not in kinds:
+        if key not in kinds or key in ("alloc", "free", "alloc_ctx", "struct_size"):
             raise TypeError("unknown option %r" % key)
         setattr(o, key, float(val) if kinds[key] is ctypes.c_double else int(val))
+    if torch_allocator:
+        o.alloc = _TORCH_ALLOC
+        o.free = _TORCH_FREE
     return o
 
 
@@ -135,20 +167,46 @@ def _stream_ptr(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _as_rhs(t, n, name):
+def _stream_obj(stream):
+    import torch
+    return stream if stream is not None else torch.cuda.current_stream()
+
+
+def _as_rhs(t, n, name, device=None):
     import torch
     if not (t.is_cuda and t.dtype == torch.complex128):
         raise TypeError("%s must be a complex128 CUDA tensor" % name)
-    t2 = t.reshape(-1, n) if t.dim() != 2 else t
-    if t2.shape[1] != n:
+    if device is not None and t.device != device:
+        raise ValueError("%s is on %s, the plan on %s" % (name, t.device, device))
+    if t.dim() == 1:
+        t2 = t.reshape(1, -1)
+    elif t.dim() == 2:
+        t2 = t
+    else:
+        raise ValueError("%s must have shape (n,) or (nrhs, n)" % name)
+    if t2.shape[1] != n or t2.shape[0] < 1:
         raise ValueError("%s must have shape (nrhs, %d)" % (name, n))
     return t2.contiguous()
+
+
+def _check_out(out, q2, name):
+    """An output buffer must match the right-hand sides exactly and not overlap them."""
+    import torch
+    if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()):
+        raise TypeError("%s must be a contiguous complex128 CUDA tensor" % name)
+    if out.device != q2.device or tuple(out.shape) not in ((q2.shape[0], q2.shape[1]),) + \
+            (((q2.shape[1],),) if q2.shape[0] == 1 else ()):
+        raise ValueError("%s must have shape %s on %s" % (name, tuple(q2.shape), q2.device))
+    a0, a1 = out.data_ptr(), out.data_ptr() + out.numel() * 16
+    b0, b1 = q2.data_ptr(), q2.data_ptr() + q2.numel() * 16
+    if a0 < b1 and b0 < a1:
+        raise ValueError("%s overlaps the right-hand sides" % name)
 
 
 class Plan:
     """A plan of the heterogeneous FMM for fixed points and medium (hfmm_plan)."""
 
-    def __init__(self, k, interfaces, points, tol=1e-8, stream=None, **options):
+    def __init__(self, k, interfaces, points, tol=1e-8, stream=None, torch_allocator=True, **options):
         import torch
         lib = load()
         k = [float(v) for v in k]
@@ -161,7 +219,8 @@ class Plan:
         self.interfaces = tuple(interfaces)
         kk = (ctypes.c_double * len(k))(*k)
         ii = (ctypes.c_double * max(1, len(interfaces)))(*(interfaces or [0.0]))
-        opts = default_options(**options)
+        opts = default_options(torch_allocator=torch_allocator, **options)
+        self.device = pts.device
         h = ctypes.c_void_p()
         _check(lib.hfmm_plan(ctypes.byref(h), len(k), kk, ii, self.n, ctypes.c_void_p(pts.data_ptr()),
                              float(tol), ctypes.byref(opts), _stream_ptr(stream)))
@@ -171,7 +230,9 @@ class Plan:
     def apply(self, q, out=None, stream=None):
         """u = A q for q of shape (n,) or (nrhs, n), complex128 on the GPU."""
         import torch
-        q2 = _as_rhs(q, self.n, "q")
+        q2 = _as_rhs(q, self.n, "q", self.device)
+        if out is not None:
+            _check_out(out, q2, "out")
         u = out if out is not None else torch.empty_like(q2)
         _check(self._lib.hfmm_apply(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                     q2.shape[0], _stream_ptr(stream)))
@@ -180,13 +241,23 @@ class Plan:
     def apply_adjoint(self, v, q=None, grad_xy=False, stream=None):
         """w = A^H v; with grad_xy also the source-coordinate gradient (see hfmm.h)."""
         import torch
-        v2 = _as_rhs(v, self.n, "v")
+        v2 = _as_rhs(v, self.n, "v", self.device)
+        if grad_xy and q is None:
+            raise ValueError("grad_xy needs q")
         w = torch.empty_like(v2)
-        qp = ctypes.c_void_p(_as_rhs(q, self.n, "q").data_ptr()) if q is not None else None
+        # the contiguous copy of q must outlive the call (the library reads it
+        # asynchronously on the stream)
+        q2 = _as_rhs(q, self.n, "q", self.device) if q is not None else None
+        if q2 is not None and q2.shape != v2.shape:
+            raise ValueError("q and v must have the same shape")
+        qp = ctypes.c_void_p(q2.data_ptr()) if q2 is not None else None
         g = torch.zeros((self.n, 2), dtype=torch.float64, device=v2.device) if grad_xy else None
         _check(self._lib.hfmm_apply_adjoint(self._h, ctypes.c_void_p(v2.data_ptr()), ctypes.c_void_p(w.data_ptr()),
                                             v2.shape[0], qp, ctypes.c_void_p(g.data_ptr()) if g is not None else None,
                                             _stream_ptr(stream)))
+        if q2 is not None and q2.data_ptr() != q.data_ptr():
+            # a temporary copy: keep it until the work on the stream has read it
+            q2.record_stream(_stream_obj(stream))
         w = w.reshape(v.shape)
         return (w, g) if grad_xy else w
 
@@ -227,7 +298,7 @@ class Batch:
     graph(True) makes repeated applies with the same tensors replay a captured
     HIP graph; that needs a stream other than the legacy null stream."""
 
-    def __init__(self, k, interfaces, points, tol=1e-8, stream=None, **options):
+    def __init__(self, k, interfaces, points, tol=1e-8, stream=None, torch_allocator=True, **options):
         import torch
         lib = load()
         k = [float(v) for v in k]
@@ -244,7 +315,7 @@ class Batch:
         ii = (ctypes.c_double * max(1, len(interfaces)))(*(interfaces or [0.0]))
         nn = (ctypes.c_int64 * G)(*self.ns)
         pp = (ctypes.c_void_p * G)(*[p.data_ptr() for p in pts])
-        opts = default_options(**options)
+        opts = default_options(torch_allocator=torch_allocator, **options)
         h = ctypes.c_void_p()
         _check(lib.hfmm_plan_batch(ctypes.byref(h), G, len(k), kk, ii, nn, pp, float(tol), ctypes.byref(opts),
                                    _stream_ptr(stream)))
@@ -262,10 +333,15 @@ class Batch:
         G = len(self.ns)
         if len(qs) != G:
             raise ValueError("one right-hand side tensor per geometry")
-        q2 = [_as_rhs(q, n, "q") for q, n in zip(qs, self.ns)]
+        q2 = [_as_rhs(q, n, "q", p.device) for q, n, p in zip(qs, self.ns, self._pts)]
         nrhs = q2[0].shape[0]
         if any(q.shape[0] != nrhs for q in q2):
             raise ValueError("every geometry needs the same number of right-hand sides")
+        if outs is not None:
+            if len(outs) != G:
+                raise ValueError("one output tensor per geometry")
+            for o, q in zip(outs, q2):
+                _check_out(o, q, "outs[g]")
         us = outs if outs is not None else [torch.empty_like(q) for q in q2]
         qa = (ctypes.c_void_p * G)(*[q.data_ptr() for q in q2])
         ua = (ctypes.c_void_p * G)(*[u.data_ptr() for u in us])

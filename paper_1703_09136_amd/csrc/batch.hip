@@ -18,6 +18,7 @@
 namespace hfmm {
 hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs);
 int64_t plan_points(hfmm_plan_t pl);
+int64_t plan_workspace_generation(hfmm_plan_t pl);
 hfmm_status_t report(hfmm_status_t st, const std::string& msg);  // sets hfmm_last_error_message
 }  // namespace hfmm
 
@@ -33,10 +34,12 @@ struct hfmm_batch_s {
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> joins;
   hipEvent_t fork = nullptr;
+  hipEvent_t done = nullptr;  // recorded on the caller's stream after every batch apply
   bool graph_on = false;
   hipGraphExec_t exec = nullptr;
   std::vector<const double*> gq;
   std::vector<double*> gu;
+  std::vector<int64_t> ggen;  // the plans' workspace generations the graph was captured with
   int gnrhs = 0;
   hipStream_t gstream = nullptr;
 
@@ -45,10 +48,15 @@ struct hfmm_batch_s {
     exec = nullptr;
     gq.clear();
     gu.clear();
+    ggen.clear();
     gnrhs = 0;
   }
   ~hfmm_batch_s() {
+    // the last apply (eager or a graph replay) has ended before anything is freed
+    if (done) (void)hipEventSynchronize(done);
+    for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     release_graph();
+    if (done) (void)hipEventDestroy(done);
     for (hipEvent_t e : joins) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
     for (hipStream_t s : streams) (void)hipStreamDestroy(s);
@@ -120,7 +128,8 @@ hfmm_status_t hfmm_plan_batch(hfmm_batch_t* out, int32_t nplans, int32_t layers,
     b->streams.push_back(s);
     b->joins.push_back(e);
   }
-  const hipError_t fe = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  hipError_t fe = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  if (fe == hipSuccess) fe = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (fe != hipSuccess) {
     delete b;
     return batch_fail(HFMM_ERR_DEVICE, "events", fe);
@@ -157,8 +166,18 @@ hfmm_status_t hfmm_apply_batch(hfmm_batch_t b, const double* const* q, double* c
     hfmm_status_t st = hfmm::plan_reserve(p, nrhs);
     if (st != HFMM_OK) return st;
   }
-  if (!b->graph_on) return enqueue(b, q, u, nrhs, s);
-  const bool same = b->exec && b->gnrhs == nrhs && b->gstream == s &&
+  if (!b->graph_on) {
+    const hfmm_status_t st = enqueue(b, q, u, nrhs, s);
+    if (st != HFMM_OK) return st;
+    const hipError_t e = hipEventRecord(b->done, s);
+    return e == hipSuccess ? HFMM_OK : batch_fail(HFMM_ERR_DEVICE, "record", e);
+  }
+  // A captured graph holds the plans' workspace pointers: a plan whose
+  // workspace was reallocated since (a direct apply with more right-hand
+  // sides) makes the graph stale.
+  std::vector<int64_t> gen(G);
+  for (int g = 0; g < G; ++g) gen[g] = hfmm::plan_workspace_generation(b->plans[g]);
+  const bool same = b->exec && b->gnrhs == nrhs && b->gstream == s && b->ggen == gen &&
                     std::equal(b->gq.begin(), b->gq.end(), q) && std::equal(b->gu.begin(), b->gu.end(), u);
   if (!same) {
     b->release_graph();
@@ -180,10 +199,12 @@ hfmm_status_t hfmm_apply_batch(hfmm_batch_t b, const double* const* q, double* c
     }
     b->gq.assign(q, q + G);
     b->gu.assign(u, u + G);
+    b->ggen = gen;
     b->gnrhs = nrhs;
     b->gstream = s;
   }
-  const hipError_t le = hipGraphLaunch(b->exec, s);
+  hipError_t le = hipGraphLaunch(b->exec, s);
+  if (le == hipSuccess) le = hipEventRecord(b->done, s);
   return le == hipSuccess ? HFMM_OK : batch_fail(HFMM_ERR_DEVICE, "graph launch", le);
 }
 

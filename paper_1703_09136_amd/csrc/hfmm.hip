@@ -46,14 +46,41 @@ hfmm_status_t fail(hfmm_status_t s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(HFMM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Device memory of a plan comes from the caller's allocator (hfmm_options_t
+// alloc / free / alloc_ctx) or from hipMalloc. The allocator in force is set
+// for the duration of each library call that may allocate (AllocScope); every
+// buffer keeps the allocator that gave it its memory and returns it there.
+struct Allocator {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+thread_local const Allocator* tl_alloc = nullptr;
+struct AllocScope {
+  const Allocator* prev;
+  explicit AllocScope(const Allocator* a) : prev(tl_alloc) { tl_alloc = a; }
+  ~AllocScope() { tl_alloc = prev; }
+};
+
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  Allocator al{};  // the allocator p came from (alloc == nullptr: hipMalloc)
   hipError_t alloc(size_t count) {
     release();
     n = count;
     if (count == 0) return hipSuccess;
+    if (tl_alloc && tl_alloc->alloc) {
+      al = *tl_alloc;
+      p = (T*)al.alloc(count * sizeof(T), al.ctx);
+      if (!p) {
+        n = 0;
+        return hipErrorOutOfMemory;
+      }
+      return hipSuccess;
+    }
+    al = Allocator{};
     return hipMalloc((void**)&p, count * sizeof(T));
   }
   // grow only: keeps the buffer when it already holds count elements
@@ -64,7 +91,12 @@ struct DevBuf {
     return hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al.free)
+        al.free(p, al.ctx);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
   }
@@ -245,6 +277,7 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
 }  // namespace
 
 struct hfmm_plan_s {
+  Allocator al{};  // where the plan's device memory comes from
   Medium med{};
   double y_top = 0.0;
   int n = 0;
@@ -315,12 +348,18 @@ struct hfmm_plan_s {
   DevBuf<double2> qc, qky, qkx;
   int nq = 0;
   int ws_nrhs = 0;
+  int64_t ws_gen = 0;  // bumped whenever the workspace buffers are reallocated
   DevBuf<double2> qs, us, alpha, beta;
+  // HFMM_SELF_NONE: per sorted point the scattered self term G^s(x_i, x_i) and
+  // its derivative in the source height, subtracted from the output and the
+  // coordinate gradient
+  DevBuf<double2> self_g, self_dy;
   DevBuf<double2> gq, gs;  // coordinate gradient: sorted q, per-point (d/dx, d/dy)
   hfmm_info_t info{};
   // the near field runs on a stream of its own, beside the far-field chain
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_done = nullptr;  // recorded after the last launch of every call
   // stage timing
   bool prof_on = false;
   std::vector<std::vector<hipEvent_t>> prof_pending;
@@ -355,8 +394,11 @@ struct hfmm_plan_s {
     tabs.release(); tdata.release(); p2p_ptr.release();
     p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release(); gq.release(); gs.release();
+    self_g.release(); self_dy.release();
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
+    if (ev_done) (void)hipEventDestroy(ev_done);
+    ev_done = nullptr;
     if (side) (void)hipStreamDestroy(side);
     ev_fork = ev_join = nullptr;
     side = nullptr;
@@ -385,6 +427,12 @@ int rhs_chunk(hfmm_plan_t pl, int nrhs) {
 
 hfmm_status_t ensure_workspace(hfmm_plan_t pl, int nrhs) {
   if (pl->ws_nrhs >= nrhs) return HFMM_OK;
+  if (pl->ws_nrhs > 0) {
+    // earlier calls may still read the buffers about to be released
+    HIP_TRY(hipEventSynchronize(pl->ev_done));
+    HIP_TRY(hipStreamSynchronize(pl->side));
+  }
+  ++pl->ws_gen;
   HIP_TRY(pl->qs.alloc((size_t)pl->n * nrhs));
   HIP_TRY(pl->us.alloc((size_t)pl->n * nrhs));
   HIP_TRY(pl->alpha.alloc((size_t)std::max<int64_t>(pl->ctot, 1) * nrhs));
@@ -429,8 +477,12 @@ int choose_order(double k, double b, double eps, int& status) {
 
 namespace hfmm {
 // Workspace for nrhs right-hand sides, allocated ahead of a graph capture.
-hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs) { return ensure_workspace(pl, rhs_chunk(pl, nrhs)); }
+hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs) {
+  AllocScope alloc_scope(&pl->al);
+  return ensure_workspace(pl, rhs_chunk(pl, nrhs));
+}
 int64_t plan_points(hfmm_plan_t pl) { return pl->n; }
+int64_t plan_workspace_generation(hfmm_plan_t pl) { return pl->ws_gen; }
 hfmm_status_t report(hfmm_status_t st, const std::string& msg) { return fail(st, msg); }
 }  // namespace hfmm
 
@@ -465,7 +517,10 @@ const char* hfmm_last_error_message(void) { return g_err.c_str(); }
 
 void hfmm_destroy(hfmm_plan_t pl) {
   if (!pl) return;
-  (void)hipDeviceSynchronize();
+  // the plan's work ends with ev_done on the stream of its last call (calls
+  // on one plan are stream ordered); the side stream joins into that stream
+  if (pl->ev_done) (void)hipEventSynchronize(pl->ev_done);
+  if (pl->side) (void)hipStreamSynchronize(pl->side);
   pl->release_all();
   delete pl;
 }
@@ -496,9 +551,15 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     o = *opts;
   }
   if (o.leaf_size < 1 || o.leaf_size > 4096) return fail(HFMM_ERR_INVALID_ARG, "leaf_size out of range");
-  if (o.precision != HFMM_FP64 && o.precision != HFMM_FP32)
-    return fail(HFMM_ERR_UNSUPPORTED, "precision must be HFMM_FP64 or HFMM_FP32");
-  if (o.self_term != HFMM_SELF_SCATTERED) return fail(HFMM_ERR_UNSUPPORTED, "only HFMM_SELF_SCATTERED is available");
+  if (o.precision != HFMM_FP64 && o.precision != HFMM_FP32 && o.precision != HFMM_BF16)
+    return fail(HFMM_ERR_UNSUPPORTED, "precision must be HFMM_FP64, HFMM_FP32 or HFMM_BF16");
+  if (o.self_term != HFMM_SELF_SCATTERED && o.self_term != HFMM_SELF_NONE)
+    return fail(HFMM_ERR_INVALID_ARG, "self_term must be HFMM_SELF_SCATTERED or HFMM_SELF_NONE");
+  if (o.max_nrhs < 0 || o.max_nrhs > (1 << 20)) return fail(HFMM_ERR_INVALID_ARG, "max_nrhs out of range");
+  if (o.deterministic != 0 && o.deterministic != 1) return fail(HFMM_ERR_INVALID_ARG, "deterministic must be 0 or 1");
+  if (o.order < 0 || o.order > kMaxOrder) return fail(HFMM_ERR_INVALID_ARG, "order must be in [0, 255]");
+  if ((o.alloc == nullptr) != (o.free == nullptr))
+    return fail(HFMM_ERR_INVALID_ARG, "alloc and free must be given together");
   if (o.max_level < 2 || o.max_level > KEY_BITS) return fail(HFMM_ERR_INVALID_ARG, "max_level out of range");
   if (!(o.leaf_kb == 0.0 || (o.leaf_kb >= 0.25 && std::isfinite(o.leaf_kb))))
     return fail(HFMM_ERR_INVALID_ARG, "leaf_kb must be 0 or a finite value >= 0.25");
@@ -520,6 +581,10 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     if (e != hipSuccess) return fail(HFMM_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
   }
   hfmm_plan_t pl = new hfmm_plan_s();
+  pl->al.alloc = o.alloc;
+  pl->al.free = o.free;
+  pl->al.ctx = o.alloc_ctx;
+  AllocScope alloc_scope(&pl->al);
   auto bail = [&](hfmm_status_t s) {
     pl->release_all();
     delete pl;
@@ -529,6 +594,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     hipError_t e = hipStreamCreateWithFlags(&pl->side, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->ev_done, hipEventDisableTiming);
     if (e != hipSuccess) {
       fail(HFMM_ERR_DEVICE, std::string("plan stream: ") + hipGetErrorString(e));
       return bail(HFMM_ERR_DEVICE);
@@ -588,14 +654,32 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     key[i] = {spread_bits(ix) | (spread_bits(iy) << 1), (int)i};
   }
   std::sort(key.begin(), key.end());
-  for (int64_t i = 1; i < n; ++i)
-    if (key[i].first == key[i - 1].first) {
-      int a = key[i].second, b = key[i - 1].second;
-      if (hp[2 * a] == hp[2 * b] && hp[2 * a + 1] == hp[2 * b + 1]) {
-        fail(HFMM_ERR_DOMAIN, "coincident points " + std::to_string(b) + " and " + std::to_string(a));
-        return bail(HFMM_ERR_DOMAIN);
+  // Coincident points share a key. Within each run of equal keys the points
+  // are compared after sorting the run by (x, y), so that two equal points
+  // are found even when a different point with the same key lies between
+  // them in index order.
+  {
+    std::vector<std::pair<std::pair<double, double>, int>> run;
+    for (int64_t i = 0; i < n;) {
+      int64_t e = i + 1;
+      while (e < n && key[e].first == key[i].first) ++e;
+      if (e - i > 1) {
+        run.clear();
+        for (int64_t t = i; t < e; ++t) {
+          const int a = key[t].second;
+          run.push_back({{hp[2 * a], hp[2 * a + 1]}, a});
+        }
+        std::sort(run.begin(), run.end());
+        for (size_t t = 1; t < run.size(); ++t)
+          if (run[t].first == run[t - 1].first) {
+            fail(HFMM_ERR_DOMAIN, "coincident points " + std::to_string(std::min(run[t - 1].second, run[t].second)) +
+                                      " and " + std::to_string(std::max(run[t - 1].second, run[t].second)));
+            return bail(HFMM_ERR_DOMAIN);
+          }
       }
+      i = e;
     }
+  }
 
   // ---- adaptive quadtree, breadth first (boxes of a level are contiguous, Morton order)
   std::vector<Box>& B = pl->boxes;
@@ -652,8 +736,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   // ---- expansion orders (levels >= 2)
   const double eps = tol * kOrderSafety;
   for (int l = 2; l < pl->nlev; ++l) {
-    int st;
-    pl->P[l] = choose_order(k, pl->bsize[l], eps, st);
+    int st = 0;
+    pl->P[l] = o.order > 0 ? o.order : choose_order(k, pl->bsize[l], eps, st);
     if (st) {
       fail(HFMM_ERR_ACCURACY, "expansion order above the cap at level " + std::to_string(l));
       return bail(HFMM_ERR_ACCURACY);
@@ -1242,6 +1326,37 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<double2> qc, qky, qkx;
   double glx[16], glw[16];
   gauss_legendre16(glx, glw);
+  // nodes of a rule as G^s(X, Y) = sum_q c_q exp(ky_q Y + kx_q X)
+  auto rule_nodes = [&](const Rule& r, std::vector<double2>& nc, std::vector<double2>& nky,
+                        std::vector<double2>& nkx) {
+    const double inv4pi = 0.25 / M_PI;
+    for (auto& pn : r.panels) {
+      double hw = 0.5 * (pn.b - pn.a), mid = 0.5 * (pn.a + pn.b);
+      for (int g = 0; g < 16; ++g) {
+        double s = mid + hw * glx[g], w = hw * glw[g];
+        if (pn.kind == 0) {
+          double st = std::sin(s), ct = std::cos(s);
+          double2 sig = sigma1_tau(pl->med, ct, st);
+          // (i/4)(1/pi) w sigma e^{i k (Y st - X ct)}
+          nc.push_back(cmul(cmk(0.0, 0.25 / M_PI * w), sig));
+          nky.push_back(cmk(0.0, k * st));
+          nkx.push_back(cmk(0.0, -k * ct));
+        } else {
+          double2 t = cmk(s, 0.0), dt = cmk(1.0, 0.0);
+          if (s < r.send) {
+            t = cmk(s, -r.dip * std::sin(M_PI * s / r.send));
+            dt = cmk(1.0, -r.dip * M_PI / r.send * std::cos(M_PI * s / r.send));
+          }
+          double2 lam = csqrt2(cadd(cmul(t, t), cmk(k * k, 0.0)));
+          double2 sig = sigma1_t(pl->med, t);
+          double2 c = cdiv(cmul(cscale(dt, w * inv4pi), sig), lam);
+          double2 il = cmul(cmk(0.0, 1.0), lam);
+          nc.push_back(c); nky.push_back(cscale(t, -1.0)); nkx.push_back(il);
+          nc.push_back(c); nky.push_back(cscale(t, -1.0)); nkx.push_back(cscale(il, -1.0));
+        }
+      }
+    }
+  };
   if (!iu.empty()) {
     double xsp = 0.0, yhi = 0.0;
     for (auto& pr : iu) {
@@ -1256,33 +1371,18 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       fail(HFMM_ERR_ACCURACY, "near-interface quadrature rule too long");
       return bail(HFMM_ERR_ACCURACY);
     }
-    const double inv4pi = 0.25 / M_PI;
-    for (auto& pn : r.panels) {
-      double hw = 0.5 * (pn.b - pn.a), mid = 0.5 * (pn.a + pn.b);
-      for (int g = 0; g < 16; ++g) {
-        double s = mid + hw * glx[g], w = hw * glw[g];
-        if (pn.kind == 0) {
-          double st = std::sin(s), ct = std::cos(s);
-          double2 sig = sigma1_tau(pl->med, ct, st);
-          // (i/4)(1/pi) w sigma e^{i k (Y st - X ct)}
-          qc.push_back(cmul(cmk(0.0, 0.25 / M_PI * w), sig));
-          qky.push_back(cmk(0.0, k * st));
-          qkx.push_back(cmk(0.0, -k * ct));
-        } else {
-          double2 t = cmk(s, 0.0), dt = cmk(1.0, 0.0);
-          if (s < r.send) {
-            t = cmk(s, -r.dip * std::sin(M_PI * s / r.send));
-            dt = cmk(1.0, -r.dip * M_PI / r.send * std::cos(M_PI * s / r.send));
-          }
-          double2 lam = csqrt2(cadd(cmul(t, t), cmk(k * k, 0.0)));
-          double2 sig = sigma1_t(pl->med, t);
-          double2 c = cdiv(cmul(cscale(dt, w * inv4pi), sig), lam);
-          double2 il = cmul(cmk(0.0, 1.0), lam);
-          qc.push_back(c); qky.push_back(cscale(t, -1.0)); qkx.push_back(il);
-          qc.push_back(c); qky.push_back(cscale(t, -1.0)); qkx.push_back(cscale(il, -1.0));
-        }
-      }
+    rule_nodes(r, qc, qky, qkx);
+  }
+  // HFMM_SELF_NONE: a rule for X = 0 and Y over [2 ymin, 2 ymax] gives every
+  // point's scattered self term and its height derivative
+  std::vector<double2> sc_c, sc_ky, sc_kx;
+  if (o.self_term == HFMM_SELF_NONE) {
+    Rule r = build_rule(pl->med, 0.0, 2.0 * ymin, 2.0 * ymax, 0);
+    if (!r.ok) {
+      fail(HFMM_ERR_ACCURACY, "self-term quadrature rule too long");
+      return bail(HFMM_ERR_ACCURACY);
     }
+    rule_nodes(r, sc_c, sc_ky, sc_kx);
   }
 
   // ---- heterogeneous table rules
@@ -1376,6 +1476,15 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   if (e == hipSuccess) e = d_glx.upload(vglx, stream);
   if (e == hipSuccess) e = d_glw.upload(vglw, stream);
   if (e == hipSuccess) e = pl->tdata.alloc((size_t)std::max<int64_t>(toff, 1));
+  DevBuf<double2> d_scc, d_scky;
+  if (o.self_term == HFMM_SELF_NONE) {
+    if (e == hipSuccess) e = d_scc.upload(sc_c, stream);
+    if (e == hipSuccess) e = d_scky.upload(sc_ky, stream);
+    if (e == hipSuccess) e = pl->self_g.alloc((size_t)n);
+    if (e == hipSuccess) e = pl->self_dy.alloc((size_t)n);
+    if (e == hipSuccess)
+      launch_self_term(stream, (int)n, pl->pts.p, (int)sc_c.size(), d_scc.p, d_scky.p, pl->self_g.p, pl->self_dy.p);
+  }
   if (e == hipSuccess) {
     launch_table_hankel(stream, (int)fh_ref.size(), d_fhdx.p, d_fhdy.p, d_fhr.p, k, pl->tdata.p);
     launch_table_bessel(stream, (int)fb_ref.size(), d_fbdx.p, d_fbdy.p, d_fbsgn.p, d_fbr.p, k, pl->tdata.p);
@@ -1387,7 +1496,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   d_fhdx.release(); d_fhdy.release(); d_fbdx.release(); d_fbdy.release(); d_cX.release(); d_cY.release();
   d_cdip.release(); d_csend.release(); d_glx.release(); d_glw.release(); d_fhref.release(); d_fbsgn.release();
   d_fbref.release(); d_cpbeg.release(); d_imgref.release(); d_cpanels.release(); d_fhr.release();
-  d_fbr.release(); d_imr.release();
+  d_fbr.release(); d_imr.release(); d_scc.release(); d_scky.release();
   if (e != hipSuccess) {
     fail(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
          std::string("plan upload/tables: ") + hipGetErrorString(e));
@@ -1426,6 +1535,13 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   inf.flops_p2p = pl->p2p_flops;
   inf.p2p_evals = pl->p2p_evals;
   inf.top_level = pl->top;
+  if (o.max_nrhs > 0) {
+    const int chunk = rhs_chunk(pl, o.max_nrhs);
+    hfmm_status_t st = ensure_workspace(pl, chunk);
+    if (st == HFMM_OK && (pl->gq.ensure((size_t)n * chunk) != hipSuccess || pl->gs.ensure((size_t)n) != hipSuccess))
+      st = fail(HFMM_ERR_NO_MEMORY, "coordinate-gradient workspace");
+    if (st != HFMM_OK) return bail(st);
+  }
   inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   *out = pl;
   return HFMM_OK;
@@ -1595,6 +1711,7 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
   if (!pl || !q || !u) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, q or u");
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   hipStream_t s = (hipStream_t)stream_;
+  AllocScope alloc_scope(&pl->al);
   const int chunk = rhs_chunk(pl, nrhs);
   hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
@@ -1612,10 +1729,11 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
     launch_gather(s, pl->n, nc, pl->perm.p, qc, pl->qs.p, 0);
     mark();
     HIP_TRY(forward_pipeline(pl, nc, s, pl->qs.p, pl->us.p, mark));
-    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, uc, 0);
+    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, uc, 0, pl->self_g.p, pl->qs.p);
     mark();
   }
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(pl->ev_done, s));
   return HFMM_OK;
 }
 
@@ -1659,10 +1777,15 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   if (grad_xy && !q) return fail(HFMM_ERR_INVALID_ARG, "grad_xy requested without q");
   hipStream_t s = (hipStream_t)stream_;
+  AllocScope alloc_scope(&pl->al);
   const int chunk = rhs_chunk(pl, nrhs);
   hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
   if (grad_xy) {
+    if ((pl->gq.p && pl->gq.n < (size_t)pl->n * chunk) || (pl->gs.p && pl->gs.n < (size_t)pl->n)) {
+      HIP_TRY(hipEventSynchronize(pl->ev_done));  // earlier calls may still read them
+      HIP_TRY(hipStreamSynchronize(pl->side));
+    }
     HIP_TRY(pl->gq.ensure((size_t)pl->n * chunk));
     HIP_TRY(pl->gs.ensure((size_t)pl->n));
   }
@@ -1672,7 +1795,7 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
     // A^H v = conj(A^T conj(v))
     launch_gather(s, pl->n, nc, pl->perm.p, (const double2*)v + off, pl->qs.p, 1);
     HIP_TRY(transpose_pipeline(pl, nc, s, pl->qs.p, pl->us.p));
-    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, (double2*)w + off, 1);
+    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, (double2*)w + off, 1, pl->self_g.p, pl->qs.p);
     if (grad_xy) {
       // g_j = Re(q_j sum_i conj(v_i) dA_ij/dx_j): the transposed pipeline has
       // left the adjoint multipole coefficients in alpha and conj(v) in qs;
@@ -1684,10 +1807,13 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
                       pl->gq.p, pl->gs.p);
       launch_iface_grad(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p,
                         pl->qky.p, pl->qkx.p, pl->qs.p, pl->gq.p, pl->gs.p);
+      // HFMM_SELF_NONE: the pair (j, j) of the scattered part is not in A
+      if (pl->self_dy.p) launch_self_grad(s, pl->n, nc, pl->self_dy.p, pl->qs.p, pl->gq.p, pl->gs.p);
     }
   }
   if (grad_xy) launch_scatter_grad(s, pl->n, pl->perm.p, pl->gs.p, (double2*)grad_xy);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(pl->ev_done, s));
   return HFMM_OK;
 }
 

@@ -39,14 +39,64 @@ __global__ void k_gather(int n, int nrhs, const int* __restrict__ perm, const do
   dst[idx] = conj_in ? cconj(v) : v;
 }
 
+// With diag (the self term dropped by HFMM_SELF_NONE): src - diag * qsrc.
 __global__ void k_scatter(int n, int nrhs, const int* __restrict__ perm, const double2* __restrict__ src,
-                          double2* __restrict__ dst, int conj_out) {
+                          double2* __restrict__ dst, int conj_out, const double2* __restrict__ diag,
+                          const double2* __restrict__ qsrc) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t tot = (int64_t)n * nrhs;
   if (idx >= tot) return;
   int r = (int)(idx / n), i = (int)(idx % n);
   double2 v = src[idx];
+  if (diag) v = csub(v, cmul(diag[i], qsrc[idx]));
   dst[(int64_t)r * n + perm[i]] = conj_out ? cconj(v) : v;
+}
+
+// Scattered self term of every sorted point from a rule for X = 0:
+// G^s(x_i, x_i) = sum_q c_q exp(ky_q Y), Y = 2 y_i (interface frame), and its
+// derivative in the source height, sum_q c_q ky_q exp(ky_q Y). The rule's
+// nodes are staged through LDS.
+constexpr int SELF_THREADS = 256;
+__global__ void __launch_bounds__(SELF_THREADS) k_self_term(int n, const double2* __restrict__ pts, int nq,
+                                                            const double2* __restrict__ qc,
+                                                            const double2* __restrict__ qky,
+                                                            double2* __restrict__ g, double2* __restrict__ dy) {
+  __shared__ double2 s_c[SELF_THREADS], s_ky[SELF_THREADS];
+  const int i = blockIdx.x * SELF_THREADS + threadIdx.x;
+  const double Y = i < n ? 2.0 * pts[i].y : 0.0;
+  double2 a = cmk(0.0, 0.0), ad = cmk(0.0, 0.0);
+  for (int q0 = 0; q0 < nq; q0 += SELF_THREADS) {
+    __syncthreads();
+    if (q0 + threadIdx.x < nq) {
+      s_c[threadIdx.x] = qc[q0 + threadIdx.x];
+      s_ky[threadIdx.x] = qky[q0 + threadIdx.x];
+    }
+    __syncthreads();
+    const int m = min(SELF_THREADS, nq - q0);
+    for (int t = 0; t < m; ++t) {
+      const double2 e = cmul(s_c[t], cexp2(cscale(s_ky[t], Y)));
+      a = cadd(a, e);
+      ad = cadd(ad, cmul(e, s_ky[t]));
+    }
+  }
+  if (i < n) {
+    g[i] = a;
+    dy[i] = ad;
+  }
+}
+
+// HFMM_SELF_NONE: remove the self pair's term from the coordinate gradient,
+// gs[j].y -= sum_r Re(q_rj vs_rj dG^s/dY(0, 2 y_j)) (its x derivative is 0).
+__global__ void k_self_grad(int n, int nrhs, const double2* __restrict__ dy, const double2* __restrict__ vs,
+                            const double2* __restrict__ qs, double2* __restrict__ gs) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double sy = 0.0;
+  for (int r = 0; r < nrhs; ++r) {
+    const int64_t idx = (int64_t)r * n + j;
+    sy += cmul(cmul(qs[idx], vs[idx]), dy[j]).x;
+  }
+  gs[j].y -= sy;
 }
 
 // The far-field kernels form a chain of short, latency-bound launches that
@@ -1293,9 +1343,18 @@ void launch_gather(hipStream_t s, int n, int nrhs, const int* perm, const double
   int64_t tot = (int64_t)n * nrhs;
   hipLaunchKernelGGL(k_gather, dim3(blocks(tot, 256)), dim3(256), 0, s, n, nrhs, perm, src, dst, cj);
 }
-void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int cj) {
+void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int cj,
+                    const double2* diag, const double2* qsrc) {
   int64_t tot = (int64_t)n * nrhs;
-  hipLaunchKernelGGL(k_scatter, dim3(blocks(tot, 256)), dim3(256), 0, s, n, nrhs, perm, src, dst, cj);
+  hipLaunchKernelGGL(k_scatter, dim3(blocks(tot, 256)), dim3(256), 0, s, n, nrhs, perm, src, dst, cj, diag, qsrc);
+}
+void launch_self_term(hipStream_t s, int n, const double2* pts, int nq, const double2* qc, const double2* qky,
+                      double2* g, double2* dy) {
+  hipLaunchKernelGGL(k_self_term, dim3(blocks(n, SELF_THREADS)), dim3(SELF_THREADS), 0, s, n, pts, nq, qc, qky, g, dy);
+}
+void launch_self_grad(hipStream_t s, int n, int nrhs, const double2* dy, const double2* vs, const double2* qs,
+                      double2* gs) {
+  hipLaunchKernelGGL(k_self_grad, dim3(blocks(n, 256)), dim3(256), 0, s, n, nrhs, dy, vs, qs, gs);
 }
 void launch_p2m(hipStream_t s, const TreeView& tv, const int* leaves, int nl, int Pmax, const double2* qs,
                 double2* alpha, int conj_w, double2 pref) {

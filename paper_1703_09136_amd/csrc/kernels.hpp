@@ -6,7 +6,16 @@
 namespace hfmm {
 
 void launch_gather(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_in);
-void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_out);
+// scatter to user order; with diag, dst = src - diag * qsrc (sorted order)
+void launch_scatter(hipStream_t s, int n, int nrhs, const int* perm, const double2* src, double2* dst, int conj_out,
+                    const double2* diag = nullptr, const double2* qsrc = nullptr);
+// the scattered self term and its source-height derivative per sorted point
+// from a rule for X = 0 (nodes c_q, ky_q)
+void launch_self_term(hipStream_t s, int n, const double2* pts, int nq, const double2* qc, const double2* qky,
+                      double2* g, double2* dy);
+// gs[j].y -= sum_r Re(q_rj vs_rj dy_j)
+void launch_self_grad(hipStream_t s, int n, int nrhs, const double2* dy, const double2* vs, const double2* qs,
+                      double2* gs);
 // Kernel attributes that must be set before launches (and before any graph
 // capture): the dynamic LDS limit of the translation kernels.
 hipError_t init_kernel_attributes();

@@ -23,6 +23,8 @@ SPECS = {
     # name: (workload factory, number of targets, seed of the subset)
     "two_layer_hf": (workloads.two_layer_hf, 2048, 2),
     "three_layer": (workloads.three_layer_ellipses, 1000, 3),
+    # the largest geometry of the batched workload, 8 right-hand sides
+    "batched_largest": (lambda: workloads.batched_geometry(workloads.BATCHED_LARGEST, nrhs=8), 512, 4),
 }
 
 

@@ -61,6 +61,12 @@ def _plan(lib, layers, k, ifs, n, tol, opts=None, points=1):
     (dict(opts=dict(top_level=1)), 1),
     (dict(opts=dict(top_level=31)), 1),
     (dict(opts=dict(leaf_kb=0.1)), 1),
+    (dict(opts=dict(self_term=5)), 1),
+    (dict(opts=dict(order=-1)), 1),
+    (dict(opts=dict(order=256)), 1),
+    (dict(opts=dict(max_nrhs=-1)), 1),
+    (dict(opts=dict(deterministic=2)), 1),
+    (dict(opts=dict(precision=3)), 3),
 ])
 def test_plan_rejects_bad_arguments(case, expected):
     lib = hf.load()
@@ -81,3 +87,12 @@ def test_null_plan_calls_fail_cleanly():
     info = hf.Info()
     assert lib.hfmm_plan_info(None, ctypes.byref(info)) == 1
     lib.hfmm_destroy(None)
+
+
+def test_allocator_must_come_with_free():
+    lib = hf.load()
+    o = hf.default_options()
+    o.alloc = hf._TORCH_ALLOC
+    st, h = _plan(lib, 2, (5.0, 6.0), (0.0,), 10, 1e-8, o)
+    assert st == 1 and not h.value
+    assert "alloc" in lib.hfmm_last_error_message().decode()

@@ -374,3 +374,73 @@ def test_planted_sign_error_in_scattered_gradient_is_caught():
     fd = (_loss_moved_source(media, xy, q, v, j, 1, h) - _loss_moved_source(media, xy, q, v, j, 1, -h)) / (2 * h)
     assert abs(fd - good[j, 1]) <= 2e-6 * max(1.0, abs(fd))
     assert abs(fd - bad[j, 1]) > 1e-3 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- self term dropped
+
+def test_self_term_none_is_zero_diagonal_with_same_off_diagonal():
+    """direct_apply(self_term=False) applies A with A_ii = 0: the same matrix
+    as the default one off the diagonal, and nothing on it."""
+    m = Media(K3, IF3)
+    r = rng(21)
+    n = 10
+    xy = np.stack([r.uniform(0, 1, n), r.uniform(0.55, 1.2, n)], axis=1)
+    eye = np.eye(n, dtype=complex)
+    full = oracle.direct_apply(m, xy, eye, workers=1).T
+    none = oracle.direct_apply(m, xy, eye, self_term=False, workers=1).T
+    scale = np.max(np.abs(full))
+    off = ~np.eye(n, dtype=bool)
+    assert np.max(np.abs(none[off] - full[off])) < 1e-15 * scale
+    assert np.max(np.abs(np.diag(none))) < 1e-12 * np.max(np.abs(np.diag(full)))
+    # and several right-hand sides at once, targets a subset
+    q = r.standard_normal((3, n)) + 1j * r.standard_normal((3, n))
+    tid = np.array([1, 4, 8])
+    u = oracle.direct_apply(m, xy, q, targets=tid, self_term=False, workers=1)
+    ref = q @ none.T
+    assert np.max(np.abs(u - ref[:, tid])) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("X,Y", [(0.0, 0.3), (0.2, 0.15), (-0.4, 0.9)])
+def test_height_derivative_of_scattered_pair(X, Y):
+    """d/dY G^s: with sigma = 1 the closed form of the mirror-image Hankel
+    function, -(i/4) k H1(k rho) Y / rho; with the layered sigma central
+    differences of G^s itself."""
+    m = Media(K3, IF3)
+    k = m.k1
+    rho = math.hypot(X, Y)
+    d1 = oracle.scattered_pairs(m, X, Y, sigma=1.0, d_dY=True)[0]
+    ref = -0.25j * k * hankel1(1, k * rho) * Y / rho
+    assert abs(d1 - ref) < 1e-11 * abs(ref)
+    h = 1e-5
+    d = oracle.scattered_pairs(m, X, Y, d_dY=True)[0]
+    fd = (oracle.scattered_pairs(m, X, Y + h)[0] - oracle.scattered_pairs(m, X, Y - h)[0]) / (2 * h)
+    assert abs(d - fd) < 1e-6 * abs(d)
+
+
+def _loss_moved_source_no_self(media, xy, q, v, j, axis, h):
+    """_loss_moved_source for A with A_jj = 0: the pair (target j, moved
+    source j) removed from the sum."""
+    full = _loss_moved_source(media, xy, q, v, j, axis, h)
+    yf = media.to_frame(xy[:, 1])
+    X = -h if axis == 0 else 0.0
+    Y = 2 * yf[j] + (h if axis == 1 else 0.0)
+    gs = oracle.scattered_pairs(media, X, Y)[0]
+    return full - float(np.real(np.conj(v[j]) * gs * q[j]))
+
+
+def test_source_gradient_without_self_term_matches_central_differences():
+    media = Media(K2, (0.0,))
+    rng_ = np.random.default_rng([1703, 9136, 73])
+    n = 14
+    xy = np.column_stack([rng_.uniform(0, 0.5, n), rng_.uniform(0.02, 0.3, n)])
+    q = rng_.normal(size=n) + 1j * rng_.normal(size=n)
+    v = rng_.normal(size=n) + 1j * rng_.normal(size=n)
+    g_none = oracle.source_gradient(media, xy, q, v, self_term=False)
+    g_full = oracle.source_gradient(media, xy, q, v)
+    h = 1e-6
+    for j, axis in [(2, 1), (5, 0), (9, 1), (13, 1)]:
+        fd = (_loss_moved_source_no_self(media, xy, q, v, j, axis, h) -
+              _loss_moved_source_no_self(media, xy, q, v, j, axis, -h)) / (2 * h)
+        assert abs(fd - g_none[j, axis]) <= 2e-6 * max(1.0, abs(fd)), (j, axis, fd, g_none[j, axis])
+        if axis == 1:  # the self pair matters in y only, and there it must
+            assert abs(fd - g_full[j, axis]) > 1e-4 * max(1.0, abs(fd))

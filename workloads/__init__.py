@@ -124,18 +124,26 @@ def three_layer_ellipses(n=1_000_000, seed=3, nrhs=1, n_ellipses=64):
                     THREE_LAYER_IF, xy, q, leaf=64, tol=1e-8)
 
 
+def batched_geometry(g, nrhs=256, lo=12.0, hi=18.0, size_scale=1.0):
+    """Geometry g of the batched workload: three layers as above, N_g =
+    round(2**U(12,18)) points on 64 ellipses placed as in the N = 10^6
+    workload, nrhs complex N(0,1) right-hand sides."""
+    rng = rng_for(1703, 9136, 4, g)
+    n = int(round(2.0 ** rng.uniform(lo, hi) * size_scale))
+    n = max(n, 64)
+    xy = ellipse_points(rng, n, 64, (0.5, 1.0), 0.51)
+    q = complex_normal(rng, (nrhs, n))
+    return Workload("batched geometry %d N=%d" % (g, n), THREE_LAYER_K, THREE_LAYER_IF,
+                    xy, q, leaf=64, tol=1e-8)
+
+
 def batched_geometries(n_geom=32, nrhs=256, lo=12.0, hi=18.0, size_scale=1.0):
     """32 three-layer ellipse geometries, N_g = round(2**U(12,18)), nrhs each."""
-    out = []
-    for g in range(n_geom):
-        rng = rng_for(1703, 9136, 4, g)
-        n = int(round(2.0 ** rng.uniform(lo, hi) * size_scale))
-        n = max(n, 64)
-        xy = ellipse_points(rng, n, 64, (0.5, 1.0), 0.51)
-        q = complex_normal(rng, (nrhs, n))
-        out.append(Workload("batched geometry %d N=%d" % (g, n), THREE_LAYER_K, THREE_LAYER_IF,
-                            xy, q, leaf=64, tol=1e-8))
-    return out
+    return [batched_geometry(g, nrhs, lo, hi, size_scale) for g in range(n_geom)]
+
+
+# the smallest, a median and the largest geometry of the batched workload
+BATCHED_SMALLEST, BATCHED_MEDIAN, BATCHED_LARGEST = 11, 23, 8
 
 
 def two_layer_ellipses_grad(n=1 << 18, seed=5, n_fd=64):
