@@ -235,6 +235,26 @@ hfmm_status_t hfmm_batch_graph(hfmm_batch_t batch, int32_t enable);
 hfmm_status_t hfmm_batch_plan(hfmm_batch_t batch, int32_t g, hfmm_plan_t *out);
 void hfmm_batch_destroy(hfmm_batch_t batch);
 
+/*
+ * u = A q like hfmm_apply, for callers that cannot allocate device memory
+ * during the call (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the apply's workspace comes from a fixed device
+ * array of HFMM_NOALLOC_BYTES that the library holds on every GPU it runs on
+ * until the process ends, and the call makes no allocation of its own.
+ *   q, u, nrhs, stream  as for hfmm_apply.
+ * Right-hand sides go through in passes of as many as fit the array.
+ * Errors: HFMM_ERR_INVALID_ARG as hfmm_apply; HFMM_ERR_NO_MEMORY when one
+ * right-hand side of this plan needs more than HFMM_NOALLOC_BYTES (about
+ * 32 n + 32 ctot + 8 cstride bytes: points, expansion coefficients and
+ * multipole-to-local rows; roughly n <= 1.5e5 points at tolerance 1e-8);
+ * HFMM_ERR_DEVICE if the array's address cannot be found.
+ * All calls on one GPU share its array: calls that overlap on one GPU (other
+ * host threads, or streams not ordered with each other) race.
+ */
+#define HFMM_NOALLOC_BYTES ((size_t)64 << 20)
+hfmm_status_t hfmm_apply_noalloc(hfmm_plan_t plan, const double *q, double *u, int32_t nrhs,
+                                 hfmm_stream_t stream);
+
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 

@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "HFMM_OK", 1: "HFMM_ERR_INVALID_ARG", 2: "HFMM_ERR_DOMAIN", 3
 EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoint", "hfmm_plan_info",
            "hfmm_profile_enable", "hfmm_profile_read", "hfmm_stage_name",
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
-           "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy")
+           "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy",
+           "hfmm_apply_noalloc")
 NSTAGES = 9
 HFMM_FP64, HFMM_FP32, HFMM_BF16 = 0, 1, 2
 HFMM_SELF_SCATTERED, HFMM_SELF_NONE = 0, 1
@@ -107,6 +108,8 @@ def load(path: str | None = None):
     lib.hfmm_plan.restype = ctypes.c_int
     lib.hfmm_apply.argtypes = [vp, vp, vp, i32, vp]
     lib.hfmm_apply.restype = ctypes.c_int
+    lib.hfmm_apply_noalloc.argtypes = [vp, vp, vp, i32, vp]
+    lib.hfmm_apply_noalloc.restype = ctypes.c_int
     lib.hfmm_apply_adjoint.argtypes = [vp, vp, vp, i32, vp, vp, vp]
     lib.hfmm_apply_adjoint.restype = ctypes.c_int
     lib.hfmm_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
@@ -237,6 +240,14 @@ class Plan:
         _check(self._lib.hfmm_apply(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                                     q2.shape[0], _stream_ptr(stream)))
         return u.reshape(q.shape) if out is None else u
+
+    def apply_noalloc(self, q, out, stream=None):
+        """u = A q into ``out`` with the library's fixed workspace (hfmm_apply_noalloc)."""
+        q2 = _as_rhs(q, self.n, "q", self.device)
+        _check_out(out, q2, "out")
+        _check(self._lib.hfmm_apply_noalloc(self._h, ctypes.c_void_p(q2.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            q2.shape[0], _stream_ptr(stream)))
+        return out
 
     def apply_adjoint(self, v, q=None, grad_xy=False, stream=None):
         """w = A^H v; with grad_xy also the source-coordinate gradient (see hfmm.h)."""

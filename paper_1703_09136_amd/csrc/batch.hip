@@ -7,20 +7,13 @@
 // into a HIP graph (the workspaces are reserved before the capture; the
 // pipeline contains no memsets or host synchronisation) and later calls with
 // the same buffers replay it.
-#include "../../include/hfmm.h"
+#include "plan_internal.hpp"
 
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <string>
 #include <vector>
-
-namespace hfmm {
-hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs);
-int64_t plan_points(hfmm_plan_t pl);
-int64_t plan_workspace_generation(hfmm_plan_t pl);
-hfmm_status_t report(hfmm_status_t st, const std::string& msg);  // sets hfmm_last_error_message
-}  // namespace hfmm
 
 namespace {
 

@@ -17,6 +17,7 @@
 // the heterogeneous tables well conditioned at every order the level uses.
 #include "../../include/hfmm.h"
 #include "kernels.hpp"
+#include "plan_internal.hpp"
 #include "special.hpp"
 
 #include <algorithm>
@@ -483,6 +484,12 @@ hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs) {
 }
 int64_t plan_points(hfmm_plan_t pl) { return pl->n; }
 int64_t plan_workspace_generation(hfmm_plan_t pl) { return pl->ws_gen; }
+size_t workspace_bytes(hfmm_plan_t pl, int nrhs) {
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t r = (size_t)nrhs;
+  return 2 * al(sizeof(double2) * (size_t)pl->n * r) + 2 * al(sizeof(double2) * (size_t)std::max<int64_t>(pl->ctot, 1) * r) +
+         al(sizeof(double) * (size_t)std::max<int64_t>(pl->cstride, 1) * r);
+}
 hfmm_status_t report(hfmm_status_t st, const std::string& msg) { return fail(st, msg); }
 }  // namespace hfmm
 
@@ -1602,15 +1609,16 @@ void launch_level(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, bool up, in
 
 // All M2L items (forward: source -> target; transpose: target -> source) into
 // the per-pair contribution rows, then the per-box reduction into dst.
-void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* src, double2* dst, int rev) {
+void launch_m2l_all(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double2* src, double2* dst, double* contrib,
+                    int rev) {
   const int64_t* soff = rev ? pl->m2l_toff.p : pl->m2l_soff.p;
   const int64_t* doff = rev ? pl->m2l_soff.p : pl->m2l_toff.p;
   for (const auto& g : pl->m2l_groups)
     launch_trans(s, tv, pl->m2l_items.p + g.first, g.count, g.Ps, g.Pd, soff, doff,
-                 rev ? pl->m2l_pcoffT.p : pl->m2l_pcoff.p, Toff4{}, pl->tdata.p, src, nullptr, pl->contrib.p,
+                 rev ? pl->m2l_pcoffT.p : pl->m2l_pcoff.p, Toff4{}, pl->tdata.p, src, nullptr, contrib,
                  pl->cstride, rev, 0, g.ntw);
   launch_reduce_contrib(s, tv, pl->red_boxes.p, pl->nred_boxes, rev ? pl->redT_ptr.p : pl->red_ptr.p,
-                        rev ? pl->redT_beg.p : pl->red_beg.p, pl->contrib.p, pl->cstride, dst);
+                        rev ? pl->redT_beg.p : pl->red_beg.p, contrib, pl->cstride, dst);
 }
 
 // The direct parts (free-space pairs and near-interface pairs) add into us
@@ -1649,7 +1657,9 @@ bool capturing(hipStream_t s) {
 }
 
 // With stage timing on (mark.ev set) the stages run one after another on s.
-hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const double2* qs, double2* us, Marker& mark) {
+hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const Workspace& w, Marker& mark) {
+  const double2* qs = w.qs;
+  double2* us = w.us;
   TreeView tv = pl->view(nrhs);
   const bool overlap = mark.ev == nullptr && !capturing(s);
   if (overlap) {
@@ -1658,17 +1668,17 @@ hipError_t forward_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const doubl
   }
   // P2M stores the leaves' multipoles, M2M each parent's (every box of levels
   // >= 2 is one or the other)
-  launch_p2m_all(pl, tv, s, qs, pl->alpha.p, 0, cmk(1.0, 0.0));
+  launch_p2m_all(pl, tv, s, qs, w.alpha, 0, cmk(1.0, 0.0));
   mark();
   for (int l = pl->nlev - 2; l >= pl->top; --l)
-    launch_level(pl, tv, s, true, l, true, pl->alpha.p, pl->alpha.p, 0, !overlap);
+    launch_level(pl, tv, s, true, l, true, w.alpha, w.alpha, 0, !overlap);
   mark();
-  launch_m2l_all(pl, tv, s, pl->alpha.p, pl->beta.p, 0);
+  launch_m2l_all(pl, tv, s, w.alpha, w.beta, w.contrib, 0);
   mark();
   for (int l = pl->top; l + 1 < pl->nlev; ++l)
-    launch_level(pl, tv, s, false, l, false, pl->beta.p, pl->beta.p, 0, !overlap);
+    launch_level(pl, tv, s, false, l, false, w.beta, w.beta, 0, !overlap);
   mark();
-  launch_l2p_all(pl, tv, s, pl->beta.p, us, 0, cmk(0.0, 0.25), overlap ? 2 : 0);
+  launch_l2p_all(pl, tv, s, w.beta, us, 0, cmk(0.0, 0.25), overlap ? 2 : 0);
   mark();
   if (overlap) return join_near(pl, s);
   launch_near(pl, tv, s, qs, us, &mark);
@@ -1692,7 +1702,7 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
   for (int l = pl->nlev - 2; l >= pl->top; --l)
     launch_level(pl, tv, s, true, l, false, pl->beta.p, pl->beta.p, 1, !overlap);
   // M2L^T, reduced by source box
-  launch_m2l_all(pl, tv, s, pl->beta.p, pl->alpha.p, 1);
+  launch_m2l_all(pl, tv, s, pl->beta.p, pl->alpha.p, pl->contrib.p, 1);
   // M2M^T, coarse to fine: alpha'(child) += T^T alpha'(parent)
   for (int l = pl->top; l + 1 < pl->nlev; ++l)
     launch_level(pl, tv, s, false, l, true, pl->alpha.p, pl->alpha.p, 1, !overlap);
@@ -1703,7 +1713,61 @@ hipError_t transpose_pipeline(hfmm_plan_t pl, int nrhs, hipStream_t s, const dou
   return hipSuccess;
 }
 
+// u = A q in passes of `chunk` right-hand sides through the workspace w
+// (profile: stage events, for single-pass applies).
+hfmm_status_t apply_passes(hfmm_plan_t pl, const double* q, double* u, int nrhs, int chunk, hipStream_t s,
+                           const Workspace& w, bool profile) {
+  Marker mark;
+  mark.s = s;
+  if (profile && chunk >= nrhs) {
+    pl->prof_pending.emplace_back();
+    mark.ev = &pl->prof_pending.back();
+  }
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int nc = std::min(chunk, nrhs - r0);
+    const double2* qc = (const double2*)q + (int64_t)r0 * pl->n;
+    double2* uc = (double2*)u + (int64_t)r0 * pl->n;
+    mark();
+    launch_gather(s, pl->n, nc, pl->perm.p, qc, w.qs, 0);
+    mark();
+    HIP_TRY(forward_pipeline(pl, nc, s, w, mark));
+    launch_scatter(s, pl->n, nc, pl->perm.p, w.us, uc, 0, pl->self_g.p, w.qs);
+    mark();
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(pl->ev_done, s));
+  return HFMM_OK;
+}
+
 }  // namespace
+
+namespace hfmm {
+hfmm_status_t apply_in_buffer(hfmm_plan_t pl, const double* q, double* u, int nrhs, hipStream_t s, void* base,
+                              size_t bytes) {
+  if (!pl || !q || !u) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, q or u");
+  if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
+  if (!base) return fail(HFMM_ERR_INVALID_ARG, "NULL workspace");
+  if (workspace_bytes(pl, 1) > bytes)
+    return fail(HFMM_ERR_NO_MEMORY, "the plan needs " + std::to_string(workspace_bytes(pl, 1)) +
+                                        " bytes of workspace per right-hand side; " + std::to_string(bytes) +
+                                        " are available");
+  // as many right-hand sides per pass as the buffer holds (the parts grow
+  // linearly with the count, up to their 256-byte alignment)
+  int chunk = (int)std::min<size_t>((size_t)std::min(nrhs, rhs_chunk(pl, nrhs)), bytes / workspace_bytes(pl, 1));
+  chunk = std::max(chunk, 1);
+  while (chunk > 1 && workspace_bytes(pl, chunk) > bytes) --chunk;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t r = (size_t)chunk;
+  char* p = (char*)base;
+  Workspace w{};
+  w.qs = (double2*)p; p += al(sizeof(double2) * (size_t)pl->n * r);
+  w.us = (double2*)p; p += al(sizeof(double2) * (size_t)pl->n * r);
+  w.alpha = (double2*)p; p += al(sizeof(double2) * (size_t)std::max<int64_t>(pl->ctot, 1) * r);
+  w.beta = (double2*)p; p += al(sizeof(double2) * (size_t)std::max<int64_t>(pl->ctot, 1) * r);
+  w.contrib = (double*)p;
+  return apply_passes(pl, q, u, nrhs, chunk, s, w, false);
+}
+}  // namespace hfmm
 
 extern "C" {
 
@@ -1715,26 +1779,8 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
   const int chunk = rhs_chunk(pl, nrhs);
   hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
-  Marker mark;
-  mark.s = s;
-  if (pl->prof_on && chunk == nrhs) {  // stage timing covers single-pass applies
-    pl->prof_pending.emplace_back();
-    mark.ev = &pl->prof_pending.back();
-  }
-  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
-    const int nc = std::min(chunk, nrhs - r0);
-    const double2* qc = (const double2*)q + (int64_t)r0 * pl->n;
-    double2* uc = (double2*)u + (int64_t)r0 * pl->n;
-    mark();
-    launch_gather(s, pl->n, nc, pl->perm.p, qc, pl->qs.p, 0);
-    mark();
-    HIP_TRY(forward_pipeline(pl, nc, s, pl->qs.p, pl->us.p, mark));
-    launch_scatter(s, pl->n, nc, pl->perm.p, pl->us.p, uc, 0, pl->self_g.p, pl->qs.p);
-    mark();
-  }
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipEventRecord(pl->ev_done, s));
-  return HFMM_OK;
+  const Workspace w{pl->qs.p, pl->us.p, pl->alpha.p, pl->beta.p, pl->contrib.p};
+  return apply_passes(pl, q, u, nrhs, chunk, s, w, pl->prof_on);
 }
 
 hfmm_status_t hfmm_profile_enable(hfmm_plan_t pl, int32_t enable) {
