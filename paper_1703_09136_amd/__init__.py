@@ -46,10 +46,15 @@ class Options(ctypes.Structure):
                 ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
 
 
+_TORCH_DELETE = None
+
+
 def _torch_alloc(nbytes, ctx):
     """Device memory for the library from torch's caching allocator (current
     device and stream); NULL (None) makes the library report HFMM_ERR_NO_MEMORY."""
+    global _TORCH_DELETE
     import torch
+    _TORCH_DELETE = torch.cuda.caching_allocator_delete
     try:
         return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
     except Exception:
@@ -57,9 +62,13 @@ def _torch_alloc(nbytes, ctx):
 
 
 def _torch_free(ptr, ctx):
-    import torch
-    if ptr:
-        torch.cuda.caching_allocator_delete(int(ptr))
+    # at interpreter exit torch may be torn down before the last plan: the
+    # memory then goes with the process
+    if ptr and _TORCH_DELETE is not None:
+        try:
+            _TORCH_DELETE(int(ptr))
+        except Exception:
+            pass
 
 
 # kept for the life of the module: the library holds these function pointers

@@ -156,7 +156,7 @@ hfmm_status_t hfmm_apply_batch(hfmm_batch_t b, const double* const* q, double* c
     if (!q[g] || !u[g]) return hfmm::report(HFMM_ERR_INVALID_ARG, "NULL q[g] or u[g]");
   hipStream_t s = (hipStream_t)stream_;
   for (hfmm_plan_t p : b->plans) {
-    hfmm_status_t st = hfmm::plan_reserve(p, nrhs);
+    hfmm_status_t st = hfmm::plan_reserve(p, nrhs, s);
     if (st != HFMM_OK) return st;
   }
   if (!b->graph_on) {

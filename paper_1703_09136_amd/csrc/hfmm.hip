@@ -16,6 +16,7 @@
 // strategy (b)). Keeping Y >= 2b also keeps the FP64 Sommerfeld quadrature of
 // the heterogeneous tables well conditioned at every order the level uses.
 #include "../../include/hfmm.h"
+#include "blocked.hpp"
 #include "kernels.hpp"
 #include "plan_internal.hpp"
 #include "special.hpp"
@@ -186,6 +187,7 @@ constexpr double kOrderSafety = HFMM_ORDER_SAFETY;
 // largest expansion order: the batched M2L keeps a 16-pair operand tile of
 // 2P+1 coefficients and the 4P+1 table entries in LDS
 constexpr int kMaxOrder = 255;
+constexpr int kScaleStride = kMaxOrder + 1;  // scale factors per level
 // Launch shaping: the CUs of the GPU (MI355X: 256), the LDS of one CU, and the
 // most dynamic LDS a translation block may take (the CU's less the kernel's
 // static offsets).
@@ -357,6 +359,30 @@ struct hfmm_plan_s {
   DevBuf<double2> self_g, self_dy;
   DevBuf<double2> gq, gs;  // coordinate gradient: sorted q, per-point (d/dx, d/dy)
   hfmm_info_t info{};
+  // ---- right-hand-side-blocked pipeline (applies with many right-hand sides)
+  struct TgGroup {
+    int first = 0, count = 0, Ps = 0, Pd = 0, rows = 8;
+  };
+  bool blk_ok = false;   // the plan can run the blocked pipeline
+  int blk_prec_m2l = BLK_F64, blk_prec_p2p = BLK_F64;
+  DevBuf<TgItem> tg_items;
+  DevBuf<TgPair> tg_pairs;
+  std::vector<TgGroup> m2m_tg, l2l_tg;  // per parent level
+  TgGroup m2l_tg;
+  DevBuf<BpItem> bp_items;
+  DevBuf<int2> bp_rng;
+  int bp_cls_ptr[kH0Classes + 2] = {0};
+  DevBuf<int64_t> vmat_off;  // per leaf of level >= 2 (leaf order)
+  int64_t vmat_tot = 0;
+  bool vmat_ready = false;
+  DevBuf<double2> vmat;
+  DevBuf<double> blk_scale;  // a_l(n) at [l * kScaleStride + n]
+  DevBuf<int64_t> coff16;
+  int64_t ctot16 = 0;
+  int blk_Rp = 0;  // pass width the blocked workspace holds
+  DevBuf<double2> qb, ub, ab, bb;
+  DevBuf<char> alo;   // scaled reduced-precision multipoles
+  DevBuf<float2> qlo; // FP32 strengths of the FP32 near field
   // the near field runs on a stream of its own, beside the far-field chain
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -396,6 +422,9 @@ struct hfmm_plan_s {
     p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release(); gq.release(); gs.release();
     self_g.release(); self_dy.release();
+    tg_items.release(); tg_pairs.release(); bp_items.release(); bp_rng.release(); vmat_off.release(); vmat.release();
+    blk_scale.release(); coff16.release(); qb.release(); ub.release(); ab.release(); bb.release(); alo.release();
+    qlo.release();
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_done) (void)hipEventDestroy(ev_done);
@@ -443,6 +472,66 @@ hfmm_status_t ensure_workspace(hfmm_plan_t pl, int nrhs) {
   return HFMM_OK;
 }
 
+// The right-hand-side-blocked pipeline: used from kBlkMinRhs right-hand
+// sides on (HFMM_BLOCKED=0 in the environment turns it off, =1 uses it for
+// any count: diagnostics and tests). A pass holds a multiple of kBlkCols
+// right-hand sides, within kBlkBudget bytes of workspace per plan
+// (HFMM_BLK_RHS caps the pass width further).
+constexpr int kBlkMinRhs = 48;
+constexpr double kBlkBudget = 4096.0 * 1024 * 1024;
+bool use_blocked(hfmm_plan_t pl, int nrhs) {
+  if (!pl->blk_ok || pl->prof_on) return false;
+  const char* env = std::getenv("HFMM_BLOCKED");
+  if (env && env[0] == '0') return false;
+  if (env && env[0] == '1') return true;
+  return nrhs >= kBlkMinRhs;
+}
+size_t blk_bytes_per_col(hfmm_plan_t pl) {
+  size_t b = 16 * (2 * (size_t)pl->n + 2 * (size_t)std::max<int64_t>(pl->ctot, 1));
+  if (pl->blk_prec_m2l == BLK_F32) b += 8 * (size_t)std::max<int64_t>(pl->ctot, 1);
+  if (pl->blk_prec_m2l == BLK_BF16) b += 4 * (size_t)std::max<int64_t>(pl->ctot16, 1);
+  if (pl->blk_prec_p2p == BLK_F32) b += 8 * (size_t)pl->n;
+  return b;
+}
+int blk_pass_width(hfmm_plan_t pl, int nrhs) {
+  const int want = (nrhs + kBlkCols - 1) / kBlkCols * kBlkCols;
+  int cap = (int)(kBlkBudget / (double)blk_bytes_per_col(pl)) / kBlkCols * kBlkCols;
+  if (const char* env = std::getenv("HFMM_BLK_RHS")) {
+    const int c = std::atoi(env) / kBlkCols * kBlkCols;
+    if (c >= kBlkCols) cap = std::min(cap, c);
+  }
+  return std::min(want, std::max(cap, kBlkCols));
+}
+// Blocked workspace for passes of Rp right-hand sides, and the leaves'
+// expansion matrices (computed once, on stream s).
+hfmm_status_t ensure_blk_workspace(hfmm_plan_t pl, int Rp, hipStream_t s) {
+  if (pl->blk_Rp < Rp) {
+    if (pl->blk_Rp > 0) {
+      HIP_TRY(hipEventSynchronize(pl->ev_done));  // earlier calls may still read the buffers
+      HIP_TRY(hipStreamSynchronize(pl->side));
+    }
+    ++pl->ws_gen;
+    const size_t n = (size_t)pl->n, ct = (size_t)std::max<int64_t>(pl->ctot, 1), R = (size_t)Rp;
+    pl->blk_Rp = 0;
+    HIP_TRY(pl->qb.alloc(n * R));
+    HIP_TRY(pl->ub.alloc(n * R));
+    HIP_TRY(pl->ab.alloc(ct * R));
+    HIP_TRY(pl->bb.alloc(ct * R));
+    if (pl->blk_prec_m2l == BLK_F32) HIP_TRY(pl->alo.alloc(8 * ct * R));
+    if (pl->blk_prec_m2l == BLK_BF16) HIP_TRY(pl->alo.alloc(4 * (size_t)std::max<int64_t>(pl->ctot16, 1) * R));
+    if (pl->blk_prec_p2p == BLK_F32) HIP_TRY(pl->qlo.alloc(n * R));
+    pl->blk_Rp = Rp;
+  }
+  if (!pl->vmat_ready) {
+    HIP_TRY(pl->vmat.alloc((size_t)std::max<int64_t>(pl->vmat_tot, 1)));
+    const int lb2 = pl->leaf_lev[std::min(2, pl->nlev)];
+    launch_vmat(s, pl->view(1), pl->leaves.p + lb2, pl->nleaves - lb2, pl->vmat_off.p, pl->vmat.p);
+    HIP_TRY(hipGetLastError());
+    pl->vmat_ready = true;
+  }
+  return HFMM_OK;
+}
+
 uint64_t spread_bits(uint32_t v) {
   uint64_t x = v;
   x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
@@ -478,8 +567,9 @@ int choose_order(double k, double b, double eps, int& status) {
 
 namespace hfmm {
 // Workspace for nrhs right-hand sides, allocated ahead of a graph capture.
-hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs) {
+hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs, hipStream_t s) {
   AllocScope alloc_scope(&pl->al);
+  if (use_blocked(pl, nrhs)) return ensure_blk_workspace(pl, blk_pass_width(pl, nrhs), s);
   return ensure_workspace(pl, rhs_chunk(pl, nrhs));
 }
 int64_t plan_points(hfmm_plan_t pl) { return pl->n; }
@@ -584,7 +674,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     return fail(HFMM_ERR_INVALID_ARG, "interfaces must be strictly decreasing");
 
   {
-    const hipError_t e = init_kernel_attributes();
+    hipError_t e = init_kernel_attributes();
+    if (e == hipSuccess) e = init_blocked_attributes();
     if (e != hipSuccess) return fail(HFMM_ERR_DEVICE, std::string("kernel attributes: ") + hipGetErrorString(e));
   }
   hfmm_plan_t pl = new hfmm_plan_s();
@@ -886,15 +977,18 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     table_level[id] = l;
     table_image[id] = img;
   };
+  std::vector<int> fv_tab, iv_tab;  // table of each pair
   for (auto& pr : fv) {
     int l = B[pr.t].level;
     int id = free_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy - B[pr.s].iy);
     add_pair(id, l, 0, pr.s, pr.t);
+    fv_tab.push_back(id);
   }
   for (auto& pr : iv) {
     int l = B[pr.t].level;
     int id = image_table(l, B[pr.t].ix - B[pr.s].ix, B[pr.t].iy + B[pr.s].iy);
     add_pair(id, l, 1, pr.s, pr.t);
+    iv_tab.push_back(id);
   }
   // batched M2L items: per level, per table, batches of up to 64 pairs (16 when
   // 2P+1 > 64), and groups of row tiles of the real-embedded operator (ntw per
@@ -1329,6 +1423,125 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     }
   }
 
+  // ---- lists of the right-hand-side-blocked pipeline: per target box its
+  // translation pairs (M2M: its children, L2L: its parent, M2L: its free and
+  // image pairs), the direct pairs in pieces of 16 targets, the offsets of the
+  // leaves' expansion matrices and the per-level scale factors of the
+  // reduced-precision multipole-to-local contraction
+  std::vector<TgItem> tg_items_h;
+  std::vector<TgPair> tg_pairs_h;
+  std::vector<int64_t> coff16_h(nb, 0);
+  std::vector<BpItem> bp_items_h;
+  std::vector<int2> bp_rng_h;
+  std::vector<int64_t> voff_h;
+  std::vector<double> scale_h;
+  {
+    const int mprec = o.precision == HFMM_FP64 ? BLK_F64 : (o.precision == HFMM_FP32 ? BLK_F32 : BLK_BF16);
+    pl->blk_prec_m2l = mprec;
+    pl->blk_prec_p2p = o.precision == HFMM_FP64 ? BLK_F64 : BLK_F32;
+    int64_t c16 = 0;
+    for (int i = 0; i < nb; ++i) {
+      coff16_h[i] = c16;
+      if (B[i].level >= 2) c16 += (2 * pl->P[B[i].level] + 1 + 15) & ~15;
+    }
+    pl->ctot16 = c16;
+    auto toff_of = [&](int id, int Ps, int Pd) { return tabs[id].off + tabs[id].half - (Ps + Pd); };
+    // the items of one target: groups of at most ntmax row tiles sharing its pairs
+    auto add_target = [&](hfmm_plan_s::TgGroup& g, int t, int Ps, int Pd, int ntmax, int pbeg) {
+      const int Md = 2 * Pd + 1, nrt = (2 * Md + 15) / 16;
+      for (int rt = 0; rt < nrt; rt += ntmax) {
+        const int nt = std::min(ntmax, nrt - rt);
+        tg_items_h.push_back(TgItem{coff[t], pbeg, (int)tg_pairs_h.size(), rt, nt, Ps, Pd, B[t].level, 0});
+        g.rows = std::max(g.rows, 8 * nt);
+      }
+      g.Ps = std::max(g.Ps, Ps);
+      g.Pd = std::max(g.Pd, Pd);
+    };
+    // M2L: every box of levels >= top is a target (without pairs its rows are cleared)
+    std::vector<std::vector<std::pair<int, int>>> m2l_of(nb);  // (pair index, image)
+    for (size_t i = 0; i < fv.size(); ++i) m2l_of[fv[i].t].push_back({(int)i, 0});
+    for (size_t i = 0; i < iv.size(); ++i) m2l_of[iv[i].t].push_back({(int)i, 1});
+    pl->m2l_tg = hfmm_plan_s::TgGroup{};
+    pl->m2l_tg.first = (int)tg_items_h.size();
+    for (int t = pl->lev_begin[pl->top]; t < nb; ++t) {
+      const int Pl = pl->P[B[t].level];
+      const int pbeg = (int)tg_pairs_h.size();
+      for (auto& pr : m2l_of[t]) {
+        const int src = pr.second ? iv[pr.first].s : fv[pr.first].s;
+        const int id = pr.second ? iv_tab[pr.first] : fv_tab[pr.first];
+        tg_pairs_h.push_back(TgPair{coff[src], toff_of(id, Pl, Pl), coff16_h[src], pr.second, 0});
+      }
+      add_target(pl->m2l_tg, t, Pl, Pl, tgemm_max_nt(mprec, Pl), pbeg);
+    }
+    pl->m2l_tg.count = (int)tg_items_h.size() - pl->m2l_tg.first;
+    // M2M (children to parent) and L2L (parent to child) per parent level
+    pl->m2m_tg.assign(pl->nlev, hfmm_plan_s::TgGroup{});
+    pl->l2l_tg.assign(pl->nlev, hfmm_plan_s::TgGroup{});
+    for (int l = pl->top; l + 1 < pl->nlev; ++l) {
+      auto& gu = pl->m2m_tg[l];
+      gu.first = (int)tg_items_h.size();
+      for (int t = pl->lev_begin[l]; t < pl->lev_begin[l + 1]; ++t) {
+        if (B[t].leaf) continue;
+        const int pbeg = (int)tg_pairs_h.size();
+        for (int q = 0; q < 4; ++q) {
+          const int c = B[t].child[q];
+          if (c >= 0) tg_pairs_h.push_back(TgPair{coff[c], pl->m2m_q4[l].v[q], 0, 0, 0});
+        }
+        add_target(gu, t, pl->P[l + 1], pl->P[l], kTgMaxNt, pbeg);
+      }
+      gu.count = (int)tg_items_h.size() - gu.first;
+      auto& gd = pl->l2l_tg[l];
+      gd.first = (int)tg_items_h.size();
+      for (int c = pl->lev_begin[l + 1]; c < pl->lev_begin[l + 2]; ++c) {
+        const int pbeg = (int)tg_pairs_h.size();
+        tg_pairs_h.push_back(TgPair{coff[B[c].parent], pl->l2l_q4[l].v[B[c].quad], 0, 0, 0});
+        add_target(gd, c, pl->P[l], pl->P[l + 1], kTgMaxNt, pbeg);
+      }
+      gd.count = (int)tg_items_h.size() - gd.first;
+    }
+    // direct pairs: every leaf in pieces of 16 targets against its merged
+    // direct ranges, one item per series class (the class from the leaf's
+    // and the range's bounding boxes); the pieces of a leaf share the ranges
+    std::vector<BpItem> by_cls[kH0Classes + 1];
+    for (int li = 0; li < nl; ++li) {
+      const int tb = B[leaves[li]].begin, te = B[leaves[li]].end;
+      std::vector<int2> rc[kH0Classes + 1];
+      for (const int2& rg : u_per[li]) rc[series_class(leaf_bb[li], range_bb(rg))].push_back(rg);
+      for (int c = 0; c <= kH0Classes; ++c) {
+        if (rc[c].empty()) continue;
+        const int rb = (int)bp_rng_h.size();
+        bp_rng_h.insert(bp_rng_h.end(), rc[c].begin(), rc[c].end());
+        const int re = (int)bp_rng_h.size();
+        for (int t0 = tb; t0 < te; t0 += 16) by_cls[c].push_back(BpItem{t0, std::min(16, te - t0), rb, re});
+      }
+    }
+    pl->bp_cls_ptr[0] = 0;
+    for (int c = 0; c <= kH0Classes; ++c) {
+      bp_items_h.insert(bp_items_h.end(), by_cls[c].begin(), by_cls[c].end());
+      pl->bp_cls_ptr[c + 1] = (int)bp_items_h.size();
+    }
+    // expansion matrices of the leaves of levels >= 2 (leaf order)
+    int64_t vo = 0;
+    for (int i = pl->leaf_lev[std::min(2, pl->nlev)]; i < nl; ++i) {
+      voff_h.push_back(vo);
+      const Box& bx = B[leaves[i]];
+      vo += (int64_t)(2 * pl->P[bx.level] + 1) * (bx.end - bx.begin);
+    }
+    pl->vmat_tot = vo;
+    // a_l(n): |J_n(k R_l)| (R_l the box radius) where n > k R_l, 1 below;
+    // J_n(k rho) of every point of a box of level l is bounded by it there
+    scale_h.assign((size_t)pl->nlev * kScaleStride, 1.0);
+    for (int l = 2; l < pl->nlev; ++l) {
+      const double kR = k * pl->bsize[l] * std::sqrt(0.5);
+      for (int nn = 0; nn <= pl->P[l]; ++nn) {
+        double a = 1.0;
+        if (nn > kR) a = std::min(1.0, 2.0 * host_absj(kR, nn));
+        scale_h[(size_t)l * kScaleStride + nn] = std::max(a, 1e-250);
+      }
+    }
+    pl->blk_ok = iu.empty() && pl->leaf_pmax <= kBlkLeafPmax && !o.deterministic;
+  }
+
   // ---- near-interface rule (one rule covering every direct image pair)
   std::vector<double2> qc, qky, qkx;
   double glx[16], glw[16];
@@ -1457,6 +1670,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
   UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
+  UP(tg_items, tg_items_h) UP(tg_pairs, tg_pairs_h) UP(bp_items, bp_items_h) UP(bp_rng, bp_rng_h)
+  UP(vmat_off, voff_h) UP(blk_scale, scale_h) UP(coff16, coff16_h)
   DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
   DevBuf<int> d_fhref, d_fbsgn, d_fbref, d_cpbeg, d_imgref;
   DevBuf<Panel> d_cpanels;
@@ -1741,6 +1956,44 @@ hfmm_status_t apply_passes(hfmm_plan_t pl, const double* q, double* u, int nrhs,
 
 }  // namespace
 
+// u = A q through the blocked pipeline: passes of Rp right-hand sides, every
+// array blocked by right-hand side, the stages in sequence on s.
+hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrhs, hipStream_t s) {
+  const int Rp = blk_pass_width(pl, nrhs);
+  hfmm_status_t st = ensure_blk_workspace(pl, Rp, s);
+  if (st != HFMM_OK) return st;
+  const TreeView tv = pl->view(Rp);
+  const int lb2 = pl->leaf_lev[std::min(2, pl->nlev)], nl2 = pl->nleaves - lb2;
+  const int64_t n = pl->n;
+  auto tg = [&](const hfmm_plan_s::TgGroup& g, int prec, const double2* src, const void* src_lo, double2* dst,
+                int add) {
+    launch_tgemm(s, prec, Rp, pl->tg_items.p + g.first, g.count, g.Ps, g.Pd, g.rows, pl->tg_pairs.p, pl->tdata.p, src,
+                 src_lo, pl->blk_scale.p, kScaleStride, dst, add);
+  };
+  for (int r0 = 0; r0 < nrhs; r0 += Rp) {
+    const int nc = std::min(Rp, nrhs - r0);
+    const double2* qc = (const double2*)q + (int64_t)r0 * n;
+    double2* uc = (double2*)u + (int64_t)r0 * n;
+    launch_gather_blk(s, pl->n, nc, Rp, pl->perm.p, qc, pl->qb.p);
+    if (pl->blk_prec_p2p == BLK_F32) launch_to_f32(s, n * Rp, pl->qb.p, pl->qlo.p);
+    launch_fill_zero(s, pl->ub.p, n * Rp);
+    launch_p2m_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->leaf_pmax, pl->vmat_off.p, pl->vmat.p, pl->qb.p, pl->ab.p);
+    for (int l = pl->nlev - 2; l >= pl->top; --l) tg(pl->m2m_tg[l], BLK_F64, pl->ab.p, nullptr, pl->ab.p, 0);
+    if (pl->blk_prec_m2l != BLK_F64)
+      launch_scale_blk(s, pl->blk_prec_m2l, tv, Rp, pl->lev_begin[pl->top], (int)pl->boxes.size(), pl->blk_scale.p,
+                       kScaleStride, pl->coff16.p, pl->ab.p, pl->alo.p);
+    tg(pl->m2l_tg, pl->blk_prec_m2l, pl->ab.p, pl->alo.p, pl->bb.p, 0);
+    for (int l = pl->top; l + 1 < pl->nlev; ++l) tg(pl->l2l_tg[l], BLK_F64, pl->bb.p, nullptr, pl->bb.p, 1);
+    launch_l2p_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->vmat_off.p, pl->vmat.p, pl->bb.p, pl->ub.p);
+    launch_p2p_blk(s, tv, pl->blk_prec_p2p, Rp, pl->bp_items.p, pl->bp_cls_ptr, pl->bp_rng.p, pl->qb.p, pl->qlo.p,
+                   pl->ub.p);
+    launch_scatter_blk(s, pl->n, nc, Rp, pl->perm.p, pl->ub.p, uc, pl->self_g.p, pl->qb.p);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipEventRecord(pl->ev_done, s));
+  return HFMM_OK;
+}
+
 namespace hfmm {
 hfmm_status_t apply_in_buffer(hfmm_plan_t pl, const double* q, double* u, int nrhs, hipStream_t s, void* base,
                               size_t bytes) {
@@ -1776,6 +2029,7 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   hipStream_t s = (hipStream_t)stream_;
   AllocScope alloc_scope(&pl->al);
+  if (use_blocked(pl, nrhs)) return blocked_passes(pl, q, u, nrhs, s);
   const int chunk = rhs_chunk(pl, nrhs);
   hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;

@@ -21,7 +21,9 @@ struct Workspace {
   double* contrib;
 };
 
-hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs);
+// workspace for applies with nrhs right-hand sides on stream s, ahead of a
+// graph capture (allocations, and the blocked pipeline's expansion matrices)
+hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs, hipStream_t s);
 int64_t plan_points(hfmm_plan_t pl);
 int64_t plan_workspace_generation(hfmm_plan_t pl);
 // sets hfmm_last_error_message and returns st
