@@ -128,52 +128,144 @@ def extras(hf, torch, np, w, plan, pts, q, u, args, golden):
     return adj_ms / 1e3, adj_grad_ms / 1e3, mixed
 
 
-def batched(hf, torch, args):
+PEAKS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}  # dense MFMA TFLOP/s of MI355X
+
+
+def blocked_work(info):
+    """Algorithmic flops of one right-hand side through the blocked pipeline,
+    split by the arithmetic of the stage: the multipole-to-local contraction
+    (8 (2P+1)^2 per pair), P2M, M2M, L2L and L2P (the plan's count), and the
+    direct pairs as complex multiply-adds (8 per ordered pair; each H0 tile
+    is evaluated once for all right-hand sides of a block)."""
+    return {"m2l": info["flops_m2l"], "updown": info["flops_updown"], "p2p": 8.0 * info["p2p_pairs"]}
+
+
+def ideal_seconds(work, prec, nrhs):
+    """Sum over stages of work / peak (the survey's roofline definition): M2L
+    and the near field at the peak of their arithmetic, the rest FP64."""
+    m2l_peak = PEAKS[prec]
+    p2p_peak = PEAKS["f64"] if prec == "f64" else PEAKS["f32"]
+    t = 0.0
+    for w in work:
+        t += (w["m2l"] / m2l_peak + w["updown"] / PEAKS["f64"] + w["p2p"] / p2p_peak) * nrhs / 1e12
+    return t
+
+
+def batched(hf, torch, np, args):
     """32 three-layer geometries, N_g = round(2^U(12,18)), 256 right-hand sides
-    each (strengths drawn on the device from a seeded generator), applied as one
-    batch: eagerly (each plan's near field beside its far field, the plans on
-    four streams) and replayed from a HIP graph (the stages of a plan in
-    sequence). `value` is the faster of the two."""
+    each (strengths drawn on the device from a seeded generator; the first 8
+    of the largest geometry are the stored oracle case), applied as one batch
+    in FP64 (eager and graph replay), FP32 and BF16 (graph replay). Errors:
+    the smallest, median and largest geometries against FP64 single plans on
+    the same strengths, and the largest against the stored oracle values."""
     import workloads
     dev = torch.device("cuda:0")
     geos = workloads.batched_geometries(nrhs=1)
     pts = [torch.tensor(g.xy, dtype=torch.float64, device=dev) for g in geos]
     ns = [g.n for g in geos]
-    t0 = time.time()
-    b = hf.Batch(workloads.THREE_LAYER_K, workloads.THREE_LAYER_IF, pts, tol=1e-8, leaf_size=64)
-    torch.cuda.synchronize()
-    plan_s = time.time() - t0
+    nrhs = args.batch_rhs
     gen = torch.Generator(device=dev)
     gen.manual_seed(1703 * 9136 + 4)
-    nrhs = args.batch_rhs
     qs = [torch.randn((nrhs, n), dtype=torch.complex128, device=dev, generator=gen) for n in ns]
+    check = (workloads.BATCHED_SMALLEST, workloads.BATCHED_MEDIAN, workloads.BATCHED_LARGEST)
+    gold = None
+    gpath = os.path.join(ROOT, "tests", "golden", "batched_largest_oracle.npz")
+    if os.path.exists(gpath) and nrhs >= 8:
+        gold = np.load(gpath)
+        big = workloads.BATCHED_LARGEST
+        qs[big][:8] = torch.tensor(workloads.batched_geometry(big, nrhs=8).q, dtype=torch.complex128, device=dev)
+    # FP64 single plans of the checked geometries
+    refs = {}
+    for g in check:
+        p = hf.Plan(workloads.THREE_LAYER_K, workloads.THREE_LAYER_IF, pts[g], tol=1e-8, leaf_size=64)
+        refs[g] = p.apply(qs[g]).cpu().numpy()
+        p.close()
     us = [torch.empty_like(t) for t in qs]
     s = torch.cuda.Stream()
-    ms = {}
-    for mode in ("eager", "graph"):
-        b.graph(mode == "graph")
-        with torch.cuda.stream(s):
-            b.apply(qs, outs=us, stream=s)  # warm-up (graph: capture and first replay)
-        s.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = 2
-        with torch.cuda.stream(s):
-            e0.record(s)
-            for _ in range(reps):
-                b.apply(qs, outs=us, stream=s)
-            e1.record(s)
-        s.synchronize()
-        ms[mode] = e0.elapsed_time(e1) / reps
-        print("batched %s: %.1f ms per batch" % (mode, ms[mode]), file=sys.stderr, flush=True)
-    b.close()
-    best = min(ms, key=ms.get)
-    return {"workload": "32 three-layer geometries of 2^U(12,18) points (%d in all), %d right-hand sides each"
-                        % (sum(ns), nrhs),
-            "value": len(ns) * nrhs / ms[best] * 1e3, "unit": "matvecs/s (geometry x right-hand side)",
-            "ms_per_batch": ms[best], "point_rhs_per_s": sum(ns) * nrhs / ms[best] * 1e3, "plan_s": plan_s,
-            "mode": best, "ms_per_batch_eager": ms["eager"], "ms_per_batch_graph": ms["graph"],
-            "graph_value": len(ns) * nrhs / ms["graph"] * 1e3}
+    out = {"workload": "32 three-layer geometries of 2^U(12,18) points (%d in all), %d right-hand sides each"
+                       % (sum(ns), nrhs), "unit": "matvecs/s (geometry x right-hand side)"}
+    legs = [("f64", hf.HFMM_FP64, ("eager", "graph")), ("f32", hf.HFMM_FP32, ("graph",)),
+            ("bf16", hf.HFMM_BF16, ("graph",))]
+    for name, prec, modes in legs:
+        t0 = time.time()
+        b = hf.Batch(workloads.THREE_LAYER_K, workloads.THREE_LAYER_IF, pts, tol=1e-8, leaf_size=64, precision=prec)
+        torch.cuda.synchronize()
+        plan_s = time.time() - t0
+        work = [blocked_work(b.info(g)) for g in range(len(ns))]
+        ms = {}
+        for mode in modes:
+            b.graph(mode == "graph")
+            with torch.cuda.stream(s):
+                b.apply(qs, outs=us, stream=s)  # warm-up (graph: capture and first replay)
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            reps = 3
+            with torch.cuda.stream(s):
+                e0.record(s)
+                for _ in range(reps):
+                    b.apply(qs, outs=us, stream=s)
+                e1.record(s)
+            s.synchronize()
+            ms[mode] = e0.elapsed_time(e1) / reps
+            print("batched %s %s: %.1f ms per batch" % (name, mode, ms[mode]), file=sys.stderr, flush=True)
+        errs = {}
+        for g in check:
+            u = us[g].cpu().numpy()
+            errs[str(g)] = float(np.linalg.norm(u - refs[g]) / np.linalg.norm(refs[g]))
+        e_or = None
+        if gold is not None:
+            u = us[workloads.BATCHED_LARGEST][:8].cpu().numpy()[:, gold["targets"]]
+            e_or = float(np.linalg.norm(u - gold["u"]) / np.linalg.norm(gold["u"]))
+        b.close()
+        best = min(ms, key=ms.get)
+        t_ideal = ideal_seconds(work, name, nrhs)
+        out[name] = {"value": len(ns) * nrhs / ms[best] * 1e3, "ms_per_batch": ms[best], "mode": best,
+                     "ms_per_mode": ms, "point_rhs_per_s": sum(ns) * nrhs / ms[best] * 1e3, "plan_s": plan_s,
+                     "rel_err_vs_fp64_single_plans": errs, "rel_err_vs_oracle_largest_8rhs": e_or,
+                     "roofline": {"bound": "mfma", "ideal_ms": t_ideal * 1e3, "frac": t_ideal * 1e3 / ms[best],
+                                  "work_tflop": sum((w["m2l"] + w["updown"] + w["p2p"]) for w in work) * nrhs / 1e12,
+                                  "peaks_tflops": {"m2l": PEAKS[name], "near": PEAKS["f64" if name == "f64" else "f32"],
+                                                   "other": PEAKS["f64"]}}}
+        print("batched %s: %s" % (name, json.dumps(out[name])), file=sys.stderr, flush=True)
+    out["value"] = out["f64"]["value"]
+    return out
+
+
+def many_rhs(hf, torch, np, w, pts, golden, args):
+    """The N = 10^6 geometry with 64 right-hand sides per apply (the blocked
+    pipeline) in FP64, FP32 and BF16: matvecs/s as right-hand sides per
+    second, the error of the first right-hand side (the workload's strengths)
+    against the stored oracle values and of all against FP64."""
+    dev = torch.device("cuda:0")
+    nrhs = args.many_rhs
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1703 * 9136 + 3)
+    q = torch.randn((nrhs, w.n), dtype=torch.complex128, device=dev, generator=gen)
+    q[0] = torch.tensor(w.q[0], dtype=torch.complex128, device=dev)
+    u = torch.empty_like(q)
+    out = {"workload": "three-layer N=%d, %d right-hand sides per apply" % (w.n, nrhs),
+           "unit": "matvecs/s (right-hand sides per second)"}
+    u64 = None
+    for name, prec in (("f64", hf.HFMM_FP64), ("f32", hf.HFMM_FP32), ("bf16", hf.HFMM_BF16)):
+        plan = hf.Plan(w.k, w.interfaces, pts, tol=w.tol, leaf_size=w.leaf, precision=prec)
+        work = [blocked_work(plan.info())]
+        plan.apply(q, out=u)
+        torch.cuda.synchronize()
+        ms = timed(torch, lambda: plan.apply(q, out=u), max(2, args.steps // 5))
+        un = u.cpu().numpy()
+        if u64 is None:
+            u64 = un
+        e_or = None
+        if golden is not None:
+            e_or = float(np.linalg.norm(un[0:1, golden["targets"]] - golden["u"]) / np.linalg.norm(golden["u"]))
+        t_ideal = ideal_seconds(work, name, nrhs)
+        out[name] = {"value": nrhs / ms * 1e3, "ms_per_apply": ms, "rel_err_vs_oracle_rhs0": e_or,
+                     "rel_err_vs_fp64": float(np.linalg.norm(un - u64) / np.linalg.norm(u64)),
+                     "roofline": {"bound": "mfma", "ideal_ms": t_ideal * 1e3, "frac": t_ideal * 1e3 / ms}}
+        print("many rhs %s: %s" % (name, json.dumps(out[name])), file=sys.stderr, flush=True)
+        plan.close()
+    return out
 
 
 def main():
@@ -185,6 +277,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the adjoint, mixed-precision and batched legs (profiling runs)")
     ap.add_argument("--batch-rhs", type=int, default=256)
+    ap.add_argument("--many-rhs", type=int, default=64)
+    ap.add_argument("--legs", default="adjoint,mixed,many,batched",
+                    help="side legs to run besides the headline (profiling runs pick one)")
     ap.add_argument("--n", type=int, default=1_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -262,12 +357,15 @@ def main():
                 "stage_ms": {k: round(v, 4) for k, v in stage_avg.items()},
                 "ms_per_step_stages_in_sequence": ms_serial}
 
-    adj_s = adj_grad_s = mixed = batch = None
-    if not args.no_extras:
+    adj_s = adj_grad_s = mixed = batch = many = None
+    legs = set() if args.no_extras else set(args.legs.split(","))
+    if legs & {"adjoint", "mixed"}:
         adj_s, adj_grad_s, mixed = extras(hf, torch, np, w, plan, pts, q, u, args, golden)
         print("mixed: %s" % json.dumps(mixed), file=sys.stderr, flush=True)
-        batch = batched(hf, torch, args)
-        print("batched: %s" % json.dumps(batch), file=sys.stderr, flush=True)
+    if "many" in legs:
+        many = many_rhs(hf, torch, np, w, pts, golden, args)
+    if "batched" in legs:
+        batch = batched(hf, torch, np, args)
     plan.close()
 
     cpu = None
@@ -282,7 +380,7 @@ def main():
                       % w.n, "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
                       "parallelism": "single GPU"},
            "rel_err_vs_oracle": err, "adjoint_s": adj_s, "adjoint_with_coordinate_grad_s": adj_grad_s,
-           "mixed": mixed, "batched": batch, "plan_s": plan_s,
+           "mixed": mixed, "many_rhs": many, "batched": batch, "plan_s": plan_s,
            "levels": info["levels"], "orders": info["order"],
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

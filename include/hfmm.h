@@ -147,7 +147,10 @@ typedef struct {
                                each cross-leaf pair once, same-leaf pairs
                                in both orders */
   int32_t top_level;        /* coarsest level of the expansions in use */
-  int32_t reserved0;
+  int32_t m2l_tile;         /* row tiles per multipole-to-local work item of
+                               the many-right-hand-side contraction, chosen by
+                               timing the candidates 2, 4, 8 on the plan's own
+                               launch at its first such apply (0: not yet) */
 } hfmm_info_t;
 
 /* Default options. */

@@ -83,10 +83,10 @@ class Info(ctypes.Structure):
                 ("image_tables", ctypes.c_int64), ("flops_m2l", ctypes.c_double),
                 ("flops_updown", ctypes.c_double), ("flops_p2p", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("p2p_evals", ctypes.c_int64),
-                ("top_level", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
+                ("top_level", ctypes.c_int32), ("m2l_tile", ctypes.c_int32)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("order", "reserved0")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "order"}
         d["order"] = [int(self.order[i]) for i in range(self.levels)]
         return d
 

@@ -261,40 +261,105 @@ __device__ inline int tg_plane(int rp, int kp, bool neg) {
   return pl;
 }
 
+// The scaled reduced-precision operators of the multipole-to-local tables,
+// made once per plan: O[p][m] = a(|m|) a(|p|) T_pm for orders p, m in
+// [-P, P] of the table's level, T_pm = t[m - p] (free) or (-1)^m t[-m - p]
+// (image: the operator acting on unreflected multipoles). FP32: complex
+// rows [2P + 1][Ms8] (orders padded with zeros to a multiple of 8) at off[t]
+// (float2 units). BF16: the interleaved real
+// embedding, rows 2p and 2p + 1 of K = 2 Ms16 values (zero past the orders),
+// at off[t] (bf16 units). One block per table.
+__global__ void k_lo_tables(int prec, int ntab, const int64_t* __restrict__ toff, const int* __restrict__ P_of,
+                            const int* __restrict__ lev_of, const int* __restrict__ img_of,
+                            const int64_t* __restrict__ off, const double* __restrict__ scale, int sstride,
+                            const double2* __restrict__ tdata, void* __restrict__ out) {
+  const int t = blockIdx.x;
+  if (t >= ntab) return;
+  const int P = P_of[t], M = 2 * P + 1;
+  const bool img = img_of[t] != 0;
+  const double* sa = scale + lev_of[t] * sstride;
+  const double2* T = tdata + toff[t];  // t[-2P]
+  const int Ms8 = (M + 7) & ~7, Ms16 = (M + 15) & ~15, K = 2 * Ms16;
+  const int cols = prec == BLK_F32 ? Ms8 : Ms16;
+  for (int e = threadIdx.x; e < M * cols; e += blockDim.x) {
+    const int p = e / cols, m = e - p * cols;
+    double2 v = cmk(0.0, 0.0);
+    if (m < M) {
+      const int pp = p - P, mm = m - P;
+      const int idx = img ? -mm - pp + 2 * P : mm - pp + 2 * P;
+      const double sg = (img && (mm & 1)) ? -1.0 : 1.0;
+      v = cscale(T[idx], sg * sa[mm < 0 ? -mm : mm] * sa[pp < 0 ? -pp : pp]);
+    }
+    if (prec == BLK_F32) {
+      ((float2*)out)[off[t] + (int64_t)p * Ms8 + m] = make_float2((float)v.x, (float)v.y);
+    } else {
+      __bf16* r0 = (__bf16*)out + off[t] + (int64_t)(2 * p) * K + 2 * m;
+      __bf16* r1 = r0 + K;
+      r0[0] = (__bf16)(float)v.x;
+      r0[1] = (__bf16)(float)(-v.y);
+      r1[0] = (__bf16)(float)v.y;
+      r1[1] = (__bf16)(float)v.x;
+    }
+  }
+}
+
 template <int PREC>
 struct TgTraits;
 template <>
 struct TgTraits<BLK_F64> {
   using acc_t = d4;
+  using b_t = double;
 };
 template <>
 struct TgTraits<BLK_F32> {
   using acc_t = f4;
+  using b_t = float;
 };
 template <>
 struct TgTraits<BLK_BF16> {
   using acc_t = f4;
+  using b_t = bf8;
 };
+
+// Source rows of a pair arrive in LDS in chunks of TG_CH orders (16 for
+// BF16) by asynchronous global-to-LDS copies (global_load_lds_dwordx4: lane
+// i's 16 bytes go to the wave's LDS address + 16 i), double-buffered: the
+// copy of chunk s + 1 is issued right after the barrier that makes chunk s
+// visible and runs while chunk s is contracted, so the MFMA loop reads only
+// LDS. The reduced-precision operators (row-padded plan tables) are copied
+// the same way, one pair ahead; the FP64 Toeplitz planes are loaded into
+// registers one pair ahead and stored after the pair's last chunk.
+typedef __attribute__((address_space(3))) void lds_void_t;
+__device__ inline void copy16_to_lds(const void* g, void* l) {
+  __builtin_amdgcn_global_load_lds(g, (lds_void_t*)l, 16, 0, 0);
+}
+// orders per source chunk: 16 KiB per chunk in every precision
+template <int PREC>
+struct TgChunk {
+  static constexpr int CH = PREC == BLK_F64 ? 16 : (PREC == BLK_F32 ? 32 : 64);
+  static constexpr int BYTES = CH * 64 * (PREC == BLK_F64 ? 16 : (PREC == BLK_F32 ? 8 : 4));
+};
+constexpr int TG_PF64 = 2;  // Toeplitz values per thread (ntp <= 512)
 
 // dst rows of item t = (add ? dst : 0) + sum_pairs Op_pair src_pair. Block:
 // one item, 64 right-hand sides (grid y), wave w the columns 16 w .. 16 w + 15,
-// all nt row tiles of the item. FP64: A from the Toeplitz planes of each pair's
-// table (staged per pair), B from the blocked FP64 source rows. FP32 / BF16:
-// the pair's operator scaled by a_s(|m|) a_t(|p|) is built in LDS for the
-// item's rows (FP32 planes, or BF16 real-embedded rows), B from the scaled
-// low-precision source rows; the FP32 accumulators are divided by a_t(|p|) in
-// FP64 at the end. Items are spread over the XCDs in contiguous runs: the
-// grid has a multiple of 8 blocks and block b (dispatched to XCD b mod 8)
-// takes item (b mod 8) * ceil(n / 8) + b / 8, so neighbouring targets, which
-// share source boxes, share an L2.
-template <int PREC>
+// all nt row tiles of the item (at most NTM). FP64: A from the Toeplitz
+// planes (Re, Im, -Im, -Re), B the blocked FP64 source rows. FP32 / BF16: A
+// from the plan's scaled operators (FP32 complex rows of Ms8 orders; BF16
+// embedded rows of 2 Ms16 values), B the scaled low-precision source rows;
+// each pair accumulates in FP32 on the matrix cores and is added to FP64
+// sums, divided by a_t(|p|) at the end. Items are spread over the XCDs in
+// contiguous runs: the grid has a multiple of 8 blocks and block b
+// (dispatched to XCD b mod 8) takes item (b mod 8) * ceil(n / 8) + b / 8, so
+// neighbouring targets, which share source boxes, share an L2.
+template <int PREC, int NTM>
 __global__ void __launch_bounds__(BLK_THREADS) k_tgemm(int Rp, const TgItem* __restrict__ items, int nitems,
                                                        const TgPair* __restrict__ pairs,
-                                                       const double2* __restrict__ tdata,
+                                                       const double2* __restrict__ tdata, const void* __restrict__ olo,
                                                        const double2* __restrict__ src, const void* __restrict__ src_lo,
                                                        const double* __restrict__ scale, int sstride,
-                                                       double2* __restrict__ dst, int add, int lds_rows) {
-  extern __shared__ double lds[];
+                                                       double2* __restrict__ dst, int add, int abuf) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds8[];
   using acc_t = typename TgTraits<PREC>::acc_t;
   const int per_xcd = (nitems + 7) / 8;
   const int it_id = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
@@ -305,165 +370,212 @@ __global__ void __launch_bounds__(BLK_THREADS) k_tgemm(int Rp, const TgItem* __r
   const int nt_tab = 2 * (Ps + Pd) + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kl = lane >> 4;
-  const int col = blockIdx.y * kBlkCols + wave * 16 + (lane & 15);
+  const int col0 = blockIdx.y * kBlkCols;     // the block's first right-hand side
+  const int cl = wave * 16 + (lane & 15);     // this lane's column within the block
+  const int col = col0 + cl;
   const int rp = lane & 1, kp = kl & 1;
-  acc_t acc[kTgMaxNt];
+  acc_t acc[NTM];
 #pragma unroll
-  for (int j = 0; j < kTgMaxNt; ++j)
+  for (int j = 0; j < NTM; ++j)
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[j][i] = 0;
-  // reduced precision: each pair's contraction accumulates in FP32 on the
-  // matrix cores and is added to these FP64 sums (one FP32 chain per pair,
-  // not one over all the pairs of a target)
-  constexpr int NT64 = PREC == BLK_F64 ? 1 : kTgMaxNt;
+  constexpr int NT64 = PREC == BLK_F64 ? 1 : NTM;
   double acc64[NT64][4];
 #pragma unroll
   for (int j = 0; j < NT64; ++j)
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc64[j][i] = 0.0;
-  // lane's output order index per row tile (rows past 2 Md use index 0)
-  int pidx[kTgMaxNt];
+  // every one of the NTM tiles is contracted (no per-tile branches in the
+  // MFMA loops): rows past the item's tiles or past 2 Md read order 0's
+  // operator and are not stored
+  int pidx[NTM];
 #pragma unroll
-  for (int j = 0; j < kTgMaxNt; ++j) {
+  for (int j = 0; j < NTM; ++j) {
     const int R = 16 * (it.rt0 + j) + (lane & 15);
     pidx[j] = (j < it.nt && R < 2 * Md) ? (R >> 1) : 0;
   }
-  const int p_lo = 8 * it.rt0;  // first complex row of the item
+  const int p_lo = 8 * it.rt0;
   const int nrow = min(8 * it.nt, Md - p_lo);
-  for (int e = it.pbeg; e < it.pend; ++e) {
-    const TgPair pa = pairs[e];
-    __syncthreads();  // the previous pair's operator is no longer read
-    if constexpr (PREC == BLK_F64) {
-      const int ntp = tg_table_stride(nt_tab);
-      const double2* T = tdata + pa.toff;
-      for (int i = tid; i < ntp; i += BLK_THREADS) {
-        const int n = i - kTabPadB;
-        const double2 v = (n >= 0 && n < nt_tab) ? T[n] : cmk(0.0, 0.0);
-        lds[i] = v.x;
-        lds[ntp + i] = v.y;
-        lds[2 * ntp + i] = -v.y;
-        lds[3 * ntp + i] = -v.x;
+  const int ntp = tg_table_stride(nt_tab);
+  const int Ms8 = (Ms + 7) & ~7, Ms16 = (Ms + 15) & ~15, K16 = 2 * Ms16;
+  constexpr int CH = TgChunk<PREC>::CH;  // orders per chunk
+  const int nch = (Ms + CH - 1) / CH;
+  const int npair = it.pend - it.pbeg;
+  const int nstage = npair * nch;
+  // LDS: two operator buffers of abuf bytes, then two source chunks
+  constexpr int BBUF = TgChunk<PREC>::BYTES;
+  unsigned char* const Ab0 = lds8;
+  unsigned char* const Bb0 = lds8 + 2 * abuf;
+  // ---- FP64 operator: Toeplitz planes through registers
+  double2 r64[TG_PF64];
+  auto fetchA64 = [&](int e) {
+    const double2* T = tdata + pairs[e].toff;
+#pragma unroll
+    for (int u = 0; u < TG_PF64; ++u) {
+      const int i = tid + u * BLK_THREADS, n = i - kTabPadB;
+      r64[u] = (i < ntp && n >= 0 && n < nt_tab) ? T[n] : cmk(0.0, 0.0);
+    }
+  };
+  auto storeA64 = [&](int buf) {
+    double* L = (double*)(Ab0 + buf * abuf);
+#pragma unroll
+    for (int u = 0; u < TG_PF64; ++u) {
+      const int i = tid + u * BLK_THREADS;
+      if (i < ntp) {
+        L[i] = r64[u].x;
+        L[ntp + i] = r64[u].y;
+        L[2 * ntp + i] = -r64[u].y;
+        L[3 * ntp + i] = -r64[u].x;
       }
-      __syncthreads();
-      // free: index 2 Pd - p + m; image: 2 Ps + 2 Pd - p - m', sign (-1)^(m' + Ps)
-      const bool img = pa.image != 0;
-      const bool neg = img && (((kl >> 1) + Ps) & 1);
-      const double* Lp = lds + tg_plane(rp, kp, neg) * ntp + kTabPadB;
-      int base[kTgMaxNt];
+    }
+  };
+  // ---- asynchronous copies: operator rows (reduced precision) of pair e
+  auto copyA = [&](int e, int buf) {
+    const TgPair pa = pairs[e];
+    const unsigned char* g;
+    int bytes;
+    if (PREC == BLK_F32) {
+      g = (const unsigned char*)((const float2*)olo + pa.tlo + (int64_t)p_lo * Ms8);
+      bytes = nrow * Ms8 * 8;
+    } else {
+      g = (const unsigned char*)((const __bf16*)olo + pa.tlo + (int64_t)(2 * p_lo) * K16);
+      bytes = 2 * nrow * K16 * 2;
+    }
+    unsigned char* L = Ab0 + buf * abuf;
+    for (int o = wave * 1024; o < bytes; o += 4096)
+      if (o + 16 * lane < bytes) copy16_to_lds(g + o + 16 * lane, L + o);
+  };
+  // source chunk c of pair e (rows of orders c CH .. c CH + CH - 1; zeros past Ms)
+  auto copyB = [&](int e, int c, int buf) {
+    const TgPair pa = pairs[e];
+    unsigned char* L = Bb0 + buf * BBUF;
+    if constexpr (PREC == BLK_F64) {
+      // CH rows of 64 complex doubles (1 KiB each), CH / 4 per wave
 #pragma unroll
-      for (int j = 0; j < kTgMaxNt; ++j)
-        base[j] = img ? 2 * Ps + 2 * Pd - pidx[j] - (kl >> 1) : 2 * Pd - pidx[j] + (kl >> 1);
-      const int step = img ? -2 : 2;
-      const int nks = (2 * Ms + 3) / 4;
-      const double* S = (const double*)(src + pa.cs * Rp + col) + kp;
-      const int64_t rs = 2 * (int64_t)Rp;  // doubles per source row
-      double b0 = (kl >> 1) < Ms ? S[(int64_t)(kl >> 1) * rs] : 0.0;
-      for (int ks = 0; ks < nks; ++ks) {
-        const int mn = 2 * (ks + 1) + (kl >> 1);
-        const double b1 = mn < Ms ? S[(int64_t)mn * rs] : 0.0;
+      for (int rr = 0; rr < CH / 4; ++rr) {
+        const int r = wave * (CH / 4) + rr, m = c * CH + r;
+        if (m < Ms)
+          copy16_to_lds(src + (pa.cs + m) * Rp + col0 + lane, L + r * 1024);
+        else
+          ((double2*)(L + r * 1024))[lane] = cmk(0.0, 0.0);
+      }
+    } else if constexpr (PREC == BLK_F32) {
+      // CH rows of 64 complex floats (512 bytes), two per copy, CH / 8 copies per wave
 #pragma unroll
-        for (int j = 0; j < kTgMaxNt; ++j) {
-          if (j < it.nt) {
-            const double a = Lp[base[j] + step * ks];
-            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[j], 0, 0, 0);
-          }
-        }
-        b0 = b1;
+      for (int rr = 0; rr < CH / 8; ++rr) {
+        const int blk = wave * (CH / 8) + rr;
+        const int r = 2 * blk + (lane >> 5), m = c * CH + r;
+        const float2* S = (const float2*)src_lo + (pa.cs + m) * Rp + col0 + 2 * (lane & 31);
+        if (m < Ms)
+          copy16_to_lds(S, L + blk * 1024);
+        else
+          ((float4*)(L + blk * 1024))[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     } else {
-      // scaled operator rows p_lo .. p_lo + nrow - 1 for this pair
-      const double2* T = tdata + pa.toff;
-      const double* sa = scale + it.lev * sstride;  // same level for source and target
-      const bool img = pa.image != 0;
-      if constexpr (PREC == BLK_F32) {
-        const int Ms2 = Ms + 1;  // even: k-steps of two orders
-        float* Or = (float*)lds;
-        float* Oi = Or + lds_rows * Ms2;
-        float* On = Oi + lds_rows * Ms2;
-        for (int e2 = tid; e2 < nrow * Ms2; e2 += BLK_THREADS) {
-          const int pl = e2 / Ms2, m = e2 - pl * Ms2;
-          const int p = p_lo + pl;
-          double2 v = cmk(0.0, 0.0);
-          if (m < Ms) {
-            const int pp = p - Pd, mm = m - Ps;
-            const int idx = img ? -mm - pp + Ps + Pd : mm - pp + Ps + Pd;
-            v = T[idx];
-            const double s = sa[mm < 0 ? -mm : mm] * sa[pp < 0 ? -pp : pp] * ((img && ((mm & 1) != 0)) ? -1.0 : 1.0);
-            v = cscale(v, s);
-          }
-          Or[e2] = (float)v.x;
-          Oi[e2] = (float)v.y;
-          On[e2] = -(float)v.y;
-        }
-        __syncthreads();
-        const int pl_sel = (rp == kp) ? 0 : (rp ? 1 : 2);
-        const float* Lp = (pl_sel == 0 ? Or : pl_sel == 1 ? Oi : On);
-        int rowoff[kTgMaxNt];
+      // 64 columns x CH orders of 4-byte complex bf16 (CH * 4 bytes per
+      // column, 1024 / (CH * 4) columns per copy), 16 columns per wave
+      constexpr int LPC = CH * 4 / 16;  // lanes per column
 #pragma unroll
-        for (int j = 0; j < kTgMaxNt; ++j) rowoff[j] = (pidx[j] - p_lo >= 0 ? pidx[j] - p_lo : 0) * Ms2 + (kl >> 1);
-        const int nks = Ms2 / 2;
-        const float* S = (const float*)src_lo + (pa.cs * Rp + col) * 2 + kp;
-        const int64_t rs = 2 * (int64_t)Rp;
-        float b0 = (kl >> 1) < Ms ? S[(int64_t)(kl >> 1) * rs] : 0.0f;
-        for (int ks = 0; ks < nks; ++ks) {
-          const int mn = 2 * (ks + 1) + (kl >> 1);
-          const float b1 = mn < Ms ? S[(int64_t)mn * rs] : 0.0f;
+      for (int rr = 0; rr < 16 * LPC / 64; ++rr) {
+        const int cc = wave * 16 + rr * (64 / LPC) + lane / LPC;
+        const __bf16* S =
+            (const __bf16*)src_lo + 2 * (pa.cs16 * Rp + (int64_t)(col0 + cc) * Ms16 + c * CH + 4 * (lane % LPC));
+        if (c * CH + 4 * (lane % LPC) < Ms16)
+          copy16_to_lds(S, L + (wave * 16 + rr * (64 / LPC)) * CH * 4);
+        else
+          ((float4*)(L + (wave * 16 + rr * (64 / LPC)) * CH * 4))[lane] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  };
+  // stage st = chunk c of pair e: the operator of pair e goes to buffer e & 1
+  // with its first chunk (issued while the previous pair's last chunk is
+  // contracted; that buffer was last read by the pair before)
+  auto issue = [&](int st) {
+    const int pi = st / nch, c = st - pi * nch;
+    if (PREC != BLK_F64 && c == 0) copyA(it.pbeg + pi, pi & 1);
+    copyB(it.pbeg + pi, c, st & 1);
+  };
+  if (nstage > 0) {
+    if (PREC == BLK_F64) {
+      fetchA64(it.pbeg);
+      storeA64(0);
+    }
+    issue(0);
+  }
+  for (int st = 0; st < nstage; ++st) {
+    const int pi = st / nch, c = st - pi * nch;
+    const int e = it.pbeg + pi;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk st (and older) have landed
+    __syncthreads();                // every wave's; and chunk st - 1 is no longer read
+    if (PREC == BLK_F64 && c == 0 && e + 1 < it.pend) fetchA64(e + 1);
+    if (st + 1 < nstage) issue(st + 1);
+    const TgPair pa = pairs[e];
+    const bool img = pa.image != 0;
+    const unsigned char* Bb = Bb0 + (st & 1) * BBUF;
+    const unsigned char* Ab = Ab0 + (pi & 1) * abuf;
+    if constexpr (PREC == BLK_F64) {
+      const bool neg = img && (((kl >> 1) + Ps) & 1);
+      const double* Lp = (const double*)Ab + tg_plane(rp, kp, neg) * ntp + kTabPadB;
+      const int step = img ? -2 : 2;
+      int base[NTM];
 #pragma unroll
-          for (int j = 0; j < kTgMaxNt; ++j) {
-            if (j < it.nt) {
-              const float a = Lp[rowoff[j] + 2 * ks];
-              acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b0, acc[j], 0, 0, 0);
-            }
-          }
-          b0 = b1;
-        }
-      } else {
-        // BF16: rows 2p + rp of the real embedding, k = 2m + kp, Ms16 orders
-        const int Ms16 = (Ms + 15) & ~15;
-        const int K = 2 * Ms16;
-        __bf16* A = (__bf16*)lds;  // [2 nrow][K]
-        for (int e2 = tid; e2 < nrow * Ms16; e2 += BLK_THREADS) {
-          const int pl = e2 / Ms16, m = e2 - pl * Ms16;
-          const int p = p_lo + pl;
-          double2 v = cmk(0.0, 0.0);
-          if (m < Ms) {
-            const int pp = p - Pd, mm = m - Ps;
-            const int idx = img ? -mm - pp + Ps + Pd : mm - pp + Ps + Pd;
-            v = T[idx];
-            const double s = sa[mm < 0 ? -mm : mm] * sa[pp < 0 ? -pp : pp] * ((img && ((mm & 1) != 0)) ? -1.0 : 1.0);
-            v = cscale(v, s);
-          }
-          __bf16* r0 = A + (int64_t)(2 * pl) * K + 2 * m;
-          __bf16* r1 = r0 + K;
-          r0[0] = (__bf16)(float)v.x;
-          r0[1] = (__bf16)(float)(-v.y);
-          r1[0] = (__bf16)(float)v.y;
-          r1[1] = (__bf16)(float)v.x;
-        }
-        __syncthreads();
-        int rowoff[kTgMaxNt];
+      for (int j = 0; j < NTM; ++j)
+        base[j] = (img ? 2 * Ps + 2 * Pd - pidx[j] - (kl >> 1) : 2 * Pd - pidx[j] + (kl >> 1)) + step * (c * CH / 2);
+      const double* Bl = (const double*)Bb + 2 * cl + kp;
+      const int kend = min(CH / 2, (Ms - c * CH + 1) / 2);  // k-steps holding orders below Ms
 #pragma unroll
-        for (int j = 0; j < kTgMaxNt; ++j) {
-          const int R = 16 * (it.rt0 + j) + (lane & 15);
-          const int rl = R - 2 * p_lo;
-          rowoff[j] = (j < it.nt && rl >= 0 && rl < 2 * nrow ? rl : 0) * K + 8 * kl;
-        }
-        const int nks = Ms16 / 16;
-        // B: four consecutive orders of one right-hand side (16 bytes); the
-        // source's BF16 rows are laid out [Rp][Ms16] from cs16 * Rp
-        const __bf16* Src = (const __bf16*)src_lo + 2 * (pa.cs16 * Rp + (int64_t)col * Ms16);
-        for (int ks = 0; ks < nks; ++ks) {
-          const bf8 bv = *(const bf8*)(Src + 2 * (16 * ks + 4 * kl));
+      for (int ks = 0; ks < CH / 2; ++ks) {
+        if (ks < kend) {
+          const double b = Bl[(2 * ks + (kl >> 1)) * 128];
 #pragma unroll
-          for (int j = 0; j < kTgMaxNt; ++j) {
-            if (j < it.nt) {
-              const bf8 av = *(const bf8*)(A + rowoff[j] + 32 * ks);
-              acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[j], 0, 0, 0);
-            }
-          }
+          for (int j = 0; j < NTM; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(Lp[base[j] + step * ks], b, acc[j], 0, 0, 0);
         }
       }
-      if constexpr (PREC != BLK_F64) {
+      if (c == nch - 1 && e + 1 < it.pend) storeA64((pi + 1) & 1);
+    } else if constexpr (PREC == BLK_F32) {
+      // A: row (p - p_lo), order m = c CH + 2 ks + kl / 2; the lane takes the
+      // real part (rp == kp) or the imaginary part, negated for rp = 0, kp = 1
+      const float* Af = (const float*)Ab + (rp == kp ? 0 : 1);
+      const float sg = (rp == 0 && kp == 1) ? -1.0f : 1.0f;
+      int aoff[NTM];
+#pragma unroll
+      for (int j = 0; j < NTM; ++j) aoff[j] = 2 * ((pidx[j] - p_lo > 0 ? pidx[j] - p_lo : 0) * Ms8 + c * CH + (kl >> 1));
+      const float* Bl = (const float*)Bb + 2 * cl + kp;
+      const int kend = min(CH / 2, (Ms - c * CH + 1) / 2);
+#pragma unroll
+      for (int ks = 0; ks < CH / 2; ++ks) {
+        if (ks < kend) {
+          const float b = Bl[(2 * ks + (kl >> 1)) * 128];
+#pragma unroll
+          for (int j = 0; j < NTM; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(sg * Af[aoff[j] + 4 * ks], b, acc[j], 0, 0, 0);
+        }
+      }
+    } else {
+      // A: embedded row R - 2 p_lo, k = 2 (c CH + 16 ks) + 8 kl; B: column cl,
+      // orders c CH + 16 ks + 4 kl .. + 3 (k-steps of 16 orders below Ms16)
+      int ro[NTM];
+#pragma unroll
+      for (int j = 0; j < NTM; ++j) {
+        const int R = 16 * (it.rt0 + j) + (lane & 15);
+        const int rl = R - 2 * p_lo;
+        ro[j] = (rl >= 0 && rl < 2 * nrow ? rl : 0) * K16 + 2 * c * CH + 8 * kl;
+      }
+      const int kend = min(CH / 16, (Ms16 - c * CH) / 16);
+#pragma unroll
+      for (int ks = 0; ks < CH / 16; ++ks) {
+        if (ks < kend) {
+          const bf8 b = *(const bf8*)(Bb + (cl * CH + 16 * ks + 4 * kl) * 4);
+#pragma unroll
+          for (int j = 0; j < NTM; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*(const bf8*)(Ab + 2 * (ro[j] + 32 * ks)), b, acc[j], 0, 0,
+                                                             0);
+        }
+      }
+    }
+    if constexpr (PREC != BLK_F64) {
+      if (c == nch - 1) {
 #pragma unroll
         for (int j = 0; j < NT64; ++j)
 #pragma unroll
@@ -477,18 +589,18 @@ __global__ void __launch_bounds__(BLK_THREADS) k_tgemm(int Rp, const TgItem* __r
   // store / add: FP64 rows R = 4 i + kl, FP32 rows R = 4 kl + i within a tile
   const double* st = PREC == BLK_F64 ? nullptr : scale + it.lev * sstride;
 #pragma unroll
-  for (int j = 0; j < kTgMaxNt; ++j) {
+  for (int j = 0; j < NTM; ++j) {
     if (j >= it.nt) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int R = 16 * (it.rt0 + j) + (PREC == BLK_F64 ? 4 * i + kl : 4 * kl + i);
       if (R >= 2 * Md) continue;
       double v;
-      if constexpr (PREC == BLK_F64) v = acc[j][i];
-      else v = acc64[j < NT64 ? j : 0][i];
-      if (PREC != BLK_F64) {
+      if constexpr (PREC == BLK_F64) {
+        v = acc[j][i];
+      } else {
         const int pp = (R >> 1) - Pd;
-        v /= st[pp < 0 ? -pp : pp];
+        v = acc64[j][i] / st[pp < 0 ? -pp : pp];
       }
       double* o = (double*)(dst + (it.ct + (R >> 1)) * Rp + col) + (R & 1);
       *o = add ? *o + v : v;
@@ -700,40 +812,74 @@ void launch_l2p_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leave
     hipLaunchKernelGGL(k_l2p_blk, dim3(nl, Rp / kBlkCols), dim3(BLK_THREADS), 0, s, tv, Rp, leaves, nl, voff, V, bb,
                        ub);
 }
-// LDS of a translation launch: the four Toeplitz planes (FP64), or the scaled
-// operator rows of an item of at most `rows` complex rows (FP32 planes,
-// BF16 real-embedded rows).
-size_t tgemm_lds_bytes(int prec, int Pmax_s, int Pmax_d, int rows) {
-  const int Ms = 2 * Pmax_s + 1;
-  if (prec == BLK_F64) return sizeof(double) * 4 * (size_t)tg_table_stride(2 * (Pmax_s + Pmax_d) + 1);
-  if (prec == BLK_F32) return sizeof(float) * 3 * (size_t)rows * (size_t)(Ms + 1);
-  const int Ms16 = (Ms + 15) & ~15;
-  return sizeof(__bf16) * 2 * (size_t)rows * (size_t)(2 * Ms16);
+// Bytes of one operator buffer for an item with `rows` complex rows (two
+// are used): the four Toeplitz planes (FP64), its FP32 rows of Ms8 complex
+// floats, or its BF16 embedded rows (2 rows x 2 Ms16 values); and the LDS of
+// a launch: two operator buffers and two source chunks.
+int tgemm_buf_elems(int prec, int Ps, int Pd, int rows) {
+  const int Ms = 2 * Ps + 1;
+  if (prec == BLK_F64) return 8 * 4 * tg_table_stride(2 * (Ps + Pd) + 1);
+  if (prec == BLK_F32) return 8 * rows * ((Ms + 7) & ~7);
+  return 2 * 2 * rows * 2 * ((Ms + 15) & ~15);
 }
-// Most row tiles of an item so that its operator rows fit the LDS budget.
+size_t tgemm_lds_bytes(int prec, int buf_bytes) {
+  const int bbuf = prec == BLK_F64 ? TgChunk<BLK_F64>::BYTES
+                                   : (prec == BLK_F32 ? TgChunk<BLK_F32>::BYTES : TgChunk<BLK_BF16>::BYTES);
+  return 2 * (size_t)((buf_bytes + 1023) & ~1023) + 2 * (size_t)bbuf;
+}
 int tgemm_max_nt(int prec, int Ps) {
   if (prec == BLK_F64) return kTgMaxNt;
-  const size_t budget = 96 * 1024;
   for (int nt = kTgMaxNt; nt > 1; --nt)
-    if (tgemm_lds_bytes(prec, Ps, Ps, 8 * nt) <= budget) return nt;
+    if (tgemm_lds_bytes(prec, tgemm_buf_elems(prec, Ps, Ps, 8 * nt)) <= 96 * 1024) return nt;
   return 1;
 }
-void launch_tgemm(hipStream_t s, int prec, int Rp, const TgItem* items, int nitems, int Pmax_s, int Pmax_d, int rows,
-                  const TgPair* pairs, const double2* tdata, const double2* src, const void* src_lo,
+// FP64 Toeplitz staging holds ntp <= 512 (P up to 125 for M2L); the
+// reduced-precision operator rows of one row tile must fit the LDS budget
+bool tgemm_supported(int prec, int Ps, int Pd) {
+  if (prec == BLK_F64) return tg_table_stride(2 * (Ps + Pd) + 1) <= TG_PF64 * BLK_THREADS;
+  return tgemm_lds_bytes(prec, tgemm_buf_elems(prec, Ps, Pd, 8)) <= 96 * 1024;
+}
+template <int PREC, int NTM>
+static void tgemm_one(hipStream_t s, dim3 grid, size_t lds, int Rp, const TgItem* items, int nitems, int be,
+                      const TgPair* pairs, const double2* tdata, const void* olo, const double2* src,
+                      const void* src_lo, const double* scale, int sstride, double2* dst, int add) {
+  hipLaunchKernelGGL((k_tgemm<PREC, NTM>), grid, dim3(BLK_THREADS), lds, s, Rp, items, nitems, pairs, tdata, olo, src,
+                     src_lo, scale, sstride, dst, add, (be + 1023) & ~1023);
+}
+template <int PREC>
+static void tgemm_prec(int ntm, hipStream_t s, dim3 grid, size_t lds, int Rp, const TgItem* items, int nitems, int be,
+                       const TgPair* pairs, const double2* tdata, const void* olo, const double2* src,
+                       const void* src_lo, const double* scale, int sstride, double2* dst, int add) {
+  if (ntm <= 2)
+    tgemm_one<PREC, 2>(s, grid, lds, Rp, items, nitems, be, pairs, tdata, olo, src, src_lo, scale, sstride, dst, add);
+  else if (ntm <= 4)
+    tgemm_one<PREC, 4>(s, grid, lds, Rp, items, nitems, be, pairs, tdata, olo, src, src_lo, scale, sstride, dst, add);
+  else
+    tgemm_one<PREC, 8>(s, grid, lds, Rp, items, nitems, be, pairs, tdata, olo, src, src_lo, scale, sstride, dst, add);
+}
+void launch_tgemm(hipStream_t s, int prec, int ntm, int Rp, const TgItem* items, int nitems, int buf_elems,
+                  const TgPair* pairs, const double2* tdata, const void* olo, const double2* src, const void* src_lo,
                   const double* scale, int sstride, double2* dst, int add) {
   if (nitems <= 0) return;
-  const size_t lds = tgemm_lds_bytes(prec, Pmax_s, Pmax_d, rows);
+  const size_t lds = tgemm_lds_bytes(prec, buf_elems);
   // a multiple of 8 blocks: block b takes item (b mod 8) * ceil(n / 8) + b / 8
   const dim3 grid((nitems + 7) / 8 * 8, Rp / kBlkCols);
   if (prec == BLK_F64)
-    hipLaunchKernelGGL(k_tgemm<BLK_F64>, grid, dim3(BLK_THREADS), lds, s, Rp, items, nitems, pairs, tdata, src, src_lo,
-                       scale, sstride, dst, add, rows);
+    tgemm_prec<BLK_F64>(ntm, s, grid, lds, Rp, items, nitems, buf_elems, pairs, tdata, olo, src, src_lo, scale, sstride,
+                        dst, add);
   else if (prec == BLK_F32)
-    hipLaunchKernelGGL(k_tgemm<BLK_F32>, grid, dim3(BLK_THREADS), lds, s, Rp, items, nitems, pairs, tdata, src, src_lo,
-                       scale, sstride, dst, add, rows);
+    tgemm_prec<BLK_F32>(ntm, s, grid, lds, Rp, items, nitems, buf_elems, pairs, tdata, olo, src, src_lo, scale, sstride,
+                        dst, add);
   else
-    hipLaunchKernelGGL(k_tgemm<BLK_BF16>, grid, dim3(BLK_THREADS), lds, s, Rp, items, nitems, pairs, tdata, src,
-                       src_lo, scale, sstride, dst, add, rows);
+    tgemm_prec<BLK_BF16>(ntm, s, grid, lds, Rp, items, nitems, buf_elems, pairs, tdata, olo, src, src_lo, scale,
+                         sstride, dst, add);
+}
+void launch_lo_tables(hipStream_t s, int prec, int ntab, const int64_t* toff, const int* P_of, const int* lev_of,
+                      const int* img_of, const int64_t* off, const double* scale, int sstride, const double2* tdata,
+                      void* out) {
+  if (ntab > 0)
+    hipLaunchKernelGGL(k_lo_tables, dim3(ntab), dim3(256), 0, s, prec, ntab, toff, P_of, lev_of, img_of, off, scale,
+                       sstride, tdata, out);
 }
 void launch_scale_blk(hipStream_t s, int prec, const TreeView& tv, int Rp, int b0, int b1, const double* scale,
                       int sstride, const int64_t* coff16, const double2* src, void* src_lo) {
@@ -766,8 +912,11 @@ void launch_p2p_blk(hipStream_t s, const TreeView& tv, int prec, int Rp, const B
 }
 
 hipError_t init_blocked_attributes() {
-  const void* fs[] = {(const void*)k_tgemm<BLK_F64>, (const void*)k_tgemm<BLK_F32>, (const void*)k_tgemm<BLK_BF16>,
-                      (const void*)k_p2m_blk};
+  const void* fs[] = {(const void*)k_tgemm<BLK_F64, 2>,  (const void*)k_tgemm<BLK_F64, 4>,
+                      (const void*)k_tgemm<BLK_F64, 8>,  (const void*)k_tgemm<BLK_F32, 2>,
+                      (const void*)k_tgemm<BLK_F32, 4>,  (const void*)k_tgemm<BLK_F32, 8>,
+                      (const void*)k_tgemm<BLK_BF16, 2>, (const void*)k_tgemm<BLK_BF16, 4>,
+                      (const void*)k_tgemm<BLK_BF16, 8>, (const void*)k_p2m_blk};
   for (const void* f : fs) {
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, f);

@@ -36,6 +36,7 @@ struct TgPair {
   int64_t cs;
   int64_t toff;
   int64_t cs16;  // BF16 rows: the source's offset in the 16-aligned order count
+  int64_t tlo;   // FP32 / BF16: offset of the table's scaled operator
   int32_t image;
   int32_t pad;
 };
@@ -68,18 +69,33 @@ void launch_p2m_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leave
 void launch_l2p_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, const int64_t* voff,
                      const double2* V, const double2* bb, double2* ub);
 // translations: dst rows of every item = (add ? dst : 0) + sum over its pairs
-// of the operator applied to the source rows. F64: tables from tdata (FP64).
-// F32 / BF16: the operator scaled by a(|m|) a(|p|) (scale[lev * sstride + |m|]),
-// applied to the scaled source rows src_lo (converted by launch_scale_blk),
-// accumulated in FP32, and the rows divided by a(|p|) of the target level
-// before they are stored or added in FP64.
-// rows: the most complex rows of an item of the launch (8 per row tile)
-void launch_tgemm(hipStream_t s, int prec, int Rp, const TgItem* items, int nitems, int Pmax_s, int Pmax_d, int rows,
-                  const TgPair* pairs, const double2* tdata, const double2* src, const void* src_lo,
+// of the operator applied to the source rows. F64: Toeplitz tables from
+// tdata. F32 / BF16: the pair's scaled operator a(|m|) a(|p|) T (from
+// launch_lo_tables, at pair.tlo in olo) applied to the scaled source rows
+// src_lo (launch_scale_blk), accumulated in FP32 per pair and in FP64 across
+// pairs, and the rows divided by a(|p|) of the target level before they are
+// stored or added in FP64. buf_elems: the largest operator buffer of an item
+// of the launch (tgemm_buf_elems).
+// ntm: the most row tiles of an item of the launch (2, 4 or 8: the register
+// allocation of the kernel variant)
+void launch_tgemm(hipStream_t s, int prec, int ntm, int Rp, const TgItem* items, int nitems, int buf_elems,
+                  const TgPair* pairs, const double2* tdata, const void* olo, const double2* src, const void* src_lo,
                   const double* scale, int sstride, double2* dst, int add);
-size_t tgemm_lds_bytes(int prec, int Pmax_s, int Pmax_d, int rows);
-// most row tiles per item whose reduced-precision operator rows fit the LDS
+// operator buffer of an item with `rows` complex rows (bytes), and the LDS of
+// a launch (two operator buffers and two source chunks)
+int tgemm_buf_elems(int prec, int Ps, int Pd, int rows);
+size_t tgemm_lds_bytes(int prec, int buf_bytes);
+// most row tiles per item whose reduced-precision operator rows fit the
+// staging registers and the LDS; whether a pair of orders can be staged at all
 int tgemm_max_nt(int prec, int Ps);
+bool tgemm_supported(int prec, int Ps, int Pd);
+// The scaled operators of multipole-to-local tables for the reduced
+// precisions (one block per table): table t at toff[t] in tdata (t[-2P]),
+// order P_of[t], level lev_of[t], image flag img_of[t]; written at off[t] in
+// out (FP32: rows [2P + 1][Ms8] float2; BF16: embedded rows [2(2P + 1)][2 Ms16]).
+void launch_lo_tables(hipStream_t s, int prec, int ntab, const int64_t* toff, const int* P_of, const int* lev_of,
+                      const int* img_of, const int64_t* off, const double* scale, int sstride, const double2* tdata,
+                      void* out);
 // src_lo rows = src rows / a_l(|m|) in FP32 (float2) or BF16, for the boxes
 // [b0, b1) (level by box); bf16 rows are laid out per box as [Rp][Ms16]
 // (orders fastest, 16-aligned, zero padded) at offset coff16[b] * Rp.

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -188,6 +189,7 @@ constexpr double kOrderSafety = HFMM_ORDER_SAFETY;
 // 2P+1 coefficients and the 4P+1 table entries in LDS
 constexpr int kMaxOrder = 255;
 constexpr int kScaleStride = kMaxOrder + 1;  // scale factors per level
+constexpr int kUpDownNt = 4;  // row tiles per item of the blocked M2M and L2L
 // Launch shaping: the CUs of the GPU (MI355X: 256), the LDS of one CU, and the
 // most dynamic LDS a translation block may take (the CU's less the kernel's
 // static offsets).
@@ -361,14 +363,23 @@ struct hfmm_plan_s {
   hfmm_info_t info{};
   // ---- right-hand-side-blocked pipeline (applies with many right-hand sides)
   struct TgGroup {
-    int first = 0, count = 0, Ps = 0, Pd = 0, rows = 8;
+    int first = 0, count = 0;
+    int buf = 1;  // largest operator buffer of an item (elements)
   };
   bool blk_ok = false;   // the plan can run the blocked pipeline
   int blk_prec_m2l = BLK_F64, blk_prec_p2p = BLK_F64;
   DevBuf<TgItem> tg_items;
   DevBuf<TgPair> tg_pairs;
   std::vector<TgGroup> m2m_tg, l2l_tg;  // per parent level
-  TgGroup m2l_tg;
+  // M2L item lists per target level for the candidate tile shapes (row
+  // tiles per item, the kernel variant's register allocation): one launch
+  // per level, its LDS sized for that level's orders; the autotuner picks a
+  // shape per level on the first blocked apply
+  static constexpr int kTileCands = 3;
+  static constexpr int kTileNt[kTileCands] = {2, 4, 8};
+  std::vector<TgGroup> m2l_tgl[kTileCands];  // [candidate][level]
+  std::vector<int> m2l_pick;                 // per level (-1: not tuned yet)
+  bool m2l_tuned = false;
   DevBuf<BpItem> bp_items;
   DevBuf<int2> bp_rng;
   int bp_cls_ptr[kH0Classes + 2] = {0};
@@ -382,6 +393,7 @@ struct hfmm_plan_s {
   int blk_Rp = 0;  // pass width the blocked workspace holds
   DevBuf<double2> qb, ub, ab, bb;
   DevBuf<char> alo;   // scaled reduced-precision multipoles
+  DevBuf<char> olo;   // scaled reduced-precision multipole-to-local operators
   DevBuf<float2> qlo; // FP32 strengths of the FP32 near field
   // the near field runs on a stream of its own, beside the far-field chain
   hipStream_t side = nullptr;
@@ -424,7 +436,7 @@ struct hfmm_plan_s {
     self_g.release(); self_dy.release();
     tg_items.release(); tg_pairs.release(); bp_items.release(); bp_rng.release(); vmat_off.release(); vmat.release();
     blk_scale.release(); coff16.release(); qb.release(); ub.release(); ab.release(); bb.release(); alo.release();
-    qlo.release();
+    qlo.release(); olo.release();
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
     if (ev_done) (void)hipEventDestroy(ev_done);
@@ -472,13 +484,19 @@ hfmm_status_t ensure_workspace(hfmm_plan_t pl, int nrhs) {
   return HFMM_OK;
 }
 
+// HFMM_LOG=1 in the environment: plan statistics and autotuning results on stderr.
+bool log_on() {
+  const char* env = std::getenv("HFMM_LOG");
+  return env && env[0] && env[0] != '0';
+}
+
 // The right-hand-side-blocked pipeline: used from kBlkMinRhs right-hand
 // sides on (HFMM_BLOCKED=0 in the environment turns it off, =1 uses it for
 // any count: diagnostics and tests). A pass holds a multiple of kBlkCols
 // right-hand sides, within kBlkBudget bytes of workspace per plan
 // (HFMM_BLK_RHS caps the pass width further).
 constexpr int kBlkMinRhs = 48;
-constexpr double kBlkBudget = 4096.0 * 1024 * 1024;
+constexpr double kBlkBudget = 8192.0 * 1024 * 1024;
 bool use_blocked(hfmm_plan_t pl, int nrhs) {
   if (!pl->blk_ok || pl->prof_on) return false;
   const char* env = std::getenv("HFMM_BLOCKED");
@@ -521,6 +539,56 @@ hfmm_status_t ensure_blk_workspace(hfmm_plan_t pl, int Rp, hipStream_t s) {
     if (pl->blk_prec_m2l == BLK_BF16) HIP_TRY(pl->alo.alloc(4 * (size_t)std::max<int64_t>(pl->ctot16, 1) * R));
     if (pl->blk_prec_p2p == BLK_F32) HIP_TRY(pl->qlo.alloc(n * R));
     pl->blk_Rp = Rp;
+  }
+  if (!pl->m2l_tuned) {
+    // M2L tile autotuner: per target level, each candidate item shape (row
+    // tiles per item) runs that level's multipole-to-local launch on cleared
+    // coefficients, once to warm up and once timed; the fastest is kept
+    const int64_t n_ab = std::max<int64_t>(pl->ctot, 1) * Rp;
+    launch_fill_zero(s, pl->ab.p, n_ab);
+    if (pl->blk_prec_m2l == BLK_F32) launch_fill_zero(s, (double2*)pl->alo.p, n_ab / 2);
+    if (pl->blk_prec_m2l == BLK_BF16) launch_fill_zero(s, (double2*)pl->alo.p, std::max<int64_t>(pl->ctot16, 1) * Rp / 4);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    pl->m2l_pick.assign(pl->nlev, hfmm_plan_s::kTileCands - 1);
+    float total = 0.0f, most = -1.0f;
+    for (int l = 0; l < pl->nlev; ++l) {
+      float best = 1e30f, ms_c[hfmm_plan_s::kTileCands] = {0, 0, 0};
+      for (int c = 0; c < hfmm_plan_s::kTileCands; ++c) {
+        const auto& g = pl->m2l_tgl[c][l];
+        if (g.count == 0) break;
+        for (int rep = 0; rep < 2; ++rep) {
+          HIP_TRY(hipEventRecord(e0, s));
+          launch_tgemm(s, pl->blk_prec_m2l, hfmm_plan_s::kTileNt[c], Rp, pl->tg_items.p + g.first, g.count, g.buf,
+                       pl->tg_pairs.p, pl->tdata.p, pl->olo.p, pl->ab.p, pl->alo.p, pl->blk_scale.p, kScaleStride,
+                       pl->bb.p, 0);
+          HIP_TRY(hipEventRecord(e1, s));
+          HIP_TRY(hipEventSynchronize(e1));
+          HIP_TRY(hipEventElapsedTime(&ms_c[c], e0, e1));
+        }
+        if (ms_c[c] < best) {
+          best = ms_c[c];
+          pl->m2l_pick[l] = c;
+        }
+      }
+      if (pl->m2l_tgl[0][l].count == 0) continue;
+      total += best;
+      if (best > most) {
+        most = best;
+        pl->info.m2l_tile = hfmm_plan_s::kTileNt[pl->m2l_pick[l]];
+      }
+      if (log_on())
+        std::fprintf(stderr, "[hfmm] M2L tile autotune, level %d (order %d, %d right-hand sides, precision %d): "
+                             "2 -> %.3f ms, 4 -> %.3f ms, 8 -> %.3f ms; picked %d\n",
+                     l, pl->P[l], Rp, pl->blk_prec_m2l, ms_c[0], ms_c[1], ms_c[2],
+                     hfmm_plan_s::kTileNt[pl->m2l_pick[l]]);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipGetLastError());
+    pl->m2l_tuned = true;
+    if (log_on()) std::fprintf(stderr, "[hfmm] M2L tuned: %.3f ms over all levels\n", total);
   }
   if (!pl->vmat_ready) {
     HIP_TRY(pl->vmat.alloc((size_t)std::max<int64_t>(pl->vmat_tot, 1)));
@@ -1435,6 +1503,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<int2> bp_rng_h;
   std::vector<int64_t> voff_h;
   std::vector<double> scale_h;
+  // reduced-precision operators of the multipole-to-local tables (made
+  // after the tables): per table its Toeplitz offset, order, level, image
+  // flag and the offset of its scaled operator
+  std::vector<int64_t> lo_toff, lo_off;
+  std::vector<int> lo_P, lo_lev, lo_img;
+  int64_t lo_tot = 0;
   {
     const int mprec = o.precision == HFMM_FP64 ? BLK_F64 : (o.precision == HFMM_FP32 ? BLK_F32 : BLK_BF16);
     pl->blk_prec_m2l = mprec;
@@ -1447,33 +1521,66 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     pl->ctot16 = c16;
     auto toff_of = [&](int id, int Ps, int Pd) { return tabs[id].off + tabs[id].half - (Ps + Pd); };
     // the items of one target: groups of at most ntmax row tiles sharing its pairs
-    auto add_target = [&](hfmm_plan_s::TgGroup& g, int t, int Ps, int Pd, int ntmax, int pbeg) {
+    auto add_target = [&](hfmm_plan_s::TgGroup& g, int prec, int t, int Ps, int Pd, int ntmax, int pbeg) {
       const int Md = 2 * Pd + 1, nrt = (2 * Md + 15) / 16;
       for (int rt = 0; rt < nrt; rt += ntmax) {
         const int nt = std::min(ntmax, nrt - rt);
         tg_items_h.push_back(TgItem{coff[t], pbeg, (int)tg_pairs_h.size(), rt, nt, Ps, Pd, B[t].level, 0});
-        g.rows = std::max(g.rows, 8 * nt);
+        g.buf = std::max(g.buf, tgemm_buf_elems(prec, Ps, Pd, std::min(8 * nt, Md - 8 * rt)));
       }
-      g.Ps = std::max(g.Ps, Ps);
-      g.Pd = std::max(g.Pd, Pd);
     };
     // M2L: every box of levels >= top is a target (without pairs its rows are cleared)
+    std::map<int, int64_t> lo_of;  // table id -> offset of its scaled operator
+    auto lo_offset = [&](int id, int l, int img) -> int64_t {
+      if (mprec == BLK_F64) return 0;
+      auto it = lo_of.find(id);
+      if (it != lo_of.end()) return it->second;
+      const int Pl = pl->P[l], M = 2 * Pl + 1, Ms16 = (M + 15) & ~15;
+      const int64_t o = lo_tot;
+      lo_tot += mprec == BLK_F32 ? (int64_t)M * ((M + 7) & ~7) : (int64_t)(2 * M) * (2 * Ms16);
+      lo_of[id] = o;
+      lo_toff.push_back(toff_of(id, Pl, Pl));
+      lo_P.push_back(Pl);
+      lo_lev.push_back(l);
+      lo_img.push_back(img);
+      lo_off.push_back(o);
+      return o;
+    };
     std::vector<std::vector<std::pair<int, int>>> m2l_of(nb);  // (pair index, image)
     for (size_t i = 0; i < fv.size(); ++i) m2l_of[fv[i].t].push_back({(int)i, 0});
     for (size_t i = 0; i < iv.size(); ++i) m2l_of[iv[i].t].push_back({(int)i, 1});
-    pl->m2l_tg = hfmm_plan_s::TgGroup{};
-    pl->m2l_tg.first = (int)tg_items_h.size();
+    // the pairs of every target once; its items for each candidate tile shape
+    std::vector<int> m2l_pbeg(nb, 0), m2l_pend(nb, 0);
     for (int t = pl->lev_begin[pl->top]; t < nb; ++t) {
       const int Pl = pl->P[B[t].level];
-      const int pbeg = (int)tg_pairs_h.size();
+      m2l_pbeg[t] = (int)tg_pairs_h.size();
       for (auto& pr : m2l_of[t]) {
         const int src = pr.second ? iv[pr.first].s : fv[pr.first].s;
         const int id = pr.second ? iv_tab[pr.first] : fv_tab[pr.first];
-        tg_pairs_h.push_back(TgPair{coff[src], toff_of(id, Pl, Pl), coff16_h[src], pr.second, 0});
+        tg_pairs_h.push_back(
+            TgPair{coff[src], toff_of(id, Pl, Pl), coff16_h[src], lo_offset(id, B[t].level, pr.second), pr.second, 0});
       }
-      add_target(pl->m2l_tg, t, Pl, Pl, tgemm_max_nt(mprec, Pl), pbeg);
+      m2l_pend[t] = (int)tg_pairs_h.size();
     }
-    pl->m2l_tg.count = (int)tg_items_h.size() - pl->m2l_tg.first;
+    for (int c = 0; c < hfmm_plan_s::kTileCands; ++c) {
+      pl->m2l_tgl[c].assign(pl->nlev, hfmm_plan_s::TgGroup{});
+      for (int l = pl->top; l < pl->nlev; ++l) {
+        auto& g = pl->m2l_tgl[c][l];
+        g.first = (int)tg_items_h.size();
+        const int Pl = pl->P[l];
+        const int Md = 2 * Pl + 1, nrt = (2 * Md + 15) / 16;
+        const int ntmax = std::min(hfmm_plan_s::kTileNt[c], tgemm_max_nt(mprec, Pl));
+        const int tend = l + 1 < pl->nlev ? pl->lev_begin[l + 1] : nb;
+        for (int t = pl->lev_begin[l]; t < tend; ++t) {
+          for (int rt = 0; rt < nrt; rt += ntmax) {
+            const int nt = std::min(ntmax, nrt - rt);
+            tg_items_h.push_back(TgItem{coff[t], m2l_pbeg[t], m2l_pend[t], rt, nt, Pl, Pl, l, 0});
+            g.buf = std::max(g.buf, tgemm_buf_elems(mprec, Pl, Pl, std::min(8 * nt, Md - 8 * rt)));
+          }
+        }
+        g.count = (int)tg_items_h.size() - g.first;
+      }
+    }
     // M2M (children to parent) and L2L (parent to child) per parent level
     pl->m2m_tg.assign(pl->nlev, hfmm_plan_s::TgGroup{});
     pl->l2l_tg.assign(pl->nlev, hfmm_plan_s::TgGroup{});
@@ -1485,17 +1592,17 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         const int pbeg = (int)tg_pairs_h.size();
         for (int q = 0; q < 4; ++q) {
           const int c = B[t].child[q];
-          if (c >= 0) tg_pairs_h.push_back(TgPair{coff[c], pl->m2m_q4[l].v[q], 0, 0, 0});
+          if (c >= 0) tg_pairs_h.push_back(TgPair{coff[c], pl->m2m_q4[l].v[q], 0, 0, 0, 0});
         }
-        add_target(gu, t, pl->P[l + 1], pl->P[l], kTgMaxNt, pbeg);
+        add_target(gu, BLK_F64, t, pl->P[l + 1], pl->P[l], kUpDownNt, pbeg);
       }
       gu.count = (int)tg_items_h.size() - gu.first;
       auto& gd = pl->l2l_tg[l];
       gd.first = (int)tg_items_h.size();
       for (int c = pl->lev_begin[l + 1]; c < pl->lev_begin[l + 2]; ++c) {
         const int pbeg = (int)tg_pairs_h.size();
-        tg_pairs_h.push_back(TgPair{coff[B[c].parent], pl->l2l_q4[l].v[B[c].quad], 0, 0, 0});
-        add_target(gd, c, pl->P[l], pl->P[l + 1], kTgMaxNt, pbeg);
+        tg_pairs_h.push_back(TgPair{coff[B[c].parent], pl->l2l_q4[l].v[B[c].quad], 0, 0, 0, 0});
+        add_target(gd, BLK_F64, c, pl->P[l], pl->P[l + 1], kUpDownNt, pbeg);
       }
       gd.count = (int)tg_items_h.size() - gd.first;
     }
@@ -1539,7 +1646,14 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         scale_h[(size_t)l * kScaleStride + nn] = std::max(a, 1e-250);
       }
     }
-    pl->blk_ok = iu.empty() && pl->leaf_pmax <= kBlkLeafPmax && !o.deterministic;
+    bool staged = true;  // every translation's operator fits the staging of the kernel
+    for (int l = pl->top; l < pl->nlev; ++l) {
+      staged = staged && tgemm_supported(mprec, pl->P[l], pl->P[l]);
+      if (l + 1 < pl->nlev)
+        staged = staged && tgemm_supported(BLK_F64, pl->P[l + 1], pl->P[l]) &&
+                 tgemm_supported(BLK_F64, pl->P[l], pl->P[l + 1]);
+    }
+    pl->blk_ok = iu.empty() && pl->leaf_pmax <= kBlkLeafPmax && staged && !o.deterministic;
   }
 
   // ---- near-interface rule (one rule covering every direct image pair)
@@ -1714,11 +1828,27 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
                        d_cpanels.p, d_imr.p, d_glx.p, d_glw.p, pl->tdata.p);
     e = hipGetLastError();
   }
+  DevBuf<int64_t> d_lotoff, d_looff;
+  DevBuf<int> d_loP, d_lolev, d_loimg;
+  if (e == hipSuccess && !lo_off.empty()) {
+    e = pl->olo.alloc((size_t)lo_tot * (pl->blk_prec_m2l == BLK_F32 ? 8 : 2));
+    if (e == hipSuccess) e = d_lotoff.upload(lo_toff, stream);
+    if (e == hipSuccess) e = d_looff.upload(lo_off, stream);
+    if (e == hipSuccess) e = d_loP.upload(lo_P, stream);
+    if (e == hipSuccess) e = d_lolev.upload(lo_lev, stream);
+    if (e == hipSuccess) e = d_loimg.upload(lo_img, stream);
+    if (e == hipSuccess) {
+      launch_lo_tables(stream, pl->blk_prec_m2l, (int)lo_off.size(), d_lotoff.p, d_loP.p, d_lolev.p, d_loimg.p,
+                       d_looff.p, pl->blk_scale.p, kScaleStride, pl->tdata.p, pl->olo.p);
+      e = hipGetLastError();
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   d_fhdx.release(); d_fhdy.release(); d_fbdx.release(); d_fbdy.release(); d_cX.release(); d_cY.release();
   d_cdip.release(); d_csend.release(); d_glx.release(); d_glw.release(); d_fhref.release(); d_fbsgn.release();
   d_fbref.release(); d_cpbeg.release(); d_imgref.release(); d_cpanels.release(); d_fhr.release();
   d_fbr.release(); d_imr.release(); d_scc.release(); d_scky.release();
+  d_lotoff.release(); d_looff.release(); d_loP.release(); d_lolev.release(); d_loimg.release();
   if (e != hipSuccess) {
     fail(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
          std::string("plan upload/tables: ") + hipGetErrorString(e));
@@ -1965,10 +2095,10 @@ hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrh
   const TreeView tv = pl->view(Rp);
   const int lb2 = pl->leaf_lev[std::min(2, pl->nlev)], nl2 = pl->nleaves - lb2;
   const int64_t n = pl->n;
-  auto tg = [&](const hfmm_plan_s::TgGroup& g, int prec, const double2* src, const void* src_lo, double2* dst,
-                int add) {
-    launch_tgemm(s, prec, Rp, pl->tg_items.p + g.first, g.count, g.Ps, g.Pd, g.rows, pl->tg_pairs.p, pl->tdata.p, src,
-                 src_lo, pl->blk_scale.p, kScaleStride, dst, add);
+  auto tg = [&](const hfmm_plan_s::TgGroup& g, int prec, int ntm, const double2* src, const void* src_lo,
+                double2* dst, int add) {
+    launch_tgemm(s, prec, ntm, Rp, pl->tg_items.p + g.first, g.count, g.buf, pl->tg_pairs.p, pl->tdata.p,
+                 pl->olo.p, src, src_lo, pl->blk_scale.p, kScaleStride, dst, add);
   };
   for (int r0 = 0; r0 < nrhs; r0 += Rp) {
     const int nc = std::min(Rp, nrhs - r0);
@@ -1978,12 +2108,15 @@ hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrh
     if (pl->blk_prec_p2p == BLK_F32) launch_to_f32(s, n * Rp, pl->qb.p, pl->qlo.p);
     launch_fill_zero(s, pl->ub.p, n * Rp);
     launch_p2m_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->leaf_pmax, pl->vmat_off.p, pl->vmat.p, pl->qb.p, pl->ab.p);
-    for (int l = pl->nlev - 2; l >= pl->top; --l) tg(pl->m2m_tg[l], BLK_F64, pl->ab.p, nullptr, pl->ab.p, 0);
+    for (int l = pl->nlev - 2; l >= pl->top; --l) tg(pl->m2m_tg[l], BLK_F64, kUpDownNt, pl->ab.p, nullptr, pl->ab.p, 0);
     if (pl->blk_prec_m2l != BLK_F64)
       launch_scale_blk(s, pl->blk_prec_m2l, tv, Rp, pl->lev_begin[pl->top], (int)pl->boxes.size(), pl->blk_scale.p,
                        kScaleStride, pl->coff16.p, pl->ab.p, pl->alo.p);
-    tg(pl->m2l_tg, pl->blk_prec_m2l, pl->ab.p, pl->alo.p, pl->bb.p, 0);
-    for (int l = pl->top; l + 1 < pl->nlev; ++l) tg(pl->l2l_tg[l], BLK_F64, pl->bb.p, nullptr, pl->bb.p, 1);
+    for (int l = pl->top; l < pl->nlev; ++l) {
+      const int c = pl->m2l_pick[l];
+      tg(pl->m2l_tgl[c][l], pl->blk_prec_m2l, hfmm_plan_s::kTileNt[c], pl->ab.p, pl->alo.p, pl->bb.p, 0);
+    }
+    for (int l = pl->top; l + 1 < pl->nlev; ++l) tg(pl->l2l_tg[l], BLK_F64, kUpDownNt, pl->bb.p, nullptr, pl->bb.p, 1);
     launch_l2p_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->vmat_off.p, pl->vmat.p, pl->bb.p, pl->ub.p);
     launch_p2p_blk(s, tv, pl->blk_prec_p2p, Rp, pl->bp_items.p, pl->bp_cls_ptr, pl->bp_rng.p, pl->qb.p, pl->qlo.p,
                    pl->ub.p);
