@@ -647,14 +647,18 @@ __global__ void k_scale_blk(TreeView tv, int Rp, int b0, const double* __restric
 
 // ------------------------------------------------------------------ direct pairs
 // ub[i][r] += (i/4) sum_j H0^(1)(k |x_i - x_j|) qb[j][r] (i != j) for up to 16
-// targets of an item against its source ranges. A block takes every right-
-// hand side of the pass (wave w: column tiles w, w + 4, ... of 16), so each
-// H0 tile is evaluated once: 16 targets x 64 sources per chunk, four
-// evaluations per thread, staged in LDS as planes (Re G, Im G, -Im G) and
-// applied on the matrix cores (FP64, or FP32 with the FP32 series and
-// strengths).
-constexpr int BP_SC = 64;  // sources per chunk
-constexpr int BP_MAX_CTW = 4;  // column tiles per wave (256 right-hand sides per block)
+// targets of an item against its source ranges, 64 right-hand sides per
+// block (wave w: the 16 columns 16 w ..; grid y: the pass's 64-column groups).
+// The sources go in chunks of 32: every thread evaluates two H0 values of
+// the 16 x 32 tile (Horner chains interleaved), stored in LDS as the planes
+// Re G and Im G (rows padded so that the MFMA operand reads of one wave fall
+// in distinct banks); the tile is applied on the matrix cores as the real
+// embedding [[Re, -Im], [Im, Re]] (FP64, or FP32 with the FP32 series and
+// strengths). The strengths of the next chunk are loaded into registers
+// before the current chunk's contraction, so their latency hides behind it.
+constexpr int BP_SC = 32;                 // sources per chunk
+constexpr int BP_GS = 34;                 // LDS row stride of a G plane (elements)
+constexpr int BP_GP = 16 * BP_GS + 16;    // LDS plane stride (elements)
 
 template <int PREC, int CLS>
 __global__ void __launch_bounds__(BLK_THREADS) k_p2p_blk(TreeView tv, int Rp, const BpItem* __restrict__ items,
@@ -666,120 +670,123 @@ __global__ void __launch_bounds__(BLK_THREADS) k_p2p_blk(TreeView tv, int Rp, co
   constexpr int CL = CLS < kH0Classes ? CLS : kH0Classes - 1;
   constexpr int M = PREC == BLK_F64 ? kH0ClassTerms[CL] : kH0ClassTermsF32[CL];
   constexpr bool LARGE = CLS >= kH0Classes;
-  __shared__ T s_g[3][16][BP_SC];
+  constexpr int NKS = BP_SC / 2;  // k-steps per chunk (two sources each)
+  __shared__ T s_g[2 * BP_GP];
   __shared__ double2 s_ln[1 << kLogTabBits];
-  __shared__ double2 s_xs[BP_SC];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (PREC == BLK_F64)
     for (int l = tid; l < (1 << kLogTabBits); l += BLK_THREADS) s_ln[l] = cmk(kLogTab[l][0], kLogTab[l][1]);
+  __syncthreads();
   const int per_xcd = (nitems + 7) / 8;
   const int it_id = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (it_id >= nitems) return;
   const BpItem it = items[it_id];
   const int kl = lane >> 4, rp = lane & 1, kp = kl & 1;
-  const int plane = (rp == kp) ? 0 : (rp ? 1 : 2);
-  const int c0 = blockIdx.y * (4 * 16 * BP_MAX_CTW);  // first column of this block
-  const int ncol = min(Rp - c0, 4 * 16 * BP_MAX_CTW);
-  const int ctw = (ncol / 16 + 3) / 4;  // column tiles per wave
-  acc_t acc[2][BP_MAX_CTW];
+  // A operand: row R = 16 a + (lane & 15) (target R / 2, part rp), k = 4 ks + kl
+  // (source 2 ks + kl / 2, part kp): Re G if rp == kp, else +-Im G
+  const T* Gp = s_g + (rp == kp ? 0 : BP_GP) + (kl >> 1);
+  const T sg = (rp == 0 && kp == 1) ? (T)-1 : (T)1;
+  const int col = blockIdx.y * kBlkCols + wave * 16 + (lane & 15);  // this lane's right-hand side
+  acc_t acc[2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int c = 0; c < BP_MAX_CTW; ++c)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) acc[a][c][i] = 0;
-  // evaluation role: target tt, sources ss + 16 u
+    for (int i = 0; i < 4; ++i) acc[a][i] = 0;
+  // evaluation role: target tt, sources ss and ss + 16 of the chunk
   const int tt = tid >> 4, ss = tid & 15;
   const bool tvalid = tt < it.nt;
   const double2 xt = tvalid ? tv.pts[it.t0 + tt] : cmk(0.0, 0.0);
   const T qk2 = (T)(0.25 * tv.k * tv.k);
-  for (int e = it.rbeg; e < it.rend; ++e) {
-    const int2 sr = rng[e];
-    for (int j0 = sr.x; j0 < sr.y; j0 += BP_SC) {
-      const int cnt = min(BP_SC, sr.y - j0);
-      __syncthreads();
-      if (tid < BP_SC) s_xs[tid] = tid < cnt ? tv.pts[j0 + tid] : cmk(0.0, 0.0);
-      __syncthreads();
-      T z[4], hr[4], hi[4];
-      bool use[4];
+  // the chunk sequence: (range e, first source j0)
+  auto advance = [&](int& e, int& j0) {
+    j0 += BP_SC;
+    if (j0 >= rng[e].y) {
+      ++e;
+      if (e < it.rend) j0 = rng[e].x;
+    }
+  };
+  // branch-free: sources past the chunk read the item's first target and are zeroed
+  auto load_b = [&](int e, int j0, T (&b)[NKS]) {
+    const int cnt = e < it.rend ? rng[e].y - j0 : 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int sl = ss + 16 * u;
-        use[u] = tvalid && sl < cnt && (j0 + sl) != (it.t0 + tt);
-        const double2 xs = s_xs[sl];
-        const T dx = (T)(xt.x - xs.x), dy = (T)(xt.y - xs.y);
-        z[u] = use[u] ? qk2 * (dx * dx + dy * dy) : (T)1.0;
-      }
-      hankel0_x4<T, M, LARGE>(z, hr, hi, s_ln);
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int sl = 2 * ks + (kl >> 1);
+      const int js = sl < cnt ? j0 + sl : it.t0;
+      T v;
+      if constexpr (PREC == BLK_F64)
+        v = ((const double*)(qb + (int64_t)js * Rp + col))[kp];
+      else
+        v = ((const float*)((const float2*)qb_lo + (int64_t)js * Rp + col))[kp];
+      b[ks] = sl < cnt ? v : (T)0;
+    }
+  };
+  int e = it.rbeg, j0 = e < it.rend ? rng[e].x : 0;
+  T bq[NKS];
+  load_b(e, j0, bq);
+  while (e < it.rend) {
+    const int cnt = min(BP_SC, rng[e].y - j0);
+    T z[2], hr[2], hi[2];
+    bool use[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int sl = ss + 16 * u;
-        const T gr = use[u] ? hr[u] : (T)0, gi = use[u] ? hi[u] : (T)0;
-        s_g[0][tt][sl] = gr;
-        s_g[1][tt][sl] = gi;
-        s_g[2][tt][sl] = -gi;
-      }
-      __syncthreads();
-      const T* G = &s_g[plane][0][0];
-      const int nks = (2 * cnt + 3) / 4;
-      for (int ks = 0; ks < nks; ++ks) {
-        const int sl = 2 * ks + (kl >> 1);
-        T bq[BP_MAX_CTW];
+    for (int u = 0; u < 2; ++u) {
+      const int sl = ss + 16 * u;
+      use[u] = tvalid && sl < cnt && (j0 + sl) != (it.t0 + tt);
+      const double2 xs = tv.pts[sl < cnt ? j0 + sl : it.t0];
+      const T dx = (T)(xt.x - xs.x), dy = (T)(xt.y - xs.y);
+      z[u] = use[u] ? qk2 * (dx * dx + dy * dy) : (T)1.0;
+    }
+    hankel0_x4<T, M, LARGE, 2>(z, hr, hi, s_ln);
+    __syncthreads();  // the previous chunk's operand reads are done
 #pragma unroll
-        for (int c = 0; c < BP_MAX_CTW; ++c) {
-          const int cc = c0 + 16 * (wave + 4 * c) + (lane & 15);
-          bq[c] = 0;
-          if (c < ctw && sl < cnt) {
-            if (PREC == BLK_F64)
-              bq[c] = ((const double*)(qb + (int64_t)(j0 + sl) * Rp + cc))[kp];
-            else
-              bq[c] = ((const float*)((const float2*)qb_lo + (int64_t)(j0 + sl) * Rp + cc))[kp];
-          }
-        }
+    for (int u = 0; u < 2; ++u) {
+      const int sl = ss + 16 * u;
+      s_g[tt * BP_GS + sl] = use[u] ? hr[u] : (T)0;
+      s_g[BP_GP + tt * BP_GS + sl] = use[u] ? hi[u] : (T)0;
+    }
+    __syncthreads();
+    int en = e, jn = j0;
+    advance(en, jn);
+    T bn[NKS];
+    load_b(en, jn, bn);
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int R = 16 * a + (lane & 15);
-          const T av = G[(R >> 1) * BP_SC + (sl < BP_SC ? sl : 0)];
+    for (int ks = 0; ks < NKS; ++ks) {
 #pragma unroll
-          for (int c = 0; c < BP_MAX_CTW; ++c) {
-            if (c < ctw) {
-              if constexpr (PREC == BLK_F64)
-                acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bq[c], acc[a][c], 0, 0, 0);
-              else
-                acc[a][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bq[c], acc[a][c], 0, 0, 0);
-            }
-          }
-        }
+      for (int a = 0; a < 2; ++a) {
+        const T av = sg * Gp[(8 * a + ((lane & 15) >> 1)) * BP_GS + 2 * ks];
+        if constexpr (PREC == BLK_F64)
+          acc[a] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bq[ks], acc[a], 0, 0, 0);
+        else
+          acc[a] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bq[ks], acc[a], 0, 0, 0);
       }
     }
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) bq[ks] = bn[ks];
+    e = en;
+    j0 = jn;
   }
   // ub += (i/4) acc: the real row takes -Im / 4, the imaginary row Re / 4;
   // the partner row of R sits in the lane 16 apart (FP64) or in the
   // neighbouring register (FP32)
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 2; ++a) {
 #pragma unroll
-    for (int c = 0; c < BP_MAX_CTW; ++c) {
-      if (c >= ctw) continue;
-      const int cc = c0 + 16 * (wave + 4 * c) + (lane & 15);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int R;
-        double mine = (double)acc[a][c][i], other;
-        if (PREC == BLK_F64) {
-          R = 16 * a + 4 * i + kl;
-          other = __shfl_xor(mine, 16, WAVE);
-        } else {
-          R = 16 * a + 4 * kl + i;
-          other = (double)acc[a][c][i ^ 1];
-        }
-        const int t = R >> 1;
-        if (t < it.nt) {
-          double* o = (double*)(ub + (int64_t)(it.t0 + t) * Rp + cc) + (R & 1);
-          *o += (R & 1) ? 0.25 * other : -0.25 * other;
-        }
+    for (int i = 0; i < 4; ++i) {
+      int R;
+      double mine = (double)acc[a][i], other;
+      if (PREC == BLK_F64) {
+        R = 16 * a + 4 * i + kl;
+        other = __shfl_xor(mine, 16, WAVE);
+      } else {
+        R = 16 * a + 4 * kl + i;
+        other = (double)acc[a][i ^ 1];
+      }
+      const int t = R >> 1;
+      if (t < it.nt) {
+        double* o = (double*)(ub + (int64_t)(it.t0 + t) * Rp + col) + (R & 1);
+        *o += (R & 1) ? 0.25 * other : -0.25 * other;
       }
     }
+  }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -895,8 +902,7 @@ template <int PREC, int CLS>
 static void p2p_blk_class(hipStream_t s, const TreeView& tv, int Rp, const BpItem* items, int ni, const int2* rng,
                           const double2* qb, const void* qb_lo, double2* ub) {
   if (ni <= 0) return;
-  const int ngrp = (Rp + 4 * 16 * BP_MAX_CTW - 1) / (4 * 16 * BP_MAX_CTW);
-  hipLaunchKernelGGL((k_p2p_blk<PREC, CLS>), dim3((ni + 7) / 8 * 8, ngrp), dim3(BLK_THREADS), 0, s, tv, Rp, items, ni,
+  hipLaunchKernelGGL((k_p2p_blk<PREC, CLS>), dim3((ni + 7) / 8 * 8, Rp / kBlkCols), dim3(BLK_THREADS), 0, s, tv, Rp, items, ni,
                      rng, qb, qb_lo, ub);
 }
 void launch_p2p_blk(hipStream_t s, const TreeView& tv, int prec, int Rp, const BpItem* items, const int* cls_ptr,

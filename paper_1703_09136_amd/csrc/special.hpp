@@ -322,25 +322,25 @@ __device__ inline double log_tab(double z, const double2* tab) {
   return fma(de, ln2_hi, fma(de, ln2_lo, t.y) + p);
 }
 
-// Four values of H_0^(1) at once from z_u = x_u^2/4, in the precision T,
-// by the ascending series with M terms and the four Horner chains
+// NV values (four by default) of H_0^(1) at once from z_u = x_u^2/4, in the
+// precision T, by the ascending series with M terms and the NV Horner chains
 // interleaved. M is chosen by the caller from a bound on z: the first dropped
 // term max(|c_M|, |d_M|) z^M stays below the precision's half-ulp for
 // z <= the class bound (from the closed forms of c_M and d_M). With LARGE,
 // entries with z > 9 (x > 6) take the FP64 large-argument form. In FP64 the
 // logarithm takes the bin table ltab (LDS).
-template <typename T, int M, bool LARGE>
-__device__ inline void hankel0_x4(const T z[4], T hr[4], T hi[4], const double2* ltab) {
-  T j[4], s[4];
+template <typename T, int M, bool LARGE, int NV = 4>
+__device__ inline void hankel0_x4(const T z[NV], T hr[NV], T hi[NV], const double2* ltab) {
+  T j[NV], s[NV];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < NV; ++u) {
     j[u] = (T)kH0.c[M - 1];
     s[u] = (T)kH0.d[M - 1];
   }
 #pragma unroll
   for (int m = M - 2; m >= 0; --m) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < NV; ++u) {
       j[u] = fma_uniform(j[u], z[u], (T)kH0.c[m]);
       s[u] = fma_uniform(s[u], z[u], (T)kH0.d[m]);
     }
@@ -348,7 +348,7 @@ __device__ inline void hankel0_x4(const T z[4], T hr[4], T hi[4], const double2*
   const T two_over_pi = (T)0.63661977236758134308;
   const T euler = (T)0.57721566490153286061;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < NV; ++u) {
     if (!LARGE || z[u] <= (T)9.0) {
       hr[u] = j[u];
       T lz;
