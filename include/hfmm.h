@@ -116,9 +116,19 @@ typedef struct {
                                with up to max_nrhs right-hand sides allocate
                                nothing */
   int32_t deterministic;    /* 0 (default); 1: bitwise reproducible results
-                               from run to run (stages in sequence on the
-                               caller's stream, every output element summed in
-                               a fixed order; slower) */
+                               from run to run. hfmm_apply and
+                               hfmm_apply_adjoint then run the right-hand-
+                               side-blocked pipeline for any count (stages in
+                               sequence on the caller's stream, no atomic
+                               additions, every output element summed in a
+                               fixed order, a fixed M2L tile shape): slower
+                               for few right-hand sides, each pass being 64
+                               columns wide. hfmm_plan fails with
+                               HFMM_ERR_UNSUPPORTED where that pipeline
+                               cannot run (near-interface quadrature pairs, or
+                               a leaf expansion order above 40); coordinate
+                               gradients and hfmm_apply_noalloc return
+                               HFMM_ERR_UNSUPPORTED */
   int32_t order;            /* 0 (default): expansion order per level from
                                tol; > 0: this order at every level (the
                                paper's fixed-p experiments), at most 255 */

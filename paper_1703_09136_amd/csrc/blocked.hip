@@ -33,22 +33,25 @@ __device__ __noinline__ double2 hankel0_large_call(double x) { return hankel0_la
 
 // ------------------------------------------------------------------ layout changes
 __global__ void k_gather_blk(int n, int nc, int Rp, const int* __restrict__ perm, const double2* __restrict__ q,
-                             double2* __restrict__ qb) {
+                             double2* __restrict__ qb, int conj) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * Rp) return;
   const int j = (int)(idx / Rp), r = (int)(idx % Rp);
-  qb[idx] = r < nc ? q[(int64_t)r * n + perm[j]] : cmk(0.0, 0.0);
+  double2 v = r < nc ? q[(int64_t)r * n + perm[j]] : cmk(0.0, 0.0);
+  if (conj) v.y = -v.y;
+  qb[idx] = v;
 }
 
 __global__ void k_scatter_blk(int n, int nc, int Rp, const int* __restrict__ perm, const double2* __restrict__ ub,
                               double2* __restrict__ u, const double2* __restrict__ diag,
-                              const double2* __restrict__ qb) {
+                              const double2* __restrict__ qb, int conj) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)n * Rp) return;
   const int j = (int)(idx / Rp), r = (int)(idx % Rp);
   if (r >= nc) return;
   double2 v = ub[idx];
   if (diag) v = csub(v, cmul(diag[j], qb[idx]));
+  if (conj) v.y = -v.y;
   u[(int64_t)r * n + perm[j]] = v;
 }
 
@@ -792,13 +795,14 @@ __global__ void __launch_bounds__(BLK_THREADS) k_p2p_blk(TreeView tv, int Rp, co
 // ------------------------------------------------------------------ launchers
 static inline int nblk(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
-void launch_gather_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* q, double2* qb) {
-  hipLaunchKernelGGL(k_gather_blk, dim3(nblk((int64_t)n * Rp, 256)), dim3(256), 0, s, n, nc, Rp, perm, q, qb);
+void launch_gather_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* q, double2* qb,
+                       int conj) {
+  hipLaunchKernelGGL(k_gather_blk, dim3(nblk((int64_t)n * Rp, 256)), dim3(256), 0, s, n, nc, Rp, perm, q, qb, conj);
 }
 void launch_scatter_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* ub, double2* u,
-                        const double2* diag, const double2* qb) {
+                        const double2* diag, const double2* qb, int conj) {
   hipLaunchKernelGGL(k_scatter_blk, dim3(nblk((int64_t)n * Rp, 256)), dim3(256), 0, s, n, nc, Rp, perm, ub, u, diag,
-                     qb);
+                     qb, conj);
 }
 void launch_to_f32(hipStream_t s, int64_t count, const double2* src, float2* dst) {
   if (count > 0) hipLaunchKernelGGL(k_to_f32, dim3(nblk(count, 256)), dim3(256), 0, s, count, src, dst);

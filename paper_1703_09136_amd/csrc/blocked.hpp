@@ -54,11 +54,12 @@ constexpr int kTgMaxNt = 8;   // row tiles per translation item
 // (2P + 1) x 32 doubles in LDS, all row tiles of a leaf in one wave)
 constexpr int kBlkLeafPmax = 40;
 
-// gather: qb[j * Rp + r] = q[(r0 + r) * n + perm[j]] (conj_in: conjugated) for r < nc, 0 past nc
-void launch_gather_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* q, double2* qb);
-// scatter: u[(r0 + r) * n + perm[j]] = ub[j * Rp + r] (- diag[j] qb[j * Rp + r])
+// gather: qb[j * Rp + r] = q[(r0 + r) * n + perm[j]] (conj: conjugated) for r < nc, 0 past nc
+void launch_gather_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* q, double2* qb,
+                       int conj);
+// scatter: u[(r0 + r) * n + perm[j]] = ub[j * Rp + r] (- diag[j] qb[j * Rp + r]), conjugated with conj
 void launch_scatter_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* ub, double2* u,
-                        const double2* diag, const double2* qb);
+                        const double2* diag, const double2* qb, int conj);
 // The expansion matrices V[m][j] = J_m(k rho_j) e^{-i m theta_j} of the
 // leaves (geometry only: computed once per plan), per leaf [2P + 1][npts] at
 // voff[leaf]; P2M over leaves stores alpha rows = V q, L2P adds

@@ -498,6 +498,7 @@ bool log_on() {
 constexpr int kBlkMinRhs = 48;
 constexpr double kBlkBudget = 8192.0 * 1024 * 1024;
 bool use_blocked(hfmm_plan_t pl, int nrhs) {
+  if (pl->opt.deterministic) return true;  // the plan was refused unless blk_ok
   if (!pl->blk_ok || pl->prof_on) return false;
   const char* env = std::getenv("HFMM_BLOCKED");
   if (env && env[0] == '0') return false;
@@ -553,7 +554,9 @@ hfmm_status_t ensure_blk_workspace(hfmm_plan_t pl, int Rp, hipStream_t s) {
     HIP_TRY(hipEventCreate(&e1));
     pl->m2l_pick.assign(pl->nlev, hfmm_plan_s::kTileCands - 1);
     float total = 0.0f, most = -1.0f;
-    for (int l = 0; l < pl->nlev; ++l) {
+    // deterministic mode: a fixed tile shape, no timing (the choice then
+    // cannot differ from run to run)
+    for (int l = 0; l < (pl->opt.deterministic ? 0 : pl->nlev); ++l) {
       float best = 1e30f, ms_c[hfmm_plan_s::kTileCands] = {0, 0, 0};
       for (int c = 0; c < hfmm_plan_s::kTileCands; ++c) {
         const auto& g = pl->m2l_tgl[c][l];
@@ -588,6 +591,7 @@ hfmm_status_t ensure_blk_workspace(hfmm_plan_t pl, int Rp, hipStream_t s) {
     (void)hipEventDestroy(e1);
     HIP_TRY(hipGetLastError());
     pl->m2l_tuned = true;
+    if (pl->opt.deterministic) pl->info.m2l_tile = hfmm_plan_s::kTileNt[hfmm_plan_s::kTileCands - 1];
     if (log_on()) std::fprintf(stderr, "[hfmm] M2L tuned: %.3f ms over all levels\n", total);
   }
   if (!pl->vmat_ready) {
@@ -777,6 +781,14 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->med.k3 = layers == 3 ? wavenumbers[2] : wavenumbers[1];
   pl->med.d = layers == 3 ? interfaces[0] - interfaces[1] : 1.0;
   const double k = pl->med.k1;
+  // plan phases (seconds), printed when HFMM_LOG is set
+  std::vector<std::pair<const char*, double>> phases;
+  auto t_phase = t_start;
+  auto phase = [&](const char* name) {
+    const auto now = std::chrono::steady_clock::now();
+    phases.push_back({name, std::chrono::duration<double>(now - t_phase).count()});
+    t_phase = now;
+  };
 
   // ---- points to the host, interface frame
   std::vector<double> hp((size_t)2 * n);
@@ -810,6 +822,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->x0 = xmin;
   pl->y0 = ymin;
 
+  phase("points");
   // ---- Morton sort (keys of 2 x 30 bits)
   std::vector<std::pair<uint64_t, int>> key((size_t)n);
   const double scale = (double)(1u << KEY_BITS) / S;
@@ -847,6 +860,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     }
   }
 
+  phase("sort");
   // ---- adaptive quadtree, breadth first (boxes of a level are contiguous, Morton order)
   std::vector<Box>& B = pl->boxes;
   B.push_back(Box{0, 0, 0, 0, (int)n, -1, 0, {-1, -1, -1, -1}, true});
@@ -899,6 +913,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
   const int nb = (int)B.size();
 
+  phase("tree");
   // ---- expansion orders (levels >= 2)
   const double eps = tol * kOrderSafety;
   for (int l = 2; l < pl->nlev; ++l) {
@@ -950,6 +965,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     pl->top = std::max(2, std::min(top, std::min(minleaf, pl->nlev - 1)));
   }
 
+  phase("orders");
   // ---- interaction lists
   struct PairL { int t, s; };
   std::vector<PairL> fv, iv, fu, iu;
@@ -997,6 +1013,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     }
   }
 
+  phase("lists");
   // ---- tables
   std::vector<TableRef> tabs;
   int64_t toff = 0;
@@ -1266,6 +1283,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     gd.count = (int)down_items.size() - gd.first;
   }
 
+  phase("tables (host)");
   // ---- per-level box lists
   std::vector<int> leaves;
   std::vector<int> leaf_index(nb, -1);
@@ -1285,6 +1303,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   for (int l = 0; l < pl->nlev; ++l)
     if (pl->leaf_lev[l + 1] > pl->leaf_lev[l]) pl->leaf_pmax = std::max(pl->leaf_pmax, pl->P[l]);
 
+  phase("level lists");
   // ---- direct lists, grouped by target leaf, source ranges merged
   auto leaves_under = [&](int b, std::vector<int>& outv) {
     std::vector<int> st{b};
@@ -1491,6 +1510,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     }
   }
 
+  phase("direct lists");
   // ---- lists of the right-hand-side-blocked pipeline: per target box its
   // translation pairs (M2M: its children, L2L: its parent, M2L: its free and
   // image pairs), the direct pairs in pieces of 16 targets, the offsets of the
@@ -1653,9 +1673,16 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         staged = staged && tgemm_supported(BLK_F64, pl->P[l + 1], pl->P[l]) &&
                  tgemm_supported(BLK_F64, pl->P[l], pl->P[l + 1]);
     }
-    pl->blk_ok = iu.empty() && pl->leaf_pmax <= kBlkLeafPmax && staged && !o.deterministic;
+    pl->blk_ok = iu.empty() && pl->leaf_pmax <= kBlkLeafPmax && staged;
+  }
+  if (o.deterministic && !pl->blk_ok) {
+    fail(HFMM_ERR_UNSUPPORTED,
+         "deterministic mode runs every apply through the right-hand-side-blocked pipeline, which this plan cannot "
+         "use (near-interface quadrature pairs, or a leaf expansion order above " + std::to_string(kBlkLeafPmax) + ")");
+    return bail(HFMM_ERR_UNSUPPORTED);
   }
 
+  phase("blocked lists");
   // ---- near-interface rule (one rule covering every direct image pair)
   std::vector<double2> qc, qky, qkx;
   double glx[16], glw[16];
@@ -1745,6 +1772,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     cpbeg.push_back((int)cpanels.size());
   }
 
+  phase("rules");
   // ---- upload and generate tables
   std::vector<double2> hpts((size_t)n);
   std::vector<int> hperm((size_t)n);
@@ -1860,6 +1888,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->nif_leaves = (int)if_leaves.size();
   pl->nq = (int)qc.size();
 
+  phase("upload and tables");
   // ---- statistics
   hfmm_info_t& inf = pl->info;
   inf.levels = pl->nlev;
@@ -1895,6 +1924,16 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     if (st != HFMM_OK) return bail(st);
   }
   inf.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  phase("statistics");
+  if (log_on()) {
+    std::string line = "[hfmm] plan " + std::to_string(n) + " points, " + std::to_string(nb) + " boxes:";
+    char buf[64];
+    for (auto& ph : phases) {
+      std::snprintf(buf, sizeof(buf), " %s %.1f ms,", ph.first, 1e3 * ph.second);
+      line += buf;
+    }
+    std::fprintf(stderr, "%s total %.1f ms\n", line.c_str(), 1e3 * inf.plan_seconds);
+  }
   *out = pl;
   return HFMM_OK;
 }
@@ -2087,8 +2126,11 @@ hfmm_status_t apply_passes(hfmm_plan_t pl, const double* q, double* u, int nrhs,
 }  // namespace
 
 // u = A q through the blocked pipeline: passes of Rp right-hand sides, every
-// array blocked by right-hand side, the stages in sequence on s.
-hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrhs, hipStream_t s) {
+// array blocked by right-hand side, the stages in sequence on s; with conj,
+// u = conj(A conj(q)) = A^H q (A is symmetric: reciprocity of the layered
+// Green's function, Section 2). No stage adds atomically: every output
+// element is summed in a fixed order.
+hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrhs, hipStream_t s, int conj) {
   const int Rp = blk_pass_width(pl, nrhs);
   hfmm_status_t st = ensure_blk_workspace(pl, Rp, s);
   if (st != HFMM_OK) return st;
@@ -2104,7 +2146,7 @@ hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrh
     const int nc = std::min(Rp, nrhs - r0);
     const double2* qc = (const double2*)q + (int64_t)r0 * n;
     double2* uc = (double2*)u + (int64_t)r0 * n;
-    launch_gather_blk(s, pl->n, nc, Rp, pl->perm.p, qc, pl->qb.p);
+    launch_gather_blk(s, pl->n, nc, Rp, pl->perm.p, qc, pl->qb.p, conj);
     if (pl->blk_prec_p2p == BLK_F32) launch_to_f32(s, n * Rp, pl->qb.p, pl->qlo.p);
     launch_fill_zero(s, pl->ub.p, n * Rp);
     launch_p2m_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->leaf_pmax, pl->vmat_off.p, pl->vmat.p, pl->qb.p, pl->ab.p);
@@ -2120,7 +2162,7 @@ hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrh
     launch_l2p_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->vmat_off.p, pl->vmat.p, pl->bb.p, pl->ub.p);
     launch_p2p_blk(s, tv, pl->blk_prec_p2p, Rp, pl->bp_items.p, pl->bp_cls_ptr, pl->bp_rng.p, pl->qb.p, pl->qlo.p,
                    pl->ub.p);
-    launch_scatter_blk(s, pl->n, nc, Rp, pl->perm.p, pl->ub.p, uc, pl->self_g.p, pl->qb.p);
+    launch_scatter_blk(s, pl->n, nc, Rp, pl->perm.p, pl->ub.p, uc, pl->self_g.p, pl->qb.p, conj);
   }
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipEventRecord(pl->ev_done, s));
@@ -2133,6 +2175,8 @@ hfmm_status_t apply_in_buffer(hfmm_plan_t pl, const double* q, double* u, int nr
   if (!pl || !q || !u) return fail(HFMM_ERR_INVALID_ARG, "NULL plan, q or u");
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   if (!base) return fail(HFMM_ERR_INVALID_ARG, "NULL workspace");
+  if (pl->opt.deterministic)
+    return fail(HFMM_ERR_UNSUPPORTED, "deterministic plans run the blocked pipeline, whose workspace the plan owns");
   if (workspace_bytes(pl, 1) > bytes)
     return fail(HFMM_ERR_NO_MEMORY, "the plan needs " + std::to_string(workspace_bytes(pl, 1)) +
                                         " bytes of workspace per right-hand side; " + std::to_string(bytes) +
@@ -2162,7 +2206,7 @@ hfmm_status_t hfmm_apply(hfmm_plan_t pl, const double* q, double* u, int32_t nrh
   if (nrhs < 1) return fail(HFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
   hipStream_t s = (hipStream_t)stream_;
   AllocScope alloc_scope(&pl->al);
-  if (use_blocked(pl, nrhs)) return blocked_passes(pl, q, u, nrhs, s);
+  if (use_blocked(pl, nrhs)) return blocked_passes(pl, q, u, nrhs, s, 0);
   const int chunk = rhs_chunk(pl, nrhs);
   hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
@@ -2211,6 +2255,10 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
   if (grad_xy && !q) return fail(HFMM_ERR_INVALID_ARG, "grad_xy requested without q");
   hipStream_t s = (hipStream_t)stream_;
   AllocScope alloc_scope(&pl->al);
+  if (pl->opt.deterministic) {
+    if (grad_xy) return fail(HFMM_ERR_UNSUPPORTED, "deterministic mode has no coordinate gradients");
+    return blocked_passes(pl, v, w, nrhs, s, 1);
+  }
   const int chunk = rhs_chunk(pl, nrhs);
   hfmm_status_t st = ensure_workspace(pl, chunk);
   if (st != HFMM_OK) return st;
