@@ -268,6 +268,49 @@ void hfmm_batch_destroy(hfmm_batch_t batch);
 hfmm_status_t hfmm_apply_noalloc(hfmm_plan_t plan, const double *q, double *u, int32_t nrhs,
                                  hfmm_stream_t stream);
 
+/*
+ * The quadtree and interaction lists of a point set as hfmm_plan builds them
+ * (Section 3.1: the adaptive partition of the points; Section 3.3: the box
+ * pairs of the free and heterogeneous multipole-to-local translations), for
+ * inspection and tests.
+ *   wavenumbers[0], interfaces[0]: the top layer's wavenumber and the top
+ *       interface (the wavelength bound and the interface frame);
+ *   points: device pointer, n x 2 doubles (x, y), as for hfmm_plan;
+ *   opts: NULL or options; leaf_size, leaf_kb, interface_refine, max_level
+ *       and top_level are read;
+ *   builder: HFMM_TREE_GPU, the HIP kernels every plan runs (Morton keys, a
+ *       radix sort, level-by-level splitting, pair-frontier lists), or
+ *       HFMM_TREE_HOST, the host reference builder (comparison sort and a
+ *       depth-first dual-tree traversal) that the GPU builder is checked
+ *       against. Both give the same tree bit for bit.
+ * Synchronises the stream. Errors as for hfmm_plan: HFMM_ERR_DOMAIN (a point
+ * not finite, not strictly above the top interface, or two coincident
+ * points), HFMM_ERR_ACCURACY (a tree deeper than 32 levels),
+ * HFMM_ERR_INVALID_ARG, HFMM_ERR_DEVICE, HFMM_ERR_NO_MEMORY.
+ */
+typedef struct hfmm_tree_s *hfmm_tree_t;
+enum { HFMM_TREE_GPU = 0, HFMM_TREE_HOST = 1 };
+hfmm_status_t hfmm_tree_build(hfmm_tree_t *out, const double *wavenumbers, const double *interfaces, int64_t n,
+                              const double *points, const hfmm_options_t *opts, int32_t builder,
+                              hfmm_stream_t stream);
+/* counts[0..7] = n, boxes, levels, top level, and the lengths of the lists
+ * fv (free M2L pairs), iv (image M2L pairs), fu (free direct pairs), iu
+ * (near-interface direct pairs). */
+hfmm_status_t hfmm_tree_counts(hfmm_tree_t tree, int64_t counts[8]);
+/* Copies into host buffers sized from hfmm_tree_counts (a NULL buffer is
+ * skipped): frame[0..2] = root side S, x0 = min x, y0 = min (y - interface);
+ * keys[n], the sorted Morton keys (2 x 30 bits, x in the even bits); perm[n],
+ * the input index of each sorted point (ties by input index);
+ * boxes[12 * boxes]: per box level, ix, iy, begin, end (its sorted points),
+ * parent (-1 at the root), quadrant, child[4] (-1: none) and leaf (0 / 1), in
+ * breadth-first order (the boxes of a level contiguous, in Morton order);
+ * lev_begin[levels + 1], the first box of each level; each list as (t, s)
+ * pairs of box indices, sorted by t, then s. */
+hfmm_status_t hfmm_tree_copy(hfmm_tree_t tree, double *frame, uint64_t *keys, int32_t *perm, int32_t *boxes,
+                             int32_t *lev_begin, int32_t *fv, int32_t *iv, int32_t *fu, int32_t *iu);
+/* NULL is a no-op. */
+void hfmm_tree_destroy(hfmm_tree_t tree);
+
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 

@@ -29,10 +29,11 @@ EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoin
            "hfmm_profile_enable", "hfmm_profile_read", "hfmm_stage_name",
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
            "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy",
-           "hfmm_apply_noalloc")
+           "hfmm_apply_noalloc", "hfmm_tree_build", "hfmm_tree_counts", "hfmm_tree_copy", "hfmm_tree_destroy")
 NSTAGES = 9
 HFMM_FP64, HFMM_FP32, HFMM_BF16 = 0, 1, 2
 HFMM_SELF_SCATTERED, HFMM_SELF_NONE = 0, 1
+HFMM_TREE_GPU, HFMM_TREE_HOST = 0, 1
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
@@ -131,6 +132,15 @@ def load(path: str | None = None):
     lib.hfmm_stage_name.restype = ctypes.c_char_p
     lib.hfmm_destroy.argtypes = [vp]
     lib.hfmm_destroy.restype = None
+    lib.hfmm_tree_build.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64, vp,
+                                    ctypes.POINTER(Options), i32, vp]
+    lib.hfmm_tree_build.restype = ctypes.c_int
+    lib.hfmm_tree_counts.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.hfmm_tree_counts.restype = ctypes.c_int
+    lib.hfmm_tree_copy.argtypes = [vp, ctypes.POINTER(dbl), vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.hfmm_tree_copy.restype = ctypes.c_int
+    lib.hfmm_tree_destroy.argtypes = [vp]
+    lib.hfmm_tree_destroy.restype = None
     lib.hfmm_status_string.argtypes = [ctypes.c_int]
     lib.hfmm_status_string.restype = ctypes.c_char_p
     lib.hfmm_last_error_message.argtypes = []
@@ -213,6 +223,41 @@ def _check_out(out, q2, name):
     b0, b1 = q2.data_ptr(), q2.data_ptr() + q2.numel() * 16
     if a0 < b1 and b0 < a1:
         raise ValueError("%s overlaps the right-hand sides" % name)
+
+
+def build_tree(k, interfaces, points, builder=HFMM_TREE_GPU, stream=None, **options):
+    """The quadtree and interaction lists hfmm_plan builds for these points
+    (hfmm_tree_build): a dict of numpy arrays (frame, keys, perm, boxes as
+    (nboxes, 12) int32 rows, lev_begin, and the pair lists fv, iv, fu, iu as
+    (m, 2) int32) plus the counts. builder: HFMM_TREE_GPU or HFMM_TREE_HOST."""
+    import numpy as np
+    import torch
+    lib = load()
+    if not (points.is_cuda and points.dtype == torch.float64 and points.dim() == 2 and points.shape[1] == 2):
+        raise TypeError("points must be a float64 CUDA tensor of shape (n, 2)")
+    pts = points.contiguous()
+    kk = (ctypes.c_double * 1)(float(k[0]))
+    ii = (ctypes.c_double * 1)(float(interfaces[0]))
+    opts = default_options(**options)
+    h = ctypes.c_void_p()
+    _check(lib.hfmm_tree_build(ctypes.byref(h), kk, ii, int(pts.shape[0]), ctypes.c_void_p(pts.data_ptr()),
+                               ctypes.byref(opts), int(builder), _stream_ptr(stream)))
+    try:
+        c = (ctypes.c_int64 * 8)()
+        _check(lib.hfmm_tree_counts(h, c))
+        n, nb, nlev, top, nfv, niv, nfu, niu = (int(v) for v in c)
+        out = {"n": n, "boxes_count": nb, "levels": nlev, "top": top,
+               "frame": np.zeros(3), "keys": np.zeros(n, np.uint64), "perm": np.zeros(n, np.int32),
+               "boxes": np.zeros((nb, 12), np.int32), "lev_begin": np.zeros(nlev + 1, np.int32),
+               "fv": np.zeros((nfv, 2), np.int32), "iv": np.zeros((niv, 2), np.int32),
+               "fu": np.zeros((nfu, 2), np.int32), "iu": np.zeros((niu, 2), np.int32)}
+        ptr = lambda a: ctypes.c_void_p(a.ctypes.data)
+        _check(lib.hfmm_tree_copy(h, out["frame"].ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ptr(out["keys"]),
+                                  ptr(out["perm"]), ptr(out["boxes"]), ptr(out["lev_begin"]), ptr(out["fv"]),
+                                  ptr(out["iv"]), ptr(out["fu"]), ptr(out["iu"])))
+    finally:
+        lib.hfmm_tree_destroy(h)
+    return out
 
 
 class Plan:

@@ -17,8 +17,10 @@
 // the heterogeneous tables well conditioned at every order the level uses.
 #include "../../include/hfmm.h"
 #include "blocked.hpp"
+#include "devbuf.hpp"
 #include "kernels.hpp"
 #include "plan_internal.hpp"
+#include "tree_gpu.hpp"
 #include "special.hpp"
 
 #include <algorithm>
@@ -49,67 +51,6 @@ hfmm_status_t fail(hfmm_status_t s, const std::string& msg) {
     if (e_ != hipSuccess) return fail(HFMM_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-// Device memory of a plan comes from the caller's allocator (hfmm_options_t
-// alloc / free / alloc_ctx) or from hipMalloc. The allocator in force is set
-// for the duration of each library call that may allocate (AllocScope); every
-// buffer keeps the allocator that gave it its memory and returns it there.
-struct Allocator {
-  void* (*alloc)(size_t, void*) = nullptr;
-  void (*free)(void*, void*) = nullptr;
-  void* ctx = nullptr;
-};
-thread_local const Allocator* tl_alloc = nullptr;
-struct AllocScope {
-  const Allocator* prev;
-  explicit AllocScope(const Allocator* a) : prev(tl_alloc) { tl_alloc = a; }
-  ~AllocScope() { tl_alloc = prev; }
-};
-
-template <class T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t n = 0;
-  Allocator al{};  // the allocator p came from (alloc == nullptr: hipMalloc)
-  hipError_t alloc(size_t count) {
-    release();
-    n = count;
-    if (count == 0) return hipSuccess;
-    if (tl_alloc && tl_alloc->alloc) {
-      al = *tl_alloc;
-      p = (T*)al.alloc(count * sizeof(T), al.ctx);
-      if (!p) {
-        n = 0;
-        return hipErrorOutOfMemory;
-      }
-      return hipSuccess;
-    }
-    al = Allocator{};
-    return hipMalloc((void**)&p, count * sizeof(T));
-  }
-  // grow only: keeps the buffer when it already holds count elements
-  hipError_t ensure(size_t count) { return n >= count && p ? hipSuccess : alloc(count); }
-  hipError_t upload(const std::vector<T>& v, hipStream_t s) {
-    hipError_t e = alloc(v.size());
-    if (e != hipSuccess || v.empty()) return e;
-    return hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-  }
-  void release() {
-    if (p) {
-      if (al.free)
-        al.free(p, al.ctx);
-      else
-        (void)hipFree(p);
-    }
-    p = nullptr;
-    n = 0;
-  }
-};
-
-struct Box {
-  int level, ix, iy, begin, end, parent, quad;
-  int child[4];
-  bool leaf;
-};
 
 // 16-point Gauss-Legendre rule on [-1, 1] by Newton iteration on P_16.
 void gauss_legendre16(double* x, double* w) {
@@ -604,18 +545,6 @@ hfmm_status_t ensure_blk_workspace(hfmm_plan_t pl, int Rp, hipStream_t s) {
   return HFMM_OK;
 }
 
-uint64_t spread_bits(uint32_t v) {
-  uint64_t x = v;
-  x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
-  x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
-  x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
-  x = (x | (x << 2)) & 0x3333333333333333ull;
-  x = (x | (x << 1)) & 0x5555555555555555ull;
-  return x;
-}
-
-constexpr int KEY_BITS = 30;
-
 // Expansion order of a level: the smallest P with
 // |J_{P+1}(k R)| |H_{P+1}(k (D - R))| <= eps, R = b/sqrt(2) the box radius and
 // D = 2b the closest centre distance of a translated pair.
@@ -790,7 +719,32 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     t_phase = now;
   };
 
-  // ---- points to the host, interface frame
+  // ---- the tree, its interaction lists and the point order (GPU builder)
+  TreeOut tree;
+  {
+    TreeParams tp;
+    tp.n = n;
+    tp.y_top = pl->y_top;
+    tp.k = k;
+    tp.leaf_size = o.leaf_size;
+    tp.leaf_kb = o.leaf_kb;
+    tp.interface_refine = o.interface_refine;
+    tp.max_level = o.max_level;
+    tp.top_level = o.top_level;
+    TreeDev tdev;
+    gpu_tree_build(tp, points, stream, false, tree, tdev);
+    if (tree.status != TREE_OK) {
+      const hfmm_status_t st = tree.status == TREE_DOMAIN  ? HFMM_ERR_DOMAIN
+                               : tree.status == TREE_DEPTH ? HFMM_ERR_ACCURACY
+                               : tree.status == TREE_MEMORY ? HFMM_ERR_NO_MEMORY
+                                                            : HFMM_ERR_DEVICE;
+      fail(st, tree.msg);
+      return bail(st);
+    }
+    std::swap(pl->perm, tdev.perm);
+  }
+  phase("tree");
+  // ---- points on the host, interface frame
   std::vector<double> hp((size_t)2 * n);
   {
     hipError_t e = hipMemcpyAsync(hp.data(), points, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, stream);
@@ -800,120 +754,22 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       return bail(HFMM_ERR_DEVICE);
     }
   }
-  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-  for (int64_t i = 0; i < n; ++i) {
-    double x = hp[2 * i], y = hp[2 * i + 1] - pl->y_top;
-    if (!std::isfinite(x) || !std::isfinite(y)) {
-      fail(HFMM_ERR_DOMAIN, "non-finite point " + std::to_string(i));
-      return bail(HFMM_ERR_DOMAIN);
-    }
-    if (!(y > 0.0)) {
-      fail(HFMM_ERR_DOMAIN, "point " + std::to_string(i) + " is not strictly above the top interface");
-      return bail(HFMM_ERR_DOMAIN);
-    }
-    hp[2 * i + 1] = y;
-    xmin = std::min(xmin, x); xmax = std::max(xmax, x);
-    ymin = std::min(ymin, y); ymax = std::max(ymax, y);
-  }
-  double S = std::max(xmax - xmin, ymax - ymin);
-  if (!(S > 0.0)) S = std::max(1e-3, 1e-6 * std::fabs(ymin));
-  S *= (1.0 + 1e-12);
+  for (int64_t i = 0; i < n; ++i) hp[2 * i + 1] -= pl->y_top;
+  const double xmin = tree.x0, ymin = tree.y0, S = tree.S;
+  double ymax = ymin;
+  for (int64_t i = 0; i < n; ++i) ymax = std::max(ymax, hp[2 * i + 1]);
   pl->S = S;
   pl->x0 = xmin;
   pl->y0 = ymin;
-
-  phase("points");
-  // ---- Morton sort (keys of 2 x 30 bits)
-  std::vector<std::pair<uint64_t, int>> key((size_t)n);
-  const double scale = (double)(1u << KEY_BITS) / S;
-  for (int64_t i = 0; i < n; ++i) {
-    double fx = (hp[2 * i] - xmin) * scale, fy = (hp[2 * i + 1] - ymin) * scale;
-    uint32_t ix = (uint32_t)std::min(std::max(std::floor(fx), 0.0), (double)((1u << KEY_BITS) - 1));
-    uint32_t iy = (uint32_t)std::min(std::max(std::floor(fy), 0.0), (double)((1u << KEY_BITS) - 1));
-    key[i] = {spread_bits(ix) | (spread_bits(iy) << 1), (int)i};
-  }
-  std::sort(key.begin(), key.end());
-  // Coincident points share a key. Within each run of equal keys the points
-  // are compared after sorting the run by (x, y), so that two equal points
-  // are found even when a different point with the same key lies between
-  // them in index order.
-  {
-    std::vector<std::pair<std::pair<double, double>, int>> run;
-    for (int64_t i = 0; i < n;) {
-      int64_t e = i + 1;
-      while (e < n && key[e].first == key[i].first) ++e;
-      if (e - i > 1) {
-        run.clear();
-        for (int64_t t = i; t < e; ++t) {
-          const int a = key[t].second;
-          run.push_back({{hp[2 * a], hp[2 * a + 1]}, a});
-        }
-        std::sort(run.begin(), run.end());
-        for (size_t t = 1; t < run.size(); ++t)
-          if (run[t].first == run[t - 1].first) {
-            fail(HFMM_ERR_DOMAIN, "coincident points " + std::to_string(std::min(run[t - 1].second, run[t].second)) +
-                                      " and " + std::to_string(std::max(run[t - 1].second, run[t].second)));
-            return bail(HFMM_ERR_DOMAIN);
-          }
-      }
-      i = e;
-    }
-  }
-
-  phase("sort");
-  // ---- adaptive quadtree, breadth first (boxes of a level are contiguous, Morton order)
+  const std::vector<int>& perm = tree.perm;
+  pl->boxes = std::move(tree.boxes);
   std::vector<Box>& B = pl->boxes;
-  B.push_back(Box{0, 0, 0, 0, (int)n, -1, 0, {-1, -1, -1, -1}, true});
-  pl->lev_begin.push_back(0);
-  const int maxl = std::min(o.max_level, KEY_BITS);
-  for (int l = 0;; ++l) {
-    int lb = pl->lev_begin[l], le = (int)B.size();
-    pl->bsize[l] = S / (double)(1u << l);
-    double b = pl->bsize[l];
-    bool any = false;
-    for (int bi = lb; bi < le; ++bi) {
-      int cnt = B[bi].end - B[bi].begin;
-      bool split = cnt > o.leaf_size;
-      // wavelength bound: wide leaves leave direct pairs at large k1 r. Up to
-      // twice the bound, boxes holding a quarter of a leaf or less stay whole
-      // (their pairs are few); beyond it every box splits, a lone point
-      // included, so that no leaf takes a wide neighbour subtree into its
-      // direct lists (nor a near-interface image pair that is not admissible).
-      if (o.leaf_kb > 0.0 && k * b > o.leaf_kb) {
-        if (cnt > std::max(1, o.leaf_size / 4) || k * b > 2.0 * o.leaf_kb) split = true;
-      }
-      // bottom-row boxes whose own image pair is not admissible (2 y0 < b)
-      if (o.interface_refine && B[bi].iy == 0 && 2.0 * ymin < b && cnt > 1) split = true;
-      if (l >= maxl) split = false;
-      if (!split) continue;
-      any = true;
-      B[bi].leaf = false;
-      int shift = 2 * (KEY_BITS - l - 1);
-      int s = B[bi].begin;
-      for (int q = 0; q < 4; ++q) {
-        // points of quadrant q are contiguous: upper bound of digit q
-        int e = s;
-        while (e < B[bi].end && (int)((key[e].first >> shift) & 3u) == q) ++e;
-        if (e > s) {
-          Box c{l + 1, 2 * B[bi].ix + (q & 1), 2 * B[bi].iy + (q >> 1), s, e, bi, q, {-1, -1, -1, -1}, true};
-          B[bi].child[q] = (int)B.size();
-          B.push_back(c);
-        }
-        s = e;
-      }
-    }
-    if (!any) break;
-    pl->lev_begin.push_back(le);
-  }
-  pl->nlev = (int)pl->lev_begin.size();
-  pl->lev_begin.push_back((int)B.size());
-  if (pl->nlev > HFMM_MAX_LEVELS) {
-    fail(HFMM_ERR_ACCURACY, "tree deeper than supported");
-    return bail(HFMM_ERR_ACCURACY);
-  }
+  pl->lev_begin = tree.lev_begin;
+  pl->nlev = tree.nlev;
+  for (int l = 0; l < pl->nlev; ++l) pl->bsize[l] = tree.bsize[l];
   const int nb = (int)B.size();
-
-  phase("tree");
+  pl->top = tree.top;
+  phase("points");
   // ---- expansion orders (levels >= 2)
   const double eps = tol * kOrderSafety;
   for (int l = 2; l < pl->nlev; ++l) {
@@ -942,77 +798,13 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
   pl->ctot = ctot;
 
-  // ---- coarsest level of the expansions. Starting the multipole-to-local
-  // pairs at a finer level than 2 splits the coarse levels' few pairs (of the
-  // highest orders, whose launches are latency bound) into more pairs of a
-  // lower order at that level; the automatic choice keeps every pair of boxes
-  // of the top level below kTopPairs. No leaf may lie above it.
-  {
-    constexpr int64_t kTopPairs = 4096;
-    int minleaf = pl->nlev;
-    for (int i = 0; i < nb; ++i)
-      if (B[i].leaf) minleaf = std::min(minleaf, B[i].level);
-    int top = 2;
-    if (o.top_level >= 2) {
-      top = o.top_level;
-    } else {
-      for (int l = 3; l < pl->nlev; ++l) {
-        const int64_t nbl = pl->lev_begin[l + 1] - pl->lev_begin[l];
-        if (nbl * nbl > kTopPairs) break;
-        top = l;
-      }
-    }
-    pl->top = std::max(2, std::min(top, std::min(minleaf, pl->nlev - 1)));
-  }
-
   phase("orders");
-  // ---- interaction lists
-  struct PairL { int t, s; };
-  std::vector<PairL> fv, iv, fu, iu;
-  auto adjacent = [&](int t, int s) {
-    return std::abs(B[t].ix - B[s].ix) <= 1 && std::abs(B[t].iy - B[s].iy) <= 1;
-  };
-  auto kids = [&](int b, int* out) {
-    int c = 0;
-    for (int q = 0; q < 4; ++q)
-      if (B[b].child[q] >= 0) out[c++] = B[b].child[q];
-    return c;
-  };
-  std::vector<PairL> stack;
-  stack.push_back({0, 0});
-  while (!stack.empty()) {
-    PairL pr = stack.back();
-    stack.pop_back();
-    if (!adjacent(pr.t, pr.s) && B[pr.t].level >= pl->top) {
-      fv.push_back(pr);
-    } else if (B[pr.t].leaf || B[pr.s].leaf) {
-      fu.push_back(pr);
-    } else {
-      int ct[4], cs[4];
-      int nt = kids(pr.t, ct), ns = kids(pr.s, cs);
-      for (int a = 0; a < nt; ++a)
-        for (int c = 0; c < ns; ++c) stack.push_back({ct[a], cs[c]});
-    }
-  }
-  stack.push_back({0, 0});
-  while (!stack.empty()) {
-    PairL pr = stack.back();
-    stack.pop_back();
-    int l = B[pr.t].level;
-    double b = pl->bsize[l];
-    bool adm = l >= pl->top && (B[pr.t].iy + B[pr.s].iy >= 1 || 2.0 * ymin >= b);
-    if (adm) {
-      iv.push_back(pr);
-    } else if (B[pr.t].leaf || B[pr.s].leaf) {
-      iu.push_back(pr);
-    } else {
-      int ct[4], cs[4];
-      int nt = kids(pr.t, ct), ns = kids(pr.s, cs);
-      for (int a = 0; a < nt; ++a)
-        for (int c = 0; c < ns; ++c) stack.push_back({ct[a], cs[c]});
-    }
-  }
-
+  // ---- interaction lists (from the tree builder, sorted by target)
+  using PairL = TreePair;
+  const std::vector<PairL>& fv = tree.fv;
+  const std::vector<PairL>& iv = tree.iv;
+  const std::vector<PairL>& fu = tree.fu;
+  const std::vector<PairL>& iu = tree.iu;
   phase("lists");
   // ---- tables
   std::vector<TableRef> tabs;
@@ -1350,7 +1142,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     const Box& bx = B[leaves[li]];
     double4 bb = make_double4(INFINITY, -INFINITY, INFINITY, -INFINITY);
     for (int j = bx.begin; j < bx.end; ++j) {
-      const double px = hp[2 * key[j].second], py = hp[2 * key[j].second + 1];
+      const double px = hp[2 * perm[j]], py = hp[2 * perm[j] + 1];
       bb.x = std::min(bb.x, px); bb.y = std::max(bb.y, px);
       bb.z = std::min(bb.z, py); bb.w = std::max(bb.w, py);
     }
@@ -1775,10 +1567,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   phase("rules");
   // ---- upload and generate tables
   std::vector<double2> hpts((size_t)n);
-  std::vector<int> hperm((size_t)n);
   for (int64_t i = 0; i < n; ++i) {
-    int j = key[i].second;
-    hperm[i] = j;
+    const int j = perm[i];
     hpts[i] = cmk(hp[2 * j], hp[2 * j + 1]);
   }
   std::vector<double2> hctr(nb);
@@ -1804,7 +1594,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   hipError_t e = hipSuccess;
 #define UP(buf, vec)                                  \
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
-  UP(pts, hpts) UP(perm, hperm) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
+  UP(pts, hpts) UP(ctr, hctr) UP(level, hlev) UP(parent, hpar) UP(quad, hquad)
   UP(child, hchild) UP(prange, hpr) UP(coff, coff) UP(leaves, leaves) UP(pt_box, pt_box_h)
   UP(m2l_items, m2l_items) UP(m2l_soff, m2l_soff) UP(m2l_toff, m2l_toff) UP(m2l_pcoff, m2l_pcoff) UP(m2l_pcoffT, m2l_pcoffT)
   UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_beg, red_beg) UP(redT_ptr, redT_ptr)

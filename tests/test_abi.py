@@ -96,3 +96,28 @@ def test_allocator_must_come_with_free():
     st, h = _plan(lib, 2, (5.0, 6.0), (0.0,), 10, 1e-8, o)
     assert st == 1 and not h.value
     assert "alloc" in lib.hfmm_last_error_message().decode()
+
+
+def test_tree_build_rejects_bad_arguments():
+    lib = hf.load()
+    h = ctypes.c_void_p()
+    k = (ctypes.c_double * 1)(5.0)
+    ifs = (ctypes.c_double * 1)(0.0)
+    pts = ctypes.c_void_p(1)  # never dereferenced: every case fails on the host first
+
+    def build(out=ctypes.byref(h), n=10, points=pts, builder=0, **opts):
+        o = hf.default_options(**opts)
+        return lib.hfmm_tree_build(out, k, ifs, n, points, ctypes.byref(o), builder, None)
+
+    assert build(out=None) == 1
+    assert build(n=0) == 1
+    assert build(points=None) == 1
+    assert build(builder=2) == 1
+    assert build(leaf_size=0) == 1
+    assert build(max_level=1) == 1
+    assert build(leaf_kb=0.1) == 1
+    assert not h.value
+    counts = (ctypes.c_int64 * 8)()
+    assert lib.hfmm_tree_counts(None, counts) == 1
+    assert lib.hfmm_tree_copy(None, None, None, None, None, None, None, None, None, None) == 1
+    lib.hfmm_tree_destroy(None)
