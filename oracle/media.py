@@ -9,6 +9,9 @@ Paper passages followed:
 * Section 2.3: the three-layer representation (u1^s, u2^t, u2^b, u3) and the
   4x4 linear system for (sigma_1, sigma_2^+, sigma_2^-, sigma_3) obtained from
   [u] = [du/dn] = 0 at y = 0 and y = -d.
+* Section 2.2: the impedance half-space (one medium above y = 0 with
+  du/dn - i alpha u = 0 there), whose scattered field has the Sommerfeld form
+  of Eq. multisommer with sigma-hat = (gamma + i alpha)/(gamma - i alpha).
 
 Reading: the source factor in the middle and bottom layer fields is
 exp(-gamma_1 y0) (the source sits in layer 1); with that reading the system
@@ -20,17 +23,27 @@ import numpy as np
 
 
 class Media:
-    """A two- or three-layer medium, wavenumbers top layer first.
+    """A two- or three-layer medium, wavenumbers top layer first; or, with
+    ``impedance`` = alpha > 0, the impedance half-space: one wavenumber and
+    one boundary height, the boundary condition du/dn - i alpha u = 0 (n the
+    outward normal of the half-space, -y).
 
     ``interfaces`` are heights in the caller's frame, top first. The oracle
     works in the interface frame, where the top interface is y = 0; use
     ``to_frame`` to shift coordinates.
     """
 
-    def __init__(self, k, interfaces):
+    def __init__(self, k, interfaces, impedance=None):
         k = tuple(complex(v) if np.iscomplexobj(v) else float(v) for v in k)
         interfaces = tuple(float(v) for v in interfaces)
-        if len(k) not in (2, 3) or len(interfaces) != len(k) - 1:
+        self.alpha = None
+        if impedance is not None:
+            if len(k) != 1 or len(interfaces) != 1:
+                raise ValueError("the impedance half-space has one wavenumber and one boundary")
+            if not float(impedance) > 0.0:
+                raise ValueError("the impedance alpha must be > 0")
+            self.alpha = float(impedance)
+        elif len(k) not in (2, 3) or len(interfaces) != len(k) - 1:
             raise ValueError("need 2 or 3 layers and layers-1 interfaces")
         self.k = k
         self.interfaces = interfaces
@@ -52,6 +65,8 @@ class Media:
 
     def three_layer_view(self):
         """(k1, k2, k3, d): two layers are the three-layer system with k3 = k2."""
+        if self.alpha is not None:
+            raise ValueError("the impedance half-space has no interface system")
         if self.layers == 3:
             return self.k[0], self.k[1], self.k[2], self.d
         return self.k[0], self.k[1], self.k[1], 1.0
@@ -114,5 +129,10 @@ def sigma_coefficients(lam, media: Media):
 
 
 def sigma1(lam, media: Media):
-    """The reflection function sigma_1(lambda) of the top layer."""
+    """The reflection function sigma_1(lambda) of the top layer; for the
+    impedance half-space sigma-hat = (gamma + i alpha)/(gamma - i alpha)
+    (Section 2.2, after Eq. spectraldomain)."""
+    if media.alpha is not None:
+        g = gamma(np.asarray(lam, dtype=complex), media.k1)
+        return (g + 1j * media.alpha) / (g - 1j * media.alpha)
     return sigma_coefficients(lam, media)[..., 0]

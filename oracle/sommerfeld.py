@@ -34,7 +34,7 @@ import os
 
 import numpy as np
 
-from .media import Media, gamma, sigma_coefficients
+from .media import Media, gamma, sigma1, sigma_coefficients
 
 _GL_X, _GL_W = np.polynomial.legendre.leggauss(16)
 
@@ -122,7 +122,7 @@ def contour_rule(media: Media, x_span: float, y_min: float, y_max: float, *,
 
 def _sigma_or(media, lam, sigma):
     if sigma is None:
-        return sigma_coefficients(lam, media)[..., 0]
+        return sigma1(lam, media)
     if callable(sigma):
         return np.asarray(sigma(lam), dtype=complex) * np.ones_like(lam)
     return complex(sigma) * np.ones_like(lam)
