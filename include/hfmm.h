@@ -132,6 +132,14 @@ typedef struct {
   int32_t order;            /* 0 (default): expansion order per level from
                                tol; > 0: this order at every level (the
                                paper's fixed-p experiments), at most 255 */
+  double impedance;         /* layers == 1 only: alpha > 0 of the impedance
+                               half-space (Section 2.2): one medium of
+                               wavenumber wavenumbers[0] above y =
+                               interfaces[0], with du/dn - i alpha u = 0 on
+                               that line (n the outward normal, -y), whose
+                               reflection function is (g + i alpha)/(g - i
+                               alpha), g = sqrt(lambda^2 - k^2). Must be 0
+                               (default) with two or three layers. */
   hfmm_alloc_fn alloc;      /* NULL (default): hipMalloc / hipFree */
   hfmm_free_fn free;        /* must be set together with alloc */
   void *alloc_ctx;
@@ -171,16 +179,19 @@ void hfmm_default_options(hfmm_options_t *opts);
  * tables (Algorithm 1, step 1; tables by FP64 quadrature of the Sommerfeld
  * form of the multipole-to-local operator, Section 3.3 Eq. m2loperator with
  * sigma_1 as in Section 5).
- *   layers       2 or 3.
+ *   layers       2 or 3; 1: the impedance half-space of Section 2.2 (its
+ *                alpha in opts->impedance).
  *   wavenumbers  host [layers], top layer first, > 0; every lower layer must
  *                have k_j >= k_1.
- *   interfaces   host [layers-1], strictly decreasing heights.
+ *   interfaces   host [max(layers-1, 1)], strictly decreasing heights (the
+ *                half-space: its boundary).
  *   n            number of points, >= 1.
  *   points       device [n][2] doubles; every y strictly above interfaces[0].
  *   tol          requested relative accuracy, in [1e-14, 1e-2].
  *   opts         NULL for defaults.
  * On success *out owns the plan; release it with hfmm_destroy. The call
- * synchronises the stream (the tree is built from the points on the host).
+ * synchronises the stream (the tree is built on the GPU level by level, and
+ * the lists and tables are planned on the host).
  */
 hfmm_status_t hfmm_plan(hfmm_plan_t *out, int32_t layers, const double *wavenumbers,
                         const double *interfaces, int64_t n, const double *points, double tol,

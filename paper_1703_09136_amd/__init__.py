@@ -43,7 +43,8 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("self_term", ctypes.c_int32), ("interface_refine", ctypes.c_int32), ("max_level", ctypes.c_int32),
                 ("leaf_kb", ctypes.c_double), ("top_level", ctypes.c_int32), ("max_nrhs", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("order", ctypes.c_int32), ("alloc", ALLOC_FN),
+                ("deterministic", ctypes.c_int32), ("order", ctypes.c_int32), ("impedance", ctypes.c_double),
+                ("alloc", ALLOC_FN),
                 ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p)]
 
 

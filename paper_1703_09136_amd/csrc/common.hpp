@@ -83,15 +83,20 @@ __host__ __device__ inline double2 gamma_branch(double2 w) {
 
 // ---------------------------------------------------------------- medium
 struct Medium {
-  int layers;     // 2 or 3
-  double k1, k2, k3;  // k3 == k2 for two layers
+  int layers;     // 2 or 3; 1: the impedance half-space
+  double k1, k2, k3;  // k3 == k2 for two layers, k2 == k3 == k1 for the half-space
   double d;       // slab thickness (three layers)
+  double alpha;   // impedance of the half-space's boundary (layers == 1)
 };
 
 // sigma_1 from the physical gammas of the three layers (two layers: r12).
 // Closed form of the interface system: a slab of thickness d between the
 // half-spaces, sigma_1 = (r12 + r23 E)/(1 + r12 r23 E), E = exp(-2 g2 d).
+// The impedance half-space (Section 2.2, Eq. multisommer): sigma-hat =
+// (g1 + i alpha)/(g1 - i alpha); with alpha > 0 its pole g1 = i alpha lies
+// off the physical sheet's contours (there Im g1 <= 0).
 __host__ __device__ inline double2 sigma1_from(const Medium& m, double2 g1, double2 g2, double2 g3) {
+  if (m.layers == 1) return cdiv(cmk(g1.x, g1.y + m.alpha), cmk(g1.x, g1.y - m.alpha));
   double2 r12 = cdiv(csub(g1, g2), cadd(g1, g2));
   if (m.layers == 2) return r12;
   double2 r23 = cdiv(csub(g2, g3), cadd(g2, g3));

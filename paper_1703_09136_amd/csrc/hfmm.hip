@@ -150,6 +150,8 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
     for (double kj : {m.k2, m.k3})
       if (kj > k) kmin_over = std::min(kmin_over, std::sqrt(kj * kj - k * k) / k);
     double eps = (kmin_over < 1e299) ? kmin_over : 1.0;  // scale of sigma near tau = 0, pi
+    // the impedance sigma-hat turns from -1 at tau = 0 over k sin(tau) ~ alpha
+    if (m.layers == 1) eps = std::min(1.0, m.alpha / k);
     double wmax = std::min(4.0 / (k * rho + N + 1.0), M_PI / 4.0);
     double s = 0.0;
     while (s < M_PI) {
@@ -198,6 +200,8 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
     double w = wcap;
     double h = (s < r.send) ? r.dip * std::sin(M_PI * s / r.send) : 0.0;
     for (int i = 0; i < nsing; ++i) w = std::min(w, 0.5 * std::hypot(s - tj[i], h));
+    // the impedance sigma-hat's pole at t = i alpha
+    if (m.layers == 1) w = std::min(w, 0.5 * std::hypot(s, m.alpha));
     if (m.layers == 3 && nsing && s > tsmin - 1.0 && s < tsmax + 1.0) w = std::min(w, 0.5 * std::max(h, 1e-6));
     return std::max(w, 1e-6);
   };
@@ -636,9 +640,9 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   hipStream_t stream = (hipStream_t)stream_;
   if (!out) return fail(HFMM_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
-  if (!wavenumbers || !points || (layers > 1 && !interfaces))
+  if (!wavenumbers || !points || !interfaces)
     return fail(HFMM_ERR_INVALID_ARG, "NULL wavenumbers, interfaces or points");
-  if (layers != 2 && layers != 3) return fail(HFMM_ERR_UNSUPPORTED, "layers must be 2 or 3");
+  if (layers != 1 && layers != 2 && layers != 3) return fail(HFMM_ERR_UNSUPPORTED, "layers must be 1, 2 or 3");
   if (n < 1 || n > (int64_t)1 << 30) return fail(HFMM_ERR_INVALID_ARG, "n out of range");
   if (!(tol >= 1e-14 && tol <= 1e-2)) return fail(HFMM_ERR_INVALID_ARG, "tol must be in [1e-14, 1e-2]");
   hfmm_options_t o;
@@ -669,8 +673,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   for (int i = 1; i < layers; ++i)
     if (wavenumbers[i] < wavenumbers[0])
       return fail(HFMM_ERR_UNSUPPORTED, "a lower layer has a smaller wavenumber than the top layer");
-  for (int i = 0; i + 1 < layers; ++i)
+  for (int i = 0; i < std::max(1, layers - 1); ++i)
     if (!std::isfinite(interfaces[i])) return fail(HFMM_ERR_INVALID_ARG, "interfaces must be finite");
+  if (layers == 1 && !(o.impedance > 0.0 && std::isfinite(o.impedance)))
+    return fail(HFMM_ERR_INVALID_ARG, "the impedance half-space (layers = 1) needs impedance > 0");
+  if (layers > 1 && o.impedance != 0.0)
+    return fail(HFMM_ERR_INVALID_ARG, "impedance applies to the half-space (layers = 1) only");
   if (layers == 3 && !(interfaces[0] > interfaces[1]))
     return fail(HFMM_ERR_INVALID_ARG, "interfaces must be strictly decreasing");
 
@@ -706,9 +714,10 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->y_top = interfaces[0];
   pl->med.layers = layers;
   pl->med.k1 = wavenumbers[0];
-  pl->med.k2 = wavenumbers[1];
-  pl->med.k3 = layers == 3 ? wavenumbers[2] : wavenumbers[1];
+  pl->med.k2 = layers == 1 ? wavenumbers[0] : wavenumbers[1];
+  pl->med.k3 = layers == 3 ? wavenumbers[2] : pl->med.k2;
   pl->med.d = layers == 3 ? interfaces[0] - interfaces[1] : 1.0;
+  pl->med.alpha = layers == 1 ? o.impedance : 0.0;
   const double k = pl->med.k1;
   // plan phases (seconds), printed when HFMM_LOG is set
   std::vector<std::pair<const char*, double>> phases;

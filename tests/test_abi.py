@@ -46,7 +46,10 @@ def _plan(lib, layers, k, ifs, n, tol, opts=None, points=1):
 
 @pytest.mark.parametrize("case,expected", [
     (dict(layers=4), 3),
-    (dict(layers=1), 3),
+    (dict(layers=1), 1),
+    (dict(layers=1, opts=dict(impedance=-1.0)), 1),
+    (dict(layers=1, opts=dict(impedance=float("inf"))), 1),
+    (dict(opts=dict(impedance=1.0)), 1),
     (dict(n=0), 1),
     (dict(tol=1e-16), 1),
     (dict(tol=0.5), 1),
