@@ -322,6 +322,37 @@ hfmm_status_t hfmm_tree_copy(hfmm_tree_t tree, double *frame, uint64_t *keys, in
 /* NULL is a no-op. */
 void hfmm_tree_destroy(hfmm_tree_t tree);
 
+/*
+ * A boundary integral equation solved around the matvec (Section 1: the
+ * dense Nystrom system whose applications the method provides): restarted
+ * GMRES(restart) for (A W + D) phi = f with W = diag(w) and
+ *   D_ii = (i/4) w_i [1 + (2i/pi)(ln(k1 w_i / 4) + gamma_E - 1)],
+ * the trapezoidal Nystrom form of the single-layer equation S phi = f on
+ * closed curves in the top layer: the plan's points are the nodes, equispaced
+ * in a periodic parameter of each curve, w_i = |x'(t_i)| dt their weights; A
+ * is the plan's matrix (the domain Green's function between distinct nodes
+ * and the smooth scattered self term), and D adds the free part's logarithmic
+ * singularity integrated over each node's own panel by the small-argument
+ * form of H0^(1) (a first-order local correction, no high-order end-point
+ * corrections). E.g. a sound-soft obstacle lit by u_inc: f = -u_inc at the
+ * nodes; the scattered field is then sum_j G(x, x_j) w_j phi_j.
+ *   w      device [n] doubles, user point order.
+ *   f      device complex [n].
+ *   phi    device complex [n]: the initial guess on entry, the solution on
+ *          return.
+ *   tol    relative residual ||f - (A W + D) phi|| / ||f|| to reach, (0, 1).
+ *   restart, max_iter  Krylov dimension (1..1000) and most matvecs.
+ *   iterations, residual  NULL or host outputs: matvecs used and the final
+ *          relative residual (recomputed with a true product).
+ * The plan's applies run on the stream; the call synchronises it after every
+ * inner product. Returns HFMM_OK also when max_iter ends the iteration: check
+ * *residual. Errors: HFMM_ERR_INVALID_ARG, HFMM_ERR_NO_MEMORY (the Krylov basis
+ * of restart + 1 vectors), and those of hfmm_apply.
+ */
+hfmm_status_t hfmm_bie_solve(hfmm_plan_t plan, const double *w, const double *f, double *phi, double tol,
+                             int32_t restart, int32_t max_iter, int32_t *iterations, double *residual,
+                             hfmm_stream_t stream);
+
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 

@@ -29,7 +29,8 @@ EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoin
            "hfmm_profile_enable", "hfmm_profile_read", "hfmm_stage_name",
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
            "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy",
-           "hfmm_apply_noalloc", "hfmm_tree_build", "hfmm_tree_counts", "hfmm_tree_copy", "hfmm_tree_destroy")
+           "hfmm_apply_noalloc", "hfmm_tree_build", "hfmm_tree_counts", "hfmm_tree_copy", "hfmm_tree_destroy",
+           "hfmm_bie_solve")
 NSTAGES = 9
 HFMM_FP64, HFMM_FP32, HFMM_BF16 = 0, 1, 2
 HFMM_SELF_SCATTERED, HFMM_SELF_NONE = 0, 1
@@ -142,6 +143,8 @@ def load(path: str | None = None):
     lib.hfmm_tree_copy.restype = ctypes.c_int
     lib.hfmm_tree_destroy.argtypes = [vp]
     lib.hfmm_tree_destroy.restype = None
+    lib.hfmm_bie_solve.argtypes = [vp, vp, vp, vp, dbl, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+    lib.hfmm_bie_solve.restype = ctypes.c_int
     lib.hfmm_status_string.argtypes = [ctypes.c_int]
     lib.hfmm_status_string.restype = ctypes.c_char_p
     lib.hfmm_last_error_message.argtypes = []
@@ -331,6 +334,25 @@ class Plan:
         inf = Info()
         _check(self._lib.hfmm_plan_info(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def bie_solve(self, w, f, phi=None, tol=1e-10, restart=50, max_iter=1000, stream=None):
+        """GMRES for (A W + D) phi = f, the Nystrom single-layer system on the
+        plan's nodes with trapezoidal weights w (hfmm_bie_solve); returns
+        (phi, matvecs, relative residual)."""
+        import torch
+        f2 = _as_rhs(f, self.n, "f", self.device)
+        if f2.shape[0] != 1:
+            raise ValueError("one right-hand side")
+        if not (w.is_cuda and w.dtype == torch.float64 and w.numel() == self.n and w.device == self.device):
+            raise TypeError("w must be a float64 CUDA tensor of n weights on the plan's device")
+        w2 = w.contiguous()
+        x = torch.zeros_like(f2) if phi is None else _as_rhs(phi, self.n, "phi", self.device).clone()
+        it = ctypes.c_int32()
+        res = ctypes.c_double()
+        _check(self._lib.hfmm_bie_solve(self._h, ctypes.c_void_p(w2.data_ptr()), ctypes.c_void_p(f2.data_ptr()),
+                                        ctypes.c_void_p(x.data_ptr()), float(tol), int(restart), int(max_iter),
+                                        ctypes.byref(it), ctypes.byref(res), _stream_ptr(stream)))
+        return x[0], int(it.value), float(res.value)
 
     def profile(self, enable=True):
         """Record HIP events between the stages of every apply (hfmm_profile_enable)."""

@@ -578,6 +578,7 @@ hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs, hipStream_t s) {
   return ensure_workspace(pl, rhs_chunk(pl, nrhs));
 }
 int64_t plan_points(hfmm_plan_t pl) { return pl->n; }
+double plan_wavenumber(hfmm_plan_t pl) { return pl->med.k1; }
 int64_t plan_workspace_generation(hfmm_plan_t pl) { return pl->ws_gen; }
 size_t workspace_bytes(hfmm_plan_t pl, int nrhs) {
   auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };

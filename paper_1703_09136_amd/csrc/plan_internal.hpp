@@ -25,6 +25,7 @@ struct Workspace {
 // graph capture (allocations, and the blocked pipeline's expansion matrices)
 hfmm_status_t plan_reserve(hfmm_plan_t pl, int nrhs, hipStream_t s);
 int64_t plan_points(hfmm_plan_t pl);
+double plan_wavenumber(hfmm_plan_t pl);  // k1, the top layer's
 int64_t plan_workspace_generation(hfmm_plan_t pl);
 // sets hfmm_last_error_message and returns st
 hfmm_status_t report(hfmm_status_t st, const std::string& msg);
