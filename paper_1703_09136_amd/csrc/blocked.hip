@@ -32,27 +32,65 @@ __device__ __noinline__ double2 hankel0_large_call(double x) { return hankel0_la
 
 
 // ------------------------------------------------------------------ layout changes
-__global__ void k_gather_blk(int n, int nc, int Rp, const int* __restrict__ perm, const double2* __restrict__ q,
-                             double2* __restrict__ qb, int conj) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * Rp) return;
-  const int j = (int)(idx / Rp), r = (int)(idx % Rp);
-  double2 v = r < nc ? q[(int64_t)r * n + perm[j]] : cmk(0.0, 0.0);
-  if (conj) v.y = -v.y;
-  qb[idx] = v;
+// Both layout changes go through 32 x 32 tiles in LDS (points j by
+// right-hand sides r): the user-order side is read or written along the
+// points (neighbouring sorted points mostly neighbour in input order too),
+// the blocked side along the right-hand sides; a block takes two tiles of
+// consecutive points.
+constexpr int LT = 32;  // tile side
+__global__ void __launch_bounds__(256) k_gather_blk(int n, int nc, int Rp, const int* __restrict__ perm,
+                                                    const double2* __restrict__ q, double2* __restrict__ qb,
+                                                    int conj) {
+  __shared__ double2 t[2][LT][LT + 1];
+  const int tx = threadIdx.x & (LT - 1), ty = threadIdx.x / LT;  // 32 x 8
+  const int w = ty >> 2, sub = ty & 3;                           // the thread's tile, its row phase
+  const int j0 = (blockIdx.x * 2 + w) * LT, r0 = blockIdx.y * LT;
+  // read: lane tx along the points, rows r of the tile by 2
+  const int j = j0 + tx;
+  const int pj = j < n ? perm[j] : 0;
+  for (int rr = sub; rr < LT; rr += 4) {
+    const int r = r0 + rr;
+    double2 v = (j < n && r < nc) ? q[(int64_t)r * n + pj] : cmk(0.0, 0.0);
+    if (conj) v.y = -v.y;
+    t[w][rr][tx] = v;
+  }
+  __syncthreads();
+  // write: lane tx along the right-hand sides
+  for (int jj = sub; jj < LT; jj += 4) {
+    const int jw = j0 + jj, r = r0 + tx;
+    if (jw < n && r < Rp) qb[(int64_t)jw * Rp + r] = t[w][tx][jj];
+  }
 }
 
-__global__ void k_scatter_blk(int n, int nc, int Rp, const int* __restrict__ perm, const double2* __restrict__ ub,
-                              double2* __restrict__ u, const double2* __restrict__ diag,
-                              const double2* __restrict__ qb, int conj) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * Rp) return;
-  const int j = (int)(idx / Rp), r = (int)(idx % Rp);
-  if (r >= nc) return;
-  double2 v = ub[idx];
-  if (diag) v = csub(v, cmul(diag[j], qb[idx]));
-  if (conj) v.y = -v.y;
-  u[(int64_t)r * n + perm[j]] = v;
+__global__ void __launch_bounds__(256) k_scatter_blk(int n, int nc, int Rp, const int* __restrict__ perm,
+                                                     const double2* __restrict__ ub, double2* __restrict__ u,
+                                                     const double2* __restrict__ diag,
+                                                     const double2* __restrict__ qb, int conj) {
+  __shared__ double2 t[2][LT][LT + 1];
+  const int tx = threadIdx.x & (LT - 1), ty = threadIdx.x / LT;
+  const int w = ty >> 2, sub = ty & 3;
+  const int j0 = (blockIdx.x * 2 + w) * LT, r0 = blockIdx.y * LT;
+  // read along the right-hand sides
+  for (int jj = sub; jj < LT; jj += 4) {
+    const int j = j0 + jj, r = r0 + tx;
+    double2 v = cmk(0.0, 0.0);
+    if (j < n && r < nc) {
+      const int64_t idx = (int64_t)j * Rp + r;
+      v = ub[idx];
+      if (diag) v = csub(v, cmul(diag[j], qb[idx]));
+      if (conj) v.y = -v.y;
+    }
+    t[w][jj][tx] = v;
+  }
+  __syncthreads();
+  // write along the points
+  const int j = j0 + tx;
+  if (j >= n) return;
+  const int pj = perm[j];
+  for (int rr = sub; rr < LT; rr += 4) {
+    const int r = r0 + rr;
+    if (r < nc) u[(int64_t)r * n + pj] = t[w][tx][rr];
+  }
 }
 
 __global__ void k_to_f32(int64_t count, const double2* __restrict__ src, float2* __restrict__ dst) {
@@ -100,18 +138,24 @@ __global__ void k_vmat(TreeView tv, const int* __restrict__ leaves, int nl, cons
   }
 }
 
-// alpha[c_b + m][r] = sum_j V[m][j] q[j][r] for one leaf, 64 right-hand sides
-// per block (grid y), a 16-column tile per wave, all row tiles of the leaf's
-// 2(2P + 1) real rows per wave (at most kBlkLeafPmax). The V chunk (32
-// points) is staged in LDS as planes (Re V, Im V, -Im V).
-constexpr int P2M_PC = 32;
-constexpr int BLK_MAX_RT = (2 * (2 * kBlkLeafPmax + 1) + 15) / 16;
+// alpha[c_b + m][r] = sum_j V[m][j] q[j][r] for the leaves of one level, 64
+// right-hand sides per block (grid y), a 16-column tile per wave and all NRT
+// row tiles of the level's 2(2P + 1) real rows per wave. V goes through LDS
+// in chunks of 32 points as the planes Re V and Im V (rows padded so that
+// one wave's operand reads fall in distinct banks; the embedding's -Im V is a
+// sign per lane); the chunk's strengths are loaded into registers before the
+// chunk is staged, so their latency hides behind the staging.
+constexpr int P2M_PC = 32;  // points per chunk
+constexpr int P2M_PS = 34;  // LDS row stride (doubles)
 
+template <int NRT>
 __global__ void __launch_bounds__(BLK_THREADS) k_p2m_blk(TreeView tv, int Rp, const int* __restrict__ leaves,
                                                          int nl, const int64_t* __restrict__ voff,
                                                          const double2* __restrict__ V, const double2* __restrict__ qb,
                                                          double2* __restrict__ ab) {
-  extern __shared__ double lds[];
+  constexpr int MR = 8 * NRT;  // orders the planes hold
+  constexpr int PL = MR * P2M_PS + ((NRT & 1) ? 0 : 16);  // plane stride: the second plane 32 banks over
+  __shared__ double s_v[2 * PL];
   const int li = blockIdx.x;
   if (li >= nl) return;
   const int b = leaves[li];
@@ -122,49 +166,46 @@ __global__ void __launch_bounds__(BLK_THREADS) k_p2m_blk(TreeView tv, int Rp, co
   const double2* Vl = V + voff[li];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = blockIdx.y * kBlkCols + wave * 16 + (lane & 15);
-  const int nrt = (2 * Md + 15) / 16;
-  const int kl = lane >> 4;
-  // lane's operand plane and row offset per row tile: row R = 16 rt + lane % 16
-  const int rp = lane & 1, kp = kl & 1;
-  const int plane = (rp == kp) ? 0 : (rp ? 1 : 2);
-  d4 acc[BLK_MAX_RT];
+  const int kl = lane >> 4, rp = lane & 1, kp = kl & 1;
+  // A = [[Re, -Im], [Im, Re]] V: the lane's plane and sign
+  const double* Lp = s_v + (rp == kp ? 0 : PL) + (kl >> 1);
+  const double sg = (rp == 0 && kp == 1) ? -1.0 : 1.0;
+  int mrow[NRT];
 #pragma unroll
-  for (int j = 0; j < BLK_MAX_RT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-  double* Lr = lds;                     // [Md][P2M_PC] real parts
-  double* Li = Lr + Md * P2M_PC;        // imaginary parts
-  double* Ln = Li + Md * P2M_PC;        // negated imaginary parts
-  const double* Lp = plane == 0 ? Lr : plane == 1 ? Li : Ln;
+  for (int j = 0; j < NRT; ++j) {
+    const int R = 16 * j + (lane & 15);
+    mrow[j] = (R < 2 * Md ? R >> 1 : 0) * P2M_PS;
+  }
+  d4 acc[NRT];
+#pragma unroll
+  for (int j = 0; j < NRT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
   for (int j0 = 0; j0 < np; j0 += P2M_PC) {
     const int nj = min(P2M_PC, np - j0);
-    __syncthreads();
+    double bq[P2M_PC / 2];
+#pragma unroll
+    for (int ks = 0; ks < P2M_PC / 2; ++ks) {
+      const int jj = 2 * ks + (kl >> 1);
+      const double v = ((const double*)(qb + (int64_t)(pr.x + j0 + (jj < nj ? jj : 0)) * Rp + col))[kp];
+      bq[ks] = jj < nj ? v : 0.0;
+    }
+    __syncthreads();  // the previous chunk's operand reads are done
     for (int e = tid; e < Md * P2M_PC; e += BLK_THREADS) {
       const int m = e / P2M_PC, jj = e - m * P2M_PC;
       const double2 v = jj < nj ? Vl[(int64_t)m * np + j0 + jj] : cmk(0.0, 0.0);
-      Lr[e] = v.x;
-      Li[e] = v.y;
-      Ln[e] = -v.y;
+      s_v[m * P2M_PS + jj] = v.x;
+      s_v[PL + m * P2M_PS + jj] = v.y;
     }
     __syncthreads();
-    // k = 2 jj + part over the chunk's points, four per step
-    const int nks = (2 * nj + 3) / 4;
-    for (int ks = 0; ks < nks; ++ks) {
-      const int jj = 2 * ks + (kl >> 1);
-      const double bq = jj < nj ? ((const double*)(qb + (int64_t)(pr.x + j0 + jj) * Rp + col))[kp] : 0.0;
 #pragma unroll
-      for (int j = 0; j < BLK_MAX_RT; ++j) {
-        if (j < nrt) {
-          const int R = 16 * j + (lane & 15);
-          const int m = R < 2 * Md ? R >> 1 : 0;
-          const double a = Lp[m * P2M_PC + jj];
-          acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq, acc[j], 0, 0, 0);
-        }
-      }
+    for (int ks = 0; ks < P2M_PC / 2; ++ks) {
+#pragma unroll
+      for (int j = 0; j < NRT; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sg * Lp[mrow[j] + 2 * ks], bq[ks], acc[j], 0, 0, 0);
     }
   }
   const int64_t cb = tv.coff[b];
 #pragma unroll
-  for (int j = 0; j < BLK_MAX_RT; ++j) {
-    if (j >= nrt) continue;
+  for (int j = 0; j < NRT; ++j) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int R = 16 * j + 4 * i + kl;
@@ -174,16 +215,76 @@ __global__ void __launch_bounds__(BLK_THREADS) k_p2m_blk(TreeView tv, int Rp, co
 }
 
 // u[j][r] += (i/4) sum_m conj(V[m][j]) beta[c_b + m][r] for the points of one
-// leaf: rows are the leaf's points (2 np real rows, 64 points per group of
-// eight row tiles), k the 2(2P + 1) real orders. The embedding of conj(V):
-// [2j][2m] = Re V, [2j][2m+1] = Im V, [2j+1][2m] = -Im V, [2j+1][2m+1] = Re V;
-// V is staged in LDS sixteen orders at a time as planes (Re V, Im V, -Im V).
-constexpr int L2P_MC = 16;
+// leaf: rows are the leaf's points (2 np real rows; groups of up to 64 points,
+// NRT row tiles for the group's rows), k the 2(2P + 1) real orders. The
+// embedding of conj(V): [2j][2m] = Re V, [2j][2m+1] = Im V, [2j+1][2m] =
+// -Im V, [2j+1][2m+1] = Re V; V is staged in LDS sixteen orders at a time as
+// the planes Re V and Im V (padded rows: one wave's reads in distinct banks),
+// the chunk's local coefficients loaded into registers before the staging.
+constexpr int L2P_MC = 16;  // orders per chunk
+constexpr int L2P_RS = 72;  // LDS row stride (doubles)
+constexpr int L2P_PL = L2P_MC * L2P_RS + 16;  // plane stride: the second plane 32 banks over
+
+template <int NRT>
+__device__ inline void l2p_group(int Md, int np, int g0, int ng, int64_t cb, int pr0, int Rp, int col,
+                                 const double2* __restrict__ Vl, const double2* __restrict__ bb,
+                                 double2* __restrict__ ub, double* s_v) {
+  const int tid = threadIdx.x, lane = tid & 63, kl = lane >> 4, rp = lane & 1, kp = kl & 1;
+  const double* Lp = s_v + (rp == kp ? 0 : L2P_PL) + (kl >> 1) * L2P_RS;
+  const double sg = (rp == 1 && kp == 0) ? -1.0 : 1.0;
+  int prow[NRT];
+#pragma unroll
+  for (int j = 0; j < NRT; ++j) {
+    const int R = 16 * j + (lane & 15);
+    prow[j] = R < 2 * ng ? R >> 1 : 0;
+  }
+  d4 acc[NRT];
+#pragma unroll
+  for (int j = 0; j < NRT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int m0 = 0; m0 < Md; m0 += L2P_MC) {
+    double bq[L2P_MC / 2];
+#pragma unroll
+    for (int ks = 0; ks < L2P_MC / 2; ++ks) {
+      const int m = m0 + 2 * ks + (kl >> 1);
+      const double v = ((const double*)(bb + (cb + (m < Md ? m : 0)) * Rp + col))[kp];
+      bq[ks] = m < Md ? v : 0.0;
+    }
+    __syncthreads();  // the previous chunk's operand reads are done
+    for (int e = tid; e < L2P_MC * 64; e += BLK_THREADS) {
+      const int mi = e >> 6, jp = e & 63;
+      const double2 v = (m0 + mi < Md && jp < ng) ? Vl[(int64_t)(m0 + mi) * np + g0 + jp] : cmk(0.0, 0.0);
+      s_v[mi * L2P_RS + jp] = v.x;
+      s_v[L2P_PL + mi * L2P_RS + jp] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < L2P_MC / 2; ++ks) {
+#pragma unroll
+      for (int j = 0; j < NRT; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(sg * Lp[2 * ks * L2P_RS + prow[j]], bq[ks], acc[j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NRT; ++j) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      // (i/4) z: the real row takes -Im z / 4, the imaginary row Re z / 4;
+      // the partner row (R ^ 1) sits in the lane 16 apart (kl ^ 1)
+      const int R = 16 * j + 4 * i + kl;
+      const double other = __shfl_xor(acc[j][i], 16, WAVE);
+      if (R < 2 * ng) {
+        double* o = (double*)(ub + (int64_t)(pr0 + g0 + (R >> 1)) * Rp + col) + (R & 1);
+        *o += (R & 1) ? 0.25 * other : -0.25 * other;
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(BLK_THREADS) k_l2p_blk(TreeView tv, int Rp, const int* __restrict__ leaves,
                                                          int nl, const int64_t* __restrict__ voff,
                                                          const double2* __restrict__ V, const double2* __restrict__ bb,
                                                          double2* __restrict__ ub) {
-  __shared__ double s_v[3][L2P_MC][64];
+  __shared__ double s_v[2 * L2P_PL];
   const int li = blockIdx.x;
   if (li >= nl) return;
   const int b = leaves[li];
@@ -192,58 +293,20 @@ __global__ void __launch_bounds__(BLK_THREADS) k_l2p_blk(TreeView tv, int Rp, co
   const int2 pr = tv.prange[b];
   const int np = pr.y - pr.x;
   const double2* Vl = V + voff[li];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int col = blockIdx.y * kBlkCols + wave * 16 + (lane & 15);
-  const int kl = lane >> 4;
-  const int rp = lane & 1, kp = kl & 1;
-  const int plane = (rp == kp) ? 0 : (rp ? 2 : 1);
+  const int wave = threadIdx.x >> 6;
+  const int col = blockIdx.y * kBlkCols + wave * 16 + (threadIdx.x & 15);
   const int64_t cb = tv.coff[b];
-  for (int g0 = 0; g0 < np; g0 += 64) {  // groups of 64 points: 8 row tiles
+  for (int g0 = 0; g0 < np; g0 += 64) {  // groups of 64 points, the last one by its row tiles
     const int ng = min(64, np - g0);
-    const int nrt = (2 * ng + 15) / 16;
-    d4 acc[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int m0 = 0; m0 < Md; m0 += L2P_MC) {
-      __syncthreads();
-      for (int e = tid; e < L2P_MC * 64; e += BLK_THREADS) {
-        const int mi = e >> 6, jp = e & 63;
-        const double2 v = (m0 + mi < Md && jp < ng) ? Vl[(int64_t)(m0 + mi) * np + g0 + jp] : cmk(0.0, 0.0);
-        s_v[0][mi][jp] = v.x;
-        s_v[1][mi][jp] = v.y;
-        s_v[2][mi][jp] = -v.y;
-      }
-      __syncthreads();
-      const int nks = (2 * min(L2P_MC, Md - m0) + 3) / 4;
-      for (int ks = 0; ks < nks; ++ks) {
-        const int mi = 2 * ks + (kl >> 1);
-        const int m = m0 + mi;
-        const double bq = m < Md ? ((const double*)(bb + (cb + m) * Rp + col))[kp] : 0.0;
-        const double* Lp = &s_v[plane][mi][0];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          if (j < nrt) {
-            const int R = 16 * j + (lane & 15);
-            const double a = Lp[R < 2 * ng ? (R >> 1) : 0];
-            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq, acc[j], 0, 0, 0);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (j >= nrt) continue;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        // (i/4) z: the real row takes -Im z / 4, the imaginary row Re z / 4;
-        // the partner row (R ^ 1) sits in the lane 16 apart (kl ^ 1)
-        const int R = 16 * j + 4 * i + kl;
-        const double other = __shfl_xor(acc[j][i], 16, WAVE);
-        if (R < 2 * ng) {
-          double* o = (double*)(ub + (int64_t)(pr.x + g0 + (R >> 1)) * Rp + col) + (R & 1);
-          *o += (R & 1) ? 0.25 * other : -0.25 * other;
-        }
-      }
+    switch ((2 * ng + 15) / 16) {
+      case 1: l2p_group<1>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      case 2: l2p_group<2>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      case 3: l2p_group<3>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      case 4: l2p_group<4>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      case 5: l2p_group<5>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      case 6: l2p_group<6>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      case 7: l2p_group<7>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
+      default: l2p_group<8>(Md, np, g0, ng, cb, pr.x, Rp, col, Vl, bb, ub, s_v); break;
     }
   }
 }
@@ -797,12 +860,12 @@ static inline int nblk(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 void launch_gather_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* q, double2* qb,
                        int conj) {
-  hipLaunchKernelGGL(k_gather_blk, dim3(nblk((int64_t)n * Rp, 256)), dim3(256), 0, s, n, nc, Rp, perm, q, qb, conj);
+  hipLaunchKernelGGL(k_gather_blk, dim3(nblk(n, 2 * LT), Rp / LT), dim3(256), 0, s, n, nc, Rp, perm, q, qb, conj);
 }
 void launch_scatter_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, const double2* ub, double2* u,
                         const double2* diag, const double2* qb, int conj) {
-  hipLaunchKernelGGL(k_scatter_blk, dim3(nblk((int64_t)n * Rp, 256)), dim3(256), 0, s, n, nc, Rp, perm, ub, u, diag,
-                     qb, conj);
+  hipLaunchKernelGGL(k_scatter_blk, dim3(nblk(n, 2 * LT), (nc + LT - 1) / LT), dim3(256), 0, s, n, nc, Rp, perm, ub,
+                     u, diag, qb, conj);
 }
 void launch_to_f32(hipStream_t s, int64_t count, const double2* src, float2* dst) {
   if (count > 0) hipLaunchKernelGGL(k_to_f32, dim3(nblk(count, 256)), dim3(256), 0, s, count, src, dst);
@@ -810,12 +873,23 @@ void launch_to_f32(hipStream_t s, int64_t count, const double2* src, float2* dst
 void launch_vmat(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int64_t* voff, double2* V) {
   if (nl > 0) hipLaunchKernelGGL(k_vmat, dim3(nl), dim3(64), 0, s, tv, leaves, nl, voff, V);
 }
-static size_t p2m_blk_lds(int Pmax) { return sizeof(double) * 3 * (size_t)(2 * Pmax + 1) * P2M_PC; }
-void launch_p2m_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, int Pmax,
+template <int NRT>
+static void p2m_one(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, const int64_t* voff,
+                    const double2* V, const double2* qb, double2* ab) {
+  hipLaunchKernelGGL((k_p2m_blk<NRT>), dim3(nl, Rp / kBlkCols), dim3(BLK_THREADS), 0, s, tv, Rp, leaves, nl, voff, V,
+                     qb, ab);
+}
+void launch_p2m_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, int P,
                      const int64_t* voff, const double2* V, const double2* qb, double2* ab) {
-  if (nl > 0)
-    hipLaunchKernelGGL(k_p2m_blk, dim3(nl, Rp / kBlkCols), dim3(BLK_THREADS), p2m_blk_lds(Pmax), s, tv, Rp, leaves, nl,
-                       voff, V, qb, ab);
+  if (nl <= 0) return;
+  switch ((2 * (2 * P + 1) + 15) / 16) {
+#define HFMM_P2M(N) \
+  case N: p2m_one<N>(s, tv, Rp, leaves, nl, voff, V, qb, ab); break;
+    HFMM_P2M(1) HFMM_P2M(2) HFMM_P2M(3) HFMM_P2M(4) HFMM_P2M(5) HFMM_P2M(6) HFMM_P2M(7) HFMM_P2M(8) HFMM_P2M(9)
+    HFMM_P2M(10) HFMM_P2M(11)
+#undef HFMM_P2M
+    default: break;
+  }
 }
 void launch_l2p_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, const int64_t* voff,
                      const double2* V, const double2* bb, double2* ub) {
@@ -926,7 +1000,7 @@ hipError_t init_blocked_attributes() {
                       (const void*)k_tgemm<BLK_F64, 8>,  (const void*)k_tgemm<BLK_F32, 2>,
                       (const void*)k_tgemm<BLK_F32, 4>,  (const void*)k_tgemm<BLK_F32, 8>,
                       (const void*)k_tgemm<BLK_BF16, 2>, (const void*)k_tgemm<BLK_BF16, 4>,
-                      (const void*)k_tgemm<BLK_BF16, 8>, (const void*)k_p2m_blk};
+                      (const void*)k_tgemm<BLK_BF16, 8>};
   for (const void* f : fs) {
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, f);

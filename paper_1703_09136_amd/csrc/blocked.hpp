@@ -50,8 +50,8 @@ struct BpItem {
 
 constexpr int kBlkCols = 64;  // right-hand sides per block (four 16-column tiles)
 constexpr int kTgMaxNt = 8;   // row tiles per translation item
-// most expansion order of a leaf for the blocked P2M stage (three planes of
-// (2P + 1) x 32 doubles in LDS, all row tiles of a leaf in one wave)
+// most expansion order of a leaf for the blocked P2M stage (two planes of
+// (2P + 1) x 34 doubles in LDS, all row tiles of a leaf in one wave)
 constexpr int kBlkLeafPmax = 40;
 
 // gather: qb[j * Rp + r] = q[(r0 + r) * n + perm[j]] (conj: conjugated) for r < nc, 0 past nc
@@ -65,7 +65,9 @@ void launch_scatter_blk(hipStream_t s, int n, int nc, int Rp, const int* perm, c
 // voff[leaf]; P2M over leaves stores alpha rows = V q, L2P adds
 // u rows += (i/4) conj(V)^T beta.
 void launch_vmat(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int64_t* voff, double2* V);
-void launch_p2m_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, int Pmax,
+// P2M for leaves of one level (order P): leaves and voff point at that
+// level's first leaf
+void launch_p2m_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, int P,
                      const int64_t* voff, const double2* V, const double2* qb, double2* ab);
 void launch_l2p_blk2(hipStream_t s, const TreeView& tv, int Rp, const int* leaves, int nl, const int64_t* voff,
                      const double2* V, const double2* bb, double2* ub);

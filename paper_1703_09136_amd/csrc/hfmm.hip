@@ -130,7 +130,7 @@ constexpr double kOrderSafety = HFMM_ORDER_SAFETY;
 // 2P+1 coefficients and the 4P+1 table entries in LDS
 constexpr int kMaxOrder = 255;
 constexpr int kScaleStride = kMaxOrder + 1;  // scale factors per level
-constexpr int kUpDownNt = 4;  // row tiles per item of the blocked M2M and L2L
+constexpr int kUpDownNt = 8;  // row tiles per item of the blocked M2M and L2L
 // Launch shaping: the CUs of the GPU (MI355X: 256), the LDS of one CU, and the
 // most dynamic LDS a translation block may take (the CU's less the kernel's
 // static offsets).
@@ -1949,7 +1949,11 @@ hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrh
     launch_gather_blk(s, pl->n, nc, Rp, pl->perm.p, qc, pl->qb.p, conj);
     if (pl->blk_prec_p2p == BLK_F32) launch_to_f32(s, n * Rp, pl->qb.p, pl->qlo.p);
     launch_fill_zero(s, pl->ub.p, n * Rp);
-    launch_p2m_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->leaf_pmax, pl->vmat_off.p, pl->vmat.p, pl->qb.p, pl->ab.p);
+    for (int l = 2; l < pl->nlev; ++l) {
+      const int l0 = pl->leaf_lev[l], l1 = pl->leaf_lev[l + 1];
+      launch_p2m_blk2(s, tv, Rp, pl->leaves.p + l0, l1 - l0, pl->P[l], pl->vmat_off.p + (l0 - lb2), pl->vmat.p,
+                      pl->qb.p, pl->ab.p);
+    }
     for (int l = pl->nlev - 2; l >= pl->top; --l) tg(pl->m2m_tg[l], BLK_F64, kUpDownNt, pl->ab.p, nullptr, pl->ab.p, 0);
     if (pl->blk_prec_m2l != BLK_F64)
       launch_scale_blk(s, pl->blk_prec_m2l, tv, Rp, pl->lev_begin[pl->top], (int)pl->boxes.size(), pl->blk_scale.p,
