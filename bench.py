@@ -141,7 +141,7 @@ def blocked_work(info):
 
 
 def ideal_seconds(work, prec, nrhs):
-    """Sum over stages of work / peak (the survey's roofline definition): M2L
+    """Sum over stages of algorithmic work / peak (the roofline bound): M2L
     and the near field at the peak of their arithmetic, the rest FP64."""
     m2l_peak = PEAKS[prec]
     p2p_peak = PEAKS["f64"] if prec == "f64" else PEAKS["f32"]
