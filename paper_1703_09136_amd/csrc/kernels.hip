@@ -1217,7 +1217,10 @@ __global__ void k_table_bessel(int ntab, const double* __restrict__ dx, const do
 //                 + e^{-i lambda X} (-1)^n z^{-n}] sigma_1(lambda) dt,
 // lambda = sqrt(t^2 + k^2), z = (lambda - t)/k (so that (-lambda - t)/k = -1/z).
 // The t contour dips below the real axis over the branch points and guided-mode
-// poles of sigma_1. One block per (X, Y); a thread owns 8 consecutive orders.
+// poles of sigma_1. One block per (X, Y): the block's threads split into G
+// groups of 8 consecutive orders and H = 256 / G phases of the quadrature
+// nodes (thread (g, h) sums the nodes h, h + H, ... for its orders), and the
+// H partial sums of each group are added through LDS.
 struct ImageTableArgs {
   Medium med;
   int ncombo;
@@ -1239,6 +1242,7 @@ constexpr int TB_NB = 8;
 __global__ void __launch_bounds__(TB_THREADS) k_table_image(ImageTableArgs a) {
   __shared__ double2 s_l0a[TB_THREADS], s_lsa[TB_THREADS], s_l0b[TB_THREADS], s_lsb[TB_THREADS];
   __shared__ int s_kind[TB_THREADS];
+  __shared__ double2 s_red[TB_THREADS * TB_NB];
   int cb = blockIdx.x;
   if (cb >= a.ncombo) return;
   int tid = threadIdx.x;
@@ -1247,7 +1251,12 @@ __global__ void __launch_bounds__(TB_THREADS) k_table_image(ImageTableArgs a) {
   const double dip = a.dip[cb], send = a.send[cb];
   TableRef tr = a.refs[cb];
   const int N = tr.half;
-  const int n0 = -N + TB_NB * tid;
+  // order groups (at most 128: N <= 2 kMaxOrder) and node phases
+  const int G = (2 * N + TB_NB) / TB_NB;
+  const int H = TB_THREADS / G;
+  const int grp = tid % G, ph = tid / G;
+  const bool active = ph < H;
+  const int n0 = -N + TB_NB * grp;
   // class "i":  i^n * sum exp(l0 + n ls)   (tau nodes; t nodes' minus branch)
   // class "mi": (-i)^n * sum exp(l0 + n ls) (t nodes' plus branch)
   double2 acc_i[TB_NB], acc_mi[TB_NB];
@@ -1302,9 +1311,9 @@ __global__ void __launch_bounds__(TB_THREADS) k_table_image(ImageTableArgs a) {
     s_kind[tid] = kind;
     s_l0a[tid] = l0a; s_lsa[tid] = lsa; s_l0b[tid] = l0b; s_lsb[tid] = lsb;
     __syncthreads();
-    if (n0 <= N) {
+    if (active) {
       int qn = min(TB_THREADS, nnode - q0);
-      for (int qq = 0; qq < qn; ++qq) {
+      for (int qq = ph; qq < qn; qq += H) {
         int kd = s_kind[qq];
         double2 la = s_l0a[qq], sa = s_lsa[qq];
         double2 v = cexp2(cadd(la, cscale(sa, (double)n0)));
@@ -1325,6 +1334,24 @@ __global__ void __launch_bounds__(TB_THREADS) k_table_image(ImageTableArgs a) {
       }
     }
   }
+  // sum the node phases of each order group (phase order fixed)
+  for (int cls = 0; cls < 2; ++cls) {
+    __syncthreads();
+    if (active)
+      for (int j = 0; j < TB_NB; ++j) s_red[tid * TB_NB + j] = cls == 0 ? acc_i[j] : acc_mi[j];
+    __syncthreads();
+    if (ph == 0) {
+      for (int j = 0; j < TB_NB; ++j) {
+        double2 v = s_red[grp * TB_NB + j];
+        for (int h = 1; h < H; ++h) v = cadd(v, s_red[(h * G + grp) * TB_NB + j]);
+        if (cls == 0)
+          acc_i[j] = v;
+        else
+          acc_mi[j] = v;
+      }
+    }
+  }
+  if (ph != 0) return;
   double2* T = a.tdata + tr.off + tr.half;
   for (int j = 0; j < TB_NB; ++j) {
     int n = n0 + j;
