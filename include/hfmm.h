@@ -125,8 +125,8 @@ typedef struct {
                                for few right-hand sides, each pass being 64
                                columns wide. hfmm_plan fails with
                                HFMM_ERR_UNSUPPORTED where that pipeline
-                               cannot run (near-interface quadrature pairs, or
-                               a leaf expansion order above 40); coordinate
+                               cannot run (a leaf expansion order above
+                               40); coordinate
                                gradients and hfmm_apply_noalloc return
                                HFMM_ERR_UNSUPPORTED */
   int32_t order;            /* 0 (default): expansion order per level from
@@ -169,6 +169,10 @@ typedef struct {
                                the many-right-hand-side contraction, chosen by
                                timing the candidates 2, 4, 8 on the plan's own
                                launch at its first such apply (0: not yet) */
+  int32_t interface_nodes;  /* nodes of the near-interface quadrature rule
+                               (0 without direct Sommerfeld pairs) */
+  int64_t interface_leaf_pairs; /* (target leaf, source box) pairs of the
+                               direct Sommerfeld part */
 } hfmm_info_t;
 
 /* Default options. */

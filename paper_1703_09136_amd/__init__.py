@@ -86,7 +86,8 @@ class Info(ctypes.Structure):
                 ("image_tables", ctypes.c_int64), ("flops_m2l", ctypes.c_double),
                 ("flops_updown", ctypes.c_double), ("flops_p2p", ctypes.c_double),
                 ("plan_seconds", ctypes.c_double), ("p2p_evals", ctypes.c_int64),
-                ("top_level", ctypes.c_int32), ("m2l_tile", ctypes.c_int32)]
+                ("top_level", ctypes.c_int32), ("m2l_tile", ctypes.c_int32),
+                ("interface_nodes", ctypes.c_int32), ("interface_leaf_pairs", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "order"}
@@ -212,7 +213,8 @@ def _as_rhs(t, n, name, device=None):
         raise ValueError("%s must have shape (n,) or (nrhs, n)" % name)
     if t2.shape[1] != n or t2.shape[0] < 1:
         raise ValueError("%s must have shape (nrhs, %d)" % (name, n))
-    return t2.contiguous()
+    # a lazily conjugated or negated view holds the unconjugated values in memory
+    return t2.resolve_conj().resolve_neg().contiguous()
 
 
 def _check_out(out, q2, name):
@@ -220,6 +222,8 @@ def _check_out(out, q2, name):
     import torch
     if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous()):
         raise TypeError("%s must be a contiguous complex128 CUDA tensor" % name)
+    if out.is_conj() or out.is_neg():
+        raise TypeError("%s must not be a conjugated or negated view" % name)
     if out.device != q2.device or tuple(out.shape) not in ((q2.shape[0], q2.shape[1]),) + \
             (((q2.shape[1],),) if q2.shape[0] == 1 else ()):
         raise ValueError("%s must have shape %s on %s" % (name, tuple(q2.shape), q2.device))

@@ -24,6 +24,7 @@
 #include "special.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -31,6 +32,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -138,13 +140,16 @@ constexpr int64_t kNumCu = 256;
 constexpr size_t kCuLds = 160 * 1024;
 constexpr size_t kSplitLdsMax = kCuLds - 1024;
 
-Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
+// cut: the t range ends where the integrand has fallen by e^-cut from its
+// largest value (44 by default, below double precision)
+Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N, double cut = 44.0) {
   Rule r;
   const double k = m.k1;
   xmax = std::fabs(xmax);
   double rho = std::hypot(xmax, ymax);
   // tau part: the phase k (Y sin tau - X cos tau) - n tau changes by at most
-  // k rho + N per unit tau; <= 4 radians per 16-point panel.
+  // k rho + N per unit tau (plus the slab's, below); <= 4 radians per 16-point
+  // panel.
   {
     double kmin_over = 1e300;
     for (double kj : {m.k2, m.k3})
@@ -152,7 +157,12 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
     double eps = (kmin_over < 1e299) ? kmin_over : 1.0;  // scale of sigma near tau = 0, pi
     // the impedance sigma-hat turns from -1 at tau = 0 over k sin(tau) ~ alpha
     if (m.layers == 1) eps = std::min(1.0, m.alpha / k);
-    double wmax = std::min(4.0 / (k * rho + N + 1.0), M_PI / 4.0);
+    // three layers: sigma_1 carries the slab round trip e^{-2 gamma_2 d}, whose
+    // phase 2 d sqrt(k2^2 - k1^2 cos^2 tau) turns at up to
+    // min(d k1^2 / sqrt(k2^2 - k1^2), 2 d k1) per unit tau
+    double slab = 0.0;
+    if (m.layers == 3 && m.k2 > k) slab = std::min(m.d * k * k / std::sqrt(m.k2 * m.k2 - k * k), 2.0 * m.d * k);
+    double wmax = std::min(4.0 / (k * rho + N + 1.0 + slab), M_PI / 4.0);
     double s = 0.0;
     while (s < M_PI) {
       double dist = std::min(s, M_PI - s);
@@ -192,7 +202,7 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
     }
   }
   double tend = std::max(tpk, 1.0);
-  while (f(tend) > fmaxv - 44.0) tend *= 1.25;
+  while (f(tend) > fmaxv - cut) tend *= 1.25;
   tend = std::max(tend, r.send + 1.0);
   const double rate = ymax + xmax + (double)N / k;
   const double wcap = std::max(4.0 / rate, 1e-6);
@@ -225,6 +235,25 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N) {
 }
 
 }  // namespace
+
+// fn(i) for i in [0, n) on up to 16 host threads (plan-time work whose items
+// are independent; each item writes only its own slot)
+template <class F>
+void parallel_for(int n, F fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min({hw, 16, std::max(1, n / 8)});
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::atomic<int> next{0};
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&]() {
+      for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) fn(i);
+    });
+  for (auto& t : th) t.join();
+}
 
 struct hfmm_plan_s {
   Allocator al{};  // where the plan's device memory comes from
@@ -292,11 +321,21 @@ struct hfmm_plan_s {
   int p2p_cls_ptr[kH0Classes + 2] = {0};  // items of series class c: [p2p_cls_ptr[c], p2p_cls_ptr[c + 1])
   DevBuf<int2> p2p_rng;
   int np2p_items = 0;
-  DevBuf<int> if_leaves, if_ptr;
-  DevBuf<int2> if_rng;
-  int nif_leaves = 0;
-  DevBuf<double2> qc, qky, qkx;
-  int nq = 0;
+  // near-interface pairs: source boxes, target leaves and their source slots,
+  // the rules' nodes (the classes' lists and nodes one after another), the
+  // node sums of one group of right-hand sides (shared by the classes, which
+  // run in sequence); ifl holds the classes' device pointers and sizes
+  DevBuf<int> if_sbox, if_tleaf, if_tptr, if_tsrc;
+  DevBuf<double2> qc, qky, qkx, if_S, if_T;
+  std::vector<IfaceLists> ifl;  // one per class of pairs (one rule each)
+  // tables of the horizontally separated near-interface pairs, one per class
+  // that has such pairs (lists, panel edges and coefficients one after another)
+  DevBuf<int> ift_tleaf, ift_tptr, ift_tsrc, ift_item_t;
+  DevBuf<int2> ift_item_e;
+  DevBuf<double4> ift_xpan;
+  DevBuf<int2> ift_ypan;
+  DevBuf<double2> ift_coef;
+  std::vector<IfTable> ift;
   int ws_nrhs = 0;
   int64_t ws_gen = 0;  // bumped whenever the workspace buffers are reallocated
   DevBuf<double2> qs, us, alpha, beta;
@@ -376,7 +415,10 @@ struct hfmm_plan_s {
     red_boxes.release(); red_ptr.release(); red_beg.release(); redT_ptr.release(); redT_beg.release(); cp_child.release();
     cp_parent.release(); up_doff.release(); up_soff4.release(); up_items.release(); down_items.release(); contrib.release();
     tabs.release(); tdata.release(); p2p_ptr.release();
-    p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_leaves.release(); if_ptr.release(); if_rng.release(); qc.release();
+    p2p_items.release(); p2p_sym.release(); p2p_rng.release(); if_sbox.release(); if_tleaf.release(); if_tptr.release(); if_tsrc.release(); qc.release();
+    if_S.release(); if_T.release(); ift_tleaf.release(); ift_tptr.release(); ift_tsrc.release(); ift_xpan.release(); ift_ypan.release();
+    ift_item_t.release(); ift_item_e.release();
+    ift_coef.release();
     qky.release(); qkx.release(); qs.release(); us.release(); alpha.release(); beta.release(); gq.release(); gs.release();
     self_g.release(); self_dy.release();
     tg_items.release(); tg_pairs.release(); bp_items.release(); bp_rng.release(); vmat_off.release(); vmat.release();
@@ -402,6 +444,11 @@ namespace {
 // on 32 geometries x 256 right-hand sides, 4 GiB the same as 2). HFMM_RHS_CHUNK
 // in the environment caps the pass size further (diagnostics and tests).
 constexpr double kContribBudget = 2048.0 * 1024 * 1024;
+// device bytes of the near-interface node sums of one group of right-hand
+// sides, and the classes of near-interface pairs (octaves of the least height
+// sum)
+constexpr size_t kIfBufBudget = (size_t)256 << 20;
+constexpr int kIfClasses = 24;
 int rhs_chunk(hfmm_plan_t pl, int nrhs) {
   const double per_rhs = 8.0 * (double)std::max<int64_t>(pl->cstride, 1);
   int c = std::max(1, std::min(nrhs, (int)std::max(1.0, kContribBudget / per_rhs)));
@@ -1141,10 +1188,9 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       v.swap(m);
     }
   };
-  std::vector<std::vector<int2>> u_per, i_per;
+  std::vector<std::vector<int2>> u_per;
   int64_t np2p = 0, nifp = 0;
   group(fu, u_per, np2p);
-  group(iu, i_per, nifp);
   // Bounding boxes of the points of every leaf, then of every merged source
   // range (a union of whole leaves, found through the leaves in point order).
   std::vector<double4> leaf_bb(leaves.size());
@@ -1172,6 +1218,116 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     }
     return bb;
   };
+  // Near-interface pairs: per target leaf (every leaf under a pair's target
+  // box) its source boxes in point order; a source box inside another box of
+  // the same leaf's list adds no pairs (the pairs form a set), so it is
+  // dropped. Each (leaf, source box) pair then goes to a class by the least
+  // height sum Y = y_i + y_j its point bounding boxes allow, in octaves above
+  // the least over all pairs: the Sommerfeld rule of a class reaches t ~ 44 /
+  // Y_min with panels ~ 4 / (Y_max + X_max) wide, so the few pairs right at
+  // the interface get the long rule and the rest short ones.
+  struct IfPair {
+    int li, sb, cls;
+    double ylo, yhi, xsp, gap;  // Y range, largest |X| and least |X| of the pair
+    double tw;                  // width in x of the target leaf's points
+  };
+  std::vector<IfPair> ifp;
+  {
+    std::vector<std::vector<int>> per_leaf(leaves.size());
+    std::vector<int> tl;
+    for (auto& pr : iu) {
+      tl.clear();
+      leaves_under(pr.t, tl);
+      for (int t : tl) per_leaf[leaf_index[t]].push_back(pr.s);
+    }
+    for (size_t li = 0; li < leaves.size(); ++li) {
+      std::vector<int>& v = per_leaf[li];
+      if (v.empty()) continue;
+      // by first point, the larger of two boxes with the same first point first
+      std::sort(v.begin(), v.end(), [&](int a, int b) {
+        return B[a].begin != B[b].begin ? B[a].begin < B[b].begin : B[a].end > B[b].end;
+      });
+      const int nt = B[leaves[li]].end - B[leaves[li]].begin;
+      const double4& tb = leaf_bb[li];
+      int reach = -1;
+      for (int sb : v) {
+        if (B[sb].end <= reach) continue;  // box ranges nest or are disjoint
+        reach = B[sb].end;
+        const double4 sbb = range_bb(make_int2(B[sb].begin, B[sb].end));
+        if (std::isfinite(sbb.z) && std::isfinite(sbb.w))
+          ifp.push_back({(int)li, sb, 0, tb.z + sbb.z, tb.w + sbb.w, std::max(tb.y - sbb.x, sbb.y - tb.x),
+                         std::max(0.0, std::max(tb.x - sbb.y, sbb.x - tb.y)), tb.y - tb.x});
+        else  // not a union of leaves: the extent of all points
+          ifp.push_back({(int)li, sb, 0, 2.0 * ymin, 2.0 * ymax, S, 0.0, tb.y - tb.x});
+        nifp += (int64_t)nt * (B[sb].end - B[sb].begin);
+      }
+    }
+  }
+  // Within a class, pairs at least X0 apart in x go to its table, the rest
+  // (neighbours) to its quadrature rule: X0 is the class's widest target leaf,
+  // at most its largest Y. The quadrature rule's length grows with its |X|
+  // range; the table's panels only in number as X0 shrinks.
+  struct IfClass {
+    std::vector<int> sbox, tleaf, tptr{0}, tsrc;  // quadrature pairs
+    double xsp = 0.0, ylo = INFINITY, yhi = 0.0;
+    std::vector<int> ftleaf, ftptr{0}, ftsrc;      // table pairs (source box ids)
+    double x0 = 0.0, fxmax = 0.0, fylo = INFINITY, fyhi = 0.0;
+  };
+  std::vector<IfClass> ifc;
+  {
+    double y0 = INFINITY;
+    for (const IfPair& p : ifp) y0 = std::min(y0, p.ylo);
+    y0 = std::max(y0, 1e-12);
+    for (IfPair& p : ifp)
+      p.cls = std::min(kIfClasses - 1, (int)std::floor(std::log2(std::max(p.ylo, y0) / y0)));
+    std::stable_sort(ifp.begin(), ifp.end(), [](const IfPair& a, const IfPair& b) { return a.cls < b.cls; });
+    std::vector<int> slot_of(nb, -1);
+    for (size_t a = 0; a < ifp.size();) {
+      size_t b = a;
+      double yall = 0.0, wall = 0.0;
+      for (; b < ifp.size() && ifp[b].cls == ifp[a].cls; ++b) {
+        yall = std::max(yall, ifp[b].yhi);
+        wall = std::max(wall, ifp[b].tw);
+      }
+      IfClass C;
+      C.x0 = std::max(std::min(yall, wall), 1e-3 * yall);
+      // HFMM_IFACE_TABLE=0 in the environment: every pair by quadrature
+      // (diagnostics and tests)
+      if (const char* env = std::getenv("HFMM_IFACE_TABLE"))
+        if (env[0] == '0') C.x0 = INFINITY;
+      for (size_t i = a; i < b; ++i) {  // leaves in order, each one's pairs together
+        const IfPair& p = ifp[i];
+        if (p.gap >= C.x0) {
+          if (C.ftleaf.empty() || C.ftleaf.back() != leaves[p.li]) {
+            if (!C.ftleaf.empty()) C.ftptr.push_back((int)C.ftsrc.size());
+            C.ftleaf.push_back(leaves[p.li]);
+          }
+          C.ftsrc.push_back(p.sb);
+          C.fxmax = std::max(C.fxmax, p.xsp);
+          C.fylo = std::min(C.fylo, p.ylo);
+          C.fyhi = std::max(C.fyhi, p.yhi);
+          continue;
+        }
+        if (C.tleaf.empty() || C.tleaf.back() != leaves[p.li]) {
+          if (!C.tleaf.empty()) C.tptr.push_back((int)C.tsrc.size());
+          C.tleaf.push_back(leaves[p.li]);
+        }
+        if (slot_of[p.sb] < 0) {
+          slot_of[p.sb] = (int)C.sbox.size();
+          C.sbox.push_back(p.sb);
+        }
+        C.tsrc.push_back(slot_of[p.sb]);
+        C.xsp = std::max(C.xsp, p.xsp);
+        C.ylo = std::min(C.ylo, p.ylo);
+        C.yhi = std::max(C.yhi, p.yhi);
+      }
+      if (!C.tleaf.empty()) C.tptr.push_back((int)C.tsrc.size());
+      if (!C.ftleaf.empty()) C.ftptr.push_back((int)C.ftsrc.size());
+      for (int sb : C.sbox) slot_of[sb] = -1;
+      ifc.push_back(std::move(C));
+      a = b;
+    }
+  }
   // H0 series class of a (target leaf, source range) pair from the largest
   // z = (k r / 2)^2 its two boxes allow
   const double qk2 = 0.25 * pl->med.k1 * pl->med.k1;
@@ -1283,8 +1439,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   for (int c = 0; c <= kH0Classes + 1; ++c) pl->p2p_cls_ptr[c] = 0;
   for (auto& it : items) ++pl->p2p_cls_ptr[it.cls + 1];
   for (int c = 1; c <= kH0Classes + 1; ++c) pl->p2p_cls_ptr[c] += pl->p2p_cls_ptr[c - 1];
-  std::vector<int> p2p_ptr(1, 0), p2p_items, p2p_sym, if_ptr(1, 0), if_leaves;
-  std::vector<int2> p2p_rng, if_rng;
+  std::vector<int> p2p_ptr(1, 0), p2p_items, p2p_sym;
+  std::vector<int2> p2p_rng;
   int64_t p2p_evals = 0;
   double p2p_flops = 0.0;
   for (auto& it : items) {
@@ -1304,13 +1460,6 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   }
   pl->p2p_evals = p2p_evals;
   pl->p2p_flops = p2p_flops;
-  for (size_t li = 0; li < leaves.size(); ++li) {
-    if (!i_per[li].empty()) {
-      if_leaves.push_back(leaves[li]);
-      if_rng.insert(if_rng.end(), i_per[li].begin(), i_per[li].end());
-      if_ptr.push_back((int)if_rng.size());
-    }
-  }
 
   phase("direct lists");
   // ---- lists of the right-hand-side-blocked pipeline: per target box its
@@ -1475,17 +1624,20 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         staged = staged && tgemm_supported(BLK_F64, pl->P[l + 1], pl->P[l]) &&
                  tgemm_supported(BLK_F64, pl->P[l], pl->P[l + 1]);
     }
-    pl->blk_ok = iu.empty() && pl->leaf_pmax <= kBlkLeafPmax && staged;
+    pl->blk_ok = pl->leaf_pmax <= kBlkLeafPmax && staged;
   }
   if (o.deterministic && !pl->blk_ok) {
     fail(HFMM_ERR_UNSUPPORTED,
          "deterministic mode runs every apply through the right-hand-side-blocked pipeline, which this plan cannot "
-         "use (near-interface quadrature pairs, or a leaf expansion order above " + std::to_string(kBlkLeafPmax) + ")");
+         "use (a leaf expansion order above " + std::to_string(kBlkLeafPmax) + ")");
     return bail(HFMM_ERR_UNSUPPORTED);
   }
 
   phase("blocked lists");
-  // ---- near-interface rule (one rule covering every direct image pair)
+  // ---- near-interface rules. Their t ranges end where e^{-t Y_min} has
+  // fallen to tol / 100 (times e^-3): past it the tail of the integral, about
+  // e^{-t Y} / (t Y), is below the plan's accuracy.
+  const double if_cut = std::log(100.0 / pl->tol) + 3.0;
   std::vector<double2> qc, qky, qkx;
   double glx[16], glw[16];
   gauss_legendre16(glx, glw);
@@ -1520,22 +1672,25 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       }
     }
   };
-  if (!iu.empty()) {
-    double xsp = 0.0, yhi = 0.0;
-    for (auto& pr : iu) {
-      double bt = pl->bsize[B[pr.t].level];
-      double xt0 = xmin + B[pr.t].ix * bt, xs0 = xmin + B[pr.s].ix * bt;
-      xsp = std::max(xsp, std::fabs(xt0 - xs0) + bt);
-      yhi = std::max(yhi, 2.0 * ymin + (B[pr.t].iy + B[pr.s].iy + 2) * bt);
+  // one rule per class of near-interface pairs, over its X and Y ranges
+  std::vector<int> if_node_off;
+  for (const IfClass& C : ifc) {
+    if (C.tleaf.empty()) {
+      if_node_off.push_back((int)qc.size());
+      continue;
     }
-    const double ylo = std::max(2.0 * ymin, 1e-12);
-    Rule r = build_rule(pl->med, xsp, ylo, yhi, 0);
+    Rule r = build_rule(pl->med, C.xsp, C.ylo, C.yhi, 0, if_cut);
     if (!r.ok) {
       fail(HFMM_ERR_ACCURACY, "near-interface quadrature rule too long");
       return bail(HFMM_ERR_ACCURACY);
     }
+    if_node_off.push_back((int)qc.size());
     rule_nodes(r, qc, qky, qkx);
+    if (log_on())
+      std::fprintf(stderr, "[hfmm] near-interface class: %zu leaves, %zu pairs, X <= %.3g, Y in [%.3g, %.3g]: %d nodes\n",
+                   C.tleaf.size(), C.tsrc.size(), C.xsp, C.ylo, C.yhi, (int)qc.size() - if_node_off.back());
   }
+  if_node_off.push_back((int)qc.size());
   // HFMM_SELF_NONE: a rule for X = 0 and Y over [2 ymin, 2 ymax] gives every
   // point's scattered self term and its height derivative
   std::vector<double2> sc_c, sc_ky, sc_kx;
@@ -1552,7 +1707,16 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   std::vector<double> cX, cY, cdip, csend;
   std::vector<int> cpbeg(1, 0);
   std::vector<Panel> cpanels;
-  for (auto& cb : combos) {
+  // the rules are independent: built on a few host threads, joined in order
+  std::vector<Rule> crules(combos.size());
+  parallel_for((int)combos.size(), [&](int i) {
+    const auto& cb = combos[i];
+    const double b = pl->bsize[cb.level];
+    crules[i] = build_rule(pl->med, cb.dix * b, 2.0 * ymin + (cb.m + 1) * b, 2.0 * ymin + (cb.m + 1) * b,
+                           2 * pl->P[cb.level]);
+  });
+  for (size_t i = 0; i < combos.size(); ++i) {
+    const auto& cb = combos[i];
     double b = pl->bsize[cb.level];
     double X = cb.dix * b;
     double Y = 2.0 * ymin + (cb.m + 1) * b;
@@ -1561,7 +1725,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       fail(HFMM_ERR_ACCURACY, "heterogeneous table order too large");
       return bail(HFMM_ERR_ACCURACY);
     }
-    Rule r = build_rule(pl->med, X, Y, Y, N);
+    const Rule& r = crules[i];
     if (!r.ok) {
       fail(HFMM_ERR_ACCURACY, "heterogeneous table quadrature rule too long");
       return bail(HFMM_ERR_ACCURACY);
@@ -1601,6 +1765,13 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   };
   const std::vector<int64_t> m2l_soff = offsets_of(m2l_psrc), m2l_toff = offsets_of(m2l_pdst);
   const std::vector<int64_t> cp_child_off = offsets_of(cp_child), cp_parent_off = offsets_of(cp_parent);
+  std::vector<int> if_sbox, if_tleaf, if_tptr, if_tsrc;
+  for (const IfClass& C : ifc) {
+    if_sbox.insert(if_sbox.end(), C.sbox.begin(), C.sbox.end());
+    if_tleaf.insert(if_tleaf.end(), C.tleaf.begin(), C.tleaf.end());
+    if_tptr.insert(if_tptr.end(), C.tptr.begin(), C.tptr.end());
+    if_tsrc.insert(if_tsrc.end(), C.tsrc.begin(), C.tsrc.end());
+  }
   hipError_t e = hipSuccess;
 #define UP(buf, vec)                                  \
   if (e == hipSuccess) e = pl->buf.upload(vec, stream);
@@ -1610,10 +1781,26 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   UP(red_boxes, red_boxes) UP(red_ptr, red_ptr) UP(red_beg, red_beg) UP(redT_ptr, redT_ptr)
   UP(redT_beg, redT_beg) UP(cp_child, cp_child_off) UP(cp_parent, cp_parent_off) UP(up_doff, up_doff_h) UP(up_soff4, up_soff4_h) UP(up_items, up_items)
   UP(down_items, down_items) UP(tabs, tabs) UP(p2p_ptr, p2p_ptr)
-  UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_leaves, if_leaves) UP(if_ptr, if_ptr) UP(if_rng, if_rng) UP(qc, qc)
+  UP(p2p_items, p2p_items) UP(p2p_sym, p2p_sym) UP(p2p_rng, p2p_rng) UP(if_sbox, if_sbox) UP(if_tleaf, if_tleaf) UP(if_tptr, if_tptr) UP(if_tsrc, if_tsrc) UP(qc, qc)
   UP(qky, qky) UP(qkx, qkx)
   UP(tg_items, tg_items_h) UP(tg_pairs, tg_pairs_h) UP(bp_items, bp_items_h) UP(bp_rng, bp_rng_h)
   UP(vmat_off, voff_h) UP(blk_scale, scale_h) UP(coff16, coff16_h)
+  // node sums of the near-interface stages, for groups of up to kIfRhs
+  // right-hand sides (fewer where the group would pass kIfBufBudget)
+  {
+    size_t s_max = 0, t_max = 0;
+    for (size_t c = 0; c < ifc.size(); ++c) {
+      const size_t nqp = (size_t)(if_node_off[c + 1] - if_node_off[c] + 63) / 64 * 64;
+      s_max = std::max(s_max, nqp * ifc[c].sbox.size());
+      t_max = std::max(t_max, nqp * ifc[c].tleaf.size());
+    }
+    int rif = kIfRhs;
+    while (rif > 1 && sizeof(double2) * (s_max + t_max) * (size_t)rif > kIfBufBudget) rif /= 2;
+    if (e == hipSuccess) e = pl->if_S.alloc(s_max * rif);
+    if (e == hipSuccess) e = pl->if_T.alloc(t_max * rif);
+    pl->ifl.assign(ifc.size(), IfaceLists{});
+    for (IfaceLists& L : pl->ifl) L.rif = rif;
+  }
   DevBuf<double> d_fhdx, d_fhdy, d_fbdx, d_fbdy, d_cX, d_cY, d_cdip, d_csend, d_glx, d_glw;
   DevBuf<int> d_fhref, d_fbsgn, d_fbref, d_cpbeg, d_imgref;
   DevBuf<Panel> d_cpanels;
@@ -1685,8 +1872,207 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   pl->nleaves = (int)leaves.size();
   pl->np2p_items = (int)p2p_items.size();
   pl->nred_boxes = (int)red_boxes.size();
-  pl->nif_leaves = (int)if_leaves.size();
-  pl->nq = (int)qc.size();
+  {
+    size_t o_sb = 0, o_tl = 0, o_tp = 0, o_ts = 0;
+    for (size_t c = 0; c < ifc.size(); ++c) {
+      IfaceLists& L = pl->ifl[c];
+      L.nsb = (int)ifc[c].sbox.size();
+      L.ntl = (int)ifc[c].tleaf.size();
+      L.nq = if_node_off[c + 1] - if_node_off[c];
+      L.nqp = (L.nq + 63) / 64 * 64;
+      L.sbox = pl->if_sbox.p + o_sb;
+      L.tleaf = pl->if_tleaf.p + o_tl;
+      L.tptr = pl->if_tptr.p + o_tp;
+      L.tsrc = pl->if_tsrc.p + o_ts;
+      L.qc = pl->qc.p + if_node_off[c];
+      L.qky = pl->qky.p + if_node_off[c];
+      L.qkx = pl->qkx.p + if_node_off[c];
+      L.S = pl->if_S.p;
+      L.T = pl->if_T.p;
+      o_sb += ifc[c].sbox.size();
+      o_tl += ifc[c].tleaf.size();
+      o_tp += ifc[c].tptr.size();
+      o_ts += ifc[c].tsrc.size();
+    }
+  }
+
+  // ---- tables of the horizontally separated near-interface pairs. Panel
+  // sizes for a relative error tol / 100 with kIfTP Chebyshev points: the
+  // Bernstein ellipse of a panel [a, a + w] of |X| stays clear of the
+  // singularities at X = +-iY when w <= 2 a / (A - 1), A = (rho + 1 / rho) / 2,
+  // rho^P = 100 / tol; the wave part e^{i k X} (k up to the largest wavenumber
+  // of the medium, or of the impedance surface wave) needs half widths with
+  // (k h / 2)^P / P! <= tol / 100. Y panels likewise, X >= X0 away.
+  int64_t if_table_pairs = 0;
+  {
+    const double tol_eff = 0.01 * pl->tol;
+    const double rho = std::pow(1.0 / tol_eff, 1.0 / kIfTP);
+    const double A = 0.5 * (rho + 1.0 / rho);
+    double kmax = std::max(pl->med.k1, std::max(pl->med.k2, pl->med.k3));
+    if (pl->med.layers == 1) kmax = std::hypot(pl->med.k1, pl->med.alpha);
+    double fact = 1.0;
+    for (int i = 2; i <= kIfTP; ++i) fact *= i;
+    const double wosc = 4.0 * std::pow(fact * tol_eff, 1.0 / kIfTP) / kmax;
+    double cosm[kIfTP][kIfTP];  // cos(pi a (m + 1/2) / P)
+    for (int a = 0; a < kIfTP; ++a)
+      for (int m = 0; m < kIfTP; ++m) cosm[a][m] = std::cos(M_PI * a * (m + 0.5) / kIfTP);
+    std::vector<int> tl_all, tp_all, ts_all, it_all;
+    std::vector<int2> ie_all;
+    std::vector<double4> xe_all;
+    std::vector<int2> yp_all;
+    std::vector<double2> cf_all;
+    std::vector<size_t> offs;  // per table: tleaf, tptr, tsrc, xpan, coef, item offsets
+    for (const IfClass& C : ifc) {
+      if (C.ftleaf.empty()) continue;
+      IfTable T{};
+      const double g = 1.0 + 2.0 / (A - 1.0);
+      std::vector<double> xe{C.x0};
+      int p1 = 0;
+      while (xe.size() < 2 || xe.back() < C.fxmax) {
+        const double a = xe.back();
+        if (p1 == (int)xe.size() - 1 && 2.0 * a / (A - 1.0) < wosc) {
+          xe.push_back(a * g);
+          ++p1;
+        } else {
+          xe.push_back(xe[p1] + (double)((int)xe.size() - p1) * wosc);
+        }
+        if (xe.size() > 200000) {
+          fail(HFMM_ERR_ACCURACY, "near-interface table too long");
+          return bail(HFMM_ERR_ACCURACY);
+        }
+      }
+      T.npx = (int)xe.size() - 1;
+      T.x0 = C.x0;
+      T.p1 = p1;
+      T.a1 = xe[p1];
+      T.wmax = wosc;
+      T.inv_x0 = 1.0 / C.x0;
+      T.inv_wmax = 1.0 / wosc;
+      T.inv_lg2 = (float)(1.0 / std::log2(g));
+      // Y panels per panel of |X|: the singularities in Y sit |X| off the
+      // real axis, so the farther panels take wider ones
+      const double yr = std::max(C.fyhi - C.fylo, 1e-12 * std::max(1.0, C.fylo));
+      T.ylo = C.fylo;
+      std::vector<double4> xp(T.npx);
+      std::vector<int2> yp(T.npx);
+      int64_t npan = 0;
+      for (int px = 0; px < T.npx; ++px) {
+        const double wy_max = std::min(2.0 * xe[px] / (A - 1.0), wosc);
+        const int npy = std::max(1, (int)std::ceil(yr / wy_max));
+        xp[px] = make_double4(xe[px], 1.0 / (xe[px + 1] - xe[px]), yr / npy, npy / yr);
+        yp[px] = make_int2(npy, (int)npan);
+        npan += npy;
+      }
+      // values at the panels' Chebyshev points from one rule over the whole range
+      const int64_t npts = npan * kIfTP * kIfTP;
+      std::vector<double2> gxy((size_t)npts);
+      for (int px = 0; px < T.npx; ++px)
+        for (int py = 0; py < yp[px].x; ++py)
+          for (int m = 0; m < kIfTP; ++m)
+            for (int nn = 0; nn < kIfTP; ++nn) {
+              const double u = std::cos(M_PI * (m + 0.5) / kIfTP), v = std::cos(M_PI * (nn + 0.5) / kIfTP);
+              const double X = 0.5 * (xe[px] + xe[px + 1]) + 0.5 * (xe[px + 1] - xe[px]) * u;
+              const double wy = xp[px].z;
+              const double Y = T.ylo + (py + 0.5) * wy + 0.5 * wy * v;
+              gxy[(((size_t)(yp[px].y + py)) * kIfTP + m) * kIfTP + nn] = cmk(X, Y);
+            }
+      Rule r = build_rule(pl->med, xe.back(), C.fylo, C.fylo + yr, 0, if_cut);
+      if (!r.ok) {
+        fail(HFMM_ERR_ACCURACY, "near-interface table rule too long");
+        return bail(HFMM_ERR_ACCURACY);
+      }
+      std::vector<double2> rc, rky, rkx;
+      rule_nodes(r, rc, rky, rkx);
+      DevBuf<double2> d_xy, d_c, d_ky, d_kx, d_out;
+      hipError_t eg = d_xy.upload(gxy, stream);
+      if (eg == hipSuccess) eg = d_c.upload(rc, stream);
+      if (eg == hipSuccess) eg = d_ky.upload(rky, stream);
+      if (eg == hipSuccess) eg = d_kx.upload(rkx, stream);
+      if (eg == hipSuccess) eg = d_out.alloc((size_t)3 * npts);
+      std::vector<double2> vals((size_t)3 * npts);
+      if (eg == hipSuccess) {
+        launch_if_grid(stream, (int)npts, d_xy.p, (int)rc.size(), d_c.p, d_ky.p, d_kx.p, d_out.p);
+        eg = hipMemcpyAsync(vals.data(), d_out.p, sizeof(double2) * vals.size(), hipMemcpyDeviceToHost, stream);
+      }
+      if (eg == hipSuccess) eg = hipStreamSynchronize(stream);
+      if (eg != hipSuccess) {
+        fail(eg == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
+             std::string("near-interface table: ") + hipGetErrorString(eg));
+        return bail(eg == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE);
+      }
+      // coefficients c_ab = (2/P)^2 sum_mn f_mn cos(pi a (m+1/2)/P) cos(pi b (n+1/2)/P),
+      // halved for a = 0 and for b = 0
+      const size_t cf0 = cf_all.size();
+      cf_all.resize(cf0 + (size_t)npan * 3 * kIfTri);
+      std::vector<double2> tmp((size_t)kIfTP * kIfTP);
+      for (int64_t pn = 0; pn < npan; ++pn)
+        for (int f = 0; f < 3; ++f) {
+          const double2* fv = vals.data() + (size_t)f * npts + (size_t)pn * kIfTP * kIfTP;
+          for (int a = 0; a < kIfTP; ++a)
+            for (int nn = 0; nn < kIfTP; ++nn) {
+              double2 acc = cmk(0, 0);
+              for (int m = 0; m < kIfTP; ++m) acc = cadd(acc, cscale(fv[m * kIfTP + nn], cosm[a][m]));
+              tmp[a * kIfTP + nn] = acc;
+            }
+          double2* out = cf_all.data() + cf0 + ((size_t)pn * 3 + f) * kIfTri;
+          int k = 0;  // rows a = 0, 1, ... of b < P - a, packed
+          for (int a = 0; a < kIfTP; ++a)
+            for (int b = 0; b < kIfTP - a; ++b) {
+              double2 acc = cmk(0, 0);
+              for (int nn = 0; nn < kIfTP; ++nn) acc = cadd(acc, cscale(tmp[a * kIfTP + nn], cosm[b][nn]));
+              const double sc = (2.0 / kIfTP) * (2.0 / kIfTP) * (a == 0 ? 0.5 : 1.0) * (b == 0 ? 0.5 : 1.0);
+              out[k++] = cscale(acc, sc);
+            }
+        }
+      if (log_on())
+        std::fprintf(stderr,
+                     "[hfmm] near-interface table: %zu leaves, %zu pairs, |X| in [%.3g, %.3g], Y in [%.3g, %.3g]: "
+                     "%d x %d panels (%lld in all) from a rule of %zu nodes\n",
+                     C.ftleaf.size(), C.ftsrc.size(), C.x0, xe.back(), C.fylo, C.fylo + yr, T.npx, yp[0].x,
+                     (long long)npan, rc.size());
+      offs.insert(offs.end(), {tl_all.size(), tp_all.size(), ts_all.size(), xe_all.size(), cf0, it_all.size()});
+      // work items for launches with atomic additions: four source boxes of
+      // one leaf (one per wave of the block)
+      for (int t = 0; t < (int)C.ftleaf.size(); ++t)
+        for (int e = C.ftptr[t]; e < C.ftptr[t + 1]; e += 4) {
+          it_all.push_back(t);
+          ie_all.push_back(make_int2(e, std::min(e + 4, C.ftptr[t + 1])));
+        }
+      T.nitem = (int)(it_all.size() - offs.back());
+      tl_all.insert(tl_all.end(), C.ftleaf.begin(), C.ftleaf.end());
+      tp_all.insert(tp_all.end(), C.ftptr.begin(), C.ftptr.end());
+      ts_all.insert(ts_all.end(), C.ftsrc.begin(), C.ftsrc.end());
+      xe_all.insert(xe_all.end(), xp.begin(), xp.end());
+      yp_all.insert(yp_all.end(), yp.begin(), yp.end());
+      T.ntl = (int)C.ftleaf.size();
+      pl->ift.push_back(T);
+      if_table_pairs += (int64_t)C.ftsrc.size();
+    }
+    hipError_t et = pl->ift_tleaf.upload(tl_all, stream);
+    if (et == hipSuccess) et = pl->ift_tptr.upload(tp_all, stream);
+    if (et == hipSuccess) et = pl->ift_tsrc.upload(ts_all, stream);
+    if (et == hipSuccess) et = pl->ift_xpan.upload(xe_all, stream);
+    if (et == hipSuccess) et = pl->ift_ypan.upload(yp_all, stream);
+    if (et == hipSuccess) et = pl->ift_coef.upload(cf_all, stream);
+    if (et == hipSuccess) et = pl->ift_item_t.upload(it_all, stream);
+    if (et == hipSuccess) et = pl->ift_item_e.upload(ie_all, stream);
+    if (et != hipSuccess) {
+      fail(et == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
+           std::string("near-interface tables: ") + hipGetErrorString(et));
+      return bail(et == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE);
+    }
+    for (size_t c = 0; c < pl->ift.size(); ++c) {
+      IfTable& T = pl->ift[c];
+      T.tleaf = pl->ift_tleaf.p + offs[6 * c];
+      T.tptr = pl->ift_tptr.p + offs[6 * c + 1];
+      T.tsrc = pl->ift_tsrc.p + offs[6 * c + 2];
+      T.xpan = pl->ift_xpan.p + offs[6 * c + 3];
+      T.ypan = pl->ift_ypan.p + offs[6 * c + 3];
+      T.coef = pl->ift_coef.p + offs[6 * c + 4];
+      T.item_t = pl->ift_item_t.p + offs[6 * c + 5];
+      T.item_e = pl->ift_item_e.p + offs[6 * c + 5];
+    }
+  }
 
   phase("upload and tables");
   // ---- statistics
@@ -1699,6 +2085,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   inf.image_pairs = (int64_t)iv.size();
   inf.p2p_pairs = np2p;
   inf.interface_pairs = nifp;
+  inf.interface_nodes = (int32_t)qc.size();
+  inf.interface_leaf_pairs = (int64_t)if_tsrc.size() + if_table_pairs;
   inf.image_tables = (int64_t)combos.size();
   double fm2l = 0.0;
   for (auto& pr : fv) { double m = 2.0 * pl->P[B[pr.t].level] + 1; fm2l += 8.0 * m * m; }
@@ -1811,8 +2199,8 @@ void launch_near(hfmm_plan_t pl, const TreeView& tv, hipStream_t s, const double
   launch_p2p(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, qs, us,
              pl->precision == HFMM_FP32);
   if (mark) (*mark)();
-  launch_iface(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p, pl->qky.p,
-               pl->qkx.p, qs, us);
+  launch_iface(s, tv, pl->ifl.data(), (int)pl->ifl.size(), tv.nrhs, qs, us, 1, tv.n, 1);
+  launch_iface_table(s, tv, pl->ift.data(), (int)pl->ift.size(), tv.nrhs, qs, us, 1, tv.n, 1);
   if (mark) (*mark)();
 }
 
@@ -1966,6 +2354,8 @@ hfmm_status_t blocked_passes(hfmm_plan_t pl, const double* q, double* u, int nrh
     launch_l2p_blk2(s, tv, Rp, pl->leaves.p + lb2, nl2, pl->vmat_off.p, pl->vmat.p, pl->bb.p, pl->ub.p);
     launch_p2p_blk(s, tv, pl->blk_prec_p2p, Rp, pl->bp_items.p, pl->bp_cls_ptr, pl->bp_rng.p, pl->qb.p, pl->qlo.p,
                    pl->ub.p);
+    launch_iface(s, tv, pl->ifl.data(), (int)pl->ifl.size(), nc, pl->qb.p, pl->ub.p, Rp, 1, 0);
+    launch_iface_table(s, tv, pl->ift.data(), (int)pl->ift.size(), nc, pl->qb.p, pl->ub.p, Rp, 1, 0);
     launch_scatter_blk(s, pl->n, nc, Rp, pl->perm.p, pl->ub.p, uc, pl->self_g.p, pl->qb.p, conj);
   }
   HIP_TRY(hipGetLastError());
@@ -2090,8 +2480,8 @@ hfmm_status_t hfmm_apply_adjoint(hfmm_plan_t pl, const double* v, double* w, int
       launch_l2p_grad(s, tv, pl->leaves.p, pl->nleaves, pl->leaf_pmax, pl->alpha.p, pl->gq.p, pl->gs.p, r0 > 0);
       launch_p2p_grad(s, tv, pl->p2p_items.p, pl->p2p_cls_ptr, pl->p2p_ptr.p, pl->p2p_rng.p, pl->p2p_sym.p, pl->qs.p,
                       pl->gq.p, pl->gs.p);
-      launch_iface_grad(s, tv, pl->if_leaves.p, pl->nif_leaves, pl->if_ptr.p, pl->if_rng.p, pl->nq, pl->qc.p,
-                        pl->qky.p, pl->qkx.p, pl->qs.p, pl->gq.p, pl->gs.p);
+      launch_iface_grad(s, tv, pl->ifl.data(), (int)pl->ifl.size(), nc, pl->qs.p, pl->gq.p, pl->gs.p);
+      launch_iface_table_grad(s, tv, pl->ift.data(), (int)pl->ift.size(), nc, pl->qs.p, pl->gq.p, pl->gs.p);
       // HFMM_SELF_NONE: the pair (j, j) of the scattered part is not in A
       if (pl->self_dy.p) launch_self_grad(s, pl->n, nc, pl->self_dy.p, pl->qs.p, pl->gq.p, pl->gs.p);
     }

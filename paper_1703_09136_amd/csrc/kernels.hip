@@ -1021,122 +1021,390 @@ __global__ void __launch_bounds__(WAVE) k_p2p_grad(TreeView tv, const int* __res
 // ------------------------------------------------------------------ near-interface direct
 // u_i += sum_j q_j G^s(x_i, x_j) for image pairs that are not admissible, with
 // G^s = sum_q c_q exp(ky_q (y_i + y_j) + kx_q (x_i - x_j)) the Sommerfeld
-// integral under a fixed rule (the propagating tau part and the evanescent t
-// part on a contour below the real-axis singularities). The sum over sources
-// moves inside the rule: per node S_q = sum_j q_j exp(ky_q y_j - kx_q x_j).
-__global__ void __launch_bounds__(WAVE) k_iface(TreeView tv, const int* __restrict__ leaves, int nleaves,
-                                                const int* __restrict__ ptr, const int2* __restrict__ rng,
-                                                int nq, const double2* __restrict__ qc, const double2* __restrict__ qky,
-                                                const double2* __restrict__ qkx, const double2* __restrict__ qs,
-                                                double2* __restrict__ us) {
-  __shared__ double2 s_c[WAVE], s_ky[WAVE], s_kx[WAVE];
-  int li = blockIdx.x;
-  if (li >= nleaves) return;
-  int b = leaves[li];
-  int lane = threadIdx.x;
-  int2 pr = tv.prange[b];
-  double xref = tv.ctr[b].x;
-  for (int r = 0; r < tv.nrhs; ++r) {
-    for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
-      int i = c0 + lane;
-      bool valid = i < pr.y;
-      double2 xi = valid ? tv.pts[i] : cmk(0, 0);
-      double2 acc = cmk(0, 0);
-      for (int e = ptr[li]; e < ptr[li + 1]; ++e) {
-        int2 sr = rng[e];
-        for (int q0 = 0; q0 < nq; q0 += WAVE) {
-          int q = q0 + lane;
-          double2 sq = cmk(0, 0), ky = cmk(0, 0), kx = cmk(0, 0), cq = cmk(0, 0);
-          if (q < nq) {
-            ky = qky[q]; kx = qkx[q]; cq = qc[q];
-            for (int j = sr.x; j < sr.y; ++j) {
-              double2 xj = tv.pts[j];
-              double2 ex = cadd(cscale(ky, xj.y), cscale(kx, -(xj.x - xref)));
-              sq = cadd(sq, cmul(qs[(int64_t)r * tv.n + j], cexp2(ex)));
-            }
-          }
-          __syncthreads();
-          s_c[lane] = cmul(cq, sq);
-          s_ky[lane] = ky;
-          s_kx[lane] = kx;
-          __syncthreads();
-          int qn = min(WAVE, nq - q0);
-          if (valid)
-            for (int qq = 0; qq < qn; ++qq) {
-              double2 ex = cadd(cscale(s_ky[qq], xi.y), cscale(s_kx[qq], xi.x - xref));
-              acc = cadd(acc, cmul(s_c[qq], cexp2(ex)));
+// integral under one fixed rule (the propagating tau part and the evanescent t
+// part on a contour below the real-axis singularities). Every node term
+// factors through box centres, kx (x_i - x_j) = kx (x_i - x_t) + kx (x_t -
+// x_s) + kx (x_s - x_j), so the pairs go in three stages:
+//   k_if_src    S_q(s) = sum_{j in s} q_j exp(ky_q y_j - kx_q (x_j - x_s)),
+//               once per source box;
+//   k_if_trans  T_q(t) = c_q sum_s S_q(s) exp(kx_q (x_t - x_s)) over the source
+//               boxes of target leaf t;
+//   k_if_eval   u_i += sum_q T_q(t) exp(ky_q y_i + kx_q (x_i - x_t)) for the
+//               points of t.
+// Every factor stays bounded: Re(ky) <= 0 above the interface, and the x
+// offsets are at most the rule's x separation. The right-hand sides go in
+// groups of up to kIfRhs (one exponential serves the whole group); element r
+// of point j sits at j * ps + r * rs.
+
+// S for the source boxes: grid (nsb, nqp / 64), four waves split the points
+// of a box, lane = node
+__global__ void __launch_bounds__(256) k_if_src(TreeView tv, const int* __restrict__ sbox, int nq, int nqp, int rif,
+                                                const double2* __restrict__ qky, const double2* __restrict__ qkx,
+                                                const double2* __restrict__ qs, int64_t ps, int64_t rs, int nr,
+                                                double2* __restrict__ S) {
+  __shared__ double2 s_red[3][kIfRhs][WAVE];
+  const int slot = blockIdx.x, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int q = blockIdx.y * WAVE + lane;
+  const int b = sbox[slot];
+  const int2 pr = tv.prange[b];
+  const double xs = tv.ctr[b].x;
+  double2 ky = cmk(0, 0), kx = cmk(0, 0);
+  if (q < nq) {
+    ky = qky[q];
+    kx = qkx[q];
+  }
+  double2 acc[kIfRhs];
+#pragma unroll
+  for (int r = 0; r < kIfRhs; ++r) acc[r] = cmk(0, 0);
+  for (int j = pr.x + w; j < pr.y; j += 4) {
+    const double2 xj = tv.pts[j];
+    const double2 e = cexp2(cadd(cscale(ky, xj.y), cscale(kx, xs - xj.x)));
+    const double2* qj = qs + (int64_t)j * ps;
+#pragma unroll
+    for (int r = 0; r < kIfRhs; ++r)
+      if (r < nr) acc[r] = cadd(acc[r], cmul(qj[r * rs], e));
+  }
+  if (w > 0)
+#pragma unroll
+    for (int r = 0; r < kIfRhs; ++r)
+      if (r < nr) s_red[w - 1][r][lane] = acc[r];
+  __syncthreads();
+  if (w == 0)
+#pragma unroll
+    for (int r = 0; r < kIfRhs; ++r)
+      if (r < nr) {
+        double2 v = cadd(cadd(acc[r], s_red[0][r][lane]), cadd(s_red[1][r][lane], s_red[2][r][lane]));
+        S[((int64_t)slot * rif + r) * nqp + q] = q < nq ? v : cmk(0, 0);
+      }
+}
+
+// T for the target leaves: grid (ntl, nqp / 64), lane = node
+__global__ void __launch_bounds__(WAVE) k_if_trans(TreeView tv, const int* __restrict__ tleaf,
+                                                   const int* __restrict__ tptr, const int* __restrict__ tsrc,
+                                                   const int* __restrict__ sbox, int nq, int nqp, int rif,
+                                                   const double2* __restrict__ qc, const double2* __restrict__ qkx,
+                                                   const double2* __restrict__ S, int nr, double2* __restrict__ T) {
+  const int t = blockIdx.x, lane = threadIdx.x;
+  const int q = blockIdx.y * WAVE + lane;
+  const double xt = tv.ctr[tleaf[t]].x;
+  double2 kx = cmk(0, 0), c = cmk(0, 0);
+  if (q < nq) {
+    kx = qkx[q];
+    c = qc[q];
+  }
+  double2 acc[kIfRhs];
+#pragma unroll
+  for (int r = 0; r < kIfRhs; ++r) acc[r] = cmk(0, 0);
+  for (int e = tptr[t]; e < tptr[t + 1]; ++e) {
+    const int sl = tsrc[e];
+    const double2 f = cexp2(cscale(kx, xt - tv.ctr[sbox[sl]].x));
+    const double2* Ss = S + (int64_t)sl * rif * nqp + q;
+#pragma unroll
+    for (int r = 0; r < kIfRhs; ++r)
+      if (r < nr) acc[r] = cadd(acc[r], cmul(Ss[(int64_t)r * nqp], f));
+  }
+#pragma unroll
+  for (int r = 0; r < kIfRhs; ++r)
+    if (r < nr) T[((int64_t)t * rif + r) * nqp + q] = cmul(c, acc[r]);
+}
+
+// Evaluation at the points of the target leaves: a block per (leaf, range
+// of nodes), four waves taking every fourth 64-node chunk of the range. A
+// chunk of nt <= 64 target points occupies the lanes of a wave floor(64 / nt)
+// times over (lane groups), the groups taking every G-th node; the groups'
+// and waves' sums meet in LDS in a fixed order. With one range per leaf
+// (gridDim.y = 1) and atomic = 0 each point has one writer. GRAD: the
+// coordinate gradient of the adjoint (T from the adjoint vector, see
+// launch_iface_grad) instead of u.
+template <bool GRAD>
+__global__ void __launch_bounds__(4 * WAVE) k_if_eval(TreeView tv, const int* __restrict__ tleaf, int nq, int nqp,
+                                                      int rif, const double2* __restrict__ qky,
+                                                      const double2* __restrict__ qkx, const double2* __restrict__ T,
+                                                      int nr, const double2* __restrict__ qg, double2* __restrict__ us,
+                                                      int64_t ps, int64_t rs, int atomic) {
+  __shared__ double2 s_red[4][kIfRhs][WAVE];
+  const int t = blockIdx.x, lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int b = tleaf[t];
+  const int2 pr = tv.prange[b];
+  const double xt = tv.ctr[b].x;
+  const double2* Tt = T + (int64_t)t * rif * nqp;
+  const int nch = nqp / WAVE;
+  const int cb = (int)((int64_t)blockIdx.y * nch / gridDim.y), ce = (int)((int64_t)(blockIdx.y + 1) * nch / gridDim.y);
+  for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
+    const int nt = min(WAVE, pr.y - c0), G = WAVE / nt;
+    const int g = lane / nt, il = lane - g * nt;
+    const bool act = g < G;
+    const int i = c0 + il;
+    const double2 xi = act ? tv.pts[i] : cmk(xt, 0.0);
+    double2 acc[kIfRhs], accy[kIfRhs];
+#pragma unroll
+    for (int r = 0; r < kIfRhs; ++r) acc[r] = accy[r] = cmk(0, 0);
+    if (act)
+      for (int ch = cb + w; ch < ce; ch += 4) {
+        const int q1 = min(nq, (ch + 1) * WAVE);
+        for (int q = ch * WAVE + g; q < q1; q += G) {
+          const double2 ky = qky[q], kx = qkx[q];
+          const double2 e = cexp2(cadd(cscale(ky, xi.y), cscale(kx, xi.x - xt)));
+#pragma unroll
+          for (int r = 0; r < kIfRhs; ++r)
+            if (r < nr) {
+              const double2 v = cmul(Tt[(int64_t)r * nqp + q], e);
+              if (GRAD) {
+                acc[r] = cadd(acc[r], cmul(kx, v));
+                accy[r] = cadd(accy[r], cmul(ky, v));
+              } else {
+                acc[r] = cadd(acc[r], v);
+              }
             }
         }
       }
-      if (valid) {  // other writers of us may run at the same time
-        int64_t idx = (int64_t)r * tv.n + i;
-        unsafeAtomicAdd(&us[idx].x, acc.x);
-        unsafeAtomicAdd(&us[idx].y, acc.y);
+    // groups and waves in a fixed order (GRAD: sum_r Re(q_ri (d/dx, d/dy)) first)
+    __syncthreads();
+    if (GRAD) {
+      double sx = 0.0, sy = 0.0;
+      if (act)
+#pragma unroll
+        for (int r = 0; r < kIfRhs; ++r)
+          if (r < nr) {
+            const double2 q = qg[(int64_t)i * ps + r * rs];
+            sx += cmul(q, acc[r]).x;
+            sy += cmul(q, accy[r]).x;
+          }
+      s_red[w][0][lane] = cmk(sx, sy);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kIfRhs; ++r)
+        if (r < nr) s_red[w][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (w == 0 && lane < nt) {
+      const int nrr = GRAD ? 1 : nr;
+      for (int r = 0; r < nrr; ++r) {
+        double2 a = cmk(0, 0);
+        for (int ww = 0; ww < 4; ++ww)
+          for (int gg = 0; gg < G; ++gg) a = cadd(a, s_red[ww][r][gg * nt + lane]);
+        double2* ui = GRAD ? us + i : us + (int64_t)i * ps + r * rs;
+        if (atomic) {  // other writers of us may run at the same time
+          unsafeAtomicAdd(&ui->x, a.x);
+          unsafeAtomicAdd(&ui->y, a.y);
+        } else {
+          *ui = cadd(*ui, a);
+        }
       }
     }
   }
 }
 
-// Gradient of the near-interface part. The rule's nodes come in pairs
-// (kx, -kx) with equal weights, so G^s(x_i, x_j) = G^s(x_j, x_i) node by node
-// and the derivative of sum_j vs_j G^s(x_j, x_i) with respect to the source x_i
-// weights each node term by kx (x) or ky (y). Added into gs[i] as
-// sum_r Re(q_ri d(...)/dx_i); one block per leaf owns its points.
-__global__ void __launch_bounds__(WAVE) k_iface_grad(TreeView tv, const int* __restrict__ leaves, int nleaves,
-                                                     const int* __restrict__ ptr, const int2* __restrict__ rng,
-                                                     int nq, const double2* __restrict__ qc,
-                                                     const double2* __restrict__ qky, const double2* __restrict__ qkx,
-                                                     const double2* __restrict__ vs, const double2* __restrict__ qs,
-                                                     double2* __restrict__ gs) {
+// Horizontally separated near-interface pairs by interpolation: G^s depends
+// only on (|X|, Y), X = x_i - x_j, Y = y_i + y_j, and is analytic away from
+// X = +-iY, so on pairs with |X| >= X0 >= Y it is a tensor Chebyshev series
+// of kIfTP x kIfTP terms per panel (panels graded geometrically from X0 and
+// at most a fraction of the shortest wavelength wide). The panel values come
+// from the Sommerfeld rule once per plan (k_if_grid); the series coefficients
+// from the host.
+
+// G, dG/d|X| and dG/dY at npts points (|X|, Y) from one rule: three planes of
+// npts values
+__global__ void __launch_bounds__(WAVE) k_if_grid(int npts, const double2* __restrict__ xy, int nq,
+                                                  const double2* __restrict__ qc, const double2* __restrict__ qky,
+                                                  const double2* __restrict__ qkx, double2* __restrict__ out) {
   __shared__ double2 s_c[WAVE], s_ky[WAVE], s_kx[WAVE];
-  int li = blockIdx.x;
-  if (li >= nleaves) return;
-  int b = leaves[li];
-  int lane = threadIdx.x;
-  int2 pr = tv.prange[b];
-  double xref = tv.ctr[b].x;
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * WAVE + lane;
+  const double2 p = i < npts ? xy[i] : cmk(0.0, 0.0);
+  double2 g = cmk(0, 0), gx = cmk(0, 0), gy = cmk(0, 0);
+  for (int q0 = 0; q0 < nq; q0 += WAVE) {
+    __syncthreads();
+    const bool qv = q0 + lane < nq;
+    s_c[lane] = qv ? qc[q0 + lane] : cmk(0, 0);
+    s_ky[lane] = qv ? qky[q0 + lane] : cmk(0, 0);
+    s_kx[lane] = qv ? qkx[q0 + lane] : cmk(0, 0);
+    __syncthreads();
+    const int qn = min(WAVE, nq - q0);
+    for (int qq = 0; qq < qn; ++qq) {
+      const double2 v = cmul(s_c[qq], cexp2(cadd(cscale(s_ky[qq], p.y), cscale(s_kx[qq], p.x))));
+      g = cadd(g, v);
+      gx = cadd(gx, cmul(s_kx[qq], v));
+      gy = cadd(gy, cmul(s_ky[qq], v));
+    }
+  }
+  if (i < npts) {
+    out[i] = g;
+    out[(int64_t)npts + i] = gx;
+    out[2 * (int64_t)npts + i] = gy;
+  }
+}
+
+// the series of one panel at local coordinates (u, v): sum_{a + b < P} c_ab
+// T_a(u) T_b(v), the coefficients packed row by row (kIfTri of them). Only the
+// terms with a + b < P enter: the coefficients of a function analytic in a
+// polyellipse fall off like rho_x^-a rho_y^-b, so the dropped ones are each
+// below the truncation level the panels are sized for (tol / 100).
+template <typename P>
+__device__ inline double2 cheb2(P c, const double* tu, const double* tv) {
+  double2 acc = cmk(0, 0);
+  int k = 0;
+#pragma unroll
+  for (int a = 0; a < kIfTP; ++a) {
+    double2 row = cmk(0, 0);
+#pragma unroll
+    for (int b = 0; b < kIfTP - a; ++b, ++k) {
+      const double2 cab = c[k];
+      row.x = fma(cab.x, tv[b], row.x);
+      row.y = fma(cab.y, tv[b], row.y);
+    }
+    acc.x = fma(row.x, tu[a], acc.x);
+    acc.y = fma(row.y, tu[a], acc.y);
+  }
+  return acc;
+}
+
+// LDS written by some lanes of a wave and read by others: order the two
+// within the wave (no block barrier: the waves of a block run different
+// loops here)
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Table pairs of the target leaves: a block per work item (a leaf and up to
+// four of its source boxes), or per leaf without items; wave w takes every
+// fourth source box. A chunk of nt <= 64 target points occupies the lanes
+// floor(64 / nt) times over (lane groups), the groups taking every G-th
+// source point, so that every lane works on small leaves too; the groups'
+// and waves' sums meet in LDS in a fixed order. GRAD: the coordinate
+// gradient (sources vs, owner strengths qg; X = owner - source, d/dx =
+// sign(X) dG/d|X|, d/dy = dG/dY).
+template <bool GRAD>
+__global__ void __launch_bounds__(4 * WAVE) k_if_table(TreeView tv, IfTable tb,
+                                                       const double2* __restrict__ coef, int nr,
+                                                       const double2* __restrict__ qs,
+                                                       const double2* __restrict__ qg, double2* __restrict__ us,
+                                                       int64_t ps, int64_t rs, int atomic) {
+  __shared__ double2 s_red[4][kIfRhs][WAVE];
+  __shared__ double2 s_cf[4][2 * kIfTri];  // per wave: the panel in use (one or two series)
+  constexpr int NF = GRAD ? 2 : 1;
+  int staged = -1;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int t = tb.item_t ? tb.item_t[blockIdx.x] : blockIdx.x;
+  const int b = tb.tleaf[t];
+  const int2 pr = tv.prange[b];
+  const int e0 = tb.item_t ? tb.item_e[blockIdx.x].x : tb.tptr[t];
+  const int e1 = tb.item_t ? tb.item_e[blockIdx.x].y : tb.tptr[t + 1];
   for (int c0 = pr.x; c0 < pr.y; c0 += WAVE) {
-    int i = c0 + lane;
-    bool valid = i < pr.y;
-    double2 xi = valid ? tv.pts[i] : cmk(0, 0);
-    double sx = 0.0, sy = 0.0;
-    for (int r = 0; r < tv.nrhs; ++r) {
-      double2 ax = cmk(0, 0), ay = cmk(0, 0);
-      for (int e = ptr[li]; e < ptr[li + 1]; ++e) {
-        int2 sr = rng[e];
-        for (int q0 = 0; q0 < nq; q0 += WAVE) {
-          int q = q0 + lane;
-          double2 sq = cmk(0, 0), ky = cmk(0, 0), kx = cmk(0, 0), cq = cmk(0, 0);
-          if (q < nq) {
-            ky = qky[q]; kx = qkx[q]; cq = qc[q];
-            for (int j = sr.x; j < sr.y; ++j) {
-              double2 xj = tv.pts[j];
-              double2 ex = cadd(cscale(ky, xj.y), cscale(kx, -(xj.x - xref)));
-              sq = cadd(sq, cmul(vs[(int64_t)r * tv.n + j], cexp2(ex)));
-            }
+    const int nt = min(WAVE, pr.y - c0), G = WAVE / nt;
+    const int g = lane / nt, il = lane - g * nt;
+    const bool act = g < G;
+    const int i = c0 + il;
+    const double2 xi = tv.pts[act ? i : c0];
+    double2 acc[kIfRhs], accy[kIfRhs];
+#pragma unroll
+    for (int r = 0; r < kIfRhs; ++r) acc[r] = accy[r] = cmk(0, 0);
+    for (int e = e0 + w; e < e1; e += 4) {
+      const int2 sr = tv.prange[tb.tsrc[e]];
+      // every lane runs every step (the LDS staging below needs the whole
+      // wave); lanes past the box's end add nothing
+      for (int jj = sr.x; jj < sr.y; jj += G) {
+        const int j = jj + g;
+        const bool ok = act && j < sr.y;
+        const double2 xj = tv.pts[ok ? j : sr.x];
+        const double X = xi.x - xj.x, ax = fabs(X), Y = xi.y + xj.y;
+        // panel of |X| (the index in single precision: a point a rounding off
+        // the panel edge evaluates the neighbour's series a hair outside
+        // [-1, 1], where it is just as accurate)
+        const int pg = (int)floorf(__log2f(fmaxf((float)(ax * tb.inv_x0), 1.0f)) * tb.inv_lg2);
+        const int pu = tb.p1 + (int)floorf((float)((ax - tb.a1) * tb.inv_wmax));
+        const int px = min(max(ax < tb.a1 ? pg : pu, 0), tb.npx - 1);
+        const double4 xw = tb.xpan[px];  // left edge, 1 / width; Y panel width, 1 / width
+        const int2 yw = tb.ypan[px];     // Y panels: count, first
+        const int py = min(max((int)floorf((float)((Y - tb.ylo) * xw.w)), 0), yw.x - 1);
+        const double u = (2.0 * (ax - xw.x)) * xw.y - 1.0;
+        const double v = (2.0 * (Y - tb.ylo - py * xw.z)) * xw.w - 1.0;
+        double tu[kIfTP], tvv[kIfTP];
+        tu[0] = 1.0;
+        tu[1] = u;
+        tvv[0] = 1.0;
+        tvv[1] = v;
+#pragma unroll
+        for (int a = 2; a < kIfTP; ++a) {
+          tu[a] = 2.0 * u * tu[a - 1] - tu[a - 2];
+          tvv[a] = 2.0 * v * tvv[a - 1] - tvv[a - 2];
+        }
+        // a panel shared by the whole wave (the usual case: a leaf is
+        // narrower than a panel) is staged in LDS and read as broadcasts;
+        // lanes in different panels read their own from memory
+        const int pp = yw.y + py;
+        const int p0 = __builtin_amdgcn_readfirstlane(pp);
+        const bool uni = __all(pp == p0);
+        const double2* cs;
+        if (uni) {
+          if (p0 != staged) {
+            const double2* src = coef + ((int64_t)p0 * 3 + (GRAD ? 1 : 0)) * kIfTri;
+            wave_lds_sync();
+            for (int l = lane; l < NF * kIfTri; l += WAVE) s_cf[w][l] = src[l];
+            wave_lds_sync();
+            staged = p0;
           }
-          __syncthreads();
-          s_c[lane] = cmul(cq, sq);
-          s_ky[lane] = ky;
-          s_kx[lane] = kx;
-          __syncthreads();
-          int qn = min(WAVE, nq - q0);
-          if (valid)
-            for (int qq = 0; qq < qn; ++qq) {
-              double2 ex = cadd(cscale(s_ky[qq], xi.y), cscale(s_kx[qq], xi.x - xref));
-              double2 t = cmul(s_c[qq], cexp2(ex));
-              ax = cadd(ax, cmul(s_kx[qq], t));
-              ay = cadd(ay, cmul(s_ky[qq], t));
+          cs = &s_cf[w][0];
+        } else {
+          cs = coef + ((int64_t)pp * 3 + (GRAD ? 1 : 0)) * kIfTri;
+        }
+        if (!ok) continue;
+        const double2* qj = qs + (int64_t)j * ps;
+        if (GRAD) {
+          double2 gx = cheb2(cs, tu, tvv);
+          const double2 gy = cheb2(cs + kIfTri, tu, tvv);
+          if (X < 0.0) gx = cscale(gx, -1.0);
+#pragma unroll
+          for (int r = 0; r < kIfRhs; ++r)
+            if (r < nr) {
+              const double2 q = qj[r * rs];
+              acc[r] = cadd(acc[r], cmul(gx, q));
+              accy[r] = cadd(accy[r], cmul(gy, q));
             }
+        } else {
+          const double2 gv = cheb2(cs, tu, tvv);
+#pragma unroll
+          for (int r = 0; r < kIfRhs; ++r)
+            if (r < nr) acc[r] = cadd(acc[r], cmul(gv, qj[r * rs]));
         }
       }
-      if (valid) {
-        const double2 q = qs[(int64_t)r * tv.n + i];
-        sx += cmul(q, ax).x;
-        sy += cmul(q, ay).x;
+    }
+    // groups and waves in a fixed order (GRAD: sum_r Re(q_ri (d/dx, d/dy)) first)
+    __syncthreads();
+    if (GRAD) {
+      double sx = 0.0, sy = 0.0;
+      if (act)
+#pragma unroll
+        for (int r = 0; r < kIfRhs; ++r)
+          if (r < nr) {
+            const double2 q = qg[(int64_t)i * ps + r * rs];
+            sx += cmul(q, acc[r]).x;
+            sy += cmul(q, accy[r]).x;
+          }
+      s_red[w][0][lane] = cmk(sx, sy);
+    } else {
+#pragma unroll
+      for (int r = 0; r < kIfRhs; ++r)
+        if (r < nr) s_red[w][r][lane] = acc[r];
+    }
+    __syncthreads();
+    if (w == 0 && lane < nt) {
+      const int nrr = GRAD ? 1 : nr;
+      for (int r = 0; r < nrr; ++r) {
+        double2 a = cmk(0, 0);
+        for (int ww = 0; ww < 4; ++ww)
+          for (int gg = 0; gg < G; ++gg) a = cadd(a, s_red[ww][r][gg * nt + lane]);
+        double2* ui = GRAD ? us + i : us + (int64_t)i * ps + r * rs;
+        if (atomic) {
+          unsafeAtomicAdd(&ui->x, a.x);
+          unsafeAtomicAdd(&ui->y, a.y);
+        } else {
+          *ui = cadd(*ui, a);
+        }
       }
     }
-    if (valid) gs[i] = cadd(gs[i], cmk(sx, sy));
   }
 }
 
@@ -1498,9 +1766,44 @@ void launch_reduce_contrib(hipStream_t s, const TreeView& tv, const int* boxes, 
 void launch_fill_zero(hipStream_t s, double2* p, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fill_zero, dim3(blocks(n, 256)), dim3(256), 0, s, p, n);
 }
-void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
-                  int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* qs, double2* us) {
-  if (nl && nq) hipLaunchKernelGGL(k_iface, dim3(nl), dim3(WAVE), 0, s, tv, leaves, nl, ptr, rng, nq, qc, qky, qkx, qs, us);
+// node ranges per leaf for the evaluation: enough blocks to fill the GPU
+static int if_qsplit(const IfaceLists& L, int atomic) {
+  if (!atomic) return 1;
+  const int nch = L.nqp / WAVE;
+  return max(1, min(nch / 4, (2048 + L.ntl - 1) / max(L.ntl, 1)));
+}
+void launch_iface(hipStream_t s, const TreeView& tv, const IfaceLists* Ls, int ncls, int nrhs, const double2* qs,
+                  double2* us, int64_t ps, int64_t rs, int atomic) {
+  for (int c = 0; c < ncls; ++c) {
+    const IfaceLists& L = Ls[c];
+    if (!L.ntl || !L.nq) continue;
+    for (int r0 = 0; r0 < nrhs; r0 += L.rif) {
+      const int nr = min(L.rif, nrhs - r0);
+      hipLaunchKernelGGL(k_if_src, dim3(L.nsb, L.nqp / WAVE), dim3(4 * WAVE), 0, s, tv, L.sbox, L.nq, L.nqp, L.rif,
+                         L.qky, L.qkx, qs + r0 * rs, ps, rs, nr, L.S);
+      hipLaunchKernelGGL(k_if_trans, dim3(L.ntl, L.nqp / WAVE), dim3(WAVE), 0, s, tv, L.tleaf, L.tptr, L.tsrc,
+                         L.sbox, L.nq, L.nqp, L.rif, L.qc, L.qkx, L.S, nr, L.T);
+      hipLaunchKernelGGL(k_if_eval<false>, dim3(L.ntl, if_qsplit(L, atomic)), dim3(4 * WAVE), 0, s, tv, L.tleaf,
+                         L.nq, L.nqp, L.rif, L.qky, L.qkx, L.T, nr, nullptr, us + r0 * rs, ps, rs, atomic);
+    }
+  }
+}
+void launch_if_grid(hipStream_t s, int npts, const double2* xy, int nq, const double2* qc, const double2* qky,
+                    const double2* qkx, double2* out) {
+  if (npts > 0) hipLaunchKernelGGL(k_if_grid, dim3(blocks(npts, WAVE)), dim3(WAVE), 0, s, npts, xy, nq, qc, qky, qkx, out);
+}
+void launch_iface_table(hipStream_t s, const TreeView& tv, const IfTable* tabs, int ntab, int nrhs, const double2* qs,
+                        double2* us, int64_t ps, int64_t rs, int atomic) {
+  for (int c = 0; c < ntab; ++c) {
+    if (!tabs[c].ntl) continue;
+    // with atomic additions a block per work item, else a block per leaf
+    IfTable tb = tabs[c];
+    if (!atomic) tb.item_t = nullptr;
+    const int nblk = atomic ? tb.nitem : tb.ntl;
+    for (int r0 = 0; r0 < nrhs; r0 += kIfRhs)
+      hipLaunchKernelGGL(k_if_table<false>, dim3(nblk), dim3(4 * WAVE), 0, s, tv, tb, tb.coef, min(kIfRhs, nrhs - r0),
+                         qs + r0 * rs, nullptr, us + r0 * rs, ps, rs, atomic);
+  }
 }
 void launch_table_hankel(hipStream_t s, int ntab, const double* dx, const double* dy, const TableRef* refs, double k,
                          double2* tdata) {
@@ -1545,12 +1848,32 @@ void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, const 
 #undef HFMM_P2P_GRAD
   static_assert(kH0Classes == 5, "one launch per class and one for the large-argument class");
 }
-void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
-                       int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,
-                       const double2* qs, double2* gs) {
-  if (nl <= 0 || nq <= 0) return;
-  hipLaunchKernelGGL(k_iface_grad, dim3(nl), dim3(WAVE), 0, s, tv, leaves, nl, ptr, rng, nq, qc, qky, qkx, vs, qs,
-                     gs);
+void launch_iface_grad(hipStream_t s, const TreeView& tv, const IfaceLists* Ls, int ncls, int nrhs,
+                       const double2* vs, const double2* qs, double2* gs) {
+  const int64_t rs = tv.n;
+  for (int c = 0; c < ncls; ++c) {
+    const IfaceLists& L = Ls[c];
+    if (!L.ntl || !L.nq) continue;
+    for (int r0 = 0; r0 < nrhs; r0 += L.rif) {
+      const int nr = min(L.rif, nrhs - r0);
+      hipLaunchKernelGGL(k_if_src, dim3(L.nsb, L.nqp / WAVE), dim3(4 * WAVE), 0, s, tv, L.sbox, L.nq, L.nqp, L.rif,
+                         L.qky, L.qkx, vs + r0 * rs, (int64_t)1, rs, nr, L.S);
+      hipLaunchKernelGGL(k_if_trans, dim3(L.ntl, L.nqp / WAVE), dim3(WAVE), 0, s, tv, L.tleaf, L.tptr, L.tsrc,
+                         L.sbox, L.nq, L.nqp, L.rif, L.qc, L.qkx, L.S, nr, L.T);
+      hipLaunchKernelGGL(k_if_eval<true>, dim3(L.ntl, if_qsplit(L, 1)), dim3(4 * WAVE), 0, s, tv, L.tleaf, L.nq,
+                         L.nqp, L.rif, L.qky, L.qkx, L.T, nr, qs + r0 * rs, gs, (int64_t)1, rs, 1);
+    }
+  }
+}
+void launch_iface_table_grad(hipStream_t s, const TreeView& tv, const IfTable* tabs, int ntab, int nrhs,
+                             const double2* vs, const double2* qs, double2* gs) {
+  const int64_t rs = tv.n;
+  for (int c = 0; c < ntab; ++c) {
+    if (!tabs[c].ntl) continue;
+    for (int r0 = 0; r0 < nrhs; r0 += kIfRhs)
+      hipLaunchKernelGGL(k_if_table<true>, dim3(tabs[c].nitem), dim3(4 * WAVE), 0, s, tv, tabs[c], tabs[c].coef,
+                         min(kIfRhs, nrhs - r0), vs + r0 * rs, qs + r0 * rs, gs, (int64_t)1, rs, 1);
+  }
 }
 void launch_scatter_grad(hipStream_t s, int n, const int* perm, const double2* gs, double2* grad) {
   hipLaunchKernelGGL(k_scatter_grad, dim3(blocks(n, 256)), dim3(256), 0, s, n, perm, gs, grad);

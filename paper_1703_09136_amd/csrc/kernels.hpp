@@ -61,8 +61,67 @@ void launch_fill_zero(hipStream_t s, double2* p, int64_t n);
 // atomically. fp32: pair arithmetic and per-item sums in single precision.
 void launch_p2p(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
                 const int2* rng, const int* sym, const double2* qs, double2* us, int fp32);
-void launch_iface(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
-                  int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* qs, double2* us);
+// Near-interface pairs (Section 5: direct quadrature of the Sommerfeld
+// integral for image pairs that are not admissible) in three stages, see
+// kernels.hip. The device lists of a plan and its node-sum buffers:
+constexpr int kIfRhs = 8;  // right-hand sides per group, at most
+struct IfaceLists {
+  int nsb = 0;        // source boxes (any level)
+  int ntl = 0;        // target leaves
+  int nq = 0;         // rule nodes
+  int nqp = 0;        // nq rounded up to a multiple of 64
+  int rif = 1;        // right-hand sides per group (<= kIfRhs): the buffers' width
+  const int* sbox = nullptr;   // [nsb] box ids
+  const int* tleaf = nullptr;  // [ntl] leaf box ids, distinct
+  const int* tptr = nullptr;   // [ntl + 1] CSR into tsrc
+  const int* tsrc = nullptr;   // source slots (indices into sbox), point ranges disjoint per leaf
+  const double2* qc = nullptr;
+  const double2* qky = nullptr;
+  const double2* qkx = nullptr;
+  double2* S = nullptr;        // [nsb][rif][nqp] source sums
+  double2* T = nullptr;        // [ntl][rif][nqp] translated sums
+  // one class of pairs: its own rule (qc, qky, qkx: nq nodes) and lists
+};
+// us += (near-interface part of A) qs for nrhs right-hand sides, element r of
+// point j at j * ps + r * rs for both; atomic: add atomically (other writers
+// of us run at the same time), else read-add-write (one writer per point).
+// The classes L[0..ncls) run in sequence (they share the node-sum buffers).
+void launch_iface(hipStream_t s, const TreeView& tv, const IfaceLists* L, int ncls, int nrhs, const double2* qs,
+                  double2* us, int64_t ps, int64_t rs, int atomic);
+// Horizontally separated near-interface pairs by tables of G^s(|X|, Y) (see
+// kernels.hip): per class a Chebyshev series (the terms T_a T_b with a + b <
+// kIfTP) on each panel: panels of |X| from x0 on, each split in Y over the
+// class's range from ylo. The panels of |X| (xpan) are geometric (ratio 2^{1 /
+// inv_lg2}) from x0 for p < p1, then wmax wide from a1.
+constexpr int kIfTP = 12;
+constexpr int kIfTri = kIfTP * (kIfTP + 1) / 2;  // coefficients with a + b < kIfTP
+struct IfTable {
+  int ntl = 0;                 // target leaves
+  const int* tleaf = nullptr;  // [ntl] leaf box ids
+  const int* tptr = nullptr;   // [ntl + 1] CSR into tsrc
+  const int* tsrc = nullptr;   // source box ids
+  // work items for launches with atomic additions: leaf index (into tleaf)
+  // and a range of its entries in tsrc
+  int nitem = 0;
+  const int* item_t = nullptr;
+  const int2* item_e = nullptr;
+  double x0 = 0.0, a1 = 0.0, wmax = 1.0, ylo = 0.0;
+  double inv_x0 = 0.0, inv_wmax = 1.0;
+  float inv_lg2 = 0.0f;  // 1 / log2 of the geometric ratio
+  int p1 = 0, npx = 0;
+  // per panel of |X|: left edge, 1 / width, and the width and its inverse of
+  // its Y panels; their count and the first one's index
+  const double4* xpan = nullptr;
+  const int2* ypan = nullptr;
+  const double2* coef = nullptr;  // [panel][3][kIfTri]: G, dG/d|X|, dG/dY, rows a = 0.. packed
+};
+// G, dG/d|X|, dG/dY of the rule (nq nodes) at npts points (|X|, Y): out holds
+// three planes of npts values (plan time)
+void launch_if_grid(hipStream_t s, int npts, const double2* xy, int nq, const double2* qc, const double2* qky,
+                    const double2* qkx, double2* out);
+// us += table pairs of every class; layout and atomic as launch_iface
+void launch_iface_table(hipStream_t s, const TreeView& tv, const IfTable* tabs, int ntab, int nrhs, const double2* qs,
+                        double2* us, int64_t ps, int64_t rs, int atomic);
 void launch_table_hankel(hipStream_t s, int ntab, const double* dx, const double* dy, const TableRef* refs, double k,
                          double2* tdata);
 void launch_table_bessel(hipStream_t s, int ntab, const double* dx, const double* dy, const int* sgn,
@@ -80,9 +139,12 @@ void launch_l2p_grad(hipStream_t s, const TreeView& tv, const int* leaves, int n
 // (cls_ptr: host array of kH0Classes + 2 entries, as for launch_p2p).
 void launch_p2p_grad(hipStream_t s, const TreeView& tv, const int* items, const int* cls_ptr, const int* ptr,
                      const int2* rng, const int* sym, const double2* vs, const double2* qs, double2* gs);
-void launch_iface_grad(hipStream_t s, const TreeView& tv, const int* leaves, int nl, const int* ptr, const int2* rng,
-                       int nq, const double2* qc, const double2* qky, const double2* qkx, const double2* vs,
-                       const double2* qs, double2* gs);
+// Near-interface part of the gradient: vs (adjoint, sources) and qs
+// (strengths at the owning points) as [nrhs][n]; adds into gs.
+void launch_iface_grad(hipStream_t s, const TreeView& tv, const IfaceLists* L, int ncls, int nrhs,
+                       const double2* vs, const double2* qs, double2* gs);
+void launch_iface_table_grad(hipStream_t s, const TreeView& tv, const IfTable* tabs, int ntab, int nrhs,
+                             const double2* vs, const double2* qs, double2* gs);
 void launch_scatter_grad(hipStream_t s, int n, const int* perm, const double2* gs, double2* grad);
 
 }  // namespace hfmm

@@ -6,7 +6,8 @@ Bars: two calls equal bitwise (one and three right-hand sides, forward and
 adjoint); deterministic vs default plan 1e-12 (the same FP64 approximation
 summed in another order); vs the oracle at the plan tolerance; the adjoint
 against the oracle's conjugate transpose; coordinate gradients and the
-allocation-free entry point refused with HFMM_ERR_UNSUPPORTED.
+allocation-free entry point refused with HFMM_ERR_UNSUPPORTED; a plan with
+near-interface quadrature pairs repeats bitwise and matches the oracle.
 """
 import numpy as np
 import pytest
@@ -59,17 +60,27 @@ def test_deterministic_repeats_bitwise_and_matches(gpu_lib):
     ref.close()
 
 
-def test_deterministic_refused_with_near_interface_pairs(gpu_lib):
+def test_deterministic_with_near_interface_pairs(gpu_lib):
     """Without interface refinement and wavelength bound the bottom boxes keep
-    near-interface quadrature pairs, which only the default pipeline
-    evaluates: the deterministic plan is refused."""
+    near-interface quadrature pairs; the blocked pipeline evaluates them too
+    (one writer per point), so the deterministic plan repeats bitwise and
+    matches the oracle and the default plan."""
     import torch
     dev = torch.device("cuda:0")
-    w = workloads.two_layer_uniform(n=1024, seed=12)
+    w = workloads.two_layer_uniform(n=1024, seed=12, nrhs=3)
     pts = torch.tensor(w.xy, dtype=torch.float64, device=dev)
-    probe = gpu_lib.Plan(w.k, w.interfaces, pts, tol=1e-10, leaf_size=32, interface_refine=0, leaf_kb=0.0)
-    assert probe.info()["interface_pairs"] > 0
-    probe.close()
-    with pytest.raises(gpu_lib.HFMMError, match="UNSUPPORTED|deterministic"):
-        gpu_lib.Plan(w.k, w.interfaces, pts, tol=1e-10, leaf_size=32, interface_refine=0, leaf_kb=0.0,
-                     deterministic=1)
+    q = torch.tensor(w.q, dtype=torch.complex128, device=dev)
+    kw = dict(tol=1e-10, leaf_size=32, interface_refine=0, leaf_kb=0.0)
+    ref = gpu_lib.Plan(w.k, w.interfaces, pts, **kw)
+    assert ref.info()["interface_pairs"] > 0
+    det = gpu_lib.Plan(w.k, w.interfaces, pts, deterministic=1, **kw)
+    a = det.apply(q).cpu().numpy()
+    assert np.array_equal(a, det.apply(q).cpu().numpy()), "forward applies differ between calls"
+    e = rel(a, ref.apply(q).cpu().numpy())
+    eo = rel(a[:1], oracle.direct_apply(oracle.Media(w.k, w.interfaces), w.xy, w.q[:1]))
+    print("near-interface pairs %d: deterministic vs default %.2e, vs oracle %.2e"
+          % (ref.info()["interface_pairs"], e, eo))
+    assert e < 1e-12
+    assert eo < 1e-10
+    det.close()
+    ref.close()
