@@ -10,7 +10,9 @@ the plan (tree, lists, tables) is built before the timed region. Prints one
 JSON line. Besides the headline number it reports the mixed-precision plan
 (near field in FP32) with its error, the adjoint with and without coordinate
 gradients, the batched workload (32 geometries x 256 right-hand sides), the
-roofline of the dominant kernel and the CPU oracle on a bounded sample.
+impedance half-space's scaling, points hugging an interface without
+refinement (near-interface pairs), the roofline of the dominant kernel and
+the CPU oracle on a bounded sample.
 With --gpus other than 1 it exits: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -301,6 +303,44 @@ def impedance_scaling(hf, torch, np):
     return out
 
 
+def near_interface(hf, torch, np):
+    """Points hugging the interface without interface refinement: a strip of
+    2e4 points between heights 0.002 and 0.062 over the two-layer interface
+    (k = 8 pi, 12 pi; leaf 64, no wavelength bound), whose bottom-row leaves
+    keep non-admissible image pairs with the whole bottom row. Milliseconds
+    per apply of the unrefined plan (near-interface quadrature and tables)
+    against the refined plan of the same points, and their difference (both
+    within the tolerance 1e-10 of A)."""
+    import math
+    import workloads
+    dev = torch.device("cuda:0")
+    rng = workloads.rng_for(1703, 9136, 101)
+    xy = workloads.uniform_box(rng, 20000, 0.0, 1.0, 0.002, 0.062)
+    pts = torch.tensor(xy, dtype=torch.float64, device=dev)
+    k2 = (8 * math.pi, 12 * math.pi)
+    res = {}
+    for nrhs in (1, 16):
+        q = torch.tensor(workloads.complex_normal(rng, (nrhs, xy.shape[0])), dtype=torch.complex128, device=dev)
+        row = {}
+        u = {}
+        for refine in (0, 1):
+            plan = hf.Plan(k2, (0.0,), pts, tol=1e-10, leaf_size=64, leaf_kb=0.0, interface_refine=refine)
+            u[refine] = plan.apply(q)
+            torch.cuda.synchronize()
+            inf = plan.info()
+            row["refine%d" % refine] = {"ms_per_apply": timed(torch, lambda: plan.apply(q, out=u[refine]), 10),
+                                       "interface_leaf_pairs": inf["interface_leaf_pairs"],
+                                       "interface_pairs": inf["interface_pairs"]}
+            plan.close()
+        row["ratio"] = row["refine0"]["ms_per_apply"] / row["refine1"]["ms_per_apply"]
+        row["rel_diff"] = float(torch.linalg.norm(u[0] - u[1]) / torch.linalg.norm(u[1]))
+        res["nrhs%d" % nrhs] = row
+    out = {"workload": "two-layer k=(8pi,12pi), 2e4 points in [0,1]x[0.002,0.062], leaf 64, tol 1e-10, "
+                       "interface_refine 0 vs 1", "rows": res}
+    print("near-interface: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -311,7 +351,7 @@ def main():
                     help="skip the adjoint, mixed-precision and batched legs (profiling runs)")
     ap.add_argument("--batch-rhs", type=int, default=256)
     ap.add_argument("--many-rhs", type=int, default=64)
-    ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance",
+    ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance,iface",
                     help="side legs to run besides the headline (profiling runs pick one)")
     ap.add_argument("--n", type=int, default=1_000_000)
     args = ap.parse_args()
@@ -396,6 +436,7 @@ def main():
         adj_s, adj_grad_s, mixed = extras(hf, torch, np, w, plan, pts, q, u, args, golden)
         print("mixed: %s" % json.dumps(mixed), file=sys.stderr, flush=True)
     imp = impedance_scaling(hf, torch, np) if "impedance" in legs else None
+    iface = near_interface(hf, torch, np) if "iface" in legs else None
     if "many" in legs:
         many = many_rhs(hf, torch, np, w, pts, golden, args)
     if "batched" in legs:
@@ -414,7 +455,7 @@ def main():
                       % w.n, "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
                       "parallelism": "single GPU"},
            "rel_err_vs_oracle": err, "adjoint_s": adj_s, "adjoint_with_coordinate_grad_s": adj_grad_s,
-           "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "plan_s": plan_s,
+           "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "near_interface": iface, "plan_s": plan_s,
            "levels": info["levels"], "orders": info["order"],
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
