@@ -354,6 +354,7 @@ def main():
     ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance,iface",
                     help="side legs to run besides the headline (profiling runs pick one)")
     ap.add_argument("--n", type=int, default=1_000_000)
+    ap.add_argument("--leaf", type=int, default=0, help="points per leaf (0: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -369,6 +370,8 @@ def main():
     hf.load()
     dev = torch.device("cuda:0")
     w = workloads.three_layer_ellipses(n=args.n)
+    if args.leaf > 0:
+        w.leaf = args.leaf
     print("workload: %s" % w.name, file=sys.stderr, flush=True)
     pts = torch.tensor(w.xy, dtype=torch.float64, device=dev)
     q = torch.tensor(w.q, dtype=torch.complex128, device=dev)
@@ -451,8 +454,8 @@ def main():
     out = {"metric": METRIC, "value": 1e3 / ms, "unit": "matvecs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "three-layer k=2pi*(80,120,100), N=%d on 64 ellipses, 1 RHS, tol 1e-8, leaf 64"
-                      % w.n, "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
+           "config": {"workload": "three-layer k=2pi*(80,120,100), N=%d on 64 ellipses, 1 RHS, tol 1e-8, leaf %d"
+                      % (w.n, w.leaf), "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
                       "parallelism": "single GPU"},
            "rel_err_vs_oracle": err, "adjoint_s": adj_s, "adjoint_with_coordinate_grad_s": adj_grad_s,
            "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "near_interface": iface, "plan_s": plan_s,
