@@ -52,7 +52,9 @@ typedef enum {
   HFMM_ERR_NO_MEMORY = 4,
   HFMM_ERR_DEVICE = 5,      /* a HIP runtime error */
   HFMM_ERR_ACCURACY = 6     /* the tolerance cannot be met (expansion order
-                               above its cap, or out of FP64 range) */
+                               above its cap, or out of FP64 range), or a
+                               Sommerfeld rule or near-interface table would
+                               be too long for the point set */
 } hfmm_status_t;
 
 /* Self term of the matrix. HFMM_SELF_SCATTERED (default): A_ii is the

@@ -449,6 +449,11 @@ constexpr double kContribBudget = 2048.0 * 1024 * 1024;
 // sum)
 constexpr size_t kIfBufBudget = (size_t)256 << 20;
 constexpr int kIfClasses = 24;
+// bounds on one near-interface table: panels (host and device memory of the
+// panel values, 144 points each), and rule evaluations at plan time (about a
+// second of the GPU)
+constexpr int64_t kIfMaxPanels = (int64_t)1 << 18;
+constexpr double kIfMaxGridWork = 1e12;
 int rhs_chunk(hfmm_plan_t pl, int nrhs) {
   const double per_rhs = 8.0 * (double)std::max<int64_t>(pl->cstride, 1);
   int c = std::max(1, std::min(nrhs, (int)std::max(1.0, kContribBudget / per_rhs)));
@@ -1963,6 +1968,11 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
         yp[px] = make_int2(npy, (int)npan);
         npan += npy;
       }
+      if (npan > kIfMaxPanels) {
+        fail(HFMM_ERR_ACCURACY, "near-interface table of " + std::to_string(npan) +
+                                    " panels: too large (raise leaf_size or keep interface_refine on)");
+        return bail(HFMM_ERR_ACCURACY);
+      }
       // values at the panels' Chebyshev points from one rule over the whole range
       const int64_t npts = npan * kIfTP * kIfTP;
       std::vector<double2> gxy((size_t)npts);
@@ -1983,6 +1993,12 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       }
       std::vector<double2> rc, rky, rkx;
       rule_nodes(r, rc, rky, rkx);
+      if ((double)npts * (double)rc.size() > kIfMaxGridWork) {
+        fail(HFMM_ERR_ACCURACY, "near-interface table: " + std::to_string(npts) + " points x " +
+                                    std::to_string(rc.size()) +
+                                    " rule nodes is too costly to tabulate (raise leaf_size or keep interface_refine on)");
+        return bail(HFMM_ERR_ACCURACY);
+      }
       DevBuf<double2> d_xy, d_c, d_ky, d_kx, d_out;
       hipError_t eg = d_xy.upload(gxy, stream);
       if (eg == hipSuccess) eg = d_c.upload(rc, stream);
