@@ -28,6 +28,10 @@
  *  - Errors are reported by status code only. Argument and domain checks run
  *    on the host before any launch. hfmm_last_error_message() returns a
  *    thread-local description of the last failure.
+ *  - A plan's workspaces (expansions, contribution rows, near-interface node
+ *    sums, the near field's side stream) belong to the plan: calls on one plan
+ *    from several host threads, or on streams not ordered with each other,
+ *    race. Different plans are independent.
  */
 #ifndef HFMM_H
 #define HFMM_H
