@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 METRIC = "H-FMM matvecs/sec at N=1e6, 3 layers, rel err 1e-8 (FP64) vs mixed; adjoint s"
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (and FP64 matrix) peak
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_p2p_three_layer_n1e6.txt")
 # the near-field kernels and the plan code that sizes their work items
 KERNEL_SOURCES = ["p2p.hip", "special.hpp", "common.hpp", "h0_cheb.hpp", "log_table.hpp", "hfmm.hip"]
@@ -124,9 +125,22 @@ def extras(hf, torch, np, w, plan, pts, q, u, args, golden):
     if golden is not None:
         err32 = float(np.linalg.norm(u.cpu().numpy()[:, golden["targets"]] - golden["u"]) /
                       np.linalg.norm(golden["u"]))
+    # the FP32 near field's stage time (HIP events, stages in sequence) against
+    # the FP32 vector peak, its flops as for the FP64 plan
+    plan32.profile(True)
+    plan32.profile_read()
+    timed(torch, lambda: plan32.apply(q, out=u), args.steps)
+    st32, n32 = plan32.profile_read()
+    plan32.profile(False)
+    info32 = plan32.info()
     plan32.close()
+    p2p_s = st32["p2p"] / max(n32, 1) / 1e3
+    ach = info32["flops_p2p"] / p2p_s / 1e12
     mixed = {"precision": "fp32 near field (H0 series, logarithm, per-item sums), fp64 elsewhere",
-             "value": 1e3 / ms32, "unit": "matvecs/s", "ms_per_step": ms32, "rel_err_vs_oracle": err32}
+             "value": 1e3 / ms32, "unit": "matvecs/s", "ms_per_step": ms32, "rel_err_vs_oracle": err32,
+             "roofline": {"bound": "alu", "kernel": "k_p2p<float> (six series-class launches per apply)",
+                          "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                          "frac": ach / PEAK_FP32_TFLOPS, "near_field_ms": p2p_s * 1e3}}
     return adj_ms / 1e3, adj_grad_ms / 1e3, mixed
 
 
