@@ -99,10 +99,10 @@ __global__ void k_self_grad(int n, int nrhs, const double2* __restrict__ dy, con
   gs[j].y -= sy;
 }
 
-// The far-field kernels form a chain of short, latency-bound launches that
-// share the GPU with the near field (a stream of its own): their waves take
-// the highest issue priority within a SIMD (s_setprio), so that the near
-// field's long arithmetic runs fill the cycles they leave.
+// The far-field kernels (P2M first) form a chain of short, latency-bound
+// launches that share the GPU with the near field (a stream of its own): their
+// waves take the highest issue priority within a SIMD (s_setprio), so that
+// the near field's long arithmetic runs fill the cycles they leave.
 __device__ inline void far_field_priority() { __builtin_amdgcn_s_setprio(3); }
 
 // ------------------------------------------------------------------ P2M
@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(WAVE) k_p2m(TreeView tv, const int* __restrict
   double2* s_a = s_q + RB * WAVE;           // [RB][2P + 1]
   const int li = blockIdx.x;
   if (li >= nleaves) return;
+  far_field_priority();
   const int b = leaves[li];
   const int lane = threadIdx.x;
   const int P = tv.P[tv.level[b]];
