@@ -1815,6 +1815,21 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   for (int id : fb_ref) fb_refs.push_back(tabs[id]);
   for (int id : img_ref) img_refs.push_back(tabs[id]);
   DevBuf<TableRef> d_fhr, d_fbr, d_imr;
+  // the image tables: blocks per table so that the launch has about 2048
+  // blocks (at most 32 per table); their partial tables one after another
+  const int img_split = combos.empty() ? 1 : (int)std::min<size_t>(32, std::max<size_t>(1, 2048 / combos.size()));
+  std::vector<int64_t> img_soff;
+  int64_t img_plen = 0;
+  for (const TableRef& r : img_refs) {
+    img_soff.push_back(img_plen);
+    img_plen += 2 * r.half + 1;
+  }
+  DevBuf<int64_t> d_imsoff;
+  DevBuf<double2> d_impart;
+  if (img_split > 1) {
+    if (e == hipSuccess) e = d_imsoff.upload(img_soff, stream);
+    if (e == hipSuccess) e = d_impart.alloc((size_t)img_split * (size_t)std::max<int64_t>(img_plen, 1));
+  }
   if (e == hipSuccess) e = d_fhdx.upload(fh_dx, stream);
   if (e == hipSuccess) e = d_fhdy.upload(fh_dy, stream);
   if (e == hipSuccess) e = d_fhr.upload(fh_refs, stream);
@@ -1845,7 +1860,8 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
     launch_table_hankel(stream, (int)fh_ref.size(), d_fhdx.p, d_fhdy.p, d_fhr.p, k, pl->tdata.p);
     launch_table_bessel(stream, (int)fb_ref.size(), d_fbdx.p, d_fbdy.p, d_fbsgn.p, d_fbr.p, k, pl->tdata.p);
     launch_table_image(stream, pl->med, (int)combos.size(), d_cX.p, d_cY.p, d_cdip.p, d_csend.p, d_cpbeg.p,
-                       d_cpanels.p, d_imr.p, d_glx.p, d_glw.p, pl->tdata.p);
+                       d_cpanels.p, d_imr.p, d_glx.p, d_glw.p, pl->tdata.p, img_split, d_imsoff.p, d_impart.p,
+                       img_plen);
     e = hipGetLastError();
   }
   DevBuf<int64_t> d_lotoff, d_looff;
@@ -1869,6 +1885,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
   d_fbref.release(); d_cpbeg.release(); d_imgref.release(); d_cpanels.release(); d_fhr.release();
   d_fbr.release(); d_imr.release(); d_scc.release(); d_scky.release();
   d_lotoff.release(); d_looff.release(); d_loP.release(); d_lolev.release(); d_loimg.release();
+  d_imsoff.release(); d_impart.release();
   if (e != hipSuccess) {
     fail(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
          std::string("plan upload/tables: ") + hipGetErrorString(e));

@@ -1486,10 +1486,12 @@ __global__ void k_table_bessel(int ntab, const double* __restrict__ dx, const do
 //                 + e^{-i lambda X} (-1)^n z^{-n}] sigma_1(lambda) dt,
 // lambda = sqrt(t^2 + k^2), z = (lambda - t)/k (so that (-lambda - t)/k = -1/z).
 // The t contour dips below the real axis over the branch points and guided-mode
-// poles of sigma_1. One block per (X, Y): the block's threads split into G
-// groups of 8 consecutive orders and H = 256 / G phases of the quadrature
-// nodes (thread (g, h) sums the nodes h, h + H, ... for its orders), and the
-// H partial sums of each group are added through LDS.
+// poles of sigma_1. nsplit blocks per (X, Y) (grid y), each over its share of
+// the rule's panels: the block's threads split into G groups of 8 consecutive
+// orders and H = 256 / G phases of the quadrature nodes (thread (g, h) sums
+// the nodes h, h + H, ... for its orders), and the H partial sums of each
+// group are added through LDS. With nsplit > 1 the blocks store partial
+// tables, which k_table_image_sum adds in block order.
 struct ImageTableArgs {
   Medium med;
   int ncombo;
@@ -1503,6 +1505,10 @@ struct ImageTableArgs {
   const double* glx;    // 16-point Gauss-Legendre nodes/weights on [-1, 1]
   const double* glw;
   double2* tdata;
+  int nsplit;           // blocks per table
+  const int64_t* soff;  // nsplit > 1: each table's offset in a partial table
+  double2* part;        // nsplit partial tables of plen entries each
+  int64_t plen;
 };
 
 constexpr int TB_THREADS = 256;
@@ -1530,7 +1536,9 @@ __global__ void __launch_bounds__(TB_THREADS) k_table_image(ImageTableArgs a) {
   // class "mi": (-i)^n * sum exp(l0 + n ls) (t nodes' plus branch)
   double2 acc_i[TB_NB], acc_mi[TB_NB];
   for (int j = 0; j < TB_NB; ++j) { acc_i[j] = cmk(0, 0); acc_mi[j] = cmk(0, 0); }
-  const int p0 = a.pbeg[cb], p1 = a.pbeg[cb + 1];
+  const int pa = a.pbeg[cb], pz = a.pbeg[cb + 1];
+  const int pper = (pz - pa + a.nsplit - 1) / a.nsplit;
+  const int p0 = min(pz, pa + (int)blockIdx.y * pper), p1 = min(pz, p0 + pper);
   const int nnode = (p1 - p0) * 16;
   const double inv_pi = 0.31830988618379067154;
   for (int q0 = 0; q0 < nnode; q0 += TB_THREADS) {
@@ -1621,7 +1629,7 @@ __global__ void __launch_bounds__(TB_THREADS) k_table_image(ImageTableArgs a) {
     }
   }
   if (ph != 0) return;
-  double2* T = a.tdata + tr.off + tr.half;
+  double2* T = a.nsplit > 1 ? a.part + (int64_t)blockIdx.y * a.plen + a.soff[cb] + tr.half : a.tdata + tr.off + tr.half;
   for (int j = 0; j < TB_NB; ++j) {
     int n = n0 + j;
     if (n < -N || n > N) continue;
@@ -1814,12 +1822,32 @@ void launch_table_bessel(hipStream_t s, int ntab, const double* dx, const double
                          const TableRef* refs, double k, double2* tdata) {
   if (ntab) hipLaunchKernelGGL(k_table_bessel, dim3(blocks(ntab, 64)), dim3(64), 0, s, ntab, dx, dy, sgn, refs, k, tdata);
 }
+// tdata[off + i] = sum over the partial tables in order (one block per table)
+__global__ void k_table_image_sum(int ncombo, const TableRef* __restrict__ refs, const int64_t* __restrict__ soff,
+                                  int nsplit, int64_t plen, const double2* __restrict__ part,
+                                  double2* __restrict__ tdata) {
+  const int cb = blockIdx.x;
+  if (cb >= ncombo) return;
+  const TableRef tr = refs[cb];
+  const int len = 2 * tr.half + 1;
+  for (int i = threadIdx.x; i < len; i += blockDim.x) {
+    double2 v = part[soff[cb] + i];
+    for (int sp = 1; sp < nsplit; ++sp) v = cadd(v, part[(int64_t)sp * plen + soff[cb] + i]);
+    tdata[tr.off + i] = v;
+  }
+}
+
 void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const double* X, const double* Y,
                         const double* dip, const double* send, const int* pbeg, const Panel* panels,
-                        const TableRef* refs, const double* glx, const double* glw, double2* tdata) {
+                        const TableRef* refs, const double* glx, const double* glw, double2* tdata, int nsplit,
+                        const int64_t* soff, double2* part, int64_t plen) {
   if (!ncombo) return;
-  ImageTableArgs a{med, ncombo, X, Y, dip, send, pbeg, panels, refs, glx, glw, tdata};
-  hipLaunchKernelGGL(k_table_image, dim3(ncombo), dim3(TB_THREADS), 0, s, a);
+  if (nsplit < 1 || !part) nsplit = 1;
+  ImageTableArgs a{med, ncombo, X, Y, dip, send, pbeg, panels, refs, glx, glw, tdata, nsplit, soff, part, plen};
+  hipLaunchKernelGGL(k_table_image, dim3(ncombo, nsplit), dim3(TB_THREADS), 0, s, a);
+  if (nsplit > 1)
+    hipLaunchKernelGGL(k_table_image_sum, dim3(ncombo), dim3(TB_THREADS), 0, s, ncombo, refs, soff, nsplit, plen,
+                       part, tdata);
 }
 
 

@@ -126,9 +126,13 @@ void launch_table_hankel(hipStream_t s, int ntab, const double* dx, const double
                          double2* tdata);
 void launch_table_bessel(hipStream_t s, int ntab, const double* dx, const double* dy, const int* sgn,
                          const TableRef* refs, double k, double2* tdata);
+// nsplit blocks per table, each over its share of the rule's panels; with
+// nsplit > 1 they store nsplit partial tables (table c at soff[c] in each, plen
+// entries per partial table) that a second launch adds in order into tdata.
 void launch_table_image(hipStream_t s, const Medium& med, int ncombo, const double* X, const double* Y,
                         const double* dip, const double* send, const int* pbeg, const Panel* panels,
-                        const TableRef* refs, const double* glx, const double* glw, double2* tdata);
+                        const TableRef* refs, const double* glx, const double* glw, double2* tdata, int nsplit,
+                        const int64_t* soff, double2* part, int64_t plen);
 
 // Source-coordinate gradient (see kernels.hip): far field from the adjoint
 // multipole coefficients (stores gs), then the direct and near-interface
