@@ -13,7 +13,7 @@ gradients, the batched workload (32 geometries x 256 right-hand sides), the
 impedance half-space's scaling, points hugging an interface without
 refinement (near-interface pairs), the roofline of the dominant kernel and
 the CPU oracle on a bounded sample.
-With --gpus other than 1 it exits: this build runs on one GPU.
+With --gpus other than 1 it exits: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -372,7 +372,7 @@ def main():
     ap.add_argument("--leaf", type=int, default=0, help="points per leaf (0: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
