@@ -35,5 +35,5 @@ source-coordinate gradient of Re <v, A q>, targets held fixed).
 from .media import Media, gamma, sigma_coefficients, sigma1  # noqa: F401
 from .sommerfeld import (contour_rule, scattered_pairs, scattered_matvec,  # noqa: F401
                          layer_field, m2l_entry)
-from .direct import free_matvec, direct_apply, dense_matrix  # noqa: F401
+from .direct import free_matvec, direct_apply, cross_layer_apply, dense_matrix  # noqa: F401
 from .gradient import source_gradient  # noqa: F401

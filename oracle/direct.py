@@ -6,7 +6,9 @@ Paper passages followed:
 * Section 2.4: phi(x) = int u_{x0}(x) rho(x0) dx0, discretised as A v with
   A_ij = u_{x_j}(x_i).
 * Section 2.1, Eq. freeGreen: g = (i/4) H0^(1)(k1 |x - x0|).
-* Section 2.3, Eq. multitop: the scattered part (see ``sommerfeld``).
+* Section 2.3, Eq. multitop: the scattered part (see ``sommerfeld``); the
+  middle- and bottom-layer fields of the same section for targets below the
+  top interface (``cross_layer_apply``).
 
 Self term (the paper is silent): the free term is dropped for i = j by index,
 the scattered self term G^s(x_i, x_i) is kept.
@@ -94,6 +96,42 @@ def direct_apply(media: Media, xy, q, targets=None, *, self_term=True, refine=1.
     return uf + us
 
 
+def cross_layer_apply(media: Media, xy_src, q, xy_tgt, *, refine=1.0):
+    """u_t = sum_s q_s u_{x_s}(x_t) for sources in the top layer and targets
+    below it (caller's frame): the middle- and bottom-layer fields of a
+    top-layer source (Section 2.3, u_2 = u_2^t + u_2^b and u_3, with the
+    densities sigma_2^+, sigma_2^-, sigma_3 of the interface system), summed
+    over the sources one at a time (``sommerfeld.layer_field``). A target at
+    or above the lower interface (three layers) is in the middle layer; with
+    two layers every target is in the lower half-space.
+
+    xy_src: (Ns, 2), strictly above the top interface; xy_tgt: (Nt, 2),
+    strictly below it; q: (Ns,) or (nrhs, Ns). Returns (Nt,) or (nrhs, Nt).
+    """
+    from .sommerfeld import layer_field
+
+    xs = np.asarray(xy_src, float)
+    xt = np.asarray(xy_tgt, float)
+    q = np.asarray(q, complex)
+    squeeze = q.ndim == 1
+    q = np.atleast_2d(q)
+    ys = media.to_frame(xs[:, 1])
+    yt = media.to_frame(xt[:, 1])
+    if np.any(ys <= 0) or np.any(yt >= 0):
+        raise ValueError("sources strictly above and targets strictly below the top interface")
+    layer = np.full(yt.size, 2)
+    if media.layers == 3:
+        layer[yt < -media.d] = 3
+    u = np.zeros((q.shape[0], yt.size), dtype=complex)
+    for j in range(xs.shape[0]):
+        for lay in (2, 3):
+            idx = np.nonzero(layer == lay)[0]
+            if idx.size:
+                f = layer_field(media, lay, xt[idx, 0], yt[idx], xs[j, 0], ys[j], refine=refine)
+                u[:, idx] += q[:, j:j + 1] * f[None, :]
+    return u[0] if squeeze else u
+
+
 def dense_matrix(media: Media, xy, *, refine=1.0):
     """The dense N x N matrix A (small N only): column j = A applied to e_j."""
     xy = np.asarray(xy, float)
@@ -102,4 +140,4 @@ def dense_matrix(media: Media, xy, *, refine=1.0):
     return direct_apply(media, xy, eye, refine=refine, workers=1).T
 
 
-__all__ = ["free_matvec", "direct_apply", "dense_matrix", "_SHARED"]
+__all__ = ["free_matvec", "direct_apply", "cross_layer_apply", "dense_matrix", "_SHARED"]

@@ -444,3 +444,49 @@ def test_source_gradient_without_self_term_matches_central_differences():
         assert abs(fd - g_none[j, axis]) <= 2e-6 * max(1.0, abs(fd)), (j, axis, fd, g_none[j, axis])
         if axis == 1:  # the self pair matters in y only, and there it must
             assert abs(fd - g_full[j, axis]) > 1e-4 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- fields below the top interface
+@pytest.mark.parametrize("ks,ifs", [((31.0, 31.0, 31.0), (0.5, 0.0)), ((31.0, 31.0), (0.0,))])
+def test_cross_layer_homogeneous_is_the_free_field(ks, ifs):
+    """One wavenumber everywhere: the field below the interface of a top-layer
+    source is (i/4) H0(k r) (scipy's Hankel function)."""
+    m = Media(ks, ifs)
+    rng = np.random.default_rng(5)
+    src = np.c_[rng.uniform(0, 1, 4), ifs[0] + rng.uniform(0.02, 0.3, 4)]
+    tgt = np.c_[rng.uniform(0, 1, 5), ifs[0] - rng.uniform(0.02, 0.9, 5)]
+    q = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    u = oracle.cross_layer_apply(m, src, q, tgt)
+    r = np.hypot(tgt[:, None, 0] - src[None, :, 0], tgt[:, None, 1] - src[None, :, 1])
+    ref = (0.25j * hankel1(0, ks[0] * r)) @ q
+    assert np.max(np.abs(u - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("k,ifs", [(K2, (0.0,)), (K3, IF3)])
+def test_cross_layer_meets_the_top_layer_field(k, ifs):
+    """Just below the top interface the cross-layer sum equals the top-layer
+    field just above it: the free part (i/4) H0(k1 r) plus the scattered part
+    of Eq. multitop (sigma_1), a path that shares no density with the
+    transmitted one (sigma_2^+). Across the lower interface the layer switch
+    is continuous."""
+    m = Media(k, ifs)
+    x0, y0 = 0.15, ifs[0] + 0.2
+    q = np.array([1.0 + 0.5j])
+    for x in (0.1, 0.6):
+        below = oracle.cross_layer_apply(m, [[x0, y0]], q, [[x, ifs[0] - 1e-13]])[0]
+        r = math.hypot(x - x0, y0 - ifs[0])
+        above = q[0] * (0.25j * hankel1(0, m.k1 * r) + oracle.scattered_pairs(m, x - x0, y0 - ifs[0])[0])
+        assert abs(below - above) < 1e-10 * abs(above), (x, below, above)
+        if m.layers == 3:
+            lo = ifs[1]
+            a = oracle.cross_layer_apply(m, [[x0, y0]], q, [[x, lo + 1e-13]])[0]
+            b = oracle.cross_layer_apply(m, [[x0, y0]], q, [[x, lo - 1e-13]])[0]
+            assert abs(a - b) < 1e-10 * abs(a)
+
+
+def test_cross_layer_rejects_points_on_the_wrong_side():
+    m = Media(K3, IF3)
+    with pytest.raises(ValueError):
+        oracle.cross_layer_apply(m, [[0.1, 0.4]], [1.0], [[0.2, 0.3]])
+    with pytest.raises(ValueError):
+        oracle.cross_layer_apply(m, [[0.1, 0.6]], [1.0], [[0.2, 0.7]])
