@@ -355,6 +355,39 @@ def near_interface(hf, torch, np):
     return out
 
 
+def cross_layer(hf, torch, np, w, pts, q):
+    """Fields below the top interface (hfmm_transmit): the headline workload's
+    top-layer points and strengths as sources, 10^5 targets uniform in x over
+    [0, 1] and in depth over [0.02, 0.9] below the top interface (the middle
+    layer and the bottom one). Milliseconds per call and source-target pairs
+    per second; the error against the oracle on a subset (64 sources, 16
+    targets, the same call)."""
+    import oracle
+    import workloads
+    dev = torch.device("cuda:0")
+    rng = workloads.rng_for(1703, 9136, 301)
+    yif = w.interfaces[0]
+    tgt = np.c_[rng.uniform(0.0, 1.0, 100_000), yif - rng.uniform(0.02, 0.9, 100_000)]
+    tg = torch.tensor(tgt, dtype=torch.float64, device=dev)
+    tol = 1e-8
+    u = hf.transmit(w.k, w.interfaces, pts, q, tg, tol=tol)
+    ms = timed(torch, lambda: hf.transmit(w.k, w.interfaces, pts, q, tg, tol=tol), 3)
+    si = rng.choice(pts.shape[0], 64, replace=False)
+    ti = rng.choice(tgt.shape[0], 16, replace=False)
+    xs, qs = w.xy[si], w.q[:, si]
+    us = hf.transmit(w.k, w.interfaces, torch.tensor(xs, device=dev), torch.tensor(qs, device=dev),
+                     torch.tensor(tgt[ti], device=dev), tol=tol).cpu().numpy()
+    ref = oracle.cross_layer_apply(oracle.Media(w.k, w.interfaces), xs, qs, tgt[ti])
+    err = float(np.linalg.norm(us - ref) / np.linalg.norm(ref))
+    ns, nt = int(pts.shape[0]), tgt.shape[0]
+    out = {"workload": "three-layer k=2pi*(80,120,100): %d top-layer sources (the headline points), %d targets "
+                       "at depths 0.02-0.9 below the top interface, tol %g" % (ns, nt, tol),
+           "ms_per_call": ms, "pairs_per_s": ns * nt / ms * 1e3, "rel_err_vs_oracle_subset": err,
+           "finite": bool(torch.isfinite(torch.view_as_real(u)).all())}
+    print("cross-layer: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,7 +399,7 @@ def main():
                     help="skip the adjoint, mixed-precision and batched legs (profiling runs)")
     ap.add_argument("--batch-rhs", type=int, default=256)
     ap.add_argument("--many-rhs", type=int, default=64)
-    ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance,iface",
+    ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance,iface,xlayer",
                     help="side legs to run besides the headline (profiling runs pick one)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--leaf", type=int, default=0, help="points per leaf (0: the workload's)")
@@ -455,6 +488,7 @@ def main():
         print("mixed: %s" % json.dumps(mixed), file=sys.stderr, flush=True)
     imp = impedance_scaling(hf, torch, np) if "impedance" in legs else None
     iface = near_interface(hf, torch, np) if "iface" in legs else None
+    xlayer = cross_layer(hf, torch, np, w, pts, q) if "xlayer" in legs else None
     if "many" in legs:
         many = many_rhs(hf, torch, np, w, pts, golden, args)
     if "batched" in legs:
@@ -473,7 +507,7 @@ def main():
                       % (w.n, w.leaf), "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
                       "parallelism": "single GPU"},
            "rel_err_vs_oracle": err, "adjoint_s": adj_s, "adjoint_with_coordinate_grad_s": adj_grad_s,
-           "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "near_interface": iface, "plan_s": plan_s,
+           "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "near_interface": iface, "cross_layer": xlayer, "plan_s": plan_s,
            "levels": info["levels"], "orders": info["order"],
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

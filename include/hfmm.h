@@ -363,6 +363,37 @@ hfmm_status_t hfmm_bie_solve(hfmm_plan_t plan, const double *w, const double *f,
                              int32_t restart, int32_t max_iter, int32_t *iterations, double *residual,
                              hfmm_stream_t stream);
 
+/*
+ * The field below the top interface of top-layer sources: the middle- and
+ * bottom-layer fields of Section 2.3 (u_2 = u_2^t + u_2^b with the densities
+ * sigma_2^+ and sigma_2^-, u_3 with sigma_3, from the interface system; two
+ * layers: the field of the lower half-space),
+ *   u_rt = sum_s q_rs G(x_t, x_s),  x_s in layer 1, x_t in layer 2 or 3
+ * (a target at or above the lower interface is in layer 2). The spectral
+ * integral factors into a source and a target part, so one quadrature rule
+ * for the whole point sets (a contour below the branch points and the slab's
+ * guided-mode poles, built on the host from the sets' extents) gives the sum
+ * in O((ns + nt) Q) for Q nodes; Q grows with the x range times the largest
+ * wavenumber and with 1 / (the nearest source's height + the nearest
+ * target's depth).
+ *   layers, wavenumbers, interfaces  as hfmm_plan; layers 2 or 3.
+ *   ns, src   device [ns][2] doubles, every y strictly above interfaces[0].
+ *   q         device complex [nrhs][ns].
+ *   nt, tgt   device [nt][2] doubles, every y strictly below interfaces[0].
+ *   u         device complex [nrhs][nt], written.
+ *   tol       relative accuracy of the quadrature, in [1e-14, 1e-2].
+ * Allocates its node tables and sums with hipMalloc and synchronises the
+ * stream (the points' extents are read on the host). Errors:
+ * HFMM_ERR_INVALID_ARG (NULL pointers, sizes, tol), HFMM_ERR_UNSUPPORTED
+ * (layers not 2 or 3, k not finite and > 0), HFMM_ERR_DOMAIN (a source not
+ * above or a target not below the top interface, a non-finite coordinate),
+ * HFMM_ERR_ACCURACY (the rule would pass 200000 panels), HFMM_ERR_NO_MEMORY,
+ * HFMM_ERR_DEVICE.
+ */
+hfmm_status_t hfmm_transmit(int32_t layers, const double *wavenumbers, const double *interfaces, int64_t ns,
+                            const double *src, const double *q, int32_t nrhs, int64_t nt, const double *tgt,
+                            double *u, double tol, hfmm_stream_t stream);
+
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 

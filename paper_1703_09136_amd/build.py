@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhfmm.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["hfmm.hip", "kernels.hip", "p2p.hip", "batch.hip", "blocked.hip", "noalloc.hip", "tree.hip", "tree_host.cpp", "tree_api.hip", "bie.hip"]
+SOURCES = ["hfmm.hip", "kernels.hip", "p2p.hip", "batch.hip", "blocked.hip", "noalloc.hip", "tree.hip", "tree_host.cpp", "tree_api.hip", "bie.hip", "transmit.hip"]
 ARCH = os.environ.get("HFMM_OFFLOAD_ARCH", "gfx950")
 
 
