@@ -54,22 +54,23 @@ struct XlNode {
 // Source node sums of one chunk of sources: block (node tile, source chunk,
 // right-hand-side group), a thread per node; part[chunk][r][q] holds (S+, S-)
 // as two double2.
+template <int RB>
 __global__ void __launch_bounds__(XL_THREADS) k_xl_src(int nq, const XlNode* __restrict__ nodes, int64_t ns,
                                                        const double2* __restrict__ src, double xc, double yif,
                                                        const double2* __restrict__ q, int nrhs, int64_t chunk,
                                                        double2* __restrict__ part) {
   __shared__ double s_x[XL_THREADS], s_y[XL_THREADS];
-  __shared__ double2 s_q[XL_RB][XL_THREADS];
+  __shared__ double2 s_q[RB][XL_THREADS];
   const int iq = blockIdx.x * XL_THREADS + threadIdx.x;
   const int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = min(ns, j0 + chunk);
-  const int r0 = blockIdx.z * XL_RB, nr = min(XL_RB, nrhs - r0);
+  const int r0 = blockIdx.z * RB, nr = min(RB, nrhs - r0);
   double2 lam = cmk(0.0, 0.0), g1 = cmk(0.0, 0.0);
   if (iq < nq) {
     lam = nodes[iq].lam;
     g1 = nodes[iq].g1;
   }
-  double2 sp[XL_RB], sm[XL_RB];
-  for (int r = 0; r < XL_RB; ++r) sp[r] = sm[r] = cmk(0.0, 0.0);
+  double2 sp[RB], sm[RB];
+  for (int r = 0; r < RB; ++r) sp[r] = sm[r] = cmk(0.0, 0.0);
   for (int64_t b0 = j0; b0 < j1; b0 += XL_THREADS) {
     const int cnt = (int)min((int64_t)XL_THREADS, j1 - b0);
     __syncthreads();
@@ -77,11 +78,24 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_src(int nq, const XlNode* __r
       const double2 p = src[b0 + threadIdx.x];
       s_x[threadIdx.x] = p.x - xc;
       s_y[threadIdx.x] = p.y - yif;
-      for (int r = 0; r < XL_RB; ++r)
+      for (int r = 0; r < RB; ++r)
         s_q[r][threadIdx.x] = r < nr ? q[(int64_t)(r0 + r) * ns + b0 + threadIdx.x] : cmk(0.0, 0.0);
     }
     __syncthreads();
-    if (iq < nq) {
+    if (iq < nq && lam.y == 0.0 && g1.y == 0.0) {
+      // a node on the real axis past every branch point: g1 and lambda real
+      for (int j = 0; j < cnt; ++j) {
+        const double m0 = exp(-g1.x * s_y[j]);
+        double sb, cb;
+        sincos(lam.x * s_x[j], &sb, &cb);
+        const double2 ep = cmk(m0 * cb, -m0 * sb), em = cmk(m0 * cb, m0 * sb);
+        for (int r = 0; r < RB; ++r) {
+          const double2 qq = s_q[r][j];
+          sp[r] = cadd(sp[r], cmul(qq, ep));
+          sm[r] = cadd(sm[r], cmul(qq, em));
+        }
+      }
+    } else if (iq < nq) {
       for (int j = 0; j < cnt; ++j) {
         const double x = s_x[j], y = s_y[j];
         // -g1 y -+ i lambda x: magnitudes e^{-g1.x y} e^{+- lambda.y x}, phases -g1.y y -+ lambda.x x
@@ -92,7 +106,7 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_src(int nq, const XlNode* __r
         const double mp = m0 * mx, mm = m0 / mx;
         const double2 ep = cmk(mp * (ca * cb + sa * sb), mp * (sa * cb - ca * sb));  // angle a - b
         const double2 em = cmk(mm * (ca * cb - sa * sb), mm * (sa * cb + ca * sb));  // angle a + b
-        for (int r = 0; r < XL_RB; ++r) {
+        for (int r = 0; r < RB; ++r) {
           const double2 qq = s_q[r][j];
           sp[r] = cadd(sp[r], cmul(qq, ep));
           sm[r] = cadd(sm[r], cmul(qq, em));
@@ -119,16 +133,17 @@ __global__ void k_xl_sum(int64_t len, int nchunk, const double2* __restrict__ pa
 
 // u[r][t] = sum_q T_q(y_t) (S+ e^{i lambda x'} + S- e^{-i lambda x'}); a thread
 // per target, the nodes staged through LDS.
+template <int RB>
 __global__ void __launch_bounds__(XL_THREADS) k_xl_eval(int nq, const XlNode* __restrict__ nodes,
                                                         const double2* __restrict__ S, int nrhs, int64_t nt,
                                                         const double2* __restrict__ tgt, double xc, double yif,
                                                         double d, int layers, double2* __restrict__ u) {
   __shared__ XlNode s_n[XL_THREADS / 4];
-  __shared__ double2 s_s[XL_RB][XL_THREADS / 4][2];
+  __shared__ double2 s_s[RB][XL_THREADS / 4][2];
   constexpr int NB = XL_THREADS / 4;
   const int64_t it = (int64_t)blockIdx.x * XL_THREADS + threadIdx.x;
   const bool valid = it < nt;
-  const int r0 = blockIdx.y * XL_RB, nr = min(XL_RB, nrhs - r0);
+  const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
   double x = 0.0, y = -1.0;
   if (valid) {
     const double2 p = tgt[it];
@@ -136,13 +151,13 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_eval(int nq, const XlNode* __
     y = p.y - yif;
   }
   const bool low = layers == 3 && y < -d;
-  double2 acc[XL_RB];
-  for (int r = 0; r < XL_RB; ++r) acc[r] = cmk(0.0, 0.0);
+  double2 acc[RB];
+  for (int r = 0; r < RB; ++r) acc[r] = cmk(0.0, 0.0);
   for (int q0 = 0; q0 < nq; q0 += NB) {
     const int cnt = min(NB, nq - q0);
     __syncthreads();
     if (threadIdx.x < cnt) s_n[threadIdx.x] = nodes[q0 + threadIdx.x];
-    for (int e = threadIdx.x; e < XL_RB * cnt * 2; e += XL_THREADS) {
+    for (int e = threadIdx.x; e < RB * cnt * 2; e += XL_THREADS) {
       const int r = e / (cnt * 2), rem = e - r * cnt * 2, j = rem >> 1, h = rem & 1;
       s_s[r][j][h] = r < nr ? S[((int64_t)(r0 + r) * nq + q0 + j) * 2 + h] : cmk(0.0, 0.0);
     }
@@ -150,6 +165,24 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_eval(int nq, const XlNode* __
     if (!valid) continue;
     for (int j = 0; j < cnt; ++j) {
       const XlNode nd = s_n[j];
+      if (nd.lam.y == 0.0 && nd.g2.y == 0.0 && nd.g3.y == 0.0) {
+        // a node on the real axis past every branch point: real exponentials
+        double2 T;
+        if (low) {
+          T = cscale(nd.c, exp(nd.g3.x * (y + d)));
+        } else {
+          T = cscale(nd.a, exp(nd.g2.x * y));
+          if (layers == 3) T = cadd(T, cscale(nd.b, exp(-nd.g2.x * (y + 2.0 * d))));
+        }
+        double sn, cs;
+        sincos(nd.lam.x * x, &sn, &cs);
+        const double2 wp = cmk(cs, sn), wm = cmk(cs, -sn);
+        for (int r = 0; r < RB; ++r) {
+          const double2 v = cadd(cmul(s_s[r][j][0], wp), cmul(s_s[r][j][1], wm));
+          acc[r] = cadd(acc[r], cmul(T, v));
+        }
+        continue;
+      }
       double2 T;
       if (low) {
         T = cmul(nd.c, cexp2(cscale(nd.g3, y + d)));
@@ -163,7 +196,7 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_eval(int nq, const XlNode* __
       double sn, cs;
       sincos(nd.lam.x * x, &sn, &cs);
       const double2 wp = cmk(mx * cs, mx * sn), wm = cmk(cs / mx, -sn / mx);
-      for (int r = 0; r < XL_RB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const double2 v = cadd(cmul(s_s[r][j][0], wp), cmul(s_s[r][j][1], wm));
         acc[r] = cadd(acc[r], cmul(T, v));
       }
@@ -342,7 +375,8 @@ extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers
   const int64_t maxchunk = (ns + XL_THREADS - 1) / XL_THREADS;
   const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 2048 / std::max(ntile, 1)));
   const int64_t chunk = ((ns + nchunk - 1) / nchunk + XL_THREADS - 1) / XL_THREADS * XL_THREADS;
-  const int nrg = (nrhs + XL_RB - 1) / XL_RB;
+  const int rb = nrhs == 1 ? 1 : XL_RB;  // right-hand sides per block
+  const int nrg = (nrhs + rb - 1) / rb;
   DevBuf<XlNode> d_nodes;
   DevBuf<double2> d_part, d_S;
   const int64_t slen = (int64_t)nrhs * nq * 2;
@@ -350,13 +384,21 @@ extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers
   if (e == hipSuccess) e = d_part.alloc((size_t)nchunk * slen);
   if (e == hipSuccess) e = d_S.alloc((size_t)slen);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_xl_src, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
-                       (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
+    if (rb == 1)
+      hipLaunchKernelGGL(k_xl_src<1>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
+                         (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
+    else
+      hipLaunchKernelGGL(k_xl_src<XL_RB>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
+                         (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
     hipLaunchKernelGGL(k_xl_sum, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s, slen, nchunk, d_part.p,
                        d_S.p);
-    hipLaunchKernelGGL(k_xl_eval, dim3((unsigned)((nt + XL_THREADS - 1) / XL_THREADS), nrg), dim3(XL_THREADS), 0, s,
-                       nq, d_nodes.p, d_S.p, (int)nrhs, nt, (const double2*)tgt, xc, yif, d, (int)layers,
-                       (double2*)u);
+    const dim3 ge((unsigned)((nt + XL_THREADS - 1) / XL_THREADS), nrg);
+    if (rb == 1)
+      hipLaunchKernelGGL(k_xl_eval<1>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                         (const double2*)tgt, xc, yif, d, (int)layers, (double2*)u);
+    else
+      hipLaunchKernelGGL(k_xl_eval<XL_RB>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                         (const double2*)tgt, xc, yif, d, (int)layers, (double2*)u);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
