@@ -30,10 +30,13 @@ Readings taken where the paper is silent:
 
 Modules: ``media`` (branches, sigma), ``sommerfeld`` (contour rules and the
 Sommerfeld integrals), ``direct`` (the dense direct sums), ``gradient`` (the
-source-coordinate gradient of Re <v, A q>, targets held fixed).
+source-coordinate gradient of Re <v, A q>, targets held fixed), ``middle``
+(sources in the middle layer: the interface system with a layer-2 source,
+which the paper leaves to a follow-up).
 """
 from .media import Media, gamma, sigma_coefficients, sigma1  # noqa: F401
 from .sommerfeld import (contour_rule, scattered_pairs, scattered_matvec,  # noqa: F401
                          layer_field, m2l_entry)
 from .direct import free_matvec, direct_apply, cross_layer_apply, dense_matrix  # noqa: F401
 from .gradient import source_gradient  # noqa: F401
+from .middle import middle_coefficients, middle_source_field, middle_apply  # noqa: F401

@@ -490,3 +490,84 @@ def test_cross_layer_rejects_points_on_the_wrong_side():
         oracle.cross_layer_apply(m, [[0.1, 0.4]], [1.0], [[0.2, 0.3]])
     with pytest.raises(ValueError):
         oracle.cross_layer_apply(m, [[0.1, 0.6]], [1.0], [[0.2, 0.7]])
+
+
+# ---------------------------------------------------------------- sources in the middle layer
+from oracle.middle import middle_apply, middle_coefficients, middle_source_field  # noqa: E402
+
+KM = (2 * math.pi * 8, 2 * math.pi * 12, 2 * math.pi * 10)   # slab fastest: guided modes
+
+
+def test_middle_homogeneous_has_no_scattered_field():
+    m = Media((40.0, 40.0, 40.0), IF3)
+    c = middle_coefficients(np.array([1.0, 30.0 - 2j, 60.0]), m, -0.2)
+    assert np.max(np.abs(c[..., 1:3])) < 1e-14
+    x0, y0 = 0.1, -0.2
+    for layer, y in ((1, 0.15), (3, -0.8)):
+        u = middle_source_field(m, layer, 0.4, y, x0, y0)[0]
+        ref = 0.25j * hankel1(0, 40.0 * math.hypot(0.4 - x0, y - y0))
+        assert abs(u - ref) < 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("kk,which", [((KM[0], KM[1], KM[1]), "top"), ((KM[1], KM[1], KM[2]), "bottom")])
+def test_middle_matched_interface_reduces_to_one_reflection(kk, which):
+    """A matched interface reflects nothing: the middle layer's scattered field
+    is the one-interface reflection of the other, which is the top-layer
+    oracle's two-layer field after a mirror (x, y) -> (x, -y) (about the
+    reflecting interface)."""
+    m = Media(kk, IF3)
+    d = m.d
+    for X, y, y0 in ((0.3, -0.1, -0.25), (-0.05, -0.4, -0.1)):
+        g = middle_source_field(m, 2, X, y, 0.0, y0, scattered_only=True)[0]
+        if which == "top":
+            ref = oracle.scattered_pairs(Media((kk[1], kk[0]), (0.0,)), X, -(y + y0))[0]
+        else:
+            ref = oracle.scattered_pairs(Media((kk[1], kk[2]), (0.0,)), X, (y + d) + (y0 + d))[0]
+        assert abs(g - ref) < 1e-11 * abs(ref), (which, X, y, y0, g, ref)
+
+
+def test_middle_reciprocity():
+    m = Media(KM, IF3)
+    a = middle_source_field(m, 2, 0.35, -0.1, 0.05, -0.3, scattered_only=True)[0]
+    b = middle_source_field(m, 2, 0.05, -0.3, 0.35, -0.1, scattered_only=True)[0]
+    assert abs(a - b) < 1e-11 * abs(a)
+
+
+def test_middle_interface_conditions():
+    """u and du/dy continuous across both interfaces for a middle-layer source
+    (one-sided differences, as for the top-layer source)."""
+    m = Media(KM, IF3)
+    x0, y0 = 0.1, -0.22
+    for yi, (la, lb) in ((0.0, (1, 2)), (-m.d, (2, 3))):
+        for x in (0.15, 0.5):
+            ua = middle_source_field(m, la, x, yi, x0, y0)[0]
+            ub = middle_source_field(m, lb, x, yi, x0, y0)[0]
+            assert abs(ua - ub) < 1e-10 * abs(ua), (yi, x, ua, ub)
+
+            def deriv(layer, sign, h):
+                f0 = middle_source_field(m, layer, x, yi, x0, y0)[0]
+                f1 = middle_source_field(m, layer, x, yi + sign * h, x0, y0)[0]
+                f2 = middle_source_field(m, layer, x, yi + 2 * sign * h, x0, y0)[0]
+                return sign * (-3 * f0 + 4 * f1 - f2) / (2 * h)
+
+            h = 2e-3 / KM[1]
+            da = (4 * deriv(la, +1, h / 2) - deriv(la, +1, h)) / 3
+            db = (4 * deriv(lb, -1, h / 2) - deriv(lb, -1, h)) / 3
+            assert abs(da - db) < 1e-6 * KM[1] * abs(ua), (yi, x, da, db)
+
+
+def test_middle_apply_is_the_pairwise_sum():
+    m = Media(KM, IF3)
+    rng = np.random.default_rng(9)
+    xy = np.c_[rng.uniform(0, 1, 5), IF3[0] - rng.uniform(0.05, 0.45, 5)]
+    q = rng.standard_normal(5) + 1j * rng.standard_normal(5)
+    u = middle_apply(m, xy, q)
+    y = xy[:, 1] - IF3[0]
+    for i in (0, 3):
+        ref = 0.0
+        for j in range(5):
+            g = middle_source_field(m, 2, xy[i, 0], y[i], xy[j, 0], y[j], scattered_only=True)[0]
+            if j != i:
+                g += 0.25j * hankel1(0, KM[1] * math.hypot(xy[i, 0] - xy[j, 0], y[i] - y[j]))
+            ref += q[j] * g
+        assert abs(u[i] - ref) < 1e-13 * abs(ref)
