@@ -388,6 +388,42 @@ def cross_layer(hf, torch, np, w, pts, q):
     return out
 
 
+def middle_layer(hf, torch, np):
+    """Points in the middle layer (the slab): 10^6 points on 64 ellipses with
+    centres uniform in the slab, k = 2 pi (80, 120, 100), tol 1e-8. The matvec
+    is the free part (a plan whose layers all have the slab's wavenumber) plus
+    the middle layer's scattered part (hfmm_middle_scattered); milliseconds of
+    each, and the scattered part's error against the oracle on a 32-point
+    subset (its own matvec)."""
+    import oracle
+    import workloads
+    dev = torch.device("cuda:0")
+    w = workloads.middle_layer_ellipses()
+    pts = torch.tensor(w.xy, dtype=torch.float64, device=dev)
+    q = torch.tensor(w.q, dtype=torch.complex128, device=dev)
+    k2 = w.k[1]
+    plan = hf.Plan((k2, k2), (float(w.xy[:, 1].min()) - 1.0,), pts, tol=w.tol, leaf_size=w.leaf)
+    uf = plan.apply(q)
+    ms_free = timed(torch, lambda: plan.apply(q, out=uf), 5)
+    plan.close()
+    us = hf.middle_scattered(w.k, w.interfaces, pts, q, pts, tol=w.tol)
+    ms_scat = timed(torch, lambda: hf.middle_scattered(w.k, w.interfaces, pts, q, pts, tol=w.tol), 2)
+    rng = workloads.rng_for(1703, 9136, 303)
+    si = rng.choice(w.xy.shape[0], 32, replace=False)
+    xs, qs = w.xy[si], w.q[:, si]
+    p2 = torch.tensor(xs, device=dev)
+    ug = hf.middle_scattered(w.k, w.interfaces, p2, torch.tensor(qs, device=dev), p2, tol=w.tol).cpu().numpy()
+    ref = oracle.middle_apply(oracle.Media(w.k, w.interfaces), xs, qs, scattered_only=True)
+    err = float(np.linalg.norm(ug - ref) / np.linalg.norm(ref))
+    out = {"workload": "three-layer k=2pi*(80,120,100), N=%d on 64 ellipses in the middle layer, tol %g"
+                       % (w.xy.shape[0], w.tol),
+           "ms_free_part": ms_free, "ms_scattered_part": ms_scat, "ms_per_matvec": ms_free + ms_scat,
+           "matvecs_per_s": 1e3 / (ms_free + ms_scat), "rel_err_scattered_vs_oracle_subset": err,
+           "finite": bool(torch.isfinite(torch.view_as_real(us)).all())}
+    print("middle layer: %s" % json.dumps(out), file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -399,7 +435,7 @@ def main():
                     help="skip the adjoint, mixed-precision and batched legs (profiling runs)")
     ap.add_argument("--batch-rhs", type=int, default=256)
     ap.add_argument("--many-rhs", type=int, default=64)
-    ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance,iface,xlayer",
+    ap.add_argument("--legs", default="adjoint,mixed,many,batched,impedance,iface,xlayer,middle",
                     help="side legs to run besides the headline (profiling runs pick one)")
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--leaf", type=int, default=0, help="points per leaf (0: the workload's)")
@@ -489,6 +525,7 @@ def main():
     imp = impedance_scaling(hf, torch, np) if "impedance" in legs else None
     iface = near_interface(hf, torch, np) if "iface" in legs else None
     xlayer = cross_layer(hf, torch, np, w, pts, q) if "xlayer" in legs else None
+    middle = middle_layer(hf, torch, np) if "middle" in legs else None
     if "many" in legs:
         many = many_rhs(hf, torch, np, w, pts, golden, args)
     if "batched" in legs:
@@ -507,7 +544,7 @@ def main():
                       % (w.n, w.leaf), "n": w.n, "nrhs": 1, "tol": w.tol, "leaf": w.leaf,
                       "parallelism": "single GPU"},
            "rel_err_vs_oracle": err, "adjoint_s": adj_s, "adjoint_with_coordinate_grad_s": adj_grad_s,
-           "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "near_interface": iface, "cross_layer": xlayer, "plan_s": plan_s,
+           "mixed": mixed, "many_rhs": many, "batched": batch, "impedance": imp, "near_interface": iface, "cross_layer": xlayer, "middle_layer": middle, "plan_s": plan_s,
            "levels": info["levels"], "orders": info["order"],
            "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

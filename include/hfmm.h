@@ -394,6 +394,32 @@ hfmm_status_t hfmm_transmit(int32_t layers, const double *wavenumbers, const dou
                             const double *src, const double *q, int32_t nrhs, int64_t nt, const double *tgt,
                             double *u, double tol, hfmm_stream_t stream);
 
+/*
+ * Sources and targets in the middle layer of three layers: the middle layer's
+ * scattered field (the paper leaves sources below the top layer to a
+ * follow-up; this takes the interface conditions of Section 2.3 with the free
+ * field of a layer-2 source as the incident field):
+ *   u_rt = sum_s q_rs G^s_22(x_t, x_s),
+ * G^s_22 the waves of a layer-2 source reflected at the top and at the lower
+ * interface with all their round trips (four spectral terms: two mirror
+ * images and two shifted by e^{-2 g2 d}); the smooth pair of a point with
+ * itself is included. The full middle-layer matvec adds the free part
+ * (i/4) H0(k2 |x_t - x_s|), i.e. hfmm_apply of a plan whose layers all have
+ * the wavenumber k2 (no reflection) over the same points. As hfmm_transmit:
+ * one quadrature rule for the whole point sets, O((ns + nt) Q).
+ *   wavenumbers   host [3]; interfaces host [2], strictly decreasing.
+ *   ns, src   device [ns][2] doubles; nt, tgt device [nt][2] doubles; every
+ *             point strictly between the interfaces.
+ *   q         device complex [nrhs][ns]; u device complex [nrhs][nt], written.
+ *   tol       relative accuracy of the quadrature, in [1e-14, 1e-2].
+ * Allocates with hipMalloc and synchronises the stream. Errors as
+ * hfmm_transmit (HFMM_ERR_DOMAIN: a point not strictly inside the middle
+ * layer).
+ */
+hfmm_status_t hfmm_middle_scattered(const double *wavenumbers, const double *interfaces, int64_t ns,
+                                    const double *src, const double *q, int32_t nrhs, int64_t nt,
+                                    const double *tgt, double *u, double tol, hfmm_stream_t stream);
+
 /* Plan statistics (host struct, filled synchronously). */
 hfmm_status_t hfmm_plan_info(hfmm_plan_t plan, hfmm_info_t *out);
 

@@ -30,7 +30,7 @@ EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoin
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
            "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy",
            "hfmm_apply_noalloc", "hfmm_tree_build", "hfmm_tree_counts", "hfmm_tree_copy", "hfmm_tree_destroy",
-           "hfmm_bie_solve", "hfmm_transmit")
+           "hfmm_bie_solve", "hfmm_transmit", "hfmm_middle_scattered")
 NSTAGES = 9
 HFMM_FP64, HFMM_FP32, HFMM_BF16 = 0, 1, 2
 HFMM_SELF_SCATTERED, HFMM_SELF_NONE = 0, 1
@@ -149,6 +149,9 @@ def load(path: str | None = None):
     lib.hfmm_transmit.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64, vp, vp, i32, i64, vp, vp, dbl,
                                   vp]
     lib.hfmm_transmit.restype = ctypes.c_int
+    lib.hfmm_middle_scattered.argtypes = [ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64, vp, vp, i32, i64, vp, vp,
+                                          dbl, vp]
+    lib.hfmm_middle_scattered.restype = ctypes.c_int
     lib.hfmm_status_string.argtypes = [ctypes.c_int]
     lib.hfmm_status_string.restype = ctypes.c_char_p
     lib.hfmm_last_error_message.argtypes = []
@@ -292,6 +295,32 @@ def transmit(k, interfaces, src, q, tgt, tol=1e-10, stream=None):
     _check(lib.hfmm_transmit(len(k), kk, ii, ns, ctypes.c_void_p(s2.data_ptr()), ctypes.c_void_p(q2.data_ptr()),
                              int(q2.shape[0]), nt, ctypes.c_void_p(t2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
                              float(tol), _stream_ptr(stream)))
+    return u[0] if q.dim() == 1 else u
+
+
+def middle_scattered(k, interfaces, src, q, tgt, tol=1e-10, stream=None):
+    """The middle layer's scattered field of middle-layer sources
+    (hfmm_middle_scattered): u[r, t] = sum_s q[r, s] G^s_22(tgt_t, src_s), three
+    layers. src, tgt: float64 CUDA tensors (n, 2); q: complex128 CUDA, (ns,) or
+    (nrhs, ns). Returns (nt,) or (nrhs, nt)."""
+    import torch
+    lib = load()
+    if len(k) != 3 or len(interfaces) != 2:
+        raise ValueError("the middle layer needs three wavenumbers and two interfaces")
+    for name, p in (("src", src), ("tgt", tgt)):
+        if not (p.is_cuda and p.dtype == torch.float64 and p.dim() == 2 and p.shape[1] == 2):
+            raise TypeError("%s must be a float64 CUDA tensor of shape (n, 2)" % name)
+    s2, t2 = src.contiguous(), tgt.contiguous()
+    ns, nt = int(s2.shape[0]), int(t2.shape[0])
+    q2 = _as_rhs(q, ns, "q", s2.device)
+    if t2.device != s2.device:
+        raise ValueError("tgt is on %s, src on %s" % (t2.device, s2.device))
+    u = torch.empty((q2.shape[0], nt), dtype=torch.complex128, device=s2.device)
+    kk = (ctypes.c_double * 3)(*[float(v) for v in k])
+    ii = (ctypes.c_double * 2)(*[float(v) for v in interfaces])
+    _check(lib.hfmm_middle_scattered(kk, ii, ns, ctypes.c_void_p(s2.data_ptr()), ctypes.c_void_p(q2.data_ptr()),
+                                     int(q2.shape[0]), nt, ctypes.c_void_p(t2.data_ptr()),
+                                     ctypes.c_void_p(u.data_ptr()), float(tol), _stream_ptr(stream)))
     return u[0] if q.dim() == 1 else u
 
 

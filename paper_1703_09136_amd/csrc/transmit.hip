@@ -206,6 +206,124 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_eval(int nq, const XlNode* __
   for (int r = 0; r < nr; ++r) u[(int64_t)(r0 + r) * nt + it] = acc[r];
 }
 
+// Sources and targets in the middle layer (hfmm_middle_scattered): the
+// middle layer's scattered field. With R1 = (g2 - g1)/(g2 + g1), R3 = (g2 -
+// g3)/(g2 + g3), E = e^{-g2 d} and D = 1 - R1 R3 E^2 (the waves of a layer-2
+// source reflected at the top and at the lower interface, and their repeated
+// round trips), a unit source at y0 leaves
+//   u = (1/(g2 D)) [R1 e^{g2 y} (e^{g2 y0} + R3 E e^{-g2 (y0 + d)})
+//                   + R3 e^{-g2 (y + d)} (e^{-g2 (y0 + d)} + R1 E e^{g2 y0})]
+// under (1/4pi) int ... e^{i lambda (x - x0)} d lambda, every factor at most 1
+// in modulus for -d < y, y0 < 0. Per node two source sums (the factors
+// e^{g2 y_s} and e^{-g2 (y_s + d)}, each with both plane waves) and per target
+// u_t = sum_q sum_+- w_+-(x_t) [e^{g2 y} (c1 S1 + c2E S3) + e^{-g2 (y + d)} (c3 S3 + c2E S1)].
+struct XmNode {
+  double2 lam, g2, c1, c2e, c3;
+};
+
+// part[chunk][r][q][4]: S1+, S1-, S3+, S3-
+template <int RB>
+__global__ void __launch_bounds__(XL_THREADS) k_ml_src(int nq, const XmNode* __restrict__ nodes, int64_t ns,
+                                                       const double2* __restrict__ src, double xc, double yif,
+                                                       double d, const double2* __restrict__ q, int nrhs,
+                                                       int64_t chunk, double2* __restrict__ part) {
+  __shared__ double s_x[XL_THREADS], s_y[XL_THREADS];
+  __shared__ double2 s_q[RB][XL_THREADS];
+  const int iq = blockIdx.x * XL_THREADS + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = min(ns, j0 + chunk);
+  const int r0 = blockIdx.z * RB, nr = min(RB, nrhs - r0);
+  double2 lam = cmk(0.0, 0.0), g2 = cmk(0.0, 0.0);
+  if (iq < nq) {
+    lam = nodes[iq].lam;
+    g2 = nodes[iq].g2;
+  }
+  double2 acc[RB][4];
+  for (int r = 0; r < RB; ++r)
+    for (int h = 0; h < 4; ++h) acc[r][h] = cmk(0.0, 0.0);
+  for (int64_t b0 = j0; b0 < j1; b0 += XL_THREADS) {
+    const int cnt = (int)min((int64_t)XL_THREADS, j1 - b0);
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const double2 p = src[b0 + threadIdx.x];
+      s_x[threadIdx.x] = p.x - xc;
+      s_y[threadIdx.x] = p.y - yif;
+      for (int r = 0; r < RB; ++r)
+        s_q[r][threadIdx.x] = r < nr ? q[(int64_t)(r0 + r) * ns + b0 + threadIdx.x] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (iq >= nq) continue;
+    for (int j = 0; j < cnt; ++j) {
+      const double x = s_x[j], y = s_y[j];
+      const double2 f1 = cexp2(cscale(g2, y)), f3 = cexp2(cscale(g2, -(y + d)));
+      // e^{-+ i lambda x} = e^{+- lambda.y x} (cos(lambda.x x), -+ sin(lambda.x x))
+      const double mx = exp(lam.y * x);
+      double sn, cs;
+      sincos(lam.x * x, &sn, &cs);
+      const double2 pp = cmk(mx * cs, -mx * sn), pm = cmk(cs / mx, sn / mx);
+      const double2 t[4] = {cmul(f1, pp), cmul(f1, pm), cmul(f3, pp), cmul(f3, pm)};
+      for (int r = 0; r < RB; ++r) {
+        const double2 qq = s_q[r][j];
+        for (int h = 0; h < 4; ++h) acc[r][h] = cadd(acc[r][h], cmul(qq, t[h]));
+      }
+    }
+  }
+  if (iq >= nq) return;
+  for (int r = 0; r < nr; ++r) {
+    double2* o = part + (((int64_t)blockIdx.y * nrhs + r0 + r) * nq + iq) * 4;
+    for (int h = 0; h < 4; ++h) o[h] = acc[r][h];
+  }
+}
+
+template <int RB>
+__global__ void __launch_bounds__(XL_THREADS) k_ml_eval(int nq, const XmNode* __restrict__ nodes,
+                                                        const double2* __restrict__ S, int nrhs, int64_t nt,
+                                                        const double2* __restrict__ tgt, double xc, double yif,
+                                                        double d, double2* __restrict__ u) {
+  constexpr int NB = XL_THREADS / 4;
+  __shared__ XmNode s_n[NB];
+  __shared__ double2 s_s[RB][NB][4];
+  const int64_t it = (int64_t)blockIdx.x * XL_THREADS + threadIdx.x;
+  const bool valid = it < nt;
+  const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
+  double x = 0.0, y = -0.5 * d;
+  if (valid) {
+    const double2 p = tgt[it];
+    x = p.x - xc;
+    y = p.y - yif;
+  }
+  double2 acc[RB];
+  for (int r = 0; r < RB; ++r) acc[r] = cmk(0.0, 0.0);
+  for (int q0 = 0; q0 < nq; q0 += NB) {
+    const int cnt = min(NB, nq - q0);
+    __syncthreads();
+    if (threadIdx.x < cnt) s_n[threadIdx.x] = nodes[q0 + threadIdx.x];
+    for (int e = threadIdx.x; e < RB * cnt * 4; e += XL_THREADS) {
+      const int r = e / (cnt * 4), rem = e - r * cnt * 4, j = rem >> 2, h = rem & 3;
+      s_s[r][j][h] = r < nr ? S[((int64_t)(r0 + r) * nq + q0 + j) * 4 + h] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (!valid) continue;
+    for (int j = 0; j < cnt; ++j) {
+      const XmNode nd = s_n[j];
+      const double2 ta = cexp2(cscale(nd.g2, y)), tb = cexp2(cscale(nd.g2, -(y + d)));
+      const double mx = exp(-nd.lam.y * x);
+      double sn, cs;
+      sincos(nd.lam.x * x, &sn, &cs);
+      const double2 wp = cmk(mx * cs, mx * sn), wm = cmk(cs / mx, -sn / mx);
+      for (int r = 0; r < RB; ++r) {
+        const double2 s1p = s_s[r][j][0], s1m = s_s[r][j][1], s3p = s_s[r][j][2], s3m = s_s[r][j][3];
+        const double2 xp = cadd(cmul(ta, cadd(cmul(nd.c1, s1p), cmul(nd.c2e, s3p))),
+                                cmul(tb, cadd(cmul(nd.c3, s3p), cmul(nd.c2e, s1p))));
+        const double2 xm = cadd(cmul(ta, cadd(cmul(nd.c1, s1m), cmul(nd.c2e, s3m))),
+                                cmul(tb, cadd(cmul(nd.c3, s3m), cmul(nd.c2e, s1m))));
+        acc[r] = cadd(acc[r], cadd(cmul(wp, xp), cmul(wm, xm)));
+      }
+    }
+  }
+  if (!valid) return;
+  for (int r = 0; r < nr; ++r) u[(int64_t)(r0 + r) * nt + it] = acc[r];
+}
+
 // sqrt(lambda^2 - k^2) with Re >= 0 (the principal root; on the half contour
 // below the real axis this is the outgoing branch)
 cd gam(cd lam, double k) { return std::sqrt(lam * lam - k * k); }
@@ -409,5 +527,115 @@ extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers
   if (e != hipSuccess)
     return report(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
                   std::string("hfmm_transmit: ") + hipGetErrorString(e));
+  return HFMM_OK;
+}
+
+extern "C" hfmm_status_t hfmm_middle_scattered(const double* wavenumbers, const double* interfaces, int64_t ns,
+                                               const double* src, const double* q, int32_t nrhs, int64_t nt,
+                                               const double* tgt, double* u, double tol, hfmm_stream_t stream) {
+  using namespace hfmm;
+  if (!wavenumbers || !interfaces || !src || !q || !tgt || !u)
+    return report(HFMM_ERR_INVALID_ARG, "NULL wavenumbers, interfaces, src, q, tgt or u");
+  if (ns < 1 || nt < 1 || ns > ((int64_t)1 << 31) || nt > ((int64_t)1 << 31) || nrhs < 1 || nrhs > 65536)
+    return report(HFMM_ERR_INVALID_ARG, "ns, nt or nrhs out of range");
+  if (!(tol >= 1e-14 && tol <= 1e-2)) return report(HFMM_ERR_INVALID_ARG, "tol must be in [1e-14, 1e-2]");
+  const double k[3] = {wavenumbers[0], wavenumbers[1], wavenumbers[2]};
+  for (int j = 0; j < 3; ++j)
+    if (!(k[j] > 0.0) || !std::isfinite(k[j])) return report(HFMM_ERR_UNSUPPORTED, "wavenumbers must be finite and > 0");
+  const double yif = interfaces[0], d = interfaces[0] - interfaces[1];
+  if (!std::isfinite(yif) || !(d > 0.0) || !std::isfinite(d))
+    return report(HFMM_ERR_INVALID_ARG, "interfaces must be finite and strictly decreasing");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> hs((size_t)2 * ns), ht((size_t)2 * nt);
+  hipError_t e = hipMemcpyAsync(hs.data(), src, sizeof(double) * 2 * ns, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ht.data(), tgt, sizeof(double) * 2 * nt, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return report(HFMM_ERR_DEVICE, std::string("copying points: ") + hipGetErrorString(e));
+  // the nearest approach of any point to either interface
+  double xmin = 1e300, xmax = -1e300, hmin = 1e300;
+  for (int set = 0; set < 2; ++set) {
+    const std::vector<double>& h = set ? ht : hs;
+    const int64_t n = set ? nt : ns;
+    for (int64_t i = 0; i < n; ++i) {
+      const double x = h[2 * i], y = h[2 * i + 1] - yif;
+      if (!std::isfinite(x) || !std::isfinite(y)) return report(HFMM_ERR_DOMAIN, "a coordinate is not finite");
+      if (!(y < 0.0 && y > -d)) return report(HFMM_ERR_DOMAIN, "a point is not strictly inside the middle layer");
+      xmin = std::min(xmin, x);
+      xmax = std::max(xmax, x);
+      hmin = std::min(hmin, std::min(-y, y + d));
+    }
+  }
+  const double xc = 0.5 * (xmin + xmax), xspan = xmax - xmin;
+  // slowest decay: a pair both at the nearest approach of one interface; phase
+  // rates up to the longest path (2d plus the layer's height)
+  XlRule rule = xl_rule(k, 3, xspan, 2.0 * hmin, 3.0 * d, tol);
+  if (!rule.ok)
+    return report(HFMM_ERR_ACCURACY, "hfmm_middle_scattered: quadrature rule too long (points too close to an interface for their x range)");
+  double gx[16], gw[16];
+  gauss16(gx, gw);
+  std::vector<XmNode> nodes;
+  nodes.reserve(rule.a.size() * 16);
+  const double inv4pi = 0.25 / M_PI;
+  auto d2 = [](cd v) { return make_double2(v.real(), v.imag()); };
+  for (size_t p = 0; p < rule.a.size(); ++p) {
+    const double hw = 0.5 * (rule.b[p] - rule.a[p]), mid = 0.5 * (rule.a[p] + rule.b[p]);
+    for (int g = 0; g < 16; ++g) {
+      const double sv = mid + hw * gx[g];
+      cd lam(sv, 0.0), dl(1.0, 0.0);
+      if (sv < rule.L) {
+        lam = cd(sv, -rule.dip * std::sin(M_PI * sv / rule.L));
+        dl = cd(1.0, -rule.dip * M_PI / rule.L * std::cos(M_PI * sv / rule.L));
+      }
+      const cd w = inv4pi * hw * gw[g] * dl;
+      const cd g1 = gam(lam, k[0]), g2 = gam(lam, k[1]), g3 = gam(lam, k[2]);
+      const cd E = std::exp(-g2 * d), R1 = (g2 - g1) / (g2 + g1), R3 = (g2 - g3) / (g2 + g3);
+      const cd base = w / (g2 * (1.0 - R1 * R3 * E * E));
+      nodes.push_back(XmNode{d2(lam), d2(g2), d2(base * R1), d2(base * R1 * R3 * E), d2(base * R3)});
+    }
+  }
+  const int nq = (int)nodes.size();
+  if (const char* env = std::getenv("HFMM_LOG"))
+    if (env[0] == '1')
+      std::fprintf(stderr, "[hfmm] middle layer: %zu panels, %d nodes (x range %.4g, nearest approach %.4g)\n",
+                   rule.a.size(), nq, xspan, hmin);
+  const int ntile = (nq + XL_THREADS - 1) / XL_THREADS;
+  const int64_t maxchunk = (ns + XL_THREADS - 1) / XL_THREADS;
+  const int nchunk = (int)std::max<int64_t>(1, std::min<int64_t>(maxchunk, 2048 / std::max(ntile, 1)));
+  const int64_t chunk = ((ns + nchunk - 1) / nchunk + XL_THREADS - 1) / XL_THREADS * XL_THREADS;
+  const int rb = nrhs == 1 ? 1 : XL_RB;
+  const int nrg = (nrhs + rb - 1) / rb;
+  DevBuf<XmNode> d_nodes;
+  DevBuf<double2> d_part, d_S;
+  const int64_t slen = (int64_t)nrhs * nq * 4;
+  e = d_nodes.upload(nodes, s);
+  if (e == hipSuccess) e = d_part.alloc((size_t)nchunk * slen);
+  if (e == hipSuccess) e = d_S.alloc((size_t)slen);
+  if (e == hipSuccess) {
+    const dim3 gs(ntile, nchunk, nrg);
+    if (rb == 1)
+      hipLaunchKernelGGL(k_ml_src<1>, gs, dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns, (const double2*)src, xc, yif, d,
+                         (const double2*)q, (int)nrhs, chunk, d_part.p);
+    else
+      hipLaunchKernelGGL(k_ml_src<XL_RB>, gs, dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns, (const double2*)src, xc, yif,
+                         d, (const double2*)q, (int)nrhs, chunk, d_part.p);
+    hipLaunchKernelGGL(k_xl_sum, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s, slen, nchunk, d_part.p,
+                       d_S.p);
+    const dim3 ge((unsigned)((nt + XL_THREADS - 1) / XL_THREADS), nrg);
+    if (rb == 1)
+      hipLaunchKernelGGL(k_ml_eval<1>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                         (const double2*)tgt, xc, yif, d, (double2*)u);
+    else
+      hipLaunchKernelGGL(k_ml_eval<XL_RB>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                         (const double2*)tgt, xc, yif, d, (double2*)u);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  else (void)hipStreamSynchronize(s);
+  d_nodes.release();
+  d_part.release();
+  d_S.release();
+  if (e != hipSuccess)
+    return report(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
+                  std::string("hfmm_middle_scattered: ") + hipGetErrorString(e));
   return HFMM_OK;
 }

@@ -55,12 +55,13 @@ def uniform_box(rng, n, x0, x1, y0, y1) -> np.ndarray:
 
 
 def ellipse_points(rng, n_total, n_ellipses, cy_range, min_bottom,
-                   axis_range=(0.02, 0.08), cx_range=(0.0, 1.0)) -> np.ndarray:
+                   axis_range=(0.02, 0.08), cx_range=(0.0, 1.0), max_top=None) -> np.ndarray:
     """Points on random ellipses, equispaced in the parameter.
 
     Per ellipse, in this order: semi-axes a, b ~ U(axis_range), orientation
     phi ~ U(0, pi), centre x ~ U(cx_range), centre y ~ U(cy_range), the last
-    redrawn until the lowest point of the ellipse is at least ``min_bottom``.
+    redrawn until the lowest point of the ellipse is at least ``min_bottom``
+    (and, with ``max_top``, its highest point at most ``max_top``).
     ``n_total`` points are split evenly, the remainder going to the first
     ellipses.
     """
@@ -74,7 +75,7 @@ def ellipse_points(rng, n_total, n_ellipses, cy_range, min_bottom,
         half_height = math.sqrt((a * math.sin(phi)) ** 2 + (b * math.cos(phi)) ** 2)
         while True:
             cy = rng.uniform(*cy_range)
-            if cy - half_height >= min_bottom:
+            if cy - half_height >= min_bottom and (max_top is None or cy + half_height <= max_top):
                 break
         m = base + (1 if e < rem else 0)
         t = TWO_PI * np.arange(m) / m
@@ -121,6 +122,17 @@ def three_layer_ellipses(n=1_000_000, seed=3, nrhs=1, n_ellipses=64):
     xy = ellipse_points(rng, n, n_ellipses, (0.5, 1.0), 0.51)
     q = complex_normal(rng, (nrhs, n))
     return Workload("three-layer k=2pi*(80,120,100) 64 ellipses N=%d" % n, THREE_LAYER_K,
+                    THREE_LAYER_IF, xy, q, leaf=64, tol=1e-8)
+
+
+def middle_layer_ellipses(n=1_000_000, seed=5, nrhs=1, n_ellipses=64):
+    """The three-layer medium above with the points in the middle layer: 64
+    ellipses with centres y ~ U(0, 0.5) (uniform in the slab), every ellipse
+    at least 0.01 inside both interfaces."""
+    rng = rng_for(1703, 9136, seed)
+    xy = ellipse_points(rng, n, n_ellipses, (0.0, 0.5), 0.01, max_top=0.49)
+    q = complex_normal(rng, (nrhs, n))
+    return Workload("middle layer k=2pi*(80,120,100) 64 ellipses N=%d" % n, THREE_LAYER_K,
                     THREE_LAYER_IF, xy, q, leaf=64, tol=1e-8)
 
 
