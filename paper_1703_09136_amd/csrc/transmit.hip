@@ -252,6 +252,22 @@ __global__ void __launch_bounds__(XL_THREADS) k_ml_src(int nq, const XmNode* __r
     }
     __syncthreads();
     if (iq >= nq) continue;
+    if (lam.y == 0.0 && g2.y == 0.0) {
+      // a node on the real axis past every branch point: real factors
+      for (int j = 0; j < cnt; ++j) {
+        const double x = s_x[j], y = s_y[j];
+        const double f1 = exp(g2.x * y), f3 = exp(-g2.x * (y + d));
+        double sn, cs;
+        sincos(lam.x * x, &sn, &cs);
+        const double2 t[4] = {cmk(f1 * cs, -f1 * sn), cmk(f1 * cs, f1 * sn), cmk(f3 * cs, -f3 * sn),
+                              cmk(f3 * cs, f3 * sn)};
+        for (int r = 0; r < RB; ++r) {
+          const double2 qq = s_q[r][j];
+          for (int h = 0; h < 4; ++h) acc[r][h] = cadd(acc[r][h], cmul(qq, t[h]));
+        }
+      }
+      continue;
+    }
     for (int j = 0; j < cnt; ++j) {
       const double x = s_x[j], y = s_y[j];
       const double2 f1 = cexp2(cscale(g2, y)), f3 = cexp2(cscale(g2, -(y + d)));
@@ -305,8 +321,10 @@ __global__ void __launch_bounds__(XL_THREADS) k_ml_eval(int nq, const XmNode* __
     if (!valid) continue;
     for (int j = 0; j < cnt; ++j) {
       const XmNode nd = s_n[j];
-      const double2 ta = cexp2(cscale(nd.g2, y)), tb = cexp2(cscale(nd.g2, -(y + d)));
-      const double mx = exp(-nd.lam.y * x);
+      const bool rl = nd.lam.y == 0.0 && nd.g2.y == 0.0;  // real axis past the branch points
+      const double2 ta = rl ? cmk(exp(nd.g2.x * y), 0.0) : cexp2(cscale(nd.g2, y));
+      const double2 tb = rl ? cmk(exp(-nd.g2.x * (y + d)), 0.0) : cexp2(cscale(nd.g2, -(y + d)));
+      const double mx = rl ? 1.0 : exp(-nd.lam.y * x);
       double sn, cs;
       sincos(nd.lam.x * x, &sn, &cs);
       const double2 wp = cmk(mx * cs, mx * sn), wm = cmk(cs / mx, -sn / mx);
