@@ -380,10 +380,16 @@ def cross_layer(hf, torch, np, w, pts, q):
     ref = oracle.cross_layer_apply(oracle.Media(w.k, w.interfaces), xs, qs, tgt[ti])
     err = float(np.linalg.norm(us - ref) / np.linalg.norm(ref))
     ns, nt = int(pts.shape[0]), tgt.shape[0]
+    # the reverse pairs: the 10^5 points below as sources, the headline points as targets
+    qb = torch.tensor(workloads.complex_normal(rng, (1, nt)), dtype=torch.complex128, device=dev)
+    uu = hf.transmit(w.k, w.interfaces, tg, qb, pts, tol=tol, up=True)
+    ms_up = timed(torch, lambda: hf.transmit(w.k, w.interfaces, tg, qb, pts, tol=tol, up=True), 3)
     out = {"workload": "three-layer k=2pi*(80,120,100): %d top-layer sources (the headline points), %d targets "
-                       "at depths 0.02-0.9 below the top interface, tol %g" % (ns, nt, tol),
+                       "at depths 0.02-0.9 below the top interface, tol %g; the reverse pairs with the two sets "
+                       "exchanged" % (ns, nt, tol),
            "ms_per_call": ms, "pairs_per_s": ns * nt / ms * 1e3, "rel_err_vs_oracle_subset": err,
-           "finite": bool(torch.isfinite(torch.view_as_real(u)).all())}
+           "ms_per_call_reverse": ms_up,
+           "finite": bool(torch.isfinite(torch.view_as_real(u)).all() and torch.isfinite(torch.view_as_real(uu)).all())}
     print("cross-layer: %s" % json.dumps(out), file=sys.stderr, flush=True)
     return out
 

@@ -395,6 +395,20 @@ hfmm_status_t hfmm_transmit(int32_t layers, const double *wavenumbers, const dou
                             double *u, double tol, hfmm_stream_t stream);
 
 /*
+ * The reverse pairs: sources below the top interface (layer 2 or 3), targets
+ * in the top layer, u_rt = sum_s q_rs G(x_t, x_s). The domain Green's function
+ * is symmetric (the interface conditions of Section 2.3 make the operator
+ * self-adjoint), G(x_t, x_s) = G(x_s, x_t), so this is the transpose of
+ * hfmm_transmit's sum: the same rule, the lower-layer factors in the source
+ * sums and e^{-g1 y} at the targets. Arguments as hfmm_transmit with the
+ * roles of the sets exchanged: every source y strictly below, every target y
+ * strictly above interfaces[0].
+ */
+hfmm_status_t hfmm_transmit_up(int32_t layers, const double *wavenumbers, const double *interfaces, int64_t ns,
+                               const double *src, const double *q, int32_t nrhs, int64_t nt, const double *tgt,
+                               double *u, double tol, hfmm_stream_t stream);
+
+/*
  * Sources and targets in the middle layer of three layers: the middle layer's
  * scattered field (the paper leaves sources below the top layer to a
  * follow-up; this takes the interface conditions of Section 2.3 with the free

@@ -30,7 +30,7 @@ EXPORTS = ("hfmm_default_options", "hfmm_plan", "hfmm_apply", "hfmm_apply_adjoin
            "hfmm_destroy", "hfmm_status_string", "hfmm_last_error_message",
            "hfmm_plan_batch", "hfmm_apply_batch", "hfmm_batch_graph", "hfmm_batch_plan", "hfmm_batch_destroy",
            "hfmm_apply_noalloc", "hfmm_tree_build", "hfmm_tree_counts", "hfmm_tree_copy", "hfmm_tree_destroy",
-           "hfmm_bie_solve", "hfmm_transmit", "hfmm_middle_scattered")
+           "hfmm_bie_solve", "hfmm_transmit", "hfmm_transmit_up", "hfmm_middle_scattered")
 NSTAGES = 9
 HFMM_FP64, HFMM_FP32, HFMM_BF16 = 0, 1, 2
 HFMM_SELF_SCATTERED, HFMM_SELF_NONE = 0, 1
@@ -149,6 +149,8 @@ def load(path: str | None = None):
     lib.hfmm_transmit.argtypes = [i32, ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64, vp, vp, i32, i64, vp, vp, dbl,
                                   vp]
     lib.hfmm_transmit.restype = ctypes.c_int
+    lib.hfmm_transmit_up.argtypes = lib.hfmm_transmit.argtypes
+    lib.hfmm_transmit_up.restype = ctypes.c_int
     lib.hfmm_middle_scattered.argtypes = [ctypes.POINTER(dbl), ctypes.POINTER(dbl), i64, vp, vp, i32, i64, vp, vp,
                                           dbl, vp]
     lib.hfmm_middle_scattered.restype = ctypes.c_int
@@ -274,11 +276,12 @@ def build_tree(k, interfaces, points, builder=HFMM_TREE_GPU, stream=None, **opti
     return out
 
 
-def transmit(k, interfaces, src, q, tgt, tol=1e-10, stream=None):
+def transmit(k, interfaces, src, q, tgt, tol=1e-10, stream=None, up=False):
     """The field below the top interface of top-layer sources (hfmm_transmit):
     u[r, t] = sum_s q[r, s] G(tgt_t, src_s), the middle- and bottom-layer fields
-    of Section 2.3. src, tgt: float64 CUDA tensors (n, 2); q: complex128 CUDA,
-    (ns,) or (nrhs, ns). Returns (nt,) or (nrhs, nt)."""
+    of Section 2.3; with up=True the reverse pairs, sources below and targets
+    in the top layer (hfmm_transmit_up). src, tgt: float64 CUDA tensors (n, 2);
+    q: complex128 CUDA, (ns,) or (nrhs, ns). Returns (nt,) or (nrhs, nt)."""
     import torch
     lib = load()
     for name, p in (("src", src), ("tgt", tgt)):
@@ -292,9 +295,10 @@ def transmit(k, interfaces, src, q, tgt, tol=1e-10, stream=None):
     u = torch.empty((q2.shape[0], nt), dtype=torch.complex128, device=s2.device)
     kk = (ctypes.c_double * len(k))(*[float(v) for v in k])
     ii = (ctypes.c_double * max(1, len(interfaces)))(*([float(v) for v in interfaces] or [0.0]))
-    _check(lib.hfmm_transmit(len(k), kk, ii, ns, ctypes.c_void_p(s2.data_ptr()), ctypes.c_void_p(q2.data_ptr()),
-                             int(q2.shape[0]), nt, ctypes.c_void_p(t2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
-                             float(tol), _stream_ptr(stream)))
+    fn = lib.hfmm_transmit_up if up else lib.hfmm_transmit
+    _check(fn(len(k), kk, ii, ns, ctypes.c_void_p(s2.data_ptr()), ctypes.c_void_p(q2.data_ptr()),
+              int(q2.shape[0]), nt, ctypes.c_void_p(t2.data_ptr()), ctypes.c_void_p(u.data_ptr()),
+              float(tol), _stream_ptr(stream)))
     return u[0] if q.dim() == 1 else u
 
 

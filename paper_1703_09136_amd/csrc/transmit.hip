@@ -206,6 +206,114 @@ __global__ void __launch_bounds__(XL_THREADS) k_xl_eval(int nq, const XlNode* __
   for (int r = 0; r < nr; ++r) u[(int64_t)(r0 + r) * nt + it] = acc[r];
 }
 
+// The transposed direction (hfmm_transmit with the sources below and the
+// targets in the top layer): the domain Green's function is symmetric,
+// G(x_t, x_s) = G(x_s, x_t), so the lower-layer factor T_q moves to the
+// source sums and e^{-g1 y} to the targets:
+//   S_q^+- = sum_s q_s T_q(y_s) e^{-+ i lambda_q x'_s},
+//   u_t = sum_q e^{-g1 y_t} (S_q^+ e^{i lambda_q x'_t} + S_q^- e^{-i lambda_q x'_t}).
+__device__ inline double2 xl_lower(const XlNode& nd, double y, double d, int layers) {
+  if (layers == 3 && y < -d) return cmul(nd.c, cexp2(cscale(nd.g3, y + d)));
+  double2 T = cmul(nd.a, cexp2(cscale(nd.g2, y)));
+  if (layers == 3) T = cadd(T, cmul(nd.b, cexp2(cscale(nd.g2, -(y + 2.0 * d)))));
+  return T;
+}
+
+template <int RB>
+__global__ void __launch_bounds__(XL_THREADS) k_xu_src(int nq, const XlNode* __restrict__ nodes, int64_t ns,
+                                                       const double2* __restrict__ src, double xc, double yif,
+                                                       double d, int layers, const double2* __restrict__ q, int nrhs,
+                                                       int64_t chunk, double2* __restrict__ part) {
+  __shared__ double s_x[XL_THREADS], s_y[XL_THREADS];
+  __shared__ double2 s_q[RB][XL_THREADS];
+  const int iq = blockIdx.x * XL_THREADS + threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.y * chunk, j1 = min(ns, j0 + chunk);
+  const int r0 = blockIdx.z * RB, nr = min(RB, nrhs - r0);
+  XlNode nd{};
+  if (iq < nq) nd = nodes[iq];
+  double2 sp[RB], sm[RB];
+  for (int r = 0; r < RB; ++r) sp[r] = sm[r] = cmk(0.0, 0.0);
+  for (int64_t b0 = j0; b0 < j1; b0 += XL_THREADS) {
+    const int cnt = (int)min((int64_t)XL_THREADS, j1 - b0);
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      const double2 p = src[b0 + threadIdx.x];
+      s_x[threadIdx.x] = p.x - xc;
+      s_y[threadIdx.x] = p.y - yif;
+      for (int r = 0; r < RB; ++r)
+        s_q[r][threadIdx.x] = r < nr ? q[(int64_t)(r0 + r) * ns + b0 + threadIdx.x] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (iq >= nq) continue;
+    for (int j = 0; j < cnt; ++j) {
+      const double x = s_x[j];
+      const double2 T = xl_lower(nd, s_y[j], d, layers);
+      // e^{-+ i lambda x} = e^{+- lambda.y x} (cos(lambda.x x), -+ sin(lambda.x x))
+      const double mx = exp(nd.lam.y * x);
+      double sn, cs;
+      sincos(nd.lam.x * x, &sn, &cs);
+      const double2 ep = cmul(T, cmk(mx * cs, -mx * sn)), em = cmul(T, cmk(cs / mx, sn / mx));
+      for (int r = 0; r < RB; ++r) {
+        const double2 qq = s_q[r][j];
+        sp[r] = cadd(sp[r], cmul(qq, ep));
+        sm[r] = cadd(sm[r], cmul(qq, em));
+      }
+    }
+  }
+  if (iq >= nq) return;
+  for (int r = 0; r < nr; ++r) {
+    double2* o = part + (((int64_t)blockIdx.y * nrhs + r0 + r) * nq + iq) * 2;
+    o[0] = sp[r];
+    o[1] = sm[r];
+  }
+}
+
+template <int RB>
+__global__ void __launch_bounds__(XL_THREADS) k_xu_eval(int nq, const XlNode* __restrict__ nodes,
+                                                        const double2* __restrict__ S, int nrhs, int64_t nt,
+                                                        const double2* __restrict__ tgt, double xc, double yif,
+                                                        double2* __restrict__ u) {
+  constexpr int NB = XL_THREADS / 4;
+  __shared__ double2 s_lam[NB], s_g1[NB];
+  __shared__ double2 s_s[RB][NB][2];
+  const int64_t it = (int64_t)blockIdx.x * XL_THREADS + threadIdx.x;
+  const bool valid = it < nt;
+  const int r0 = blockIdx.y * RB, nr = min(RB, nrhs - r0);
+  double x = 0.0, y = 1.0;
+  if (valid) {
+    const double2 p = tgt[it];
+    x = p.x - xc;
+    y = p.y - yif;
+  }
+  double2 acc[RB];
+  for (int r = 0; r < RB; ++r) acc[r] = cmk(0.0, 0.0);
+  for (int q0 = 0; q0 < nq; q0 += NB) {
+    const int cnt = min(NB, nq - q0);
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+      s_lam[threadIdx.x] = nodes[q0 + threadIdx.x].lam;
+      s_g1[threadIdx.x] = nodes[q0 + threadIdx.x].g1;
+    }
+    for (int e = threadIdx.x; e < RB * cnt * 2; e += XL_THREADS) {
+      const int r = e / (cnt * 2), rem = e - r * cnt * 2, j = rem >> 1, h = rem & 1;
+      s_s[r][j][h] = r < nr ? S[((int64_t)(r0 + r) * nq + q0 + j) * 2 + h] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    if (!valid) continue;
+    for (int j = 0; j < cnt; ++j) {
+      const double2 lam = s_lam[j];
+      const double2 T = cexp2(cscale(s_g1[j], -y));
+      const double mx = exp(-lam.y * x);
+      double sn, cs;
+      sincos(lam.x * x, &sn, &cs);
+      const double2 wp = cmul(T, cmk(mx * cs, mx * sn)), wm = cmul(T, cmk(cs / mx, -sn / mx));
+      for (int r = 0; r < RB; ++r) acc[r] = cadd(acc[r], cadd(cmul(s_s[r][j][0], wp), cmul(s_s[r][j][1], wm)));
+    }
+  }
+  if (!valid) return;
+  for (int r = 0; r < nr; ++r) u[(int64_t)(r0 + r) * nt + it] = acc[r];
+}
+
 // Sources and targets in the middle layer (hfmm_middle_scattered): the
 // middle layer's scattered field. With R1 = (g2 - g1)/(g2 + g1), R3 = (g2 -
 // g3)/(g2 + g3), E = e^{-g2 d} and D = 1 - R1 R3 E^2 (the waves of a layer-2
@@ -418,10 +526,13 @@ void gauss16(double* x, double* w) {
 }  // namespace
 }  // namespace hfmm
 
-extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers, const double* interfaces,
-                                       int64_t ns, const double* src, const double* q, int32_t nrhs, int64_t nt,
-                                       const double* tgt, double* u, double tol, hfmm_stream_t stream) {
-  using namespace hfmm;
+namespace hfmm {
+namespace {
+// up = false: sources in the top layer, targets below it; up = true: the
+// reverse (the transposed node sums).
+hfmm_status_t transmit_impl(bool up, int32_t layers, const double* wavenumbers, const double* interfaces, int64_t ns,
+                            const double* src, const double* q, int32_t nrhs, int64_t nt, const double* tgt,
+                            double* u, double tol, hfmm_stream_t stream) {
   if (!wavenumbers || !interfaces || !src || !q || !tgt || !u)
     return report(HFMM_ERR_INVALID_ARG, "NULL wavenumbers, interfaces, src, q, tgt or u");
   if (layers != 2 && layers != 3)
@@ -443,27 +554,32 @@ extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers
   if (e == hipSuccess) e = hipMemcpyAsync(ht.data(), tgt, sizeof(double) * 2 * nt, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return report(HFMM_ERR_DEVICE, std::string("copying points: ") + hipGetErrorString(e));
+  // hs_*: heights of the top-layer set, ht_*: depths of the set below
   double xmin = 1e300, xmax = -1e300, hs_min = 1e300, hs_max = 0.0, ht_min = 1e300, ht_max = 0.0;
-  for (int64_t i = 0; i < ns; ++i) {
-    const double x = hs[2 * i], y = hs[2 * i + 1] - yif;
-    if (!std::isfinite(x) || !std::isfinite(y)) return report(HFMM_ERR_DOMAIN, "a source coordinate is not finite");
-    if (!(y > 0.0)) return report(HFMM_ERR_DOMAIN, "a source is not above the top interface");
+  const std::vector<double>& hi = up ? ht : hs;
+  const std::vector<double>& lo = up ? hs : ht;
+  const char* hi_name = up ? "a target" : "a source";
+  const char* lo_name = up ? "a source" : "a target";
+  for (int64_t i = 0; i < (up ? nt : ns); ++i) {
+    const double x = hi[2 * i], y = hi[2 * i + 1] - yif;
+    if (!std::isfinite(x) || !std::isfinite(y)) return report(HFMM_ERR_DOMAIN, "a coordinate is not finite");
+    if (!(y > 0.0)) return report(HFMM_ERR_DOMAIN, std::string(hi_name) + " is not above the top interface");
     xmin = std::min(xmin, x);
     xmax = std::max(xmax, x);
     hs_min = std::min(hs_min, y);
     hs_max = std::max(hs_max, y);
   }
-  for (int64_t i = 0; i < nt; ++i) {
-    const double x = ht[2 * i], y = ht[2 * i + 1] - yif;
-    if (!std::isfinite(x) || !std::isfinite(y)) return report(HFMM_ERR_DOMAIN, "a target coordinate is not finite");
-    if (!(y < 0.0)) return report(HFMM_ERR_DOMAIN, "a target is not below the top interface");
+  for (int64_t i = 0; i < (up ? ns : nt); ++i) {
+    const double x = lo[2 * i], y = lo[2 * i + 1] - yif;
+    if (!std::isfinite(x) || !std::isfinite(y)) return report(HFMM_ERR_DOMAIN, "a coordinate is not finite");
+    if (!(y < 0.0)) return report(HFMM_ERR_DOMAIN, std::string(lo_name) + " is not below the top interface");
     xmin = std::min(xmin, x);
     xmax = std::max(xmax, x);
     ht_min = std::min(ht_min, -y);
     ht_max = std::max(ht_max, -y);
   }
   const double xc = 0.5 * (xmin + xmax), xspan = xmax - xmin;
-  // the slowest decay at large lambda: the nearest source over the nearest target
+  // the slowest decay at large lambda: the nearest point above over the nearest below
   const double ysum_min = hs_min + ht_min;
   // phase rates of the y factors: the heights, and the slab's round trips
   XlRule rule = xl_rule(k, layers, xspan, ysum_min, hs_max + ht_max + (layers == 3 ? 2.0 * d : 0.0), tol);
@@ -520,21 +636,41 @@ extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers
   if (e == hipSuccess) e = d_part.alloc((size_t)nchunk * slen);
   if (e == hipSuccess) e = d_S.alloc((size_t)slen);
   if (e == hipSuccess) {
-    if (rb == 1)
-      hipLaunchKernelGGL(k_xl_src<1>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
-                         (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
-    else
-      hipLaunchKernelGGL(k_xl_src<XL_RB>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
-                         (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
-    hipLaunchKernelGGL(k_xl_sum, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s, slen, nchunk, d_part.p,
-                       d_S.p);
-    const dim3 ge((unsigned)((nt + XL_THREADS - 1) / XL_THREADS), nrg);
-    if (rb == 1)
-      hipLaunchKernelGGL(k_xl_eval<1>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
-                         (const double2*)tgt, xc, yif, d, (int)layers, (double2*)u);
-    else
-      hipLaunchKernelGGL(k_xl_eval<XL_RB>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
-                         (const double2*)tgt, xc, yif, d, (int)layers, (double2*)u);
+    if (up) {
+      if (rb == 1)
+        hipLaunchKernelGGL(k_xu_src<1>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
+                           (const double2*)src, xc, yif, d, (int)layers, (const double2*)q, (int)nrhs, chunk,
+                           d_part.p);
+      else
+        hipLaunchKernelGGL(k_xu_src<XL_RB>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
+                           (const double2*)src, xc, yif, d, (int)layers, (const double2*)q, (int)nrhs, chunk,
+                           d_part.p);
+      hipLaunchKernelGGL(k_xl_sum, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s, slen, nchunk, d_part.p,
+                         d_S.p);
+      const dim3 ge((unsigned)((nt + XL_THREADS - 1) / XL_THREADS), nrg);
+      if (rb == 1)
+        hipLaunchKernelGGL(k_xu_eval<1>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                           (const double2*)tgt, xc, yif, (double2*)u);
+      else
+        hipLaunchKernelGGL(k_xu_eval<XL_RB>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                           (const double2*)tgt, xc, yif, (double2*)u);
+    } else {
+      if (rb == 1)
+        hipLaunchKernelGGL(k_xl_src<1>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
+                           (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
+      else
+        hipLaunchKernelGGL(k_xl_src<XL_RB>, dim3(ntile, nchunk, nrg), dim3(XL_THREADS), 0, s, nq, d_nodes.p, ns,
+                           (const double2*)src, xc, yif, (const double2*)q, (int)nrhs, chunk, d_part.p);
+      hipLaunchKernelGGL(k_xl_sum, dim3((unsigned)((slen + 255) / 256)), dim3(256), 0, s, slen, nchunk, d_part.p,
+                         d_S.p);
+      const dim3 ge((unsigned)((nt + XL_THREADS - 1) / XL_THREADS), nrg);
+      if (rb == 1)
+        hipLaunchKernelGGL(k_xl_eval<1>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                           (const double2*)tgt, xc, yif, d, (int)layers, (double2*)u);
+      else
+        hipLaunchKernelGGL(k_xl_eval<XL_RB>, ge, dim3(XL_THREADS), 0, s, nq, d_nodes.p, d_S.p, (int)nrhs, nt,
+                           (const double2*)tgt, xc, yif, d, (int)layers, (double2*)u);
+    }
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -546,6 +682,20 @@ extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers
     return report(e == hipErrorOutOfMemory ? HFMM_ERR_NO_MEMORY : HFMM_ERR_DEVICE,
                   std::string("hfmm_transmit: ") + hipGetErrorString(e));
   return HFMM_OK;
+}
+}  // namespace
+}  // namespace hfmm
+
+extern "C" hfmm_status_t hfmm_transmit(int32_t layers, const double* wavenumbers, const double* interfaces,
+                                       int64_t ns, const double* src, const double* q, int32_t nrhs, int64_t nt,
+                                       const double* tgt, double* u, double tol, hfmm_stream_t stream) {
+  return hfmm::transmit_impl(false, layers, wavenumbers, interfaces, ns, src, q, nrhs, nt, tgt, u, tol, stream);
+}
+
+extern "C" hfmm_status_t hfmm_transmit_up(int32_t layers, const double* wavenumbers, const double* interfaces,
+                                          int64_t ns, const double* src, const double* q, int32_t nrhs, int64_t nt,
+                                          const double* tgt, double* u, double tol, hfmm_stream_t stream) {
+  return hfmm::transmit_impl(true, layers, wavenumbers, interfaces, ns, src, q, nrhs, nt, tgt, u, tol, stream);
 }
 
 extern "C" hfmm_status_t hfmm_middle_scattered(const double* wavenumbers, const double* interfaces, int64_t ns,

@@ -5,7 +5,9 @@ layer and targets in the layers below.
 Bars: one wavenumber everywhere gives the free field (i/4) H0(k r) (scipy's
 Hankel function) to 1e-10; three layers (targets in the middle and the bottom
 layer) and two layers against the oracle's sum of the middle- and
-bottom-layer densities to 1e-10 at tol 1e-12; five right-hand sides (two
+bottom-layer densities to 1e-10 at tol 1e-12, and the reverse pairs (sources
+below, targets in the top layer) against the same fields read by
+reciprocity; five right-hand sides (two
 groups of the node sums) against single columns to 1e-14; points on the
 wrong side of the interface are HFMM_ERR_DOMAIN, the impedance half-space
 HFMM_ERR_UNSUPPORTED.
@@ -90,3 +92,35 @@ def test_domain_and_medium_errors(gpu_lib):
     with pytest.raises(gpu_lib.HFMMError) as ei:
         run(gpu_lib, (10.0,), (0.0,), src - [0, 0.5], q[0], tgt - [0, 0.5], 1e-8)
     assert ei.value.status == 3  # HFMM_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("k,ifs", [(K3, IF3), (K2, (0.0,))])
+def test_reverse_pairs_against_the_oracle(gpu_lib, k, ifs):
+    """Sources below the interface, targets in the top layer
+    (hfmm_transmit_up) against the oracle's transmitted fields read by
+    reciprocity, G(x_t, x_s) = G(x_s, x_t) (pinned between two independent
+    oracle paths in tests/test_oracle.py)."""
+    top, below, q = sets(205, ifs, 16, 40, 0.9)
+    rng = workloads.rng_for(1703, 9136, 206)
+    qb = workloads.complex_normal(rng, (1, below.shape[0]))[0]
+    u = run_up(gpu_lib, k, ifs, below, qb, top, 1e-12)
+    # M[j, i] = G(below_i; top_j): the oracle's field of each top point at the points below
+    M = oracle.cross_layer_apply(oracle.Media(k, ifs), top, np.eye(top.shape[0]), below)
+    ref = M @ qb
+    e = rel(u, ref)
+    print("%d layers, reverse pairs vs oracle: %.2e" % (len(k), e))
+    assert e < 1e-10
+
+
+def test_reverse_pairs_domain_errors(gpu_lib):
+    top, below, q = sets(207, IF3, 10, 20, 0.9)
+    with pytest.raises(gpu_lib.HFMMError) as ei:
+        run_up(gpu_lib, K3, IF3, top, q[0][:10], top, 1e-8)  # sources above the interface
+    assert ei.value.status == 2  # HFMM_ERR_DOMAIN
+
+
+def run_up(hf, k, ifs, src, q, tgt, tol):
+    import torch
+    dev = torch.device("cuda:0")
+    return hf.transmit(k, ifs, torch.tensor(src, device=dev), torch.tensor(q, device=dev),
+                       torch.tensor(tgt, device=dev), tol=tol, up=True).cpu().numpy()

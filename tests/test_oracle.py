@@ -571,3 +571,15 @@ def test_middle_apply_is_the_pairwise_sum():
                 g += 0.25j * hankel1(0, KM[1] * math.hypot(xy[i, 0] - xy[j, 0], y[i] - y[j]))
             ref += q[j] * g
         assert abs(u[i] - ref) < 1e-13 * abs(ref)
+
+
+def test_cross_layer_reciprocity_between_independent_paths():
+    """G(x, x0) = G(x0, x) across the top interface, the two values coming
+    from different interface systems: a middle-layer source seen in the top
+    layer (``middle``) and a top-layer source seen in the middle layer
+    (``layer_field``)."""
+    m = Media(KM, IF3)
+    for (xt, yt), (xm, ym) in (((0.3, 0.12), (0.05, -0.2)), ((-0.1, 0.05), (0.4, -0.41))):
+        a = middle_source_field(m, 1, xt, yt, xm, ym)[0]
+        b = oracle.layer_field(m, 2, xm, ym, xt, yt)[0]
+        assert abs(a - b) < 1e-10 * abs(a), (a, b)
