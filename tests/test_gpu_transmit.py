@@ -61,7 +61,7 @@ def test_homogeneous_medium_gives_the_free_field(gpu_lib, ks, ifs):
 def test_against_the_oracle(gpu_lib, k, ifs):
     """Three layers: targets down to 0.9 below the top interface (the lower
     interface is at depth 0.5), so both layer formulas are used."""
-    src, tgt, q = sets(202, ifs, 150, 40, 0.9)
+    src, tgt, q = sets(202, ifs, 60, 30, 0.9)
     u = run(gpu_lib, k, ifs, src, q[0], tgt, 1e-12)
     ref = oracle.cross_layer_apply(oracle.Media(k, ifs), src, q[0], tgt)
     e = rel(u, ref)
@@ -124,3 +124,25 @@ def run_up(hf, k, ifs, src, q, tgt, tol):
     dev = torch.device("cuda:0")
     return hf.transmit(k, ifs, torch.tensor(src, device=dev), torch.tensor(q, device=dev),
                        torch.tensor(tgt, device=dev), tol=tol, up=True).cpu().numpy()
+
+
+def test_middle_to_bottom_pairs_by_the_mirrored_medium(gpu_lib):
+    """Sources in the middle layer, targets in the bottom layer: mirrored in y
+    (y -> -y) the medium is (k3, k2, k1) with the old lower interface on top,
+    the targets lie in its top layer and the sources below it, so
+    hfmm_transmit_up of the mirrored medium gives them; against the oracle's
+    middle-layer source seen in the bottom layer (oracle.middle)."""
+    from oracle.middle import middle_source_field
+    rng = workloads.rng_for(1703, 9136, 208)
+    src = np.c_[rng.uniform(0.0, 1.0, 12), rng.uniform(0.03, 0.47, 12)]     # middle layer
+    tgt = np.c_[rng.uniform(0.0, 1.0, 9), -rng.uniform(0.02, 0.4, 9)]       # bottom layer
+    q = workloads.complex_normal(rng, (1, 12))[0]
+    flip = np.array([1.0, -1.0])
+    u = run_up(gpu_lib, (K3[2], K3[1], K3[0]), (-IF3[1], -IF3[0]), src * flip, q, tgt * flip, 1e-12)
+    m = oracle.Media(K3, IF3)
+    ref = np.zeros(tgt.shape[0], complex)
+    for j in range(src.shape[0]):
+        ref += q[j] * middle_source_field(m, 3, tgt[:, 0], tgt[:, 1] - IF3[0], src[j, 0], src[j, 1] - IF3[0])
+    e = rel(u, ref)
+    print("middle -> bottom by the mirrored medium vs oracle: %.2e" % e)
+    assert e < 1e-10

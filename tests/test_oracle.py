@@ -583,3 +583,15 @@ def test_cross_layer_reciprocity_between_independent_paths():
         a = middle_source_field(m, 1, xt, yt, xm, ym)[0]
         b = oracle.layer_field(m, 2, xm, ym, xt, yt)[0]
         assert abs(a - b) < 1e-10 * abs(a), (a, b)
+
+
+def test_middle_to_bottom_equals_the_mirrored_medium():
+    """A middle-layer source seen in the bottom layer (``middle``) equals, after
+    the mirror y -> -y and the symmetry of G, a top-layer source of the
+    mirrored medium (k3, k2, k1) seen in its middle layer (``layer_field``)."""
+    m = Media(KM, IF3)
+    mf = Media((KM[2], KM[1], KM[0]), (-IF3[1], -IF3[0]))
+    for (xs, ys), (xt, yt) in (((0.1, 0.3), (0.4, -0.2)), ((0.7, 0.06), (0.2, -0.05))):
+        a = middle_source_field(m, 3, xt, yt - IF3[0], xs, ys - IF3[0])[0]
+        b = oracle.layer_field(mf, 2, xs, -ys - mf.y_top, xt, -yt - mf.y_top)[0]
+        assert abs(a - b) < 1e-10 * abs(a), (a, b)
