@@ -457,7 +457,7 @@ __global__ void __launch_bounds__(XL_THREADS) k_ml_eval(int nq, const XmNode* __
 cd gam(cd lam, double k) { return std::sqrt(lam * lam - k * k); }
 
 // Panels of the half contour s in [0, send]: lambda(s) = s - i h(s), h = dip
-// sin(pi s / L) on [0, L]. Widths: 4 radians of the phase of e^{i lambda x}
+// sin(pi s / L) on [0, L]. Widths: 8 radians of the phase of e^{i lambda x}
 // and of the e^{-g y} factors away from the branch points, half the distance
 // to each branch point k_j (measured from the dipped contour), half the dip
 // over the range of the guided-mode poles; 16 Gauss-Legendre nodes per panel.
@@ -474,7 +474,9 @@ XlRule xl_rule(const double k[3], int layers, double xspan, double ysum_min, dou
   r.dip = std::min(3.0 / std::max(xspan, 1e-9), 0.15 * r.L);
   // beyond L every factor decays at least like e^{-lambda ysum_min}
   const double send = r.L + (std::log(1.0 / tol) + 10.0) / ysum_min;
-  const double wcap = std::max(4.0 / (xspan + yrate), 1e-6);
+  // at most 8 radians of phase per 16-node panel (Gauss-Legendre integrates
+  // e^{i phi} over 8 radians to about 1e-16)
+  const double wcap = std::max(8.0 / (xspan + yrate), 1e-6);
   const double ks[3] = {k[0], k[1], layers == 3 ? k[2] : k[1]};
   auto h_of = [&](double s) { return s < r.L ? r.dip * std::sin(M_PI * s / r.L) : 0.0; };
   auto width = [&](double s) {
