@@ -142,7 +142,11 @@ constexpr size_t kSplitLdsMax = kCuLds - 1024;
 
 // cut: the t range ends where the integrand has fallen by e^-cut from its
 // largest value (44 by default, below double precision)
-Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N, double cut = 44.0) {
+// phase: radians of phase per 16-point panel (4 for the tables; the direct
+// near-interface nodes, applied at every call, take 8: Gauss-Legendre
+// integrates e^{i phi} over 8 radians to about 1e-16)
+Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N, double cut = 44.0,
+                double phase = 4.0) {
   Rule r;
   const double k = m.k1;
   xmax = std::fabs(xmax);
@@ -162,7 +166,7 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N, d
     // min(d k1^2 / sqrt(k2^2 - k1^2), 2 d k1) per unit tau
     double slab = 0.0;
     if (m.layers == 3 && m.k2 > k) slab = std::min(m.d * k * k / std::sqrt(m.k2 * m.k2 - k * k), 2.0 * m.d * k);
-    double wmax = std::min(4.0 / (k * rho + N + 1.0 + slab), M_PI / 4.0);
+    double wmax = std::min(phase / (k * rho + N + 1.0 + slab), M_PI / 4.0);
     double s = 0.0;
     while (s < M_PI) {
       double dist = std::min(s, M_PI - s);
@@ -205,7 +209,7 @@ Rule build_rule(const Medium& m, double xmax, double ymin, double ymax, int N, d
   while (f(tend) > fmaxv - cut) tend *= 1.25;
   tend = std::max(tend, r.send + 1.0);
   const double rate = ymax + xmax + (double)N / k;
-  const double wcap = std::max(4.0 / rate, 1e-6);
+  const double wcap = std::max(phase / rate, 1e-6);
   auto width = [&](double s) {
     double w = wcap;
     double h = (s < r.send) ? r.dip * std::sin(M_PI * s / r.send) : 0.0;
@@ -1684,7 +1688,7 @@ hfmm_status_t hfmm_plan(hfmm_plan_t* out, int32_t layers, const double* wavenumb
       if_node_off.push_back((int)qc.size());
       continue;
     }
-    Rule r = build_rule(pl->med, C.xsp, C.ylo, C.yhi, 0, if_cut);
+    Rule r = build_rule(pl->med, C.xsp, C.ylo, C.yhi, 0, if_cut, 8.0);
     if (!r.ok) {
       fail(HFMM_ERR_ACCURACY, "near-interface quadrature rule too long");
       return bail(HFMM_ERR_ACCURACY);

@@ -18,7 +18,7 @@ the blocked pipeline against the plane pipeline at 1e-12; the adjoint
 against conj(A conj(v)) (A is symmetric) at 1e-12; the coordinate gradient of
 11 columns against the sum of single-column gradients at 1e-12; a three-layer
 strip against the oracle at 1e-10; and the apply time of the unrefined strip
-plan within 3x of the refined one (measured 1.7x).
+plan within 3x of the refined one (measured 1.6x).
 """
 import math
 
