@@ -7,7 +7,9 @@ Hankel function) to 1e-10; three layers (targets in the middle and the bottom
 layer) and two layers against the oracle's sum of the middle- and
 bottom-layer densities to 1e-10 at tol 1e-12, and the reverse pairs (sources
 below, targets in the top layer) against the same fields read by
-reciprocity; five right-hand sides (two
+reciprocity; the pairs between the middle and the bottom layer (both
+directions, by the mirrored medium) against the oracle's middle-layer source
+to 1e-10; five right-hand sides (two
 groups of the node sums) against single columns to 1e-14; points on the
 wrong side of the interface are HFMM_ERR_DOMAIN, the impedance half-space
 HFMM_ERR_UNSUPPORTED.
@@ -145,4 +147,26 @@ def test_middle_to_bottom_pairs_by_the_mirrored_medium(gpu_lib):
         ref += q[j] * middle_source_field(m, 3, tgt[:, 0], tgt[:, 1] - IF3[0], src[j, 0], src[j, 1] - IF3[0])
     e = rel(u, ref)
     print("middle -> bottom by the mirrored medium vs oracle: %.2e" % e)
+    assert e < 1e-10
+
+
+def test_bottom_to_middle_pairs_by_the_mirrored_medium(gpu_lib):
+    """Sources in the bottom layer, targets in the middle layer: mirrored in y
+    the sources lie in the top layer of (k3, k2, k1) and the targets below
+    its interface, so hfmm_transmit of the mirrored medium gives them. The
+    oracle's value by the symmetry of the Green's function: the field at each
+    bottom-layer source of a unit source at the middle-layer target
+    (oracle.middle, the middle-layer source seen in the bottom layer)."""
+    from oracle.middle import middle_source_field
+    rng = workloads.rng_for(1703, 9136, 209)
+    src = np.c_[rng.uniform(0.0, 1.0, 11), -rng.uniform(0.02, 0.4, 11)]     # bottom layer
+    tgt = np.c_[rng.uniform(0.0, 1.0, 8), rng.uniform(0.03, 0.47, 8)]       # middle layer
+    q = workloads.complex_normal(rng, (1, 11))[0]
+    flip = np.array([1.0, -1.0])
+    u = run(gpu_lib, (K3[2], K3[1], K3[0]), (-IF3[1], -IF3[0]), src * flip, q, tgt * flip, 1e-12)
+    m = oracle.Media(K3, IF3)
+    ref = np.array([np.dot(q, middle_source_field(m, 3, src[:, 0], src[:, 1] - IF3[0], t[0], t[1] - IF3[0]))
+                    for t in tgt])
+    e = rel(u, ref)
+    print("bottom -> middle by the mirrored medium vs oracle: %.2e" % e)
     assert e < 1e-10
