@@ -5,7 +5,8 @@ matvec itself on the two-layer ellipse workload.
 Bar: relative L2 error of the (N, 2) gradient below 1e-7 against the oracle
 (plans at tol 1e-10); per coordinate, central differences agree to 1e-6
 relative (h = 1e-6, FP64, the plan rebuilt for each moved point with the
-same tree).
+same tree); an FP32-near-field plan's gradient equals the FP64 plan's to
+1e-12 (both run the FP64 gradient kernels).
 """
 import numpy as np
 import pytest
@@ -194,3 +195,30 @@ def test_gradient_sums_over_right_hand_sides(gpu_lib):
     print("two right-hand sides vs the sum of single ones:", rel(g2, gs))
     assert rel(g2, gs) < 1e-12
     plan.close()
+
+
+def test_fp32_plan_gradient_is_the_fp64_one(gpu_lib):
+    """A plan with the FP32 near field computes its coordinate gradient with
+    the FP64 kernels (the direct-pair gradient has one form, and the
+    single-right-hand-side expansions stay FP64), so its gradient equals the
+    FP64 plan's up to the order of rounding and the central-difference check
+    above covers both precisions; its adjoint matvec carries the FP32 near
+    field (1e-6 of the FP64 one)."""
+    import torch
+    dev = torch.device("cuda:0")
+    w = workloads.two_layer_uniform(n=4096, seed=88)
+    pts = torch.tensor(w.xy, dtype=torch.float64, device=dev)
+    q = torch.tensor(w.q, dtype=torch.complex128, device=dev)
+    v = torch.tensor(workloads.complex_normal(workloads.rng_for(1703, 9136, 89), (1, w.n)),
+                     dtype=torch.complex128, device=dev)
+    p64 = gpu_lib.Plan(w.k, w.interfaces, pts, tol=1e-8, leaf_size=32)
+    p32 = gpu_lib.Plan(w.k, w.interfaces, pts, tol=1e-8, leaf_size=32, precision=gpu_lib.HFMM_FP32)
+    w64, g64 = p64.apply_adjoint(v, q=q, grad_xy=True)
+    w32, g32 = p32.apply_adjoint(v, q=q, grad_xy=True)
+    eg = rel(g32.cpu().numpy(), g64.cpu().numpy())
+    ew = rel(w32.cpu().numpy(), w64.cpu().numpy())
+    print("FP32 plan vs FP64 plan: gradient %.2e, adjoint %.2e" % (eg, ew))
+    assert eg < 1e-12
+    assert ew < 1e-6
+    p64.close()
+    p32.close()
